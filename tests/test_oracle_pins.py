@@ -1,0 +1,344 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these compares the oracle with itself: each check is a brute force
+written independently in NumPy, a closed form, a library routine (SciPy), an
+invariant that the paper states, a printed number of the paper, or finite
+differences.  Images are non-square so that a swapped row/column index fails.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import ndimage, special
+
+import oracle
+from synthimg import voronoi_image
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rand_img(H, W, seed, lo=0.0, hi=255.0):
+    return np.random.default_rng(seed).uniform(lo, hi, size=(H, W))
+
+
+# ---------------------------------------------------------------------------
+# eqs. (3)-(5): the factorisation and the Gauss-polynomial
+# ---------------------------------------------------------------------------
+
+def test_fig1_scaling_factor():
+    g = json.load(open(os.path.join(GOLDEN, "fig1_decomposition.json")))
+    tau, sr = g["tau"], g["sigma_r"]
+    # first factor of eq. (3): the scaling between panel (a) and (b)x(c)
+    factor = math.exp(-tau * tau / (2 * sr * sr))
+    assert abs(factor - g["scaling_factor_about"]) <= g["scaling_factor_rel_tol"] * g["scaling_factor_about"]
+    # eq. (3) is exact: with enough Taylor terms, eq. (5) reproduces g_r(t - tau)
+    for t in np.linspace(*g["range"], 52):
+        ref = math.exp(-(t - tau) ** 2 / (2 * sr * sr))
+        assert oracle.gauss_poly(t, tau, sr, 250) == pytest.approx(ref, rel=1e-12, abs=1e-300)
+
+
+@pytest.mark.parametrize("N", [10, 20])
+@pytest.mark.parametrize("tau", [0.0, 10.0, 50.0, 120.0])
+def test_gauss_poly_incomplete_gamma(N, tau):
+    # Fig. 2/3 settings (sigma_r = 30, degree 10 / 20, tau in {0,10,50,120}).
+    # The truncated exponential series is e^x Q(N+1, x) for x >= 0.
+    sr = 30.0
+    for t in np.linspace(0.0, 255.0, 35):
+        x = tau * t / sr ** 2
+        TN = math.exp(x) * special.gammaincc(N + 1, x) if x > 0 else 1.0
+        ref = math.exp(-tau ** 2 / (2 * sr ** 2)) * math.exp(-t ** 2 / (2 * sr ** 2)) * TN
+        assert oracle.gauss_poly(t, tau, sr, N) == pytest.approx(ref, rel=1e-11, abs=1e-300)
+
+
+def test_gauss_poly_exact_at_tau_zero():
+    # "when tau = 0 there is nothing to approximate"
+    for t in np.linspace(-200, 200, 41):
+        assert oracle.gauss_poly(t, 0.0, 30.0, 0) == pytest.approx(math.exp(-t * t / 1800.0), rel=1e-14)
+
+
+def test_gauss_poly_error_grows_with_tau():
+    # Fig. 3(a): for a fixed degree the error grows with |tau|; centring helps
+    sr, N = 30.0, 20
+    ts = np.linspace(0, 255, 256)
+
+    def maxerr(tau, shift=0.0):
+        return max(abs(oracle.gauss_poly(t - shift, tau - shift, sr, N) - math.exp(-(t - tau) ** 2 / (2 * sr * sr))) for t in ts)
+
+    errs = [maxerr(tau) for tau in (0.0, 10.0, 50.0, 120.0)]
+    assert errs[0] < 1e-15 or errs[0] <= errs[1]
+    assert errs[1] < errs[2] < errs[3]
+    # centring the range at 127.5 reduces the worst error for tau = 120
+    assert maxerr(120.0, shift=127.5) < 1e-3 * errs[3]
+
+
+def test_even_degree_positive_odd_not():
+    # T_N(x) > 0 for all real x when N is even; odd N goes negative
+    xs = np.linspace(-25, 25, 2001)
+    for N in (2, 10, 20, 40):
+        vals = [oracle.gauss_poly(x, 1.0, 1.0, N) for x in xs]
+        assert min(vals) > 0
+    assert min(oracle.gauss_poly(x, 1.0, 1.0, 21) for x in xs) < 0
+
+
+# ---------------------------------------------------------------------------
+# spatial filter, eq. (8), and the kernel tables
+# ---------------------------------------------------------------------------
+
+def test_spatial_matches_2d_double_sum():
+    f = rand_img(7, 11, 1)
+    for k in (oracle.gauss_table(1.3, 4), oracle.deriche_table(1.7, 6)):
+        assert np.allclose(oracle.spatial(f, k), oracle.brute_spatial(f, k), rtol=1e-13, atol=1e-10)
+
+
+def test_spatial_matches_scipy():
+    f = rand_img(23, 17, 2)
+    k = oracle.gauss_table(2.0, 6)
+    w = np.concatenate([k[:0:-1], k])
+    ref = ndimage.correlate1d(ndimage.correlate1d(f, w, axis=0, mode="constant"), w, axis=1, mode="constant")
+    assert np.allclose(oracle.spatial(f, k), ref, rtol=1e-13, atol=1e-10)
+
+
+def test_gauss_table_closed_form():
+    k = oracle.gauss_table(2.5, 8)
+    assert np.allclose(k, np.exp(-np.arange(9) ** 2 / 12.5), rtol=1e-15)
+
+
+def test_deriche_fit_to_gaussian():
+    # the published constants approximate exp(-t^2/2) with a small error
+    ts = np.linspace(0, 8, 801)
+    h = np.array([oracle.deriche_h(t) for t in ts])
+    assert np.max(np.abs(h - np.exp(-ts ** 2 / 2))) < 6e-4
+    assert h[0] == pytest.approx(1.680 - 0.6803, rel=1e-15)
+    tt = np.linspace(0, 40, 400001)
+    hh = np.array([oracle.deriche_h(t) for t in tt[::100]])
+    integ = 2 * np.trapezoid(np.array([oracle.deriche_h(t) for t in tt]), tt)
+    assert integ == pytest.approx(math.sqrt(2 * math.pi), rel=3e-4)
+    assert hh[-1] < 1e-28
+    # sampled tables agree with the sampled Gaussian at every scale
+    for s in (1.0, 3.0, 10.0, 20.0):
+        R = int(6 * s)
+        assert np.max(np.abs(oracle.deriche_table(s, R) - oracle.gauss_table(s, R))) < 6e-4
+
+
+@pytest.mark.parametrize("kind", ["gauss", "deriche"])
+def test_dtables_are_log_sigma_derivatives(kind):
+    tab = oracle.gauss_table if kind == "gauss" else oracle.deriche_table
+    dtab = oracle.gauss_dtable if kind == "gauss" else oracle.deriche_dtable
+    s, R, h = 2.3, 14, 1e-5
+    fd = (tab(s * math.exp(h), R) - tab(s * math.exp(-h), R)) / (2 * h)
+    assert np.allclose(dtab(s, R), fd, rtol=1e-7, atol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# eq. (1), the direct filter
+# ---------------------------------------------------------------------------
+
+def test_direct_matches_double_sum():
+    f = rand_img(6, 9, 3)
+    for s, r in ((1.0, 30.0), (1.5, 10.0)):
+        k = oracle.gauss_table(s, oracle.fir_radius(s))
+        assert np.allclose(oracle.direct(f, r, k), oracle.brute_direct(f, r, k), rtol=1e-13, atol=1e-10)
+
+
+def test_direct_wide_range_kernel_is_normalised_blur():
+    f = rand_img(21, 30, 4)
+    k = oracle.gauss_table(2.0, 6)
+    w = np.concatenate([k[:0:-1], k])
+
+    def blur(a):
+        return ndimage.correlate1d(ndimage.correlate1d(a, w, axis=0, mode="constant"), w, axis=1, mode="constant")
+
+    ref = blur(f) / blur(np.ones_like(f))
+    assert np.allclose(oracle.direct(f, 1e8, k), ref, rtol=1e-9, atol=1e-8)
+
+
+def test_direct_constant_image():
+    f = np.full((9, 13), 77.25)
+    assert np.allclose(oracle.direct_gauss(f, 2.0, 30.0), 77.25, rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1 against brute force, the rescaled form and the limits
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", range(6))
+def test_alg1_matches_explicit_double_sum(case):
+    rng = np.random.default_rng(100 + case)
+    H, W = int(rng.integers(5, 9)), int(rng.integers(6, 11))
+    f = rng.uniform(0, 255, size=(H, W))
+    s = float(rng.uniform(0.6, 1.8))
+    r = float(rng.uniform(25, 70))
+    N = [0, 2, 5, 8, 12, 20][case]
+    for kind in ("gauss", "deriche"):
+        R = oracle.fir_radius(s) if kind == "gauss" else 2 * oracle.fir_radius(s)
+        k = oracle.gauss_table(s, R) if kind == "gauss" else oracle.deriche_table(s, R)
+        ref = oracle.brute_gp(f, r, N, k)
+        got = oracle.gp_alg1(f, r, N, k)
+        assert np.allclose(got, ref, rtol=0, atol=1e-9), (kind, np.max(np.abs(got - ref)))
+
+
+def test_alg1_odd_degree_matches_double_sum():
+    f = rand_img(6, 7, 9, 80, 180)
+    k = oracle.gauss_table(1.2, 4)
+    for N in (1, 3, 7):
+        assert np.allclose(oracle.gp_alg1(f, 60.0, N, k), oracle.brute_gp(f, 60.0, N, k), rtol=0, atol=1e-9)
+
+
+def test_alg1_equals_rescaled_form():
+    f = voronoi_image(64, 48, 12, seed=7).astype(np.float64)
+    for mode, s in (("fir", 3.0), ("iir", 2.5)):
+        k, _ = oracle.spatial_table(mode, s, *f.shape)
+        a = oracle.gp_alg1(f, 30.0, 20, k)
+        b = oracle.gp_rescaled(f, 30.0, 20, k)
+        assert np.max(np.abs(a - b)) < 1e-9
+
+
+def test_alg1_converges_to_direct_as_degree_grows():
+    f = voronoi_image(40, 56, 10, seed=8).astype(np.float64)
+    s, r = 2.0, 30.0
+    k = oracle.gauss_table(s, oracle.fir_radius(s))
+    ref = oracle.direct(f, r, k)
+    errs = [np.max(np.abs(oracle.gp_alg1(f, r, N, k) - ref)) for N in (10, 20, 40, 60)]
+    assert errs[0] > errs[1] > errs[2] > errs[3]
+    assert errs[3] < 1e-6
+    # the same holds with the recursive-Gaussian kernel and its own direct filter
+    kd, _ = oracle.spatial_table("iir", s, *f.shape)
+    assert np.max(np.abs(oracle.gp_alg1(f, r, 60, kd) - oracle.direct(f, r, kd))) < 1e-6
+
+
+def test_alg1_wide_range_kernel_is_normalised_blur():
+    f = rand_img(19, 26, 10)
+    k = oracle.gauss_table(1.5, 5)
+    w = np.concatenate([k[:0:-1], k])
+
+    def blur(a):
+        return ndimage.correlate1d(ndimage.correlate1d(a, w, axis=0, mode="constant"), w, axis=1, mode="constant")
+
+    ref = blur(f) / blur(np.ones_like(f))
+    assert np.allclose(oracle.gp_alg1(f, 1e7, 2, k), ref, rtol=0, atol=1e-7)
+
+
+def test_alg1_constant_image_unchanged():
+    f = np.full((11, 8), 201.5)
+    for N in (0, 1, 20):
+        out = oracle.gp(f, 2.0, 30.0, N)
+        assert np.max(np.abs(out - 201.5)) < 1e-12
+
+
+def test_alg1_translation_equivariance():
+    # the Proposition, eq. (6): shifting the intensities shifts the output
+    f = voronoi_image(30, 41, 8, seed=11).astype(np.float64)
+    a = oracle.gp(f, 2.0, 30.0, 20)
+    b = oracle.gp(f + 37.5, 2.0, 30.0, 20)
+    assert np.max(np.abs(b - (a + 37.5))) < 1e-9
+
+
+def test_alg1_negation_and_scale():
+    f = voronoi_image(33, 27, 8, seed=12).astype(np.float64)
+    a = oracle.gp(f, 2.0, 30.0, 20)
+    assert np.max(np.abs(oracle.gp(-f, 2.0, 30.0, 20) + a)) < 1e-9
+    assert np.max(np.abs(oracle.gp(2.5 * f, 2.0, 75.0, 20) - 2.5 * a)) < 1e-8
+
+
+def test_alg1_transpose_and_flips():
+    f = voronoi_image(29, 37, 9, seed=13).astype(np.float64)
+    for mode in ("fir", "iir"):
+        a = oracle.gp(f, 2.0, 30.0, 20, mode)
+        assert np.max(np.abs(oracle.gp(f.T.copy(), 2.0, 30.0, 20, mode) - a.T)) < 1e-9
+        assert np.max(np.abs(oracle.gp(f[::-1].copy(), 2.0, 30.0, 20, mode) - a[::-1])) < 1e-9
+        assert np.max(np.abs(oracle.gp(f[:, ::-1].copy(), 2.0, 30.0, 20, mode) - a[:, ::-1])) < 1e-9
+
+
+def test_alg1_even_degree_stays_in_range():
+    f = voronoi_image(48, 40, 15, seed=14).astype(np.float64)
+    for N in (2, 8, 20):
+        out = oracle.gp(f, 2.0, 25.0, N)
+        assert out.min() >= f.min() - 1e-9 and out.max() <= f.max() + 1e-9
+
+
+def test_alg1_kernel_gain_invariance():
+    f = rand_img(17, 22, 15)
+    k = oracle.gauss_table(1.5, 5)
+    assert np.max(np.abs(oracle.gp_alg1(f, 30.0, 20, k) - oracle.gp_alg1(f, 30.0, 20, 3.7 * k))) < 1e-9
+
+
+def test_centres_agree_in_the_limit_and_differ_at_low_degree():
+    f = voronoi_image(24, 31, 7, seed=16).astype(np.float64)
+    k = oracle.gauss_table(1.5, 5)
+    outs = [oracle.gp_alg1(f, 30.0, 60, k, c) for c in (oracle.CENTER_MEAN, oracle.CENTER_MIDRANGE)]
+    assert np.max(np.abs(outs[0] - outs[1])) < 1e-6
+    # without centring |tau t| / sigma_r^2 reaches (255/30)^2 = 72, so the
+    # series needs a far higher degree before it reaches the same limit
+    uncentred = oracle.gp_alg1(f, 30.0, 150, k, oracle.CENTER_NONE)
+    assert np.max(np.abs(outs[0] - uncentred)) < 1e-6
+    low = [oracle.gp_alg1(f, 30.0, 8, k, c) for c in (oracle.CENTER_MEAN, oracle.CENTER_NONE)]
+    ref = oracle.direct(f, 30.0, k)
+    # centring reduces the error of a low-degree approximation
+    assert np.max(np.abs(low[0] - ref)) < np.max(np.abs(low[1] - ref))
+
+
+# ---------------------------------------------------------------------------
+# gradients
+# ---------------------------------------------------------------------------
+
+def _loss(f, target, s, r, N, mode, R):
+    k = oracle.gauss_table(s, R) if mode == "fir" else oracle.deriche_table(s, R)
+    out = oracle.gp_alg1(f, r, N, k)
+    return 0.5 * float(np.sum((out - target) ** 2)), out
+
+
+@pytest.mark.parametrize("mode", ["fir", "iir"])
+def test_gradients_match_finite_differences(mode):
+    f = voronoi_image(9, 11, 4, seed=17).astype(np.float64)
+    target = voronoi_image(9, 11, 4, seed=18).astype(np.float64)
+    s, r, N = 1.3, 25.0, 8
+    R = oracle.fir_radius(s) if mode == "fir" else 10
+    _, out = _loss(f, target, s, r, N, mode, R)
+    k = oracle.gauss_table(s, R) if mode == "fir" else oracle.deriche_table(s, R)
+    kt = oracle.gauss_dtable(s, R) if mode == "fir" else oracle.deriche_dtable(s, R)
+    gf, gls, glr = oracle.gp_grad(f, out - target, r, N, k, kt)
+    h = 1e-4
+    fd_f = np.empty_like(f)
+    for idx in np.ndindex(f.shape):
+        fp = f.copy(); fp[idx] += h
+        fm = f.copy(); fm[idx] -= h
+        fd_f[idx] = (_loss(fp, target, s, r, N, mode, R)[0] - _loss(fm, target, s, r, N, mode, R)[0]) / (2 * h)
+    scale = np.max(np.abs(fd_f))
+    assert np.max(np.abs(gf - fd_f)) < 1e-6 * scale
+    fd_s = (_loss(f, target, s * math.exp(h), r, N, mode, R)[0] - _loss(f, target, s * math.exp(-h), r, N, mode, R)[0]) / (2 * h)
+    fd_r = (_loss(f, target, s, r * math.exp(h), N, mode, R)[0] - _loss(f, target, s, r * math.exp(-h), N, mode, R)[0]) / (2 * h)
+    assert gls == pytest.approx(fd_s, rel=1e-6, abs=1e-8 * scale)
+    assert glr == pytest.approx(fd_r, rel=1e-6, abs=1e-8 * scale)
+
+
+def test_sigma_s_gradient_ignores_kernel_gain():
+    f = rand_img(10, 8, 19)
+    g = rand_img(10, 8, 20, -1, 1)
+    k = oracle.gauss_table(1.4, 5)
+    kt = oracle.gauss_dtable(1.4, 5)
+    _, a, _ = oracle.gp_grad(f, g, 30.0, 10, k, kt)
+    _, b, _ = oracle.gp_grad(f, g, 30.0, 10, k, kt + 0.37 * k)
+    assert b == pytest.approx(a, rel=1e-9, abs=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# error measure and the Table 1 trend
+# ---------------------------------------------------------------------------
+
+def test_mse_db_definition():
+    a = np.zeros((4, 4))
+    assert oracle.mse_db(a, a + 1.0) == pytest.approx(0.0)
+    assert oracle.mse_db(a, a + 10.0) == pytest.approx(20.0)
+
+
+def test_table1_trend_error_grows_with_sigma_s():
+    # Table 1: at sigma_r = 30 and N = 20 the GP error to eq. (1) rises with
+    # sigma_s (the Peppers values themselves are not reproducible here)
+    g = json.load(open(os.path.join(GOLDEN, "table1_setting.json")))
+    f = voronoi_image(64, 64, 10, seed=21).astype(np.float64)
+    db = []
+    for s in g["sigma_s"][:4]:
+        db.append(oracle.mse_db(oracle.gp(f, s, g["sigma_r"], g["N"]), oracle.direct_gauss(f, s, g["sigma_r"])))
+    assert all(b > a for a, b in zip(db, db[1:])), db
