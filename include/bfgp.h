@@ -1,0 +1,155 @@
+/*
+ * bfgp -- Gauss-polynomial (GP) bilateral filter on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libbfgp.so.  Method: K. N. Chaudhury, "Fast and Accurate Bilateral
+ * Filtering using Gauss-Polynomial Decomposition", arXiv 1505.00077.
+ *
+ * General conventions (every entry point):
+ *  - Images are single-channel float32, row-major, H rows by W columns, with a
+ *    row pitch given in ELEMENTS (pitch >= W).  Input and output share the pitch.
+ *  - All image, workspace and gradient pointers are DEVICE pointers owned by the
+ *    caller.  The library allocates no device memory in any entry point.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Every compute entry point only enqueues work on `stream` and returns; it
+ *    never synchronises, except bf_gp_status which is documented as blocking.
+ *  - Return value: BF_OK (0) or a negative bf_status.  Argument checks run on the
+ *    host before any HIP call, so a rejected call enqueues nothing.  The text of
+ *    the last failure on the calling thread is returned by bf_last_error().
+ *  - Entry points are thread-safe as long as concurrent calls do not share a
+ *    workspace.  Calls that share a workspace must be ordered on one stream.
+ */
+#ifndef BFGP_H
+#define BFGP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define BF_OK 0
+#define BF_EINVAL (-1)       /* a pointer, size or parameter is invalid            */
+#define BF_ENOMEM (-2)       /* the workspace passed is smaller than required      */
+#define BF_ERANGE (-3)       /* intensities too far from the centre for FP32
+                                channels (reported by bf_gp_status)                */
+#define BF_EHIP (-4)         /* a HIP runtime call failed                          */
+#define BF_EUNSUPPORTED (-5) /* valid but not supported (e.g. FIR radius too large) */
+
+/* ---- flags ---------------------------------------------------------------- */
+/* Spatial filter used for the Gaussian filterings of eq. (8) (bits 0-1). */
+#define BF_SPATIAL_AUTO 0u   /* FIR below the crossover sigma_s, IIR above        */
+#define BF_SPATIAL_FIR 1u    /* sampled Gaussian over |d| <= ceil(3 sigma_s), the
+                                window of eq. (1)                                 */
+#define BF_SPATIAL_IIR 2u    /* Deriche's 4th-order recursive Gaussian (causal +
+                                anticausal, zero initial state), as in the
+                                paper's experiments                                */
+#define BF_SPATIAL_MASK 3u
+/* Centre t_c of the intensity range (bits 2-3); Section 2, eq. (6). */
+#define BF_CENTER_MEAN 0u     /* the mean, as in Algorithm 1 (default)           */
+#define BF_CENTER_MIDRANGE 4u /* (min + max) / 2                                  */
+#define BF_CENTER_NONE 8u     /* t_c = 0                                          */
+#define BF_CENTER_MASK 12u
+
+#define BF_MAX_DEGREE 64      /* largest N accepted                               */
+#define BF_FIR_MAX_RADIUS 24  /* largest FIR radius ceil(3 sigma_s) (sigma_s <= 8) */
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int bf_version(void);
+
+/* Message for the last non-zero status returned on the calling thread
+ * (never NULL; empty when there was none). */
+const char *bf_last_error(void);
+
+/* ---- GP forward ------------------------------------------------------------
+ * Algorithm 1 (GPF) with the channels rescaled as u_n(x) = exp(-x^2/2) x^n /
+ * sqrt(n!), x = (f - t_c)/sigma_r, n = 0..N+1 (the images of eq. (7) divided by
+ * sqrt(n!)), the spatial filtering of eq. (8) on every channel, and the
+ * recombination of eqs. (9)-(11) in double precision:
+ *     out = t_c + sigma_r * M / D,  D = sum_{n<=N} u_n(tau) Ubar_n,
+ *                                   M = sum_{n<=N} u_n(tau) sqrt(n+1) Ubar_{n+1}.
+ * Neighbours outside the image contribute nothing (zero extension).
+ *
+ *  img, out     device, H x W with row pitch `pitch` (elements); may not alias.
+ *  sigma_s      spatial standard deviation (> 0, finite).
+ *  sigma_r      range standard deviation (> 0, finite).
+ *  N            degree of the Gauss-polynomial, 0..BF_MAX_DEGREE.  Even N keeps
+ *               every approximate weight positive; with odd N the denominator
+ *               can vanish and the output is whatever the division gives.
+ *  flags        BF_SPATIAL_* | BF_CENTER_*.
+ *  saved        NULL, or a device buffer of 16*H*W bytes that receives what
+ *               bf_gp_backward needs (per pixel: M/D and its tau-derivative as
+ *               float, the rescaled denominator as double), planar.
+ *  ws, ws_bytes device workspace of at least bf_gp_workspace_bytes(...) bytes.
+ * Intensities whose |x| is so large that the channels leave the FP32 range make
+ * the output NaN and set BF_ERANGE in the workspace status (bf_gp_status). */
+size_t bf_gp_workspace_bytes(int H, int W, int N, double sigma_s, unsigned flags);
+
+int bf_gp_forward(const float *img, float *out, int H, int W, int pitch,
+                  double sigma_s, double sigma_r, int N, unsigned flags,
+                  void *saved, void *ws, size_t ws_bytes, void *stream);
+
+/* Blocking: waits for `stream`, then stores the status of the last forward or
+ * backward that used `ws` in *status (BF_OK or BF_ERANGE). */
+int bf_gp_status(const void *ws, void *stream, int *status);
+
+/* The spatial mode BF_SPATIAL_AUTO resolves to for this sigma_s (FIR or IIR). */
+unsigned bf_gp_resolve_spatial(double sigma_s, unsigned flags);
+
+/* Sets the AUTO crossover: FIR is used while ceil(3 sigma_s) <= radius.
+ * radius in 0..BF_FIR_MAX_RADIUS (0 = always IIR).  Process-wide. */
+int bf_gp_set_fir_crossover(int radius);
+int bf_gp_get_fir_crossover(void);
+
+/* ---- GP backward -------------------------------------------------------------
+ * Adjoint of bf_gp_forward for a scalar loss L with upstream gradient
+ * grad_out = dL/dout.  Derived by the chain rule through eqs. (7)-(11) and the
+ * mean of Algorithm 1's first step; the spatial radius is held fixed when
+ * differentiating in sigma_s.
+ *  saved              the buffer filled by bf_gp_forward with the same
+ *                     image and parameters.
+ *  grad_img           NULL or device H x W (pitch) float: dL/dimg.
+ *  grad_log_sigma_s   NULL or device double: dL/d(log sigma_s) (overwritten).
+ *  grad_log_sigma_r   NULL or device double: dL/d(log sigma_r) (overwritten).
+ * Supported for BF_SPATIAL_FIR (and AUTO resolving to FIR) with centre mean or
+ * none; other modes return BF_EUNSUPPORTED. */
+size_t bf_gp_backward_workspace_bytes(int H, int W, int N, double sigma_s, unsigned flags);
+
+int bf_gp_backward(const float *img, const float *grad_out, const void *saved,
+                   int H, int W, int pitch, double sigma_s, double sigma_r, int N,
+                   unsigned flags, float *grad_img, double *grad_log_sigma_s,
+                   double *grad_log_sigma_r, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- batched GP forward ---------------------------------------------------
+ * Many images of uneven size, each with its own sigma_s and sigma_r, filtered
+ * by one persistent launch (Algorithm 1 applied per image).  Plans are host
+ * objects; bf_gp_plan_upload copies the plan's descriptors into the workspace
+ * (once, outside any graph capture); bf_gp_forward_batched then only launches
+ * kernels and may be captured into a hipGraph and replayed. */
+typedef struct bf_gp_item {
+    const float *img; /* device, H x W, row pitch `pitch` elements */
+    float *out;       /* device, same shape and pitch */
+    int H, W, pitch;
+    float sigma_s, sigma_r;
+    int N;
+} bf_gp_item;
+
+int bf_gp_plan_batched(const bf_gp_item *items, int count, unsigned flags, void **plan_out);
+size_t bf_gp_plan_workspace_bytes(const void *plan);
+int bf_gp_plan_upload(void *plan, void *ws, size_t ws_bytes, void *stream);
+int bf_gp_forward_batched(void *plan, void *ws, size_t ws_bytes, void *stream);
+void bf_gp_plan_free(void *plan);
+
+/* ---- direct filter ---------------------------------------------------------
+ * Eq. (1) evaluated directly: O((2W+1)^2) range-kernel evaluations per pixel,
+ * spatial Gaussian of eq. (2) over the square window |dy|,|dx| <= window,
+ * in-image neighbours only.  window < 0 selects ceil(3 sigma_s).  Used as the
+ * O(sigma_s^2) comparator.  window <= 64. */
+int bf_direct_forward(const float *img, float *out, int H, int W, int pitch,
+                      double sigma_s, double sigma_r, int window, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BFGP_H */

@@ -1,0 +1,168 @@
+"""Gauss-polynomial bilateral filter on MI355X (gfx950): Python binding.
+
+Thin ctypes layer over ``libbfgp.so`` (built from ``csrc/`` by ``build.py``).
+Every step of the filter runs in the library's HIP kernels; this module only
+marshals PyTorch tensors (device memory) and the current HIP stream into the
+C ABI declared in ``include/bfgp.h``.  If the library is missing, importing
+this package raises: there is no fallback.
+
+Method: K. N. Chaudhury, "Fast and Accurate Bilateral Filtering using
+Gauss-Polynomial Decomposition", arXiv 1505.00077 (Algorithm 1, eqs. (1)-(11)).
+"""
+import ctypes
+import math
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbfgp.so")
+
+BF_OK, BF_EINVAL, BF_ENOMEM, BF_ERANGE, BF_EHIP, BF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+SPATIAL = {"auto": 0, "fir": 1, "iir": 2}
+CENTER = {"mean": 0, "midrange": 4, "none": 8}
+MAX_DEGREE = 64
+FIR_MAX_RADIUS = 24
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with paper_1505_00077_amd/build.py "
+                      "(or __graft_entry__.build())")
+
+lib = ctypes.CDLL(LIB_PATH)
+
+
+class BfGpItem(ctypes.Structure):
+    _fields_ = [("img", ctypes.c_void_p), ("out", ctypes.c_void_p), ("H", ctypes.c_int), ("W", ctypes.c_int),
+                ("pitch", ctypes.c_int), ("sigma_s", ctypes.c_float), ("sigma_r", ctypes.c_float), ("N", ctypes.c_int)]
+
+
+def _sig(name, res, *args):
+    f = getattr(lib, name)
+    f.restype = res
+    f.argtypes = list(args)
+    return f
+
+
+_vp, _i, _u, _d, _sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint, ctypes.c_double, ctypes.c_size_t
+bf_version = _sig("bf_version", _i)
+bf_last_error = _sig("bf_last_error", ctypes.c_char_p)
+bf_gp_workspace_bytes = _sig("bf_gp_workspace_bytes", _sz, _i, _i, _i, _d, _u)
+bf_gp_forward = _sig("bf_gp_forward", _i, _vp, _vp, _i, _i, _i, _d, _d, _i, _u, _vp, _vp, _sz, _vp)
+bf_gp_status = _sig("bf_gp_status", _i, _vp, _vp, ctypes.POINTER(_i))
+bf_gp_resolve_spatial = _sig("bf_gp_resolve_spatial", _u, _d, _u)
+bf_gp_set_fir_crossover = _sig("bf_gp_set_fir_crossover", _i, _i)
+bf_gp_get_fir_crossover = _sig("bf_gp_get_fir_crossover", _i)
+bf_gp_backward_workspace_bytes = _sig("bf_gp_backward_workspace_bytes", _sz, _i, _i, _i, _d, _u)
+bf_gp_backward = _sig("bf_gp_backward", _i, _vp, _vp, _vp, _i, _i, _i, _d, _d, _i, _u, _vp, _vp, _vp, _vp, _sz, _vp)
+bf_gp_plan_batched = _sig("bf_gp_plan_batched", _i, ctypes.POINTER(BfGpItem), _i, _u, ctypes.POINTER(_vp))
+bf_gp_plan_workspace_bytes = _sig("bf_gp_plan_workspace_bytes", _sz, _vp)
+bf_gp_plan_upload = _sig("bf_gp_plan_upload", _i, _vp, _vp, _sz, _vp)
+bf_gp_forward_batched = _sig("bf_gp_forward_batched", _i, _vp, _vp, _sz, _vp)
+bf_gp_plan_free = _sig("bf_gp_plan_free", None, _vp)
+bf_direct_forward = _sig("bf_direct_forward", _i, _vp, _vp, _i, _i, _i, _d, _d, _i, _vp)
+
+
+class BfError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        msg = bf_last_error().decode(errors="replace")
+        super().__init__(f"{where} failed with status {code}: {msg}")
+
+
+def _check(rc, where):
+    if rc != BF_OK:
+        raise BfError(rc, where)
+
+
+def _stream(device=None):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _flags(spatial="auto", center="mean"):
+    return SPATIAL[spatial] | CENTER[center]
+
+
+def _image(t, name="img"):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float32 CUDA tensor")
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be 2-D (H, W)")
+    if t.stride(1) != 1:
+        raise ValueError(f"{name} must have unit column stride")
+    return t.shape[0], t.shape[1], t.stride(0)
+
+
+def fir_radius(sigma_s):
+    """Window half-width of eq. (1): ceil(3 sigma_s), at least 1."""
+    return max(1, int(math.ceil(3.0 * sigma_s - 1e-9)))
+
+
+def resolve_spatial(sigma_s, spatial="auto"):
+    m = bf_gp_resolve_spatial(float(sigma_s), SPATIAL[spatial])
+    return {1: "fir", 2: "iir"}[m]
+
+
+def workspace_bytes(H, W, N, sigma_s, spatial="auto", center="mean"):
+    return int(bf_gp_workspace_bytes(int(H), int(W), int(N), float(sigma_s), _flags(spatial, center)))
+
+
+def workspace(H, W, N, sigma_s, spatial="auto", device="cuda"):
+    n = workspace_bytes(H, W, N, sigma_s, spatial)
+    return torch.empty(max(n, 256), dtype=torch.uint8, device=device)
+
+
+def gp_forward(img, sigma_s, sigma_r, N=20, spatial="auto", center="mean", out=None, ws=None, saved=None,
+               check=False):
+    """GP bilateral filter of one image (Algorithm 1, rescaled channels).
+
+    img: float32 CUDA tensor (H, W).  Returns ``out``.  ``saved`` (uint8 CUDA
+    tensor of 16*H*W bytes) receives what ``gp_backward`` needs.  With
+    ``check=True`` the call synchronises and raises on BF_ERANGE."""
+    H, W, pitch = _image(img)
+    if out is None:
+        out = torch.empty_like(img)
+    else:
+        oh, ow, opitch = _image(out, "out")
+        if (oh, ow, opitch) != (H, W, pitch):
+            raise ValueError("out must have the shape and row stride of img")
+    flags = _flags(spatial, center)
+    need = int(bf_gp_workspace_bytes(H, W, int(N), float(sigma_s), flags))
+    if ws is None:
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=img.device)
+    sp = None
+    if saved is not None:
+        if saved.numel() * saved.element_size() < 16 * H * W:
+            raise ValueError("saved buffer too small")
+        sp = saved.data_ptr()
+    _check(bf_gp_forward(img.data_ptr(), out.data_ptr(), H, W, pitch, float(sigma_s), float(sigma_r), int(N), flags,
+                         sp, ws.data_ptr(), ws.numel(), _stream(img.device)), "bf_gp_forward")
+    if check:
+        st = status(ws, img.device)
+        if st != BF_OK:
+            raise BfError(st, "bf_gp_forward (device status)")
+    return out
+
+
+def status(ws, device=None):
+    """Blocking: the device status (BF_OK or BF_ERANGE) of the last call on ws."""
+    v = ctypes.c_int(0)
+    _check(bf_gp_status(ws.data_ptr(), _stream(device), ctypes.byref(v)), "bf_gp_status")
+    return v.value
+
+
+def direct_forward(img, sigma_s, sigma_r, window=-1, out=None):
+    """Eq. (1) evaluated directly on the GPU (the O(sigma_s^2) comparator)."""
+    H, W, pitch = _image(img)
+    if out is None:
+        out = torch.empty_like(img)
+    _check(bf_direct_forward(img.data_ptr(), out.data_ptr(), H, W, pitch, float(sigma_s), float(sigma_r), int(window),
+                             _stream(img.device)), "bf_direct_forward")
+    return out
+
+
+def set_fir_crossover(radius):
+    _check(bf_gp_set_fir_crossover(int(radius)), "bf_gp_set_fir_crossover")
+
+
+def get_fir_crossover():
+    return int(bf_gp_get_fir_crossover())

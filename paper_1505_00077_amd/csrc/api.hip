@@ -1,0 +1,322 @@
+// C ABI of libbfgp: argument checks, workspace layout, coefficient set-up and
+// kernel launches.  Everything here runs on the host.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <atomic>
+#include <string>
+
+#include "../../include/bfgp.h"
+#include "launch.hpp"
+#include "fir.hpp"
+#include "iir.hpp"
+#include "direct.hpp"
+
+using namespace bfgp;
+
+namespace {
+
+thread_local std::string g_err;
+std::atomic<int> g_fir_crossover{9};  // FIR while ceil(3 sigma_s) <= this radius
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(BF_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+// Window half-width of eq. (1): W = 3 sigma_s rounded up, at least 1.
+int fir_radius(double sigma_s) {
+    int r = (int)ceil(3.0 * sigma_s - 1e-9);
+    return r < 1 ? 1 : r;
+}
+
+unsigned resolve_spatial(double sigma_s, unsigned flags) {
+    unsigned m = flags & BF_SPATIAL_MASK;
+    if (m == BF_SPATIAL_FIR || m == BF_SPATIAL_IIR) return m;
+    return fir_radius(sigma_s) <= g_fir_crossover.load() ? BF_SPATIAL_FIR : BF_SPATIAL_IIR;
+}
+
+int center_code(unsigned flags) {
+    switch (flags & BF_CENTER_MASK) {
+        case BF_CENTER_MIDRANGE: return 1;
+        case BF_CENTER_NONE: return 2;
+        default: return 0;
+    }
+}
+
+// Largest |x| for which the largest channel max_n u_n(x), n <= N+1, is still at
+// least exp(-80) (well inside the FP32 normal range).  ln u_n(x) =
+// -x^2/2 + n ln x - ln(n!)/2.
+double range_limit(int N) {
+    auto ok = [N](double x) {
+        double best = -1e300;
+        for (int n = 0; n <= N + 1; ++n) {
+            double l = -0.5 * x * x + (n > 0 ? n * log(x) : 0.0) - 0.5 * lgamma(n + 1.0);
+            if (l > best) best = l;
+        }
+        return best >= -80.0;
+    };
+    double lo = 0.0, hi = 64.0;
+    for (int it = 0; it < 80; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (ok(mid)) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// IIR band height and row chunking for an image.
+constexpr int kBand = 64;
+void row_shape(int W, int *L, int *T) {
+    int l = W <= 1024 ? 4 : (W <= 4096 ? 8 : 16);
+    int t = (W + l - 1) / l;
+    t = ((t + 63) / 64) * 64;
+    *L = l;
+    *T = t;
+}
+constexpr int kIirMaxW = 8192;
+
+struct Layout {
+    size_t parts, status, carry, stack, total;
+};
+
+Layout gp_layout(int H, int W, int N, unsigned spatial) {
+    Layout L;
+    size_t off = 0;
+    L.parts = off;
+    off = align256(off + sizeof(Partial) * kMaxParts);
+    L.status = off;
+    off = align256(off + 16);
+    L.carry = L.stack = off;
+    if (spatial == BF_SPATIAL_IIR) {
+        const size_t C = (size_t)N + 2;
+        const size_t nb = ((size_t)H + kBand - 1) / kBand;
+        L.carry = off;
+        off = align256(off + sizeof(float) * nb * C * 8 * (size_t)W);
+        L.stack = off;
+        off = align256(off + sizeof(float) * C * (size_t)H * (size_t)W);
+    }
+    L.total = off;
+    return L;
+}
+
+int check_image(const void *img, const void *out, int H, int W, int pitch) {
+    if (!img || !out) return fail(BF_EINVAL, "null image pointer");
+    if (H < 1 || W < 1) return fail(BF_EINVAL, "image size %dx%d must be at least 1x1", H, W);
+    if (pitch < W) return fail(BF_EINVAL, "pitch %d is smaller than the width %d", pitch, W);
+    if ((size_t)H * (size_t)pitch >= ((size_t)1 << 40)) return fail(BF_EINVAL, "image too large");
+    return BF_OK;
+}
+
+int check_params(double sigma_s, double sigma_r, int N) {
+    if (!finite_pos(sigma_s)) return fail(BF_EINVAL, "sigma_s must be finite and > 0");
+    if (!finite_pos(sigma_r)) return fail(BF_EINVAL, "sigma_r must be finite and > 0");
+    if (N < 0 || N > BF_MAX_DEGREE) return fail(BF_EINVAL, "degree N=%d outside 0..%d", N, BF_MAX_DEGREE);
+    return BF_OK;
+}
+
+int check_spatial(unsigned spatial, double sigma_s, int W) {
+    if (spatial == BF_SPATIAL_FIR && fir_radius(sigma_s) > BF_FIR_MAX_RADIUS)
+        return fail(BF_EUNSUPPORTED, "FIR radius %d exceeds %d (use the IIR mode)", fir_radius(sigma_s),
+                    BF_FIR_MAX_RADIUS);
+    if (spatial == BF_SPATIAL_IIR && W > kIirMaxW)
+        return fail(BF_EUNSUPPORTED, "IIR mode supports widths up to %d", kIirMaxW);
+    return BF_OK;
+}
+
+GPParams make_params(const float *img, float *out, int H, int W, int pitch, double sigma_r, int N,
+                     unsigned flags, char *ws, const Layout &L, void *saved) {
+    GPParams p;
+    memset(&p, 0, sizeof p);
+    p.img = img;
+    p.out = out;
+    p.H = H;
+    p.W = W;
+    p.pitch = pitch;
+    p.N = N;
+    p.C = N + 2;
+    p.center = center_code(flags);
+    p.sigma_r = sigma_r;
+    p.inv_sigma_r = 1.0 / sigma_r;
+    p.xlim = range_limit(N);
+    p.parts = (const Partial *)(ws + L.parts);
+    p.nparts = H < kMaxParts ? H : kMaxParts;
+    p.status = (int *)(ws + L.status);
+    p.saved = saved;
+    for (int n = 0; n <= kMaxC; ++n) {
+        p.sq[n] = sqrt((double)n);
+        p.isq[n] = n > 0 ? 1.0 / sqrt((double)n) : 0.0;
+    }
+    return p;
+}
+
+FirTaps make_taps(double sigma_s, int R) {
+    FirTaps t;
+    memset(&t, 0, sizeof t);
+    for (int d = 0; d <= R; ++d) t.k[d] = (float)exp(-(double)d * d / (2.0 * sigma_s * sigma_s));
+    return t;
+}
+
+// Deriche's fourth-order recursive Gaussian (published constants): for t >= 0,
+//   h(t) = (a0 cos(w0 t) + a1 sin(w0 t)) e^{-b0 t} + (c0 cos(w1 t) + c1 sin(w1 t)) e^{-b1 t},
+// t = |d| / sigma_s.  Each damped sinusoid alpha cos(w t) + beta sin(w t) e^{-l t}
+// sampled at integers is the impulse response of the second-order section
+//   y_n = alpha x_n + r (beta sin th - alpha cos th) x_{n-1} + 2 r cos th y_{n-1} - r^2 y_{n-2},
+// th = w / sigma_s, r = e^{-l / sigma_s}; its strictly anticausal half uses
+// m1 = n1 - n0 d1, m2 = -n0 d2.
+void mat2_mul(const double *A, const double *B, double *C) {
+    double c0 = A[0] * B[0] + A[1] * B[2], c1 = A[0] * B[1] + A[1] * B[3];
+    double c2 = A[2] * B[0] + A[3] * B[2], c3 = A[2] * B[1] + A[3] * B[3];
+    C[0] = c0; C[1] = c1; C[2] = c2; C[3] = c3;
+}
+void mat2_pow(const double *A, long m, double *R) {
+    double base[4] = {A[0], A[1], A[2], A[3]};
+    R[0] = 1; R[1] = 0; R[2] = 0; R[3] = 1;
+    while (m > 0) {
+        if (m & 1) mat2_mul(R, base, R);
+        mat2_mul(base, base, base);
+        m >>= 1;
+    }
+}
+
+IirCoef make_iir(double sigma_s, int B, int L) {
+    static const double al[2] = {1.680, -0.6803}, be[2] = {3.735, -0.2598};
+    static const double la[2] = {1.783, 1.723}, om[2] = {0.6318, 1.997};
+    IirCoef c;
+    memset(&c, 0, sizeof c);
+    for (int s = 0; s < 2; ++s) {
+        const double th = om[s] / sigma_s, r = exp(-la[s] / sigma_s);
+        const double n0 = al[s], n1 = r * (be[s] * sin(th) - al[s] * cos(th));
+        const double d1 = -2.0 * r * cos(th), d2 = r * r;
+        c.n0[s] = (float)n0;
+        c.n1[s] = (float)n1;
+        c.d1[s] = (float)d1;
+        c.d2[s] = (float)d2;
+        c.m1[s] = (float)(n1 - n0 * d1);
+        c.m2[s] = (float)(-n0 * d2);
+        const double Phi[4] = {-d1, -d2, 1.0, 0.0};
+        double M[4];
+        mat2_pow(Phi, B, M);
+        for (int q = 0; q < 4; ++q) c.phiB[s][q] = (float)M[q];
+        for (int j = 0; j < 6; ++j) {
+            mat2_pow(Phi, (long)L << j, M);
+            for (int q = 0; q < 4; ++q) c.phiL[s][j][q] = (float)M[q];
+        }
+        mat2_pow(Phi, 64L * L, M);
+        for (int q = 0; q < 4; ++q) c.phiW[s][q] = (float)M[q];
+        for (int i = 0; i < L && i < kIirMaxL; ++i) {
+            mat2_pow(Phi, i + 1, M);
+            c.fix1[s][i] = (float)M[0];
+            c.fix2[s][i] = (float)M[1];
+        }
+    }
+    return c;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bf_version(void) { return 10000; }
+
+const char *bf_last_error(void) { return g_err.c_str(); }
+
+unsigned bf_gp_resolve_spatial(double sigma_s, unsigned flags) { return resolve_spatial(sigma_s, flags); }
+
+int bf_gp_set_fir_crossover(int radius) {
+    if (radius < 0 || radius > BF_FIR_MAX_RADIUS) return fail(BF_EINVAL, "crossover radius %d outside 0..%d", radius, BF_FIR_MAX_RADIUS);
+    g_fir_crossover.store(radius);
+    return BF_OK;
+}
+
+int bf_gp_get_fir_crossover(void) { return g_fir_crossover.load(); }
+
+size_t bf_gp_workspace_bytes(int H, int W, int N, double sigma_s, unsigned flags) {
+    if (H < 1 || W < 1 || N < 0 || N > BF_MAX_DEGREE || !finite_pos(sigma_s)) return 0;
+    return gp_layout(H, W, N, resolve_spatial(sigma_s, flags)).total;
+}
+
+int bf_gp_forward(const float *img, float *out, int H, int W, int pitch, double sigma_s, double sigma_r, int N,
+                  unsigned flags, void *saved, void *ws, size_t ws_bytes, void *stream) {
+    int rc;
+    if ((rc = check_image(img, out, H, W, pitch))) return rc;
+    if ((rc = check_params(sigma_s, sigma_r, N))) return rc;
+    if (!ws) return fail(BF_EINVAL, "null workspace");
+    if (flags & ~(BF_SPATIAL_MASK | BF_CENTER_MASK)) return fail(BF_EINVAL, "unknown flag bits 0x%x", flags);
+    if ((flags & BF_SPATIAL_MASK) == 3u || (flags & BF_CENTER_MASK) == 12u) return fail(BF_EINVAL, "invalid flag combination");
+    const unsigned spatial = resolve_spatial(sigma_s, flags);
+    if ((rc = check_spatial(spatial, sigma_s, W))) return rc;
+    if ((const void *)img == (const void *)out) return fail(BF_EINVAL, "img and out must not alias");
+    const Layout L = gp_layout(H, W, N, spatial);
+    if (ws_bytes < L.total) return fail(BF_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
+    if (saved && spatial != BF_SPATIAL_FIR)
+        return fail(BF_EUNSUPPORTED, "saving for the backward pass needs the FIR spatial mode");
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    GPParams p = make_params(img, out, H, W, pitch, sigma_r, N, flags, w, L, saved);
+    hipError_t e = launch_stats(img, H, W, pitch, (Partial *)(w + L.parts), p.nparts, s);
+    if (e != hipSuccess) return hip_fail(e, "statistics launch");
+    if (spatial == BF_SPATIAL_FIR) {
+        const int R = fir_radius(sigma_s);
+        e = launch_fir(p, make_taps(sigma_s, R), R, saved != nullptr, s);
+        if (e != hipSuccess) return hip_fail(e, "FIR launch");
+    } else {
+        int Lc, T;
+        row_shape(W, &Lc, &T);
+        e = launch_iir(p, make_iir(sigma_s, kBand, Lc), kBand, Lc, T, (float *)(w + L.carry), (float *)(w + L.stack), s);
+        if (e != hipSuccess) return hip_fail(e, "IIR launch");
+    }
+    return BF_OK;
+}
+
+int bf_gp_status(const void *ws, void *stream, int *status) {
+    if (!ws || !status) return fail(BF_EINVAL, "null pointer");
+    int v = 0;
+    const Layout L = gp_layout(1, 1, 0, BF_SPATIAL_FIR);
+    hipError_t e = hipMemcpyAsync(&v, (const char *)ws + L.status, sizeof v, hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "status copy");
+    e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "status sync");
+    *status = v;
+    return BF_OK;
+}
+
+int bf_direct_forward(const float *img, float *out, int H, int W, int pitch, double sigma_s, double sigma_r,
+                      int window, void *stream) {
+    int rc;
+    if ((rc = check_image(img, out, H, W, pitch))) return rc;
+    if (!finite_pos(sigma_s) || !finite_pos(sigma_r)) return fail(BF_EINVAL, "sigma_s and sigma_r must be finite and > 0");
+    const int win = window < 0 ? fir_radius(sigma_s) : window;
+    if (win > kDirectMaxW) return fail(BF_EUNSUPPORTED, "window %d exceeds %d", win, kDirectMaxW);
+    if ((const void *)img == (const void *)out) return fail(BF_EINVAL, "img and out must not alias");
+    DirectArgs a;
+    memset(&a, 0, sizeof a);
+    a.img = img;
+    a.out = out;
+    a.H = H;
+    a.W = W;
+    a.pitch = pitch;
+    a.win = win;
+    const double log2e = 1.4426950408889634;
+    a.cr = (float)(-log2e / (2.0 * sigma_r * sigma_r));
+    for (int d = 0; d <= win; ++d) a.lk[d] = (float)(-log2e * (double)d * d / (2.0 * sigma_s * sigma_s));
+    hipError_t e = launch_direct(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "direct launch");
+    return BF_OK;
+}
+
+}  // extern "C"

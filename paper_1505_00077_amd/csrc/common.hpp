@@ -1,0 +1,151 @@
+// Device-side building blocks shared by the GP kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bfgp {
+
+constexpr int kBlock = 256;          // threads per workgroup for every GP kernel
+constexpr int kMaxN = 64;            // largest Gauss-polynomial degree
+constexpr int kMaxC = kMaxN + 2;     // channels u_0..u_{N+1}
+constexpr int kFirMaxR = 24;         // largest FIR radius compiled
+constexpr int kMaxParts = 512;       // partial sums of the statistics pass
+constexpr int kDirectMaxW = 64;      // largest direct-filter window
+
+// One workgroup's share of the image statistics.
+struct Partial {
+    double sum;
+    float lo;
+    float hi;
+};
+
+// Per-image statistics: the centre t_c of Algorithm 1's first step, plus the
+// extremes used for the FP32 range check.
+struct Stats {
+    double tc;
+    double xmax;  // max |f - t_c| / sigma_r
+    int ok;       // 1 when xmax is within the representable bound
+};
+
+// Coefficients for one image that every GP kernel needs.
+struct GPParams {
+    const float *img;
+    float *out;
+    int H, W, pitch;
+    int N, C;            // degree and channel count C = N + 2
+    int center;          // 0 mean, 1 midrange, 2 none
+    double sigma_r, inv_sigma_r;
+    double xlim;         // largest |x| whose channels stay in FP32 range
+    const Partial *parts;
+    int nparts;
+    int *status;         // device status word (BF_OK / BF_ERANGE)
+    void *saved;         // nullable, 16 B per pixel (see bf_gp_forward)
+    double sq[kMaxC + 1];   // sqrt(n)
+    double isq[kMaxC + 1];  // 1 / sqrt(n)
+};
+
+// Spatial taps of the FIR mode: k[d] = exp(-d^2 / 2 sigma_s^2), d = 0..R.
+struct FirTaps {
+    float k[kFirMaxR + 1];
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Statistics pass: workgroup b reduces rows b, b + G, ... into parts[b].
+// The sum is accumulated in double, in a fixed order (deterministic).
+__device__ __forceinline__ void stats_rows(const float *__restrict__ img, int H, int W, int pitch,
+                                           int b, int G, Partial *__restrict__ parts) {
+    __shared__ double s_sum[kBlock / 64];
+    __shared__ float s_lo[kBlock / 64], s_hi[kBlock / 64];
+    double s = 0.0;
+    float lo = __builtin_inff(), hi = -__builtin_inff();
+    for (int y = b; y < H; y += G) {
+        const float *row = img + (size_t)y * pitch;
+        for (int x = threadIdx.x; x < W; x += kBlock) {
+            const float v = row[x];
+            s += (double)v;
+            lo = fminf(lo, v);
+            hi = fmaxf(hi, v);
+        }
+    }
+    s = wave_sum(s);
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_sum[w] = s;
+        s_lo[w] = lo;
+        s_hi[w] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        float l = __builtin_inff(), h = -__builtin_inff();
+        for (int i = 0; i < kBlock / 64; ++i) {
+            t += s_sum[i];
+            l = fminf(l, s_lo[i]);
+            h = fmaxf(h, s_hi[i]);
+        }
+        parts[b].sum = t;
+        parts[b].lo = l;
+        parts[b].hi = h;
+    }
+    __syncthreads();
+}
+
+// Reduces the partials (same fixed order in every workgroup) and derives the
+// centre.  Every thread of the workgroup receives the result.
+__device__ __forceinline__ Stats load_stats(const GPParams &p) {
+    __shared__ Stats s_st;
+    if (threadIdx.x < 64) {
+        double s = 0.0;
+        float lo = __builtin_inff(), hi = -__builtin_inff();
+        for (int i = threadIdx.x; i < p.nparts; i += 64) {
+            s += p.parts[i].sum;
+            lo = fminf(lo, p.parts[i].lo);
+            hi = fmaxf(hi, p.parts[i].hi);
+        }
+        s = wave_sum(s);
+        lo = wave_min(lo);
+        hi = wave_max(hi);
+        if (threadIdx.x == 0) {
+            double tc;
+            if (p.center == 1)
+                tc = 0.5 * ((double)lo + (double)hi);
+            else if (p.center == 2)
+                tc = 0.0;
+            else
+                tc = s / ((double)p.H * (double)p.W);
+            const double a = fabs((double)lo - tc) * p.inv_sigma_r;
+            const double b = fabs((double)hi - tc) * p.inv_sigma_r;
+            Stats st;
+            st.tc = tc;
+            st.xmax = a > b ? a : b;
+            st.ok = (st.xmax <= p.xlim) ? 1 : 0;
+            s_st = st;
+        }
+    }
+    __syncthreads();
+    return s_st;
+}
+
+// x = (f - t_c) / sigma_r, computed in double and rounded once to float.
+__device__ __forceinline__ float centred(float f, const Stats &st, double inv_sr) {
+    return (float)(((double)f - st.tc) * inv_sr);
+}
+
+}  // namespace bfgp

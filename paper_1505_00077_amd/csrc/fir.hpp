@@ -1,0 +1,183 @@
+// Fused FIR forward: channel generation, both spatial passes and the FP64
+// recombination for one output tile, all in LDS / registers.
+//
+// Per tile (TY x TX outputs) and per channel n = 0..N+1 (eq. (7), rescaled):
+//   1. every thread updates its share of the (TY+2R) x (TX+2R) input region,
+//      u_n = u_{n-1} * x / sqrt(n) (double), and stores it to LDS as float;
+//   2. the column pass of eq. (8): B = k (*) A along y, (TY) x (TX+2R);
+//   3. the row pass of eq. (8): Ubar_n at the thread's 8 output pixels;
+//   4. the recombination of eqs. (9)-(11) as power sums in tau (double):
+//        D' += p_n Ubar_n (n <= N),  M' += sqrt(n) p_{n-1} Ubar_n (n >= 1),
+//      p_n = tau^n / sqrt(n!).  D' = exp(tau^2/2) D and M' = exp(tau^2/2) M,
+//      so M'/D' = M/D.
+// The channel buffer never leaves the chip: HBM traffic is the input region
+// and the output tile.
+#pragma once
+#include "common.hpp"
+
+namespace bfgp {
+
+template <int R>
+struct FirShape {
+    static constexpr int TY = 32, TX = 64;       // output tile
+    static constexpr int RY = TY + 2 * R, RX = TX + 2 * R;
+    static constexpr int REG = RY * RX;           // region elements
+    static constexpr int PER = (REG + kBlock - 1) / kBlock;
+    static constexpr int SV = 4;                  // column-pass outputs per item
+    static constexpr int BP = RX + 1;             // odd pitch of the row-pass input
+    static constexpr int PX = 8;                  // output pixels per thread
+    static constexpr int SMEM_FLOATS = REG + TY * BP;
+};
+
+// Number of LDS floats needed by fir_tile<R>.
+__host__ __device__ constexpr int fir_smem_floats(int R) {
+    return (32 + 2 * R) * (64 + 2 * R) + 32 * (64 + 2 * R + 1);
+}
+
+template <int R, bool SAVE>
+__device__ __forceinline__ void fir_tile(const GPParams &p, const FirTaps &taps, const Stats &st,
+                                         int ty0, int tx0, float *smem) {
+    using S = FirShape<R>;
+    float *A = smem;             // region, RY x RX
+    float *B = smem + S::REG;    // column-pass output, TY x BP
+    const int tid = threadIdx.x;
+
+    // ---- region: centred intensities and u_0 = exp(-x^2/2) ----
+    float xr[S::PER];
+    double u[S::PER];
+#pragma unroll
+    for (int i = 0; i < S::PER; ++i) {
+        const int e = tid + i * kBlock;
+        xr[i] = 0.f;
+        u[i] = 0.0;
+        if (e < S::REG) {
+            const int gy = ty0 - R + e / S::RX;
+            const int gx = tx0 - R + e % S::RX;
+            if (gy >= 0 && gy < p.H && gx >= 0 && gx < p.W) {
+                const float x = centred(p.img[(size_t)gy * p.pitch + gx], st, p.inv_sigma_r);
+                xr[i] = x;
+                u[i] = exp(-0.5 * (double)x * (double)x);
+            }
+        }
+    }
+
+    // ---- output ownership: row y, 8 consecutive columns from x0 ----
+    const int lane = tid & 63, wave = tid >> 6;
+    const int oy = lane & 31;
+    const int ox0 = ((lane >> 5) + 2 * wave) * S::PX;
+    double tau[S::PX], Dp[S::PX], Mp[S::PX], pw[S::PX];
+    double Dt[SAVE ? S::PX : 1], Mt[SAVE ? S::PX : 1], pm[SAVE ? S::PX : 1];
+    {
+        const int gy = ty0 + oy;
+#pragma unroll
+        for (int i = 0; i < S::PX; ++i) {
+            const int gx = tx0 + ox0 + i;
+            float x = 0.f;
+            if (gy < p.H && gx < p.W) x = centred(p.img[(size_t)gy * p.pitch + gx], st, p.inv_sigma_r);
+            tau[i] = (double)x;
+            Dp[i] = 0.0;
+            Mp[i] = 0.0;
+            pw[i] = 0.0;
+            if (SAVE) {
+                Dt[i] = 0.0;
+                Mt[i] = 0.0;
+                pm[i] = 0.0;
+            }
+        }
+    }
+
+    for (int n = 0; n < p.C; ++n) {
+        // 1. channel n on the region
+        const double isq = p.isq[n];
+#pragma unroll
+        for (int i = 0; i < S::PER; ++i) {
+            const int e = tid + i * kBlock;
+            if (e < S::REG) {
+                if (n > 0) u[i] *= (double)xr[i] * isq;
+                A[e] = (float)u[i];
+            }
+        }
+        __syncthreads();
+        // 2. column pass
+        for (int it = tid; it < S::RX * (S::TY / S::SV); it += kBlock) {
+            const int xx = it % S::RX, sy = it / S::RX;
+            const float *col = A + sy * S::SV * S::RX + xx;
+            float acc[S::SV];
+#pragma unroll
+            for (int i = 0; i < S::SV; ++i) acc[i] = 0.f;
+#pragma unroll
+            for (int j = 0; j < S::SV + 2 * R; ++j) {
+                const float v = col[j * S::RX];
+#pragma unroll
+                for (int i = 0; i < S::SV; ++i) {
+                    const int d = j - i;
+                    if (d >= 0 && d <= 2 * R) acc[i] = fmaf(taps.k[d >= R ? d - R : R - d], v, acc[i]);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < S::SV; ++i) B[(sy * S::SV + i) * S::BP + xx] = acc[i];
+        }
+        __syncthreads();
+        // 3. row pass at the owned pixels
+        float h[S::PX];
+#pragma unroll
+        for (int i = 0; i < S::PX; ++i) h[i] = 0.f;
+        {
+            const float *row = B + oy * S::BP + ox0;
+#pragma unroll
+            for (int j = 0; j < S::PX + 2 * R; ++j) {
+                const float v = row[j];
+#pragma unroll
+                for (int i = 0; i < S::PX; ++i) {
+                    const int d = j - i;
+                    if (d >= 0 && d <= 2 * R) h[i] = fmaf(taps.k[d >= R ? d - R : R - d], v, h[i]);
+                }
+            }
+        }
+        // 4. recombination, double precision
+        const double sqn = p.sq[n];
+        const double sqm = n >= 1 ? p.sq[n - 1] : 0.0;
+        const bool inD = n <= p.N;
+#pragma unroll
+        for (int i = 0; i < S::PX; ++i) {
+            const double ub = (double)h[i];
+            if (n >= 1) {
+                const double q = pw[i] * sqn;  // sqrt(n) p_{n-1}
+                Mp[i] = fma(q, ub, Mp[i]);
+                if (SAVE) {
+                    if (inD) Dt[i] = fma(q, ub, Dt[i]);
+                    Mt[i] = fma(sqn * sqm * pm[i], ub, Mt[i]);
+                }
+            }
+            if (inD) {
+                if (SAVE) pm[i] = pw[i];
+                pw[i] = (n == 0) ? 1.0 : pw[i] * tau[i] * isq;
+                Dp[i] = fma(pw[i], ub, Dp[i]);
+            }
+        }
+    }
+
+    // ---- outputs ----
+    const int gy = ty0 + oy;
+    if (gy < p.H) {
+        const size_t npx = (size_t)p.H * p.W;
+#pragma unroll
+        for (int i = 0; i < S::PX; ++i) {
+            const int gx = tx0 + ox0 + i;
+            if (gx < p.W) {
+                const double rho = Mp[i] / Dp[i];
+                const float o = st.ok ? (float)(st.tc + p.sigma_r * rho) : __builtin_nanf("");
+                p.out[(size_t)gy * p.pitch + gx] = o;
+                if (SAVE) {
+                    const size_t idx = (size_t)gy * p.W + gx;
+                    float *sv = (float *)p.saved;
+                    sv[idx] = (float)rho;
+                    sv[npx + idx] = (float)(Mt[i] / Dp[i] - rho * Dt[i] / Dp[i]);
+                    ((double *)(sv + 2 * npx))[idx] = Dp[i];
+                }
+            }
+        }
+    }
+}
+
+}  // namespace bfgp

@@ -1,0 +1,125 @@
+// __global__ entry points of the single-image forward path (statistics, fused
+// FIR, recursive IIR passes, direct filter) and their host-side launchers.
+#include "launch.hpp"
+#include "fir.hpp"
+#include "iir.hpp"
+#include "direct.hpp"
+
+namespace bfgp {
+
+__global__ __launch_bounds__(kBlock) void k_stats(const float *img, int H, int W, int pitch, Partial *parts) {
+    stats_rows(img, H, W, pitch, blockIdx.x, gridDim.x, parts);
+}
+
+template <int R, bool SAVE>
+__global__ __launch_bounds__(kBlock) void k_fir(GPParams p, FirTaps taps) {
+    extern __shared__ float smem[];
+    const Stats st = load_stats(p);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *p.status = st.ok ? 0 : -3;
+    fir_tile<R, SAVE>(p, taps, st, blockIdx.y * FirShape<R>::TY, blockIdx.x * FirShape<R>::TX, smem);
+}
+
+__global__ __launch_bounds__(kBlock) void k_direct(DirectArgs a) {
+    extern __shared__ float smem[];
+    direct_tile(a, blockIdx.y * kDirTY, blockIdx.x * kDirTX, smem);
+}
+
+
+// ---- recursive (IIR) passes ----------------------------------------------------
+
+// The BIG variant (channels carried with a range shift) is a separate kernel so
+// that its register allocation does not burden the common case; both are
+// launched and the one that does not match the image's range returns at once.
+template <int B, bool AGG, bool BIG>
+__global__ __launch_bounds__(64, 2) void k_vband(GPParams p, IirCoef c, float *carry, float *S) {
+    __shared__ float sacc[AGG ? 1 : B * 64];
+    const Stats st = load_stats(p);
+    if (AGG && !BIG && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *p.status = st.ok ? 0 : -3;
+    if (!st.ok || ((st.xmax > 12.0) != BIG)) return;
+    const int col = blockIdx.x * 64 + threadIdx.x;
+    vband<B, AGG, BIG>(p, c, st, col, blockIdx.y, carry, S, sacc);
+}
+
+__global__ __launch_bounds__(kBlock) void k_vresolve(GPParams p, IirCoef c, int nb, float *carry) {
+    const int col = blockIdx.x * kBlock + threadIdx.x;
+    if (col < p.W) vresolve(p, c, nb, col, blockIdx.y, carry);
+}
+
+template <int L>
+__global__ __launch_bounds__(512, 1) void k_hrow(GPParams p, IirCoef c, const float *S) {
+    __shared__ float sm[hrow_smem_floats(8)];
+    const Stats st = load_stats(p);
+    if (!st.ok) {
+        for (int x = threadIdx.x; x < p.W; x += blockDim.x) p.out[(size_t)blockIdx.x * p.pitch + x] = __builtin_nanf("");
+        return;
+    }
+    hrow<L>(p, c, st, blockIdx.x, S, sm);
+}
+
+// ---- host launchers ----------------------------------------------------------
+
+hipError_t launch_stats(const float *img, int H, int W, int pitch, Partial *parts, int nparts, hipStream_t s) {
+    hipLaunchKernelGGL(k_stats, dim3(nparts), dim3(kBlock), 0, s, img, H, W, pitch, parts);
+    return hipGetLastError();
+}
+
+template <int R>
+static hipError_t fir_launch_r(const GPParams &p, const FirTaps &t, bool save, hipStream_t s) {
+    using S = FirShape<R>;
+    dim3 grid((p.W + S::TX - 1) / S::TX, (p.H + S::TY - 1) / S::TY);
+    const size_t sm = sizeof(float) * S::SMEM_FLOATS;
+    if (save)
+        hipLaunchKernelGGL((k_fir<R, true>), grid, dim3(kBlock), sm, s, p, t);
+    else
+        hipLaunchKernelGGL((k_fir<R, false>), grid, dim3(kBlock), sm, s, p, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_fir(const GPParams &p, const FirTaps &t, int R, bool save, hipStream_t s) {
+    switch (R) {
+#define BF_CASE(r) case r: return fir_launch_r<r>(p, t, save, s);
+        BF_CASE(1) BF_CASE(2) BF_CASE(3) BF_CASE(4) BF_CASE(5) BF_CASE(6) BF_CASE(7) BF_CASE(8)
+        BF_CASE(9) BF_CASE(10) BF_CASE(11) BF_CASE(12) BF_CASE(13) BF_CASE(14) BF_CASE(15) BF_CASE(16)
+        BF_CASE(17) BF_CASE(18) BF_CASE(19) BF_CASE(20) BF_CASE(21) BF_CASE(22) BF_CASE(23) BF_CASE(24)
+#undef BF_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+
+hipError_t launch_iir(const GPParams &p, const IirCoef &c, int B, int L, int T, float *carry, float *S, hipStream_t s) {
+    const int nb = (p.H + B - 1) / B;
+    dim3 gv((p.W + 63) / 64, nb);
+#define BF_VB(b, agg)                                                                        \
+    do {                                                                                     \
+        hipLaunchKernelGGL((k_vband<b, agg, false>), gv, dim3(64), 0, s, p, c, carry, S);    \
+        hipLaunchKernelGGL((k_vband<b, agg, true>), gv, dim3(64), 0, s, p, c, carry, S);     \
+    } while (0)
+    if (B == 64)
+        BF_VB(64, true);
+    else if (B == 32)
+        BF_VB(32, true);
+    else
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_vresolve, dim3((p.W + kBlock - 1) / kBlock, p.C), dim3(kBlock), 0, s, p, c, nb, carry);
+    if (B == 64)
+        BF_VB(64, false);
+    else
+        BF_VB(32, false);
+#undef BF_VB
+    switch (L) {
+        case 4: hipLaunchKernelGGL((k_hrow<4>), dim3(p.H), dim3(T), 0, s, p, c, S); break;
+        case 8: hipLaunchKernelGGL((k_hrow<8>), dim3(p.H), dim3(T), 0, s, p, c, S); break;
+        case 16: hipLaunchKernelGGL((k_hrow<16>), dim3(p.H), dim3(T), 0, s, p, c, S); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_direct(const DirectArgs &a, hipStream_t s) {
+    dim3 grid((a.W + kDirTX - 1) / kDirTX, (a.H + kDirTY - 1) / kDirTY);
+    hipLaunchKernelGGL(k_direct, grid, dim3(kBlock), sizeof(float) * direct_smem_floats(), s, a);
+    return hipGetLastError();
+}
+
+}  // namespace bfgp

@@ -1,0 +1,111 @@
+"""Host-side contract of libbfgp.so: exports, argument checks, workspace sizes.
+
+Every call here is rejected (or is a pure host query) before any HIP call, so
+these tests run without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1505_00077_amd as bf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bfgp.h")
+FAKE = 0x10000  # never dereferenced: every call below fails validation first
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bf_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 15
+    lib = ctypes.CDLL(bf.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_version_and_error_text():
+    assert bf.bf_version() >= 10000
+    assert isinstance(bf.bf_last_error(), bytes)
+
+
+def fwd(img=FAKE, out=FAKE + 4096, H=8, W=8, pitch=8, ss=2.0, sr=30.0, N=20, flags=0, saved=None, ws=FAKE + 8192,
+        ws_bytes=1 << 30):
+    return bf.bf_gp_forward(img, out, H, W, pitch, ss, sr, N, flags, saved, ws, ws_bytes, None)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(img=None), dict(out=None), dict(ws=None), dict(H=0), dict(W=0), dict(H=-3), dict(pitch=7),
+    dict(ss=0.0), dict(ss=-1.0), dict(ss=float("nan")), dict(ss=float("inf")), dict(sr=0.0), dict(sr=float("nan")),
+    dict(N=-1), dict(N=65), dict(flags=3), dict(flags=12), dict(flags=16), dict(out=FAKE),
+])
+def test_forward_rejects_invalid_arguments(kw):
+    assert fwd(**kw) == bf.BF_EINVAL
+    assert len(bf.bf_last_error()) > 0
+
+
+def test_forward_rejects_small_workspace():
+    need = bf.workspace_bytes(64, 64, 20, 2.0, "iir")
+    assert fwd(H=64, W=64, pitch=64, flags=bf.SPATIAL["iir"], ws_bytes=need - 1) == bf.BF_ENOMEM
+
+
+def test_forward_rejects_unsupported_modes():
+    # FIR radius ceil(3 * 9) = 27 > 24
+    assert fwd(ss=9.0, flags=bf.SPATIAL["fir"]) == bf.BF_EUNSUPPORTED
+    # saving for the backward pass needs the FIR mode
+    assert fwd(flags=bf.SPATIAL["iir"], saved=FAKE + 65536) == bf.BF_EUNSUPPORTED
+    # IIR width limit
+    assert fwd(H=4, W=9000, pitch=9000, flags=bf.SPATIAL["iir"]) == bf.BF_EUNSUPPORTED
+
+
+def test_workspace_sizes():
+    fir = bf.workspace_bytes(1024, 1024, 20, 2.0, "fir")
+    iir = bf.workspace_bytes(1024, 1024, 20, 2.0, "iir")
+    assert 0 < fir < 1 << 20
+    # the IIR stack holds N + 2 = 22 channels of the image
+    assert iir >= 22 * 1024 * 1024 * 4
+    assert bf.workspace_bytes(0, 10, 20, 2.0) == 0
+    assert bf.workspace_bytes(10, 10, 99, 2.0) == 0
+
+
+def test_spatial_resolution_and_crossover():
+    old = bf.get_fir_crossover()
+    try:
+        bf.set_fir_crossover(6)
+        assert bf.resolve_spatial(2.0) == "fir"      # radius 6
+        assert bf.resolve_spatial(2.1) == "iir"      # radius 7
+        assert bf.resolve_spatial(10.0, "fir") == "fir"
+        assert bf.resolve_spatial(0.5, "iir") == "iir"
+        bf.set_fir_crossover(0)
+        assert bf.resolve_spatial(0.1) == "iir"
+        with pytest.raises(bf.BfError):
+            bf.set_fir_crossover(25)
+    finally:
+        bf.set_fir_crossover(old)
+
+
+def test_direct_rejects_invalid_arguments():
+    f = bf.bf_direct_forward
+    assert f(None, FAKE, 8, 8, 8, 2.0, 30.0, -1, None) == bf.BF_EINVAL
+    assert f(FAKE, FAKE + 4096, 8, 8, 7, 2.0, 30.0, -1, None) == bf.BF_EINVAL
+    assert f(FAKE, FAKE + 4096, 8, 8, 8, 0.0, 30.0, -1, None) == bf.BF_EINVAL
+    assert f(FAKE, FAKE + 4096, 8, 8, 8, 2.0, 30.0, 65, None) == bf.BF_EUNSUPPORTED
+    assert f(FAKE, FAKE, 8, 8, 8, 2.0, 30.0, -1, None) == bf.BF_EINVAL
+
+
+def test_status_rejects_null():
+    v = ctypes.c_int()
+    assert bf.bf_gp_status(None, None, ctypes.byref(v)) == bf.BF_EINVAL
+
+
+def test_fir_radius_rule():
+    # eq. (1): W = 3 sigma_s, rounded up
+    assert bf.fir_radius(3.0) == 9
+    assert bf.fir_radius(2.0) == 6
+    assert bf.fir_radius(0.1) == 1
+    assert bf.fir_radius(3.01) == 10
