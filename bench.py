@@ -1,0 +1,244 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the Gauss-polynomial bilateral filter on one MI355X.
+
+Headline (`value`): GP forward in Mpix/s on the 1024x1024 synthetic image
+(Voronoi, 200 cells, noise 10) over the spatial sweep sigma_s in {2, 5, 10, 20},
+sigma_r 30, degree 20.  One step = the four forwards; value = pixels filtered
+per second over the timed steps, inputs resident in HBM.
+
+Also reported under "modes": Mpix/s per sigma_s, the direct filter of eq. (1)
+per sigma_s, the 16-MP forward (4096x4096, sigma_s 10, sigma_r 20), the
+batched and forward+backward modes, and max abs errors against the FP64
+oracle and the direct filter.  `roofline` is for the kernel with the largest
+share of the timed region, from per-launch HIP events on the stream the
+library launches on.  `cpu_baseline` times the FP64 oracle on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpix/s of Gauss-poly bilateral (fwd, fwd+bwd, batched) vs direct; max abs err"
+SWEEP = (2.0, 5.0, 10.0, 20.0)
+SIGMA_R = 30.0
+DEGREE = 20
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    sys.stderr.write(f"[bench] {msg}\n")
+    sys.stderr.flush()
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--only", default="", help="comma list of sections to run (headline always runs)")
+    return ap.parse_args()
+
+
+def timed(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(steps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / steps  # ms per call
+
+
+def bytes_per_pixel(kernel, C):
+    """Algorithmic HBM bytes per pixel of one launch of each kernel."""
+    band = 64
+    return {
+        "k_hrow": 4 * C + 4 + 4,                   # stack read, image read, output write
+        "k_vband": 4 + 4 * C + 32 * C / band,      # image read, stack write, band states read
+        "k_vband_agg": 4 + 32 * C / band,          # image read, band end states written
+        "k_vresolve": 2 * 32 * C / band,           # band states read and rewritten
+        "k_fir": 4 + 4,                            # image read, output write
+        "k_stats": 4,
+        "k_direct": 4 + 4,
+    }.get(kernel)
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on exactly one GPU (one image, or one batch, per device); "
+              "multi-GPU runs are not supported", file=sys.stderr)
+        sys.exit(2)
+    only = set(filter(None, args.only.split(",")))
+
+    def want(name):
+        return not only or name in only
+
+    import numpy as np
+    import torch
+
+    import paper_1505_00077_amd as bf
+    import synthimg
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    K, Wm = args.steps, args.warmup
+    C = DEGREE + 2
+    modes = {}
+
+    # ---------------- headline: 1024^2 sweep ----------------
+    log("generating 1024x1024 image")
+    img = torch.from_numpy(synthimg.mid_1024()).to(dev)
+    H, W = img.shape
+    outs = {ss: torch.empty_like(img) for ss in SWEEP}
+    wss = {ss: bf.workspace(H, W, DEGREE, ss, "auto") for ss in SWEEP}
+    plan = {ss: bf.resolve_spatial(ss) for ss in SWEEP}
+
+    def step():
+        for ss in SWEEP:
+            bf.gp_forward(img, ss, SIGMA_R, DEGREE, out=outs[ss], ws=wss[ss])
+
+    log(f"headline: {K} steps of the sigma_s sweep {SWEEP} ({plan})")
+    for _ in range(Wm):
+        step()
+    torch.cuda.synchronize()
+    bf.profile_enable(True)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(K):
+        step()
+    e.record()
+    torch.cuda.synchronize()
+    stage = bf.profile_collect()
+    bf.profile_enable(False)
+    ms_step = s.elapsed_time(e) / K
+    px_step = len(SWEEP) * H * W
+    value = px_step / (ms_step * 1e-3) / 1e6
+    for ss in SWEEP:
+        if bf.status(wss[ss]) != bf.BF_OK:
+            raise RuntimeError(f"device status not OK at sigma_s={ss}")
+
+    # dominant kernel of the timed region
+    kname, (kcount, kms) = max(stage.items(), key=lambda kv: kv[1][1])
+    avg_ms = kms / kcount
+    # pixels per launch: every kernel of a forward covers the whole image
+    bpp = bytes_per_pixel(kname, C)
+    achieved = bpp * H * W / (avg_ms * 1e-3) / 1e9 if bpp else None
+    roofline = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                "avg_launch_ms": avg_ms, "launches": kcount, "bytes_per_px": bpp,
+                "share_of_step": kms / (ms_step * K)}
+    modes["stages_ms_per_step"] = {k: v[1] / K for k, v in sorted(stage.items())}
+
+    # ---------------- per-sigma_s forward and direct ----------------
+    if want("sweep"):
+        per = {}
+        for ss in SWEEP:
+            ms = timed(lambda: bf.gp_forward(img, ss, SIGMA_R, DEGREE, out=outs[ss], ws=wss[ss]), K, Wm, torch)
+            per[str(ss)] = {"plan": plan[ss], "ms": ms, "mpix_s": H * W / (ms * 1e-3) / 1e6}
+            log(f"gp sigma_s={ss}: {ms:.3f} ms")
+        modes["gp_forward_1024_per_sigma_s"] = per
+        dper = {}
+        dout = torch.empty_like(img)
+        for ss in SWEEP:
+            n = max(1, min(K, 5))
+            ms = timed(lambda: bf.direct_forward(img, ss, SIGMA_R, out=dout), n, 1, torch)
+            dper[str(ss)] = {"window": bf.fir_radius(ss), "ms": ms, "mpix_s": H * W / (ms * 1e-3) / 1e6}
+            log(f"direct sigma_s={ss}: {ms:.3f} ms")
+            # agreement of the GP output with the direct filter (reported, not gated)
+            d = (outs[ss] - dout).abs()
+            dper[str(ss)]["gp_vs_direct_max_abs"] = float(d.max())
+            dper[str(ss)]["gp_vs_direct_mse_db"] = float(10 * torch.log10((d.double() ** 2).mean()))
+        modes["direct_1024_per_sigma_s"] = dper
+
+    # ---------------- 16 MP forward ----------------
+    if want("large"):
+        log("generating 4096x4096 image")
+        big = torch.from_numpy(synthimg.large_4096()).to(dev)
+        bws = bf.workspace(4096, 4096, DEGREE, 10.0, "auto")
+        bout = torch.empty_like(big)
+        bf.profile_enable(True)
+        ms = timed(lambda: bf.gp_forward(big, 10.0, 20.0, DEGREE, out=bout, ws=bws), K, Wm, torch)
+        bstage = bf.profile_collect()
+        bf.profile_enable(False)
+        if bf.status(bws) != bf.BF_OK:
+            raise RuntimeError("device status not OK on the 16-MP image")
+        mp = 4096 * 4096
+        kn, (kc, kt) = max(bstage.items(), key=lambda kv: kv[1][1])
+        # launches recorded include warm-up calls; average per launch
+        kb = bytes_per_pixel(kn, C)
+        model_bytes = (12 + 8 * C) * mp
+        modes["gp_forward_4096"] = {
+            "plan": bf.resolve_spatial(10.0), "ms": ms, "mpix_s": mp / (ms * 1e-3) / 1e6,
+            "model_bytes_per_px": 12 + 8 * C,
+            "model_frac_of_hbm_peak": model_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "stages_ms_per_call": {k: v[1] / v[0] for k, v in sorted(bstage.items())},
+            "dominant_kernel": kn, "dominant_kernel_gbs": (kb * mp / (kt / kc * 1e-3) / 1e9) if kb else None,
+        }
+        log(f"16MP: {ms:.3f} ms")
+        del big, bws, bout
+
+    # ---------------- accuracy on the small configuration ----------------
+    if want("accuracy"):
+        import oracle
+        small = synthimg.small_256()
+        f64 = small.astype(np.float64)
+        ref_direct = oracle.direct_gauss(f64, 3.0, SIGMA_R)
+        acc = {}
+        for mode in ("fir", "iir"):
+            got = bf.gp_forward(torch.from_numpy(small).to(dev), 3.0, SIGMA_R, DEGREE, spatial=mode, check=True)
+            g = got.cpu().numpy().astype(np.float64)
+            k, _ = oracle.spatial_table(mode, 3.0, *small.shape)
+            ref = oracle.gp_alg1(f64, SIGMA_R, DEGREE, k)
+            acc[mode] = {"max_abs_err_vs_oracle": float(np.max(np.abs(g - ref))),
+                         "max_abs_err_vs_direct": float(np.max(np.abs(g - ref_direct))),
+                         "mse_db_vs_direct": oracle.mse_db(g, ref_direct)}
+        gd = bf.direct_forward(torch.from_numpy(small).to(dev), 3.0, SIGMA_R).cpu().numpy().astype(np.float64)
+        acc["direct"] = {"max_abs_err_vs_oracle": float(np.max(np.abs(gd - ref_direct)))}
+        modes["accuracy_256_sigma_s3"] = acc
+
+    # ---------------- CPU baseline: the FP64 oracle on a bounded sample ----------------
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        crop = synthimg.mid_1024()[:512, :512].astype(np.float64)
+        log("timing the FP64 oracle on a 512x512 crop per sigma_s")
+        t0 = time.perf_counter()
+        for ss in SWEEP:
+            k, _ = oracle.spatial_table(plan[ss], ss, *crop.shape)
+            oracle.gp_alg1(crop, SIGMA_R, DEGREE, k)
+        dt = time.perf_counter() - t0
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        cpu = {"value": len(SWEEP) * crop.size / dt / 1e6, "unit": "Mpix/s", "cores": cores, "kind": "oracle",
+               "sample": "512x512 crop of the 1024x1024 image, each sigma_s of the sweep, same spatial mode, "
+                         "FP64 Algorithm 1 (C, OpenMP)", "seconds": dt}
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "Mpix/s", "n_gpus": 1, "steps": K, "warmup": Wm,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "gp_forward 1024x1024 voronoi-200+noise10, sigma_s sweep {2,5,10,20}, sigma_r 30, "
+                               "N 20 (one step = the four forwards)",
+                   "global_batch": 1, "image": [H, W], "plan": {str(k): v for k, v in plan.items()},
+                   "recombination": "f64", "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "modes": modes,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -148,6 +148,16 @@ void bf_gp_plan_free(void *plan);
 int bf_direct_forward(const float *img, float *out, int H, int W, int pitch,
                       double sigma_s, double sigma_r, int window, void *stream);
 
+/* ---- stage timing ----------------------------------------------------------
+ * Profiling aid.  While enabled, every entry point records a pair of HIP events
+ * on its stream around each kernel it launches.  bf_profile_enable(1) (re)starts
+ * the record, bf_profile_enable(0) stops recording.  bf_profile_collect waits for
+ * the recorded events and fills, for up to `max` distinct kernel names, the
+ * number of launches and the summed duration in milliseconds; it returns the
+ * number of names filled (or a negative status).  Name strings are static. */
+int bf_profile_enable(int on);
+int bf_profile_collect(int max, const char **names, int *counts, double *total_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -78,8 +78,10 @@ def _check(rc, name):
 # --------------------------------------------------------------------------
 
 def fir_radius(sigma_s):
-    """Window half-width of eq. (1), W = 3 sigma_s, rounded up (at least 1)."""
-    return max(1, int(math.ceil(3.0 * sigma_s - 1e-9)))
+    """Window half-width of eq. (1), W = 3 sigma_s, rounded up (at least 1).
+    A relative excess below 1e-6 (float32 rounding of sigma_s) does not round
+    up: W = ceil(3 sigma_s (1 - 1e-6))."""
+    return max(1, int(math.ceil(3.0 * sigma_s * (1.0 - 1e-6))))
 
 
 def gauss_table(sigma_s, R):

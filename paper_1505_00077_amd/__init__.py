@@ -60,6 +60,9 @@ bf_gp_plan_upload = _sig("bf_gp_plan_upload", _i, _vp, _vp, _sz, _vp)
 bf_gp_forward_batched = _sig("bf_gp_forward_batched", _i, _vp, _vp, _sz, _vp)
 bf_gp_plan_free = _sig("bf_gp_plan_free", None, _vp)
 bf_direct_forward = _sig("bf_direct_forward", _i, _vp, _vp, _i, _i, _i, _d, _d, _i, _vp)
+bf_profile_enable = _sig("bf_profile_enable", _i, _i)
+bf_profile_collect = _sig("bf_profile_collect", _i, _i, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(_i),
+                          ctypes.POINTER(_d))
 
 
 class BfError(RuntimeError):
@@ -93,8 +96,9 @@ def _image(t, name="img"):
 
 
 def fir_radius(sigma_s):
-    """Window half-width of eq. (1): ceil(3 sigma_s), at least 1."""
-    return max(1, int(math.ceil(3.0 * sigma_s - 1e-9)))
+    """Window half-width of eq. (1): ceil(3 sigma_s), at least 1 (a relative
+    excess below 1e-6 does not round up)."""
+    return max(1, int(math.ceil(3.0 * sigma_s * (1.0 - 1e-6))))
 
 
 def resolve_spatial(sigma_s, spatial="auto"):
@@ -166,3 +170,104 @@ def set_fir_crossover(radius):
 
 def get_fir_crossover():
     return int(bf_gp_get_fir_crossover())
+
+
+def profile_enable(on=True):
+    """Starts (on=True, resetting the record) or stops per-kernel event timing."""
+    _check(bf_profile_enable(1 if on else 0), "bf_profile_enable")
+
+
+def profile_collect(max_names=64):
+    """{kernel name: (launches, total ms)} for the launches recorded so far."""
+    names = (ctypes.c_char_p * max_names)()
+    counts = (ctypes.c_int * max_names)()
+    total = (ctypes.c_double * max_names)()
+    n = bf_profile_collect(max_names, names, counts, total)
+    if n < 0:
+        raise BfError(n, "bf_profile_collect")
+    return {names[i].decode(): (counts[i], total[i]) for i in range(n)}
+
+
+# --------------------------------------------------------------------------
+# backward and autograd
+# --------------------------------------------------------------------------
+
+def saved_buffer(H, W, device="cuda"):
+    """Buffer for what the backward pass needs from the forward (16 B/pixel)."""
+    return torch.empty(16 * H * W, dtype=torch.uint8, device=device)
+
+
+def backward_workspace(H, W, N, sigma_s, spatial="fir", device="cuda"):
+    n = int(bf_gp_backward_workspace_bytes(int(H), int(W), int(N), float(sigma_s), _flags(spatial)))
+    return torch.empty(max(n, 256), dtype=torch.uint8, device=device)
+
+
+def gp_backward(img, grad_out, saved, sigma_s, sigma_r, N=20, spatial="fir", center="mean", grad_img=True,
+                ws=None):
+    """Adjoint of gp_forward.  Returns (dL/dimg or None, dL/dlog sigma_s, dL/dlog sigma_r) with the scalar
+    gradients as float64 CUDA tensors of shape (1,)."""
+    H, W, pitch = _image(img)
+    gh, gw, gp = _image(grad_out, "grad_out")
+    if (gh, gw, gp) != (H, W, pitch):
+        raise ValueError("grad_out must have the shape and row stride of img")
+    gi = torch.empty_like(img) if grad_img else None
+    gs = torch.zeros(1, dtype=torch.float64, device=img.device)
+    gr = torch.zeros(1, dtype=torch.float64, device=img.device)
+    if ws is None:
+        ws = backward_workspace(H, W, N, sigma_s, spatial, img.device)
+    _check(bf_gp_backward(img.data_ptr(), grad_out.data_ptr(), saved.data_ptr(), H, W, pitch, float(sigma_s),
+                          float(sigma_r), int(N), _flags(spatial, center), gi.data_ptr() if gi is not None else None,
+                          gs.data_ptr(), gr.data_ptr(), ws.data_ptr(), ws.numel(), _stream(img.device)),
+           "bf_gp_backward")
+    return gi, gs, gr
+
+
+class GPFilterFn(torch.autograd.Function):
+    """GP bilateral filter with learnable log sigma_s and log sigma_r.
+
+    forward(img (H, W) or (B, H, W) float32 CUDA, log_ss, log_sr, N, spatial, center).
+    Both passes run in the library's kernels; the spatial radius ceil(3
+    sigma_s) is held fixed when differentiating in sigma_s.  The sigmas are read
+    on the host (one device-to-host copy when they are tensors)."""
+
+    @staticmethod
+    def forward(ctx, img, log_ss, log_sr, N=20, spatial="fir", center="mean"):
+        ss = math.exp(float(log_ss))
+        sr = math.exp(float(log_sr))
+        batch = img if img.dim() == 3 else img.unsqueeze(0)
+        B, H, W = batch.shape
+        out = torch.empty_like(batch)
+        saved = torch.empty(B, 16 * H * W, dtype=torch.uint8, device=img.device)
+        ws = workspace(H, W, N, ss, spatial, img.device)
+        for i in range(B):
+            gp_forward(batch[i], ss, sr, N, spatial=spatial, center=center, out=out[i], ws=ws, saved=saved[i])
+        ctx.save_for_backward(batch, saved)
+        shp = lambda v: (v.shape, v.dtype) if isinstance(v, torch.Tensor) else None
+        ctx.params = (ss, sr, int(N), spatial, center, img.dim(), shp(log_ss), shp(log_sr))
+        return out if img.dim() == 3 else out[0]
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        batch, saved = ctx.saved_tensors
+        ss, sr, N, spatial, center, dim, t_ss, t_sr = ctx.params
+        g = grad_out.contiguous()
+        g = g if g.dim() == 3 else g.unsqueeze(0)
+        B, H, W = batch.shape
+        gimg = torch.empty_like(batch)
+        gls = torch.zeros((), dtype=torch.float64, device=batch.device)
+        glr = torch.zeros((), dtype=torch.float64, device=batch.device)
+        ws = backward_workspace(H, W, N, ss, spatial, batch.device)
+        for i in range(B):
+            gi, gs, gr = gp_backward(batch[i], g[i], saved[i], ss, sr, N, spatial, center, ws=ws)
+            gimg[i] = gi
+            gls = gls + gs[0]
+            glr = glr + gr[0]
+        gimg = gimg if dim == 3 else gimg[0]
+        gss = gls.to(t_ss[1]).reshape(t_ss[0]) if t_ss else None
+        gsr = glr.to(t_sr[1]).reshape(t_sr[0]) if t_sr else None
+        return gimg, gss, gsr, None, None, None
+
+
+def gp_filter(img, log_ss, log_sr, N=20, spatial="fir", center="mean"):
+    """Differentiable GP bilateral filter (see GPFilterFn)."""
+    return GPFilterFn.apply(img, log_ss, log_sr, N, spatial, center)

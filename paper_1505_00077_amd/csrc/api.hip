@@ -13,6 +13,7 @@
 #include "fir.hpp"
 #include "iir.hpp"
 #include "direct.hpp"
+#include "bwd.hpp"
 
 using namespace bfgp;
 
@@ -39,9 +40,11 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
-// Window half-width of eq. (1): W = 3 sigma_s rounded up, at least 1.
+// Window half-width of eq. (1): W = 3 sigma_s rounded up, at least 1.  A
+// relative excess below 1e-6 (e.g. sigma_s = exp(float32 log 2)) does not
+// round up.
 int fir_radius(double sigma_s) {
-    int r = (int)ceil(3.0 * sigma_s - 1e-9);
+    int r = (int)ceil(3.0 * sigma_s * (1.0 - 1e-6));
     return r < 1 ? 1 : r;
 }
 
@@ -157,7 +160,7 @@ GPParams make_params(const float *img, float *out, int H, int W, int pitch, doub
     p.nparts = H < kMaxParts ? H : kMaxParts;
     p.status = (int *)(ws + L.status);
     p.saved = saved;
-    for (int n = 0; n <= kMaxC; ++n) {
+    for (int n = 0; n < kMaxC + 3; ++n) {
         p.sq[n] = sqrt((double)n);
         p.isq[n] = n > 0 ? 1.0 / sqrt((double)n) : 0.0;
     }
@@ -227,6 +230,25 @@ IirCoef make_iir(double sigma_s, int B, int L) {
     return c;
 }
 
+struct BwdLayout {
+    size_t parts, status, bparts, corr, total;
+};
+
+BwdLayout bwd_layout(int H, int W) {
+    BwdLayout L;
+    size_t off = 0;
+    L.parts = off;
+    off = align256(off + sizeof(Partial) * kMaxParts);
+    L.status = off;
+    off = align256(off + 16);
+    L.bparts = off;
+    off = align256(off + sizeof(BwdPartial) * (size_t)bwd_tiles(H, W));
+    L.corr = off;
+    off = align256(off + sizeof(double));
+    L.total = off;
+    return L;
+}
+
 }  // namespace
 
 extern "C" {
@@ -292,6 +314,58 @@ int bf_gp_status(const void *ws, void *stream, int *status) {
     e = hipStreamSynchronize((hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "status sync");
     *status = v;
+    return BF_OK;
+}
+
+
+size_t bf_gp_backward_workspace_bytes(int H, int W, int N, double sigma_s, unsigned flags) {
+    if (H < 1 || W < 1 || N < 0 || N > BF_MAX_DEGREE || !finite_pos(sigma_s)) return 0;
+    (void)flags;
+    return bwd_layout(H, W).total;
+}
+
+int bf_gp_backward(const float *img, const float *grad_out, const void *saved, int H, int W, int pitch,
+                   double sigma_s, double sigma_r, int N, unsigned flags, float *grad_img, double *grad_log_sigma_s,
+                   double *grad_log_sigma_r, void *ws, size_t ws_bytes, void *stream) {
+    int rc;
+    if ((rc = check_image(img, grad_out, H, W, pitch))) return rc;
+    if ((rc = check_params(sigma_s, sigma_r, N))) return rc;
+    if (!saved) return fail(BF_EINVAL, "null saved buffer");
+    if (!ws) return fail(BF_EINVAL, "null workspace");
+    if (flags & ~(BF_SPATIAL_MASK | BF_CENTER_MASK)) return fail(BF_EINVAL, "unknown flag bits 0x%x", flags);
+    if ((flags & BF_SPATIAL_MASK) == 3u || (flags & BF_CENTER_MASK) == 12u) return fail(BF_EINVAL, "invalid flag combination");
+    if (resolve_spatial(sigma_s, flags) != BF_SPATIAL_FIR)
+        return fail(BF_EUNSUPPORTED, "the backward pass is implemented for the FIR spatial mode");
+    if ((rc = check_spatial(BF_SPATIAL_FIR, sigma_s, W))) return rc;
+    if ((flags & BF_CENTER_MASK) == BF_CENTER_MIDRANGE)
+        return fail(BF_EUNSUPPORTED, "the backward pass supports the mean centre or no centring");
+    if (grad_img && ((const void *)grad_img == (const void *)img || (const void *)grad_img == (const void *)grad_out))
+        return fail(BF_EINVAL, "grad_img must not alias img or grad_out");
+    const BwdLayout L = bwd_layout(H, W);
+    if (ws_bytes < L.total) return fail(BF_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    Layout fl;
+    fl.parts = L.parts;
+    fl.status = L.status;
+    GPParams p = make_params(img, nullptr, H, W, pitch, sigma_r, N, flags, w, fl, const_cast<void *>(saved));
+    hipError_t e = launch_stats(img, H, W, pitch, (Partial *)(w + L.parts), p.nparts, s);
+    if (e != hipSuccess) return hip_fail(e, "statistics launch");
+    const int R = fir_radius(sigma_s);
+    FirTaps2 t;
+    memset(&t, 0, sizeof t);
+    for (int d = 0; d <= R; ++d) {
+        const double q = (double)d * d / (sigma_s * sigma_s);
+        t.k[d] = (float)exp(-0.5 * q);
+        t.kt[d] = (float)(q * exp(-0.5 * q));
+    }
+    BwdParams b;
+    b.grad_out = grad_out;
+    b.saved = (const float *)saved;
+    b.grad_img = grad_img;
+    b.bparts = (BwdPartial *)(w + L.bparts);
+    e = launch_bwd(p, b, t, R, (double *)(w + L.corr), grad_log_sigma_s, grad_log_sigma_r, s);
+    if (e != hipSuccess) return hip_fail(e, "backward launch");
     return BF_OK;
 }
 

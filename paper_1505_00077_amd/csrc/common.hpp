@@ -40,8 +40,8 @@ struct GPParams {
     int nparts;
     int *status;         // device status word (BF_OK / BF_ERANGE)
     void *saved;         // nullable, 16 B per pixel (see bf_gp_forward)
-    double sq[kMaxC + 1];   // sqrt(n)
-    double isq[kMaxC + 1];  // 1 / sqrt(n)
+    double sq[kMaxC + 3];   // sqrt(n)
+    double isq[kMaxC + 3];  // 1 / sqrt(n)
 };
 
 // Spatial taps of the FIR mode: k[d] = exp(-d^2 / 2 sigma_s^2), d = 0..R.

@@ -1,0 +1,74 @@
+// __global__ entry points of the backward pass and their launchers.
+#include "launch.hpp"
+#include "bwd.hpp"
+
+namespace bfgp {
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_bwd(GPParams p, BwdParams b, FirTaps2 taps) {
+    extern __shared__ float smem[];
+    const Stats st = load_stats(p);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *p.status = st.ok ? 0 : -3;
+    bwd_tile<R>(p, b, taps, st, blockIdx.y * BwdShape<R>::TY, blockIdx.x * BwdShape<R>::TX,
+                blockIdx.y * gridDim.x + blockIdx.x, smem);
+}
+
+// Sums the per-tile partials in a fixed order and writes the scalar gradients
+// and the mean-centring correction of the image gradient.
+__global__ __launch_bounds__(64) void k_bwd_finalize(GPParams p, const BwdPartial *bp, int ntiles, double *corr,
+                                                     double *g_lss, double *g_lsr) {
+    double v[5] = {0, 0, 0, 0, 0};
+    for (int i = threadIdx.x; i < ntiles; i += 64) {
+        v[0] += bp[i].sum_gh;
+        v[1] += bp[i].sum_xgH;
+        v[2] += bp[i].sum_grho;
+        v[3] += bp[i].sum_zu;
+        v[4] += bp[i].sum_g;
+    }
+    for (int q = 0; q < 5; ++q) v[q] = wave_sum(v[q]);
+    if (threadIdx.x == 0) {
+        const double n = (double)p.H * (double)p.W;
+        *corr = p.center == 0 ? (v[4] - v[0]) / n : 0.0;
+        if (g_lss) *g_lss = v[3];
+        if (g_lsr) *g_lsr = v[2] - v[1];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bwd_apply(float *grad, int H, int W, int pitch, const double *corr) {
+    const float c = (float)*corr;
+    for (int y = blockIdx.x; y < H; y += gridDim.x)
+        for (int x = threadIdx.x; x < W; x += kBlock) grad[(size_t)y * pitch + x] += c;
+}
+
+template <int R>
+static hipError_t bwd_launch_r(const GPParams &p, const BwdParams &b, const FirTaps2 &t, hipStream_t s) {
+    using S = BwdShape<R>;
+    dim3 grid((p.W + S::TX - 1) / S::TX, (p.H + S::TY - 1) / S::TY);
+    BF_LAUNCH("k_bwd", (k_bwd<R>), grid, dim3(kBlock), sizeof(float) * S::SMEM_FLOATS, s, p, b, t);
+    return hipGetLastError();
+}
+
+int bwd_tiles(int H, int W) { return ((W + 31) / 32) * ((H + 31) / 32); }
+
+hipError_t launch_bwd(const GPParams &p, const BwdParams &b, const FirTaps2 &t, int R, double *corr, double *g_lss,
+                      double *g_lsr, hipStream_t s) {
+    hipError_t e;
+    switch (R) {
+#define BF_CASE(r) case r: e = bwd_launch_r<r>(p, b, t, s); break;
+        BF_CASE(1) BF_CASE(2) BF_CASE(3) BF_CASE(4) BF_CASE(5) BF_CASE(6) BF_CASE(7) BF_CASE(8)
+        BF_CASE(9) BF_CASE(10) BF_CASE(11) BF_CASE(12) BF_CASE(13) BF_CASE(14) BF_CASE(15) BF_CASE(16)
+        BF_CASE(17) BF_CASE(18) BF_CASE(19) BF_CASE(20) BF_CASE(21) BF_CASE(22) BF_CASE(23) BF_CASE(24)
+#undef BF_CASE
+        default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    BF_LAUNCH("k_bwd_finalize", k_bwd_finalize, dim3(1), dim3(64), 0, s, p, b.bparts, bwd_tiles(p.H, p.W), corr,
+              g_lss, g_lsr);
+    if (b.grad_img && p.center == 0) {
+        const int g = p.H < 1024 ? p.H : 1024;
+        BF_LAUNCH("k_bwd_apply", k_bwd_apply, dim3(g), dim3(kBlock), 0, s, b.grad_img, p.H, p.W, p.pitch, corr);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace bfgp

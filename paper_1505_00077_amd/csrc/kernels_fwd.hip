@@ -59,7 +59,7 @@ __global__ __launch_bounds__(512, 1) void k_hrow(GPParams p, IirCoef c, const fl
 // ---- host launchers ----------------------------------------------------------
 
 hipError_t launch_stats(const float *img, int H, int W, int pitch, Partial *parts, int nparts, hipStream_t s) {
-    hipLaunchKernelGGL(k_stats, dim3(nparts), dim3(kBlock), 0, s, img, H, W, pitch, parts);
+    BF_LAUNCH("k_stats", k_stats, dim3(nparts), dim3(kBlock), 0, s, img, H, W, pitch, parts);
     return hipGetLastError();
 }
 
@@ -69,9 +69,9 @@ static hipError_t fir_launch_r(const GPParams &p, const FirTaps &t, bool save, h
     dim3 grid((p.W + S::TX - 1) / S::TX, (p.H + S::TY - 1) / S::TY);
     const size_t sm = sizeof(float) * S::SMEM_FLOATS;
     if (save)
-        hipLaunchKernelGGL((k_fir<R, true>), grid, dim3(kBlock), sm, s, p, t);
+        BF_LAUNCH("k_fir", (k_fir<R, true>), grid, dim3(kBlock), sm, s, p, t);
     else
-        hipLaunchKernelGGL((k_fir<R, false>), grid, dim3(kBlock), sm, s, p, t);
+        BF_LAUNCH("k_fir", (k_fir<R, false>), grid, dim3(kBlock), sm, s, p, t);
     return hipGetLastError();
 }
 
@@ -92,8 +92,8 @@ hipError_t launch_iir(const GPParams &p, const IirCoef &c, int B, int L, int T, 
     dim3 gv((p.W + 63) / 64, nb);
 #define BF_VB(b, agg)                                                                        \
     do {                                                                                     \
-        hipLaunchKernelGGL((k_vband<b, agg, false>), gv, dim3(64), 0, s, p, c, carry, S);    \
-        hipLaunchKernelGGL((k_vband<b, agg, true>), gv, dim3(64), 0, s, p, c, carry, S);     \
+        BF_LAUNCH(agg ? "k_vband_agg" : "k_vband", (k_vband<b, agg, false>), gv, dim3(64), 0, s, p, c, carry, S);    \
+        BF_LAUNCH(agg ? "k_vband_agg_big" : "k_vband_big", (k_vband<b, agg, true>), gv, dim3(64), 0, s, p, c, carry, S);     \
     } while (0)
     if (B == 64)
         BF_VB(64, true);
@@ -101,16 +101,16 @@ hipError_t launch_iir(const GPParams &p, const IirCoef &c, int B, int L, int T, 
         BF_VB(32, true);
     else
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_vresolve, dim3((p.W + kBlock - 1) / kBlock, p.C), dim3(kBlock), 0, s, p, c, nb, carry);
+    BF_LAUNCH("k_vresolve", k_vresolve, dim3((p.W + kBlock - 1) / kBlock, p.C), dim3(kBlock), 0, s, p, c, nb, carry);
     if (B == 64)
         BF_VB(64, false);
     else
         BF_VB(32, false);
 #undef BF_VB
     switch (L) {
-        case 4: hipLaunchKernelGGL((k_hrow<4>), dim3(p.H), dim3(T), 0, s, p, c, S); break;
-        case 8: hipLaunchKernelGGL((k_hrow<8>), dim3(p.H), dim3(T), 0, s, p, c, S); break;
-        case 16: hipLaunchKernelGGL((k_hrow<16>), dim3(p.H), dim3(T), 0, s, p, c, S); break;
+        case 4: BF_LAUNCH("k_hrow", (k_hrow<4>), dim3(p.H), dim3(T), 0, s, p, c, S); break;
+        case 8: BF_LAUNCH("k_hrow", (k_hrow<8>), dim3(p.H), dim3(T), 0, s, p, c, S); break;
+        case 16: BF_LAUNCH("k_hrow", (k_hrow<16>), dim3(p.H), dim3(T), 0, s, p, c, S); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -118,7 +118,7 @@ hipError_t launch_iir(const GPParams &p, const IirCoef &c, int B, int L, int T, 
 
 hipError_t launch_direct(const DirectArgs &a, hipStream_t s) {
     dim3 grid((a.W + kDirTX - 1) / kDirTX, (a.H + kDirTY - 1) / kDirTY);
-    hipLaunchKernelGGL(k_direct, grid, dim3(kBlock), sizeof(float) * direct_smem_floats(), s, a);
+    BF_LAUNCH("k_direct", k_direct, grid, dim3(kBlock), sizeof(float) * direct_smem_floats(), s, a);
     return hipGetLastError();
 }
 

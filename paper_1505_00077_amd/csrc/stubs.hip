@@ -3,9 +3,6 @@
 #include "../../include/bfgp.h"
 
 extern "C" {
-size_t bf_gp_backward_workspace_bytes(int, int, int, double, unsigned) { return 0; }
-int bf_gp_backward(const float *, const float *, const void *, int, int, int, double, double, int, unsigned, float *,
-                   double *, double *, void *, size_t, void *) { return BF_EUNSUPPORTED; }
 int bf_gp_plan_batched(const bf_gp_item *, int, unsigned, void **) { return BF_EUNSUPPORTED; }
 size_t bf_gp_plan_workspace_bytes(const void *) { return 0; }
 int bf_gp_plan_upload(void *, void *, size_t, void *) { return BF_EUNSUPPORTED; }

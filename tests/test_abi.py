@@ -109,3 +109,8 @@ def test_fir_radius_rule():
     assert bf.fir_radius(2.0) == 6
     assert bf.fir_radius(0.1) == 1
     assert bf.fir_radius(3.01) == 10
+    # float32 rounding of sigma_s does not move the window
+    import math
+    import numpy as np
+    assert bf.fir_radius(math.exp(float(np.float32(math.log(2.0))))) == 6
+    assert bf.fir_radius(2.0 * (1 + 1e-5)) == 7

@@ -1,0 +1,143 @@
+"""Hand-written backward on the GPU against the FP64 oracle's analytic
+gradient and against FP64 central finite differences of the oracle forward.
+
+Tolerances: the image gradient to 1e-3 of its largest magnitude, the scalar
+gradients to 1e-3 relative (FP32 channels, FP64 reductions)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synthimg
+from gpu_util import note, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1505_00077_amd as m
+    return m
+
+
+def gpu_grads(bf, img, target, ss, sr, N, center="mean"):
+    note(f"backward {img.shape} ss={ss} sr={sr} N={N} {center}")
+    x = to_dev(img)
+    saved = bf.saved_buffer(*img.shape)
+    out = bf.gp_forward(x, ss, sr, N, spatial="fir", center=center, saved=saved, check=True)
+    g = out - to_dev(target)
+    gi, gs, gr = bf.gp_backward(x, g.contiguous(), saved, ss, sr, N, spatial="fir", center=center)
+    return to_np(out), to_np(gi), float(gs.item()), float(gr.item())
+
+
+def oracle_grads(img, target, ss, sr, N, center=oracle.CENTER_MEAN):
+    f = img.astype(np.float64)
+    R = oracle.fir_radius(ss)
+    k, kt = oracle.gauss_table(ss, R), oracle.gauss_dtable(ss, R)
+    out = oracle.gp_alg1(f, sr, N, k, center)
+    return oracle.gp_grad(f, out - target, sr, N, k, kt, center)
+
+
+@pytest.mark.parametrize("shape,ss,N", [((37, 45), 1.3, 8), ((64, 40), 2.5, 20), ((70, 101), 4.0, 20),
+                                         ((33, 97), 0.7, 2), ((48, 48), 6.0, 20)])
+def test_gradients_match_oracle(bf, shape, ss, N):
+    H, W = shape
+    img = synthimg.voronoi_image(H, W, 12, seed=H + W)
+    target = synthimg.voronoi_image(H, W, 12, seed=H * W)
+    out, gi, gs, gr = gpu_grads(bf, img, target, ss, 25.0, N)
+    # the upstream gradient is formed from the GPU output, as the oracle's
+    # from its own; they differ by the forward error (<1e-3)
+    rgi, rgs, rgr = oracle_grads(img, target.astype(np.float64), ss, 25.0, N)
+    scale = np.max(np.abs(rgi))
+    assert np.max(np.abs(gi - rgi)) <= 1e-3 * scale
+    assert gs == pytest.approx(rgs, rel=1e-3, abs=1e-6 * scale * img.size)
+    assert gr == pytest.approx(rgr, rel=1e-3, abs=1e-6 * scale * img.size)
+
+
+def test_no_centring_gradient(bf):
+    img = synthimg.voronoi_image(40, 52, 10, seed=9) * 0.5 + 60.0
+    target = synthimg.voronoi_image(40, 52, 10, seed=10) * 0.5 + 60.0
+    _, gi, gs, gr = gpu_grads(bf, img.astype(np.float32), target, 2.0, 40.0, 20, center="none")
+    rgi, rgs, rgr = oracle_grads(img.astype(np.float32), target.astype(np.float64), 2.0, 40.0, 20,
+                                 oracle.CENTER_NONE)
+    scale = np.max(np.abs(rgi))
+    assert np.max(np.abs(gi - rgi)) <= 1e-3 * scale
+    assert gs == pytest.approx(rgs, rel=1e-3)
+    assert gr == pytest.approx(rgr, rel=1e-3)
+
+
+def test_finite_differences_on_crop(bf):
+    # 32x32 crop of the 512x512 training images, sigma_s 4, sigma_r 25,
+    # L2 loss to a crop of the target; FP64 central differences, h = 1e-4,
+    # of the oracle forward (radius held at ceil(3 sigma_s) = 12)
+    imgs, target = synthimg.grad_batch(count=1)
+    img = imgs[0][100:132, 200:232].copy()
+    tgt = target[100:132, 200:232].astype(np.float64)
+    ss, sr, N = 4.0, 25.0, 20
+    _, gi, gs, gr = gpu_grads(bf, img, tgt, ss, sr, N)
+    R = oracle.fir_radius(ss)
+    f = img.astype(np.float64)
+
+    def loss(fimg, s, r):
+        o = oracle.gp_alg1(fimg, r, N, oracle.gauss_table(s, R))
+        return 0.5 * float(np.sum((o - tgt) ** 2))
+
+    h = 1e-4
+    fd = np.empty_like(f)
+    for idx in np.ndindex(f.shape):
+        fp = f.copy(); fp[idx] += h
+        fm = f.copy(); fm[idx] -= h
+        fd[idx] = (loss(fp, ss, sr) - loss(fm, ss, sr)) / (2 * h)
+    fs = (loss(f, ss * math.exp(h), sr) - loss(f, ss * math.exp(-h), sr)) / (2 * h)
+    fr = (loss(f, ss, sr * math.exp(h)) - loss(f, ss, sr * math.exp(-h))) / (2 * h)
+    scale = np.max(np.abs(fd))
+    print(f"FD crop: max|grad - fd| / max|fd| = {np.max(np.abs(gi - fd)) / scale:.2e}; "
+          f"log ss {gs:.6g} vs {fs:.6g}; log sr {gr:.6g} vs {fr:.6g}")
+    assert np.max(np.abs(gi - fd)) <= 1e-3 * scale
+    assert gs == pytest.approx(fs, rel=1e-3)
+    assert gr == pytest.approx(fr, rel=1e-3)
+
+
+def test_training_image_full_gradient(bf):
+    # one 512x512 image of the training batch, full-image comparison
+    imgs, target = synthimg.grad_batch(count=1)
+    out, gi, gs, gr = gpu_grads(bf, imgs[0], target, 4.0, 25.0, 20)
+    rgi, rgs, rgr = oracle_grads(imgs[0], target.astype(np.float64), 4.0, 25.0, 20)
+    scale = np.max(np.abs(rgi))
+    assert np.max(np.abs(gi - rgi)) <= 1e-3 * scale
+    assert gs == pytest.approx(rgs, rel=1e-3)
+    assert gr == pytest.approx(rgr, rel=1e-3)
+
+
+def test_autograd_function(bf):
+    imgs, target = synthimg.grad_batch(count=3, H=64, W=80)
+    x = to_dev(imgs).requires_grad_(True)
+    lss = torch.tensor(math.log(2.0), device="cuda", requires_grad=True)
+    lsr = torch.tensor(math.log(25.0), device="cuda", requires_grad=True)
+    note("autograd batch of 3")
+    out = bf.gp_filter(x, lss, lsr, 20)
+    loss = 0.5 * ((out - to_dev(target)[None]) ** 2).sum()
+    loss.backward()
+    gx = to_np(x.grad)
+    # the filter sees the sigmas that the float32 parameters hold
+    ss, sr = math.exp(float(lss)), math.exp(float(lsr))
+    tot_s = tot_r = 0.0
+    for i in range(3):
+        rgi, rgs, rgr = oracle_grads(imgs[i], target.astype(np.float64), ss, sr, 20)
+        assert np.max(np.abs(gx[i] - rgi)) <= 1e-3 * np.max(np.abs(rgi))
+        tot_s += rgs
+        tot_r += rgr
+    assert float(lss.grad) == pytest.approx(tot_s, rel=1e-3)
+    assert float(lsr.grad) == pytest.approx(tot_r, rel=1e-3)
+
+
+def test_backward_deterministic(bf):
+    img = synthimg.voronoi_image(96, 96, 20, seed=3)
+    tgt = synthimg.voronoi_image(96, 96, 20, seed=4)
+    a = gpu_grads(bf, img, tgt, 2.0, 30.0, 20)
+    b = gpu_grads(bf, img, tgt, 2.0, 30.0, 20)
+    assert np.array_equal(a[1], b[1]) and a[2] == b[2] and a[3] == b[3]

@@ -74,17 +74,24 @@ def test_degrees(bf, N, spatial):
     if spatial == "iir" and N == 0:
         # Deriche's kernel dips below zero (about -1.4e-4 of its peak near 5.4
         # sigma_s).  At degree 0 the weights exp(-(t^2 + tau^2)/2) of dark or
-        # bright pixels are so small that these negative lobes can make the
-        # denominator D vanish or change sign (the FP64 oracle's own D is
-        # negative at some pixels): the output there is an ill-conditioned
-        # ratio.  Compare where D is at least half of the pixel's own term
-        # u_0(tau)^2 h(0)^2, and require that to be almost every pixel.
+        # bright pixels are tiny, so a ring of opposite-intensity pixels seen
+        # through these negative lobes nearly cancels the denominator (the
+        # FP64 oracle's own D is negative at some pixels).  The FP32 result
+        # then legitimately differs from FP64 by the condition number of that
+        # sum, cond = (sum |h| w) / |sum h w|.  Compare where cond <= 2 (over
+        # 99% of the pixels) and show the rest is genuinely ill-conditioned.
         k, _ = oracle.spatial_table("iir", 2.0, *img.shape)
-        _, D, _ = oracle.gp_rescaled(img.astype(np.float64), 30.0, 0, k, return_dm=True)
-        x = (img.astype(np.float64) - img.astype(np.float64).mean()) / 30.0
-        well = D >= 0.5 * np.exp(-x * x) * k[0] ** 2
+        f = img.astype(np.float64)
+        _, D, _ = oracle.gp_rescaled(f, 30.0, 0, k, return_dm=True)
+        _, Da, _ = oracle.gp_rescaled(f, 30.0, 0, np.abs(k), return_dm=True)
+        cond = Da / np.abs(D)
+        well = cond <= 2.0
+        err = np.abs(got - ref)
+        worst = np.unravel_index(np.argmax(err), err.shape)
+        print(f"N=0 iir: well-conditioned {well.mean():.4f}, max err there {err[well].max():.2e}, "
+              f"worst pixel {worst} err {err[worst]:.3e} cond {cond[worst]:.1f}")
         assert well.mean() > 0.99
-        assert np.max(np.abs(got - ref)[well]) <= TOL
+        assert err[well].max() <= TOL
         return
     assert np.max(np.abs(got - ref)) <= TOL
 
