@@ -190,6 +190,78 @@ def main():
         log(f"16MP: {ms:.3f} ms")
         del big, bws, bout
 
+
+    # ---------------- batched: one persistent launch in a graph ----------------
+    if want("batched"):
+        log("generating the 64-image batch")
+        batch = synthimg.batched_64()
+        bimgs = [torch.from_numpy(b[0]).to(dev) for b in batch]
+        bss = [b[1] for b in batch]
+        bsr = [b[2] for b in batch]
+        npx = sum(x.numel() for x in bimgs)
+        plan_b = bf.BatchPlan(bimgs, bss, bsr, DEGREE)
+        plan_b.run()
+        torch.cuda.synchronize()
+        graph = plan_b.graph()
+        ms_graph = timed(graph.replay, K, Wm, torch)
+        souts = [torch.empty_like(x) for x in bimgs]
+        swss = [bf.workspace(x.shape[0], x.shape[1], DEGREE, s) for x, s in zip(bimgs, bss)]
+        # the batch descriptors hold float32 sigmas; the sequential calls use the same values
+        bss32 = [float(np.float32(v)) for v in bss]
+        bsr32 = [float(np.float32(v)) for v in bsr]
+
+        def seq():
+            for x, o, w, s_, r_ in zip(bimgs, souts, swss, bss32, bsr32):
+                bf.gp_forward(x, s_, r_, DEGREE, out=o, ws=w)
+
+        ms_seq = timed(seq, K, Wm, torch)
+        worst = max(float((a - b).abs().max()) for a, b in zip(plan_b.outs, souts))
+        modes["batched_64"] = {"images": len(bimgs), "megapixels": npx / 1e6, "ms_graph": ms_graph,
+                               "mpix_s_graph": npx / (ms_graph * 1e-3) / 1e6, "ms_sequential": ms_seq,
+                               "mpix_s_sequential": npx / (ms_seq * 1e-3) / 1e6,
+                               "max_abs_diff_vs_sequential": worst,
+                               "plans": {m: sum(1 for s_ in bss if bf.resolve_spatial(s_) == m) for m in ("fir", "iir")}}
+        log(f"batched: graph {ms_graph:.3f} ms, sequential {ms_seq:.3f} ms")
+        del plan_b, graph, bimgs, souts, swss
+
+    # ---------------- forward + backward: 16 x 512^2, sigma_s 4, sigma_r 25 ----------------
+    if want("fwdbwd"):
+        imgs_np, tgt_np = synthimg.grad_batch()
+        gimgs = torch.from_numpy(imgs_np).to(dev)
+        tgt = torch.from_numpy(tgt_np).to(dev)
+        B_, H_, W_ = gimgs.shape
+        ss_g, sr_g = 4.0, 25.0
+        fws = bf.workspace(H_, W_, DEGREE, ss_g, "fir")
+        bws = bf.backward_workspace(H_, W_, DEGREE, ss_g, "fir")
+        saved = torch.empty(B_, 16 * H_ * W_, dtype=torch.uint8, device=dev)
+        fout = torch.empty_like(gimgs)
+        gout = torch.empty_like(gimgs)
+        gimg = torch.empty_like(gimgs)
+        gls = torch.zeros(B_, dtype=torch.float64, device=dev)
+        glr = torch.zeros(B_, dtype=torch.float64, device=dev)
+        stream = bf._stream(dev)
+        flags = bf._flags("fir")
+
+        def fwd_bwd():
+            for i in range(B_):
+                bf.gp_forward(gimgs[i], ss_g, sr_g, DEGREE, spatial="fir", out=fout[i], ws=fws, saved=saved[i])
+                torch.sub(fout[i], tgt, out=gout[i])
+                bf._check(bf.bf_gp_backward(gimgs[i].data_ptr(), gout[i].data_ptr(), saved[i].data_ptr(), H_, W_, W_,
+                                            ss_g, sr_g, DEGREE, flags, gimg[i].data_ptr(), gls[i:].data_ptr(),
+                                            glr[i:].data_ptr(), bws.data_ptr(), bws.numel(), stream), "backward")
+
+        def fwd_only():
+            for i in range(B_):
+                bf.gp_forward(gimgs[i], ss_g, sr_g, DEGREE, spatial="fir", out=fout[i], ws=fws)
+
+        ms_fb = timed(fwd_bwd, K, Wm, torch)
+        ms_f = timed(fwd_only, K, Wm, torch)
+        npx = B_ * H_ * W_
+        modes["fwd_bwd_16x512"] = {"ms": ms_fb, "mpix_s": npx / (ms_fb * 1e-3) / 1e6, "fwd_only_ms": ms_f,
+                                   "fwd_only_mpix_s": npx / (ms_f * 1e-3) / 1e6, "plan": "fir",
+                                   "grad_log_sigma_s_sum": float(gls.sum()), "grad_log_sigma_r_sum": float(glr.sum())}
+        log(f"fwd+bwd: {ms_fb:.3f} ms (fwd only {ms_f:.3f} ms)")
+
     # ---------------- accuracy on the small configuration ----------------
     if want("accuracy"):
         import oracle

@@ -121,11 +121,15 @@ int bf_gp_backward(const float *img, const float *grad_out, const void *saved,
                    double *grad_log_sigma_r, void *ws, size_t ws_bytes, void *stream);
 
 /* ---- batched GP forward ---------------------------------------------------
- * Many images of uneven size, each with its own sigma_s and sigma_r, filtered
- * by one persistent launch (Algorithm 1 applied per image).  Plans are host
- * objects; bf_gp_plan_upload copies the plan's descriptors into the workspace
- * (once, outside any graph capture); bf_gp_forward_batched then only launches
- * kernels and may be captured into a hipGraph and replayed. */
+ * Many images of uneven size, each with its own sigma_s and sigma_r (Algorithm 1
+ * applied per image), filtered by one short sequence of grouped launches: one
+ * launch per stage (statistics, FIR tiles, column-band states, carry
+ * resolution, column pass, row pass), each covering every image of the batch,
+ * so no workgroup ever waits on another.  Plans are host objects;
+ * bf_gp_plan_upload copies the plan's descriptors into the workspace (once,
+ * outside any graph capture, synchronising `stream`); bf_gp_forward_batched
+ * then only launches kernels and may be captured into a hipGraph and replayed.
+ * Images are limited to 2048 columns; FIR is used up to radius 12. */
 typedef struct bf_gp_item {
     const float *img; /* device, H x W, row pitch `pitch` elements */
     float *out;       /* device, same shape and pitch */

@@ -271,3 +271,52 @@ class GPFilterFn(torch.autograd.Function):
 def gp_filter(img, log_ss, log_sr, N=20, spatial="fir", center="mean"):
     """Differentiable GP bilateral filter (see GPFilterFn)."""
     return GPFilterFn.apply(img, log_ss, log_sr, N, spatial, center)
+
+
+# --------------------------------------------------------------------------
+# batched forward
+# --------------------------------------------------------------------------
+
+class BatchPlan:
+    """One persistent launch over many images of uneven size, each with its
+    own sigma_s and sigma_r.  The plan owns its device workspace; `run()`
+    enqueues the launch on the current stream and `graph()` captures it into a
+    CUDA/HIP graph for replay."""
+
+    def __init__(self, imgs, sigmas_s, sigmas_r, N=20, outs=None, spatial="auto", center="mean"):
+        n = len(imgs)
+        if not (len(sigmas_s) == len(sigmas_r) == n) or n == 0:
+            raise ValueError("one sigma_s and one sigma_r per image")
+        self.imgs = list(imgs)
+        self.outs = list(outs) if outs is not None else [torch.empty_like(x) for x in self.imgs]
+        items = (BfGpItem * n)()
+        for i, (x, o) in enumerate(zip(self.imgs, self.outs)):
+            H, W, pitch = _image(x)
+            if _image(o, "out") != (H, W, pitch):
+                raise ValueError("each output must match its image's shape and row stride")
+            items[i] = BfGpItem(x.data_ptr(), o.data_ptr(), H, W, pitch, float(sigmas_s[i]), float(sigmas_r[i]),
+                                int(N))
+        self._plan = ctypes.c_void_p()
+        _check(bf_gp_plan_batched(items, n, _flags(spatial, center), ctypes.byref(self._plan)), "bf_gp_plan_batched")
+        nbytes = int(bf_gp_plan_workspace_bytes(self._plan))
+        self.device = self.imgs[0].device
+        self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        _check(bf_gp_plan_upload(self._plan, self.ws.data_ptr(), self.ws.numel(), _stream(self.device)),
+               "bf_gp_plan_upload")
+
+    def run(self):
+        _check(bf_gp_forward_batched(self._plan, self.ws.data_ptr(), self.ws.numel(), _stream(self.device)),
+               "bf_gp_forward_batched")
+        return self.outs
+
+    def graph(self):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run()
+        return g
+
+    def __del__(self):
+        plan = getattr(self, "_plan", None)
+        if plan is not None and plan.value:
+            bf_gp_plan_free(plan)
+            self._plan = None

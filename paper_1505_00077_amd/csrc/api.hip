@@ -251,6 +251,24 @@ BwdLayout bwd_layout(int H, int W) {
 
 }  // namespace
 
+// Helpers shared with the batched path (batched.hip).
+namespace bfgp {
+GPParams gp_params_for(const float *img, float *out, int H, int W, int pitch, double sigma_r, int N, unsigned flags,
+                       const Partial *parts, int nparts, int *status) {
+    Layout L;
+    L.parts = 0;
+    L.status = 0;
+    GPParams p = make_params(img, out, H, W, pitch, sigma_r, N, flags, (char *)0, L, nullptr);
+    p.parts = parts;
+    p.nparts = nparts;
+    p.status = status;
+    return p;
+}
+IirCoef iir_coef_for(double sigma_s, int B, int L) { return make_iir(sigma_s, B, L); }
+FirTaps fir_taps_for(double sigma_s, int R) { return make_taps(sigma_s, R); }
+int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+}  // namespace bfgp
+
 extern "C" {
 
 int bf_version(void) { return 10000; }

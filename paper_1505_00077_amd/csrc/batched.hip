@@ -1,0 +1,313 @@
+// Batched GP forward: many images of uneven size, each with its own sigma_s and
+// sigma_r, in one graph of grouped launches.
+//
+// The host builds, per stage, one work list that covers every image of the
+// batch.  Each stage is one grouped launch with one workgroup per item; stage
+// order is kept by the launch order on the stream, so no workgroup ever waits
+// for another and the grid always drains.  Stages: statistics (all images),
+// fused FIR tiles (FIR images), then for IIR images the column-band end states,
+// the band carry resolution, the column pass and the row pass with the FP64
+// recombination.  The whole sequence is captured into a hipGraph by the caller
+// and replayed.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "../../include/bfgp.h"
+#include "launch.hpp"
+#include "fir.hpp"
+#include "iir.hpp"
+
+namespace bfgp {
+
+enum { kStStats = 0, kStFir, kStAgg, kStResolve, kStBand, kStRow, kNumStages };
+// same partial count as the single-image path, so that both reduce the image
+// sum in the same order and produce bit-identical centres and outputs
+constexpr int kBatchStatsParts = kMaxParts;
+constexpr int kBatchFirMaxR = 12;
+constexpr int kBatchBand = 64;
+
+struct BatchImage {
+    GPParams p;
+    IirCoef c;
+    FirTaps taps;
+    int iir;       // 0 FIR, 1 IIR
+    int R;         // FIR radius
+    int L;         // IIR row chunk
+    int nb;        // IIR bands
+    float *carry;
+    float *S;
+};
+
+struct BatchItem {
+    int img, idx;
+};
+
+__global__ __launch_bounds__(kBlock) void k_bstats(const BatchImage *imgs, const BatchItem *items) {
+    const BatchItem w = items[blockIdx.x];
+    const GPParams &p = imgs[w.img].p;
+    stats_rows(p.img, p.H, p.W, p.pitch, w.idx, p.nparts, const_cast<Partial *>(p.parts));
+}
+
+template <int R>
+__device__ __forceinline__ void fir_item(const BatchImage &B, const Stats &st, int idx, float *smem) {
+    using S = FirShape<R>;
+    const int tx = (B.p.W + S::TX - 1) / S::TX;
+    fir_tile<R, false>(B.p, B.taps, st, (idx / tx) * S::TY, (idx % tx) * S::TX, smem);
+}
+
+__global__ __launch_bounds__(kBlock) void k_bfir(const BatchImage *imgs, const BatchItem *items) {
+    extern __shared__ float smem[];
+    const BatchItem w = items[blockIdx.x];
+    const BatchImage &B = imgs[w.img];
+    const Stats st = load_stats(B.p);
+    if (threadIdx.x == 0 && w.idx == 0) *B.p.status = st.ok ? 0 : -3;
+    switch (B.R) {
+#define BF_CASE(r) case r: fir_item<r>(B, st, w.idx, smem); break;
+        BF_CASE(1) BF_CASE(2) BF_CASE(3) BF_CASE(4) BF_CASE(5) BF_CASE(6)
+        BF_CASE(7) BF_CASE(8) BF_CASE(9) BF_CASE(10) BF_CASE(11) BF_CASE(12)
+#undef BF_CASE
+        default: break;
+    }
+}
+
+// One item = one band of four 64-column groups (one per wave).
+template <bool AGG, bool BIG>
+__global__ __launch_bounds__(kBlock, 2) void k_bband(const BatchImage *imgs, const BatchItem *items) {
+    __shared__ float sacc[AGG ? 1 : 4 * kBatchBand * 64];
+    const BatchItem w = items[blockIdx.x];
+    const BatchImage &B = imgs[w.img];
+    const Stats st = load_stats(B.p);
+    if (AGG && !BIG && threadIdx.x == 0 && w.idx == 0) *B.p.status = st.ok ? 0 : -3;
+    if (!st.ok || ((st.xmax > 12.0) != BIG)) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ncg = (B.p.W + 63) / 64, ncg4 = (ncg + 3) / 4;
+    const int band = w.idx / ncg4, cg = (w.idx % ncg4) * 4 + wave;
+    if (cg >= ncg) return;
+    vband<kBatchBand, AGG, BIG>(B.p, B.c, st, cg * 64 + lane, band, B.carry, B.S, sacc + (AGG ? 0 : wave * kBatchBand * 64));
+}
+
+__global__ __launch_bounds__(kBlock) void k_bresolve(const BatchImage *imgs, const BatchItem *items) {
+    const BatchItem w = items[blockIdx.x];
+    const BatchImage &B = imgs[w.img];
+    const int ng = (B.p.W + kBlock - 1) / kBlock;
+    const int n = w.idx / ng, col = (w.idx % ng) * kBlock + threadIdx.x;
+    if (col < B.p.W) vresolve(B.p, B.c, B.nb, col, n, B.carry);
+}
+
+__global__ __launch_bounds__(kBlock) void k_brow(const BatchImage *imgs, const BatchItem *items) {
+    __shared__ float sm[hrow_smem_floats(kBlock / 64)];
+    const BatchItem w = items[blockIdx.x];
+    const BatchImage &B = imgs[w.img];
+    const Stats st = load_stats(B.p);
+    if (!st.ok) {
+        for (int x = threadIdx.x; x < B.p.W; x += kBlock) B.p.out[(size_t)w.idx * B.p.pitch + x] = __builtin_nanf("");
+        return;
+    }
+    if (B.L == 4)
+        hrow<4>(B.p, B.c, st, w.idx, B.S, sm);
+    else
+        hrow<8>(B.p, B.c, st, w.idx, B.S, sm);
+}
+
+// ---- host side -------------------------------------------------------------
+
+struct Plan {
+    std::vector<bf_gp_item> items;
+    std::vector<BatchImage> imgs;
+    std::vector<BatchItem> work;           // all stages, concatenated
+    int first[kNumStages + 1];             // stage s items: work[first[s] .. first[s+1])
+    std::vector<int> iir, R, L;
+    size_t off_imgs, off_items, total;
+    std::vector<size_t> off_parts, off_status, off_carry, off_S;
+    size_t fir_smem;
+    unsigned flags;
+    bool uploaded;
+    void *ws;
+};
+
+}  // namespace bfgp
+
+using namespace bfgp;
+
+namespace {
+
+size_t al(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int fir_radius_b(double sigma_s) {
+    int r = (int)ceil(3.0 * sigma_s * (1.0 - 1e-6));
+    return r < 1 ? 1 : r;
+}
+
+}  // namespace
+
+// defined in api.hip
+namespace bfgp {
+GPParams gp_params_for(const float *img, float *out, int H, int W, int pitch, double sigma_r, int N, unsigned flags,
+                       const Partial *parts, int nparts, int *status);
+IirCoef iir_coef_for(double sigma_s, int B, int L);
+FirTaps fir_taps_for(double sigma_s, int R);
+int set_error(int code, const char *msg);
+}  // namespace bfgp
+
+extern "C" {
+
+int bf_gp_plan_batched(const bf_gp_item *items, int count, unsigned flags, void **plan_out) {
+    if (!plan_out) return set_error(BF_EINVAL, "null plan_out");
+    *plan_out = nullptr;
+    if (!items || count < 1) return set_error(BF_EINVAL, "empty batch");
+    if (flags & ~(BF_SPATIAL_MASK | BF_CENTER_MASK)) return set_error(BF_EINVAL, "unknown flag bits");
+    if ((flags & BF_SPATIAL_MASK) == 3u || (flags & BF_CENTER_MASK) == 12u) return set_error(BF_EINVAL, "invalid flags");
+    for (int i = 0; i < count; ++i) {
+        const bf_gp_item &it = items[i];
+        if (!it.img || !it.out || it.img == it.out) return set_error(BF_EINVAL, "bad image pointers in the batch");
+        if (it.H < 1 || it.W < 1 || it.pitch < it.W) return set_error(BF_EINVAL, "bad image size in the batch");
+        if (!(it.sigma_s > 0) || !(it.sigma_r > 0) || !std::isfinite((double)it.sigma_s) ||
+            !std::isfinite((double)it.sigma_r))
+            return set_error(BF_EINVAL, "bad sigma in the batch");
+        if (it.N < 0 || it.N > BF_MAX_DEGREE) return set_error(BF_EINVAL, "bad degree in the batch");
+        if (it.W > 2048) return set_error(BF_EUNSUPPORTED, "batched images are limited to 2048 columns");
+    }
+    Plan *P = new (std::nothrow) Plan();
+    if (!P) return set_error(BF_EHIP, "out of host memory");
+    P->items.assign(items, items + count);
+    P->flags = flags;
+    P->uploaded = false;
+    P->ws = nullptr;
+    size_t off = 0;
+    P->off_imgs = off;
+    off = al(off + sizeof(BatchImage) * count);
+    size_t fir_smem = 0;
+    std::vector<std::vector<BatchItem>> per(kNumStages);
+    P->off_parts.resize(count);
+    P->off_status.resize(count);
+    P->off_carry.resize(count);
+    P->off_S.resize(count);
+    P->iir.resize(count);
+    P->R.resize(count);
+    P->L.resize(count);
+    for (int i = 0; i < count; ++i) {
+        const bf_gp_item &it = items[i];
+        unsigned m = flags & BF_SPATIAL_MASK;
+        if (m == BF_SPATIAL_AUTO) m = bf_gp_resolve_spatial(it.sigma_s, flags);
+        const int R = fir_radius_b(it.sigma_s);
+        const bool iir = (m == BF_SPATIAL_IIR) || R > kBatchFirMaxR;
+        P->iir[i] = iir;
+        P->R[i] = R;
+        P->L[i] = it.W <= 1024 ? 4 : 8;
+        const int nparts = std::min(it.H, kBatchStatsParts);
+        P->off_parts[i] = off;
+        off = al(off + sizeof(Partial) * nparts);
+        P->off_status[i] = off;
+        off = al(off + 16);
+        for (int b = 0; b < nparts; ++b) per[kStStats].push_back({i, b});
+        if (!iir) {
+            const int tiles = ((it.W + 63) / 64) * ((it.H + 31) / 32);
+            for (int t = 0; t < tiles; ++t) per[kStFir].push_back({i, t});
+            fir_smem = std::max(fir_smem, sizeof(float) * (size_t)fir_smem_floats(R));
+            P->off_carry[i] = P->off_S[i] = 0;
+        } else {
+            const size_t C = (size_t)it.N + 2;
+            const int nb = (it.H + kBatchBand - 1) / kBatchBand;
+            P->off_carry[i] = off;
+            off = al(off + sizeof(float) * nb * C * 8 * (size_t)it.W);
+            P->off_S[i] = off;
+            off = al(off + sizeof(float) * C * (size_t)it.H * it.W);
+            const int ncg4 = ((it.W + 63) / 64 + 3) / 4;
+            for (int t = 0; t < nb * ncg4; ++t) per[kStAgg].push_back({i, t});
+            const int ng = (it.W + kBlock - 1) / kBlock;
+            for (int t = 0; t < (int)C * ng; ++t) per[kStResolve].push_back({i, t});
+            for (int t = 0; t < nb * ncg4; ++t) per[kStBand].push_back({i, t});
+            for (int y = 0; y < it.H; ++y) per[kStRow].push_back({i, y});
+        }
+    }
+    for (int s = 0; s < kNumStages; ++s) {
+        P->first[s] = (int)P->work.size();
+        P->work.insert(P->work.end(), per[s].begin(), per[s].end());
+    }
+    P->first[kNumStages] = (int)P->work.size();
+    P->off_items = off;
+    off = al(off + sizeof(BatchItem) * P->work.size());
+    P->total = off;
+    P->fir_smem = fir_smem;
+    P->imgs.resize(count);
+    *plan_out = P;
+    return BF_OK;
+}
+
+size_t bf_gp_plan_workspace_bytes(const void *plan) {
+    return plan ? ((const Plan *)plan)->total : 0;
+}
+
+int bf_gp_plan_upload(void *plan, void *ws, size_t ws_bytes, void *stream) {
+    Plan *P = (Plan *)plan;
+    if (!P || !ws) return set_error(BF_EINVAL, "null plan or workspace");
+    if (ws_bytes < P->total) return set_error(BF_ENOMEM, "workspace too small for the batch plan");
+    char *w = (char *)ws;
+    const int count = (int)P->items.size();
+    for (int i = 0; i < count; ++i) {
+        const bf_gp_item &it = P->items[i];
+        BatchImage &B = P->imgs[i];
+        memset(&B, 0, sizeof B);
+        const int nparts = std::min(it.H, kBatchStatsParts);
+        B.p = gp_params_for(it.img, it.out, it.H, it.W, it.pitch, it.sigma_r, it.N, P->flags,
+                            (const Partial *)(w + P->off_parts[i]), nparts, (int *)(w + P->off_status[i]));
+        B.iir = P->iir[i];
+        B.R = P->R[i];
+        B.L = P->L[i];
+        B.nb = (it.H + kBatchBand - 1) / kBatchBand;
+        if (B.iir) {
+            B.c = iir_coef_for(it.sigma_s, kBatchBand, B.L);
+            B.carry = (float *)(w + P->off_carry[i]);
+            B.S = (float *)(w + P->off_S[i]);
+        } else {
+            B.taps = fir_taps_for(it.sigma_s, B.R);
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(w + P->off_imgs, P->imgs.data(), sizeof(BatchImage) * count,
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(w + P->off_items, P->work.data(), sizeof(BatchItem) * P->work.size(),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return set_error(BF_EHIP, hipGetErrorString(e));
+    P->uploaded = true;
+    P->ws = ws;
+    return BF_OK;
+}
+
+int bf_gp_forward_batched(void *plan, void *ws, size_t ws_bytes, void *stream) {
+    Plan *P = (Plan *)plan;
+    if (!P || !ws) return set_error(BF_EINVAL, "null plan or workspace");
+    if (!P->uploaded || P->ws != ws) return set_error(BF_EINVAL, "plan not uploaded to this workspace");
+    if (ws_bytes < P->total) return set_error(BF_ENOMEM, "workspace too small for the batch plan");
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    const BatchImage *imgs = (const BatchImage *)(w + P->off_imgs);
+    const BatchItem *work = (const BatchItem *)(w + P->off_items);
+    auto n = [P](int st) { return P->first[st + 1] - P->first[st]; };
+    auto at = [P, work](int st) { return work + P->first[st]; };
+    if (n(kStStats)) BF_LAUNCH("k_bstats", k_bstats, dim3(n(kStStats)), dim3(kBlock), 0, s, imgs, at(kStStats));
+    if (n(kStFir)) BF_LAUNCH("k_bfir", k_bfir, dim3(n(kStFir)), dim3(kBlock), P->fir_smem, s, imgs, at(kStFir));
+    if (n(kStAgg)) {
+        BF_LAUNCH("k_bband_agg", (k_bband<true, false>), dim3(n(kStAgg)), dim3(kBlock), 0, s, imgs, at(kStAgg));
+        BF_LAUNCH("k_bband_agg_big", (k_bband<true, true>), dim3(n(kStAgg)), dim3(kBlock), 0, s, imgs, at(kStAgg));
+        BF_LAUNCH("k_bresolve", k_bresolve, dim3(n(kStResolve)), dim3(kBlock), 0, s, imgs, at(kStResolve));
+        BF_LAUNCH("k_bband", (k_bband<false, false>), dim3(n(kStBand)), dim3(kBlock), 0, s, imgs, at(kStBand));
+        BF_LAUNCH("k_bband_big", (k_bband<false, true>), dim3(n(kStBand)), dim3(kBlock), 0, s, imgs, at(kStBand));
+        BF_LAUNCH("k_brow", k_brow, dim3(n(kStRow)), dim3(kBlock), 0, s, imgs, at(kStRow));
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(BF_EHIP, hipGetErrorString(e));
+    return BF_OK;
+}
+
+void bf_gp_plan_free(void *plan) { delete (Plan *)plan; }
+
+}  // extern "C"
