@@ -85,7 +85,7 @@ double range_limit(int N) {
 // IIR band height and row chunking for an image.
 constexpr int kBand = 64;
 void row_shape(int W, int *L, int *T) {
-    int l = W <= 1024 ? 4 : (W <= 4096 ? 8 : 16);
+    int l = W <= 1024 ? 4 : (W <= 2048 ? 8 : 16);
     int t = (W + l - 1) / l;
     t = ((t + 63) / 64) * 64;
     *L = l;
@@ -94,7 +94,7 @@ void row_shape(int W, int *L, int *T) {
 constexpr int kIirMaxW = 8192;
 
 struct Layout {
-    size_t parts, status, carry, stack, total;
+    size_t parts, status, stats, carry, stack, total;
 };
 
 Layout gp_layout(int H, int W, int N, unsigned spatial) {
@@ -104,6 +104,8 @@ Layout gp_layout(int H, int W, int N, unsigned spatial) {
     off = align256(off + sizeof(Partial) * kMaxParts);
     L.status = off;
     off = align256(off + 16);
+    L.stats = off;
+    off = align256(off + sizeof(Stats));
     L.carry = L.stack = off;
     if (spatial == BF_SPATIAL_IIR) {
         const size_t C = (size_t)N + 2;
@@ -159,6 +161,7 @@ GPParams make_params(const float *img, float *out, int H, int W, int pitch, doub
     p.parts = (const Partial *)(ws + L.parts);
     p.nparts = H < kMaxParts ? H : kMaxParts;
     p.status = (int *)(ws + L.status);
+    p.stats = (Stats *)(ws + L.stats);
     p.saved = saved;
     for (int n = 0; n < kMaxC + 3; ++n) {
         p.sq[n] = sqrt((double)n);
@@ -221,17 +224,12 @@ IirCoef make_iir(double sigma_s, int B, int L) {
         }
         mat2_pow(Phi, 64L * L, M);
         for (int q = 0; q < 4; ++q) c.phiW[s][q] = (float)M[q];
-        for (int i = 0; i < L && i < kIirMaxL; ++i) {
-            mat2_pow(Phi, i + 1, M);
-            c.fix1[s][i] = (float)M[0];
-            c.fix2[s][i] = (float)M[1];
-        }
     }
     return c;
 }
 
 struct BwdLayout {
-    size_t parts, status, bparts, corr, total;
+    size_t parts, status, stats, bparts, corr, total;
 };
 
 BwdLayout bwd_layout(int H, int W) {
@@ -241,6 +239,8 @@ BwdLayout bwd_layout(int H, int W) {
     off = align256(off + sizeof(Partial) * kMaxParts);
     L.status = off;
     off = align256(off + 16);
+    L.stats = off;
+    off = align256(off + sizeof(Stats));
     L.bparts = off;
     off = align256(off + sizeof(BwdPartial) * (size_t)bwd_tiles(H, W));
     L.corr = off;
@@ -254,14 +254,16 @@ BwdLayout bwd_layout(int H, int W) {
 // Helpers shared with the batched path (batched.hip).
 namespace bfgp {
 GPParams gp_params_for(const float *img, float *out, int H, int W, int pitch, double sigma_r, int N, unsigned flags,
-                       const Partial *parts, int nparts, int *status) {
+                       const Partial *parts, int nparts, int *status, Stats *stats) {
     Layout L;
     L.parts = 0;
     L.status = 0;
+    L.stats = 0;
     GPParams p = make_params(img, out, H, W, pitch, sigma_r, N, flags, (char *)0, L, nullptr);
     p.parts = parts;
     p.nparts = nparts;
     p.status = status;
+    p.stats = stats;
     return p;
 }
 IirCoef iir_coef_for(double sigma_s, int B, int L) { return make_iir(sigma_s, B, L); }
@@ -308,7 +310,7 @@ int bf_gp_forward(const float *img, float *out, int H, int W, int pitch, double 
     hipStream_t s = (hipStream_t)stream;
     char *w = (char *)ws;
     GPParams p = make_params(img, out, H, W, pitch, sigma_r, N, flags, w, L, saved);
-    hipError_t e = launch_stats(img, H, W, pitch, (Partial *)(w + L.parts), p.nparts, s);
+    hipError_t e = launch_stats(p, s);
     if (e != hipSuccess) return hip_fail(e, "statistics launch");
     if (spatial == BF_SPATIAL_FIR) {
         const int R = fir_radius(sigma_s);
@@ -366,8 +368,9 @@ int bf_gp_backward(const float *img, const float *grad_out, const void *saved, i
     Layout fl;
     fl.parts = L.parts;
     fl.status = L.status;
+    fl.stats = L.stats;
     GPParams p = make_params(img, nullptr, H, W, pitch, sigma_r, N, flags, w, fl, const_cast<void *>(saved));
-    hipError_t e = launch_stats(img, H, W, pitch, (Partial *)(w + L.parts), p.nparts, s);
+    hipError_t e = launch_stats(p, s);
     if (e != hipSuccess) return hip_fail(e, "statistics launch");
     const int R = fir_radius(sigma_s);
     FirTaps2 t;

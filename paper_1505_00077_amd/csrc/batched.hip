@@ -54,6 +54,9 @@ __global__ __launch_bounds__(kBlock) void k_bstats(const BatchImage *imgs, const
     stats_rows(p.img, p.H, p.W, p.pitch, w.idx, p.nparts, const_cast<Partial *>(p.parts));
 }
 
+// one workgroup per image
+__global__ __launch_bounds__(kBlock) void k_bstats_final(const BatchImage *imgs) { stats_final(imgs[blockIdx.x].p); }
+
 template <int R>
 __device__ __forceinline__ void fir_item(const BatchImage &B, const Stats &st, int idx, float *smem) {
     using S = FirShape<R>;
@@ -66,7 +69,6 @@ __global__ __launch_bounds__(kBlock) void k_bfir(const BatchImage *imgs, const B
     const BatchItem w = items[blockIdx.x];
     const BatchImage &B = imgs[w.img];
     const Stats st = load_stats(B.p);
-    if (threadIdx.x == 0 && w.idx == 0) *B.p.status = st.ok ? 0 : -3;
     switch (B.R) {
 #define BF_CASE(r) case r: fir_item<r>(B, st, w.idx, smem); break;
         BF_CASE(1) BF_CASE(2) BF_CASE(3) BF_CASE(4) BF_CASE(5) BF_CASE(6)
@@ -83,7 +85,6 @@ __global__ __launch_bounds__(kBlock, 2) void k_bband(const BatchImage *imgs, con
     const BatchItem w = items[blockIdx.x];
     const BatchImage &B = imgs[w.img];
     const Stats st = load_stats(B.p);
-    if (AGG && !BIG && threadIdx.x == 0 && w.idx == 0) *B.p.status = st.ok ? 0 : -3;
     if (!st.ok || ((st.xmax > 12.0) != BIG)) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int ncg = (B.p.W + 63) / 64, ncg4 = (ncg + 3) / 4;
@@ -124,7 +125,7 @@ struct Plan {
     int first[kNumStages + 1];             // stage s items: work[first[s] .. first[s+1])
     std::vector<int> iir, R, L;
     size_t off_imgs, off_items, total;
-    std::vector<size_t> off_parts, off_status, off_carry, off_S;
+    std::vector<size_t> off_parts, off_status, off_stats, off_carry, off_S;
     size_t fir_smem;
     unsigned flags;
     bool uploaded;
@@ -149,7 +150,7 @@ int fir_radius_b(double sigma_s) {
 // defined in api.hip
 namespace bfgp {
 GPParams gp_params_for(const float *img, float *out, int H, int W, int pitch, double sigma_r, int N, unsigned flags,
-                       const Partial *parts, int nparts, int *status);
+                       const Partial *parts, int nparts, int *status, Stats *stats);
 IirCoef iir_coef_for(double sigma_s, int B, int L);
 FirTaps fir_taps_for(double sigma_s, int R);
 int set_error(int code, const char *msg);
@@ -186,6 +187,7 @@ int bf_gp_plan_batched(const bf_gp_item *items, int count, unsigned flags, void 
     std::vector<std::vector<BatchItem>> per(kNumStages);
     P->off_parts.resize(count);
     P->off_status.resize(count);
+    P->off_stats.resize(count);
     P->off_carry.resize(count);
     P->off_S.resize(count);
     P->iir.resize(count);
@@ -205,6 +207,8 @@ int bf_gp_plan_batched(const bf_gp_item *items, int count, unsigned flags, void 
         off = al(off + sizeof(Partial) * nparts);
         P->off_status[i] = off;
         off = al(off + 16);
+        P->off_stats[i] = off;
+        off = al(off + sizeof(Stats));
         for (int b = 0; b < nparts; ++b) per[kStStats].push_back({i, b});
         if (!iir) {
             const int tiles = ((it.W + 63) / 64) * ((it.H + 31) / 32);
@@ -256,7 +260,8 @@ int bf_gp_plan_upload(void *plan, void *ws, size_t ws_bytes, void *stream) {
         memset(&B, 0, sizeof B);
         const int nparts = std::min(it.H, kBatchStatsParts);
         B.p = gp_params_for(it.img, it.out, it.H, it.W, it.pitch, it.sigma_r, it.N, P->flags,
-                            (const Partial *)(w + P->off_parts[i]), nparts, (int *)(w + P->off_status[i]));
+                            (const Partial *)(w + P->off_parts[i]), nparts, (int *)(w + P->off_status[i]),
+                            (Stats *)(w + P->off_stats[i]));
         B.iir = P->iir[i];
         B.R = P->R[i];
         B.L = P->L[i];
@@ -294,6 +299,7 @@ int bf_gp_forward_batched(void *plan, void *ws, size_t ws_bytes, void *stream) {
     auto n = [P](int st) { return P->first[st + 1] - P->first[st]; };
     auto at = [P, work](int st) { return work + P->first[st]; };
     if (n(kStStats)) BF_LAUNCH("k_bstats", k_bstats, dim3(n(kStStats)), dim3(kBlock), 0, s, imgs, at(kStStats));
+    BF_LAUNCH("k_bstats_final", k_bstats_final, dim3((unsigned)P->items.size()), dim3(kBlock), 0, s, imgs);
     if (n(kStFir)) BF_LAUNCH("k_bfir", k_bfir, dim3(n(kStFir)), dim3(kBlock), P->fir_smem, s, imgs, at(kStFir));
     if (n(kStAgg)) {
         BF_LAUNCH("k_bband_agg", (k_bband<true, false>), dim3(n(kStAgg)), dim3(kBlock), 0, s, imgs, at(kStAgg));

@@ -9,7 +9,7 @@ constexpr int kBlock = 256;          // threads per workgroup for every GP kerne
 constexpr int kMaxN = 64;            // largest Gauss-polynomial degree
 constexpr int kMaxC = kMaxN + 2;     // channels u_0..u_{N+1}
 constexpr int kFirMaxR = 24;         // largest FIR radius compiled
-constexpr int kMaxParts = 512;       // partial sums of the statistics pass
+constexpr int kMaxParts = 1024;      // partial sums of the statistics pass
 constexpr int kDirectMaxW = 64;      // largest direct-filter window
 
 // One workgroup's share of the image statistics.
@@ -20,11 +20,13 @@ struct Partial {
 };
 
 // Per-image statistics: the centre t_c of Algorithm 1's first step, plus the
-// extremes used for the FP32 range check.
+// extremes used for the FP32 range check.  Written once per call by the
+// statistics pass, read by every later kernel.
 struct Stats {
     double tc;
     double xmax;  // max |f - t_c| / sigma_r
     int ok;       // 1 when xmax is within the representable bound
+    int pad;
 };
 
 // Coefficients for one image that every GP kernel needs.
@@ -39,6 +41,7 @@ struct GPParams {
     const Partial *parts;
     int nparts;
     int *status;         // device status word (BF_OK / BF_ERANGE)
+    Stats *stats;        // written by stats_final
     void *saved;         // nullable, 16 B per pixel (see bf_gp_forward)
     double sq[kMaxC + 3];   // sqrt(n)
     double isq[kMaxC + 3];  // 1 / sqrt(n)
@@ -107,41 +110,56 @@ __device__ __forceinline__ void stats_rows(const float *__restrict__ img, int H,
     __syncthreads();
 }
 
-// Reduces the partials (same fixed order in every workgroup) and derives the
-// centre.  Every thread of the workgroup receives the result.
-__device__ __forceinline__ Stats load_stats(const GPParams &p) {
-    __shared__ Stats s_st;
-    if (threadIdx.x < 64) {
-        double s = 0.0;
-        float lo = __builtin_inff(), hi = -__builtin_inff();
-        for (int i = threadIdx.x; i < p.nparts; i += 64) {
-            s += p.parts[i].sum;
-            lo = fminf(lo, p.parts[i].lo);
-            hi = fmaxf(hi, p.parts[i].hi);
-        }
-        s = wave_sum(s);
-        lo = wave_min(lo);
-        hi = wave_max(hi);
-        if (threadIdx.x == 0) {
-            double tc;
-            if (p.center == 1)
-                tc = 0.5 * ((double)lo + (double)hi);
-            else if (p.center == 2)
-                tc = 0.0;
-            else
-                tc = s / ((double)p.H * (double)p.W);
-            const double a = fabs((double)lo - tc) * p.inv_sigma_r;
-            const double b = fabs((double)hi - tc) * p.inv_sigma_r;
-            Stats st;
-            st.tc = tc;
-            st.xmax = a > b ? a : b;
-            st.ok = (st.xmax <= p.xlim) ? 1 : 0;
-            s_st = st;
-        }
+// Reduces the partials in a fixed order (one workgroup), derives the centre and
+// the range check, and stores them with the status word.
+__device__ __forceinline__ void stats_final(const GPParams &p) {
+    __shared__ double s_sum[kBlock / 64];
+    __shared__ float s_lo[kBlock / 64], s_hi[kBlock / 64];
+    double s = 0.0;
+    float lo = __builtin_inff(), hi = -__builtin_inff();
+    for (int i = threadIdx.x; i < p.nparts; i += kBlock) {
+        s += p.parts[i].sum;
+        lo = fminf(lo, p.parts[i].lo);
+        hi = fmaxf(hi, p.parts[i].hi);
+    }
+    s = wave_sum(s);
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    if ((threadIdx.x & 63) == 0) {
+        s_sum[threadIdx.x >> 6] = s;
+        s_lo[threadIdx.x >> 6] = lo;
+        s_hi[threadIdx.x >> 6] = hi;
     }
     __syncthreads();
-    return s_st;
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        float l = __builtin_inff(), h = -__builtin_inff();
+        for (int i = 0; i < kBlock / 64; ++i) {
+            t += s_sum[i];
+            l = fminf(l, s_lo[i]);
+            h = fmaxf(h, s_hi[i]);
+        }
+        double tc;
+        if (p.center == 1)
+            tc = 0.5 * ((double)l + (double)h);
+        else if (p.center == 2)
+            tc = 0.0;
+        else
+            tc = t / ((double)p.H * (double)p.W);
+        const double a = fabs((double)l - tc) * p.inv_sigma_r;
+        const double b = fabs((double)h - tc) * p.inv_sigma_r;
+        Stats st;
+        st.tc = tc;
+        st.xmax = a > b ? a : b;
+        st.ok = (st.xmax <= p.xlim) ? 1 : 0;
+        st.pad = 0;
+        *p.stats = st;
+        *p.status = st.ok ? 0 : -3;
+    }
 }
+
+// The statistics of the image (written earlier in the same stream).
+__device__ __forceinline__ Stats load_stats(const GPParams &p) { return *p.stats; }
 
 // x = (f - t_c) / sigma_r, computed in double and rounded once to float.
 __device__ __forceinline__ float centred(float f, const Stats &st, double inv_sr) {

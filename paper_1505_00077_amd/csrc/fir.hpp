@@ -166,7 +166,7 @@ __device__ __forceinline__ void fir_tile(const GPParams &p, const FirTaps &taps,
             const int gx = tx0 + ox0 + i;
             if (gx < p.W) {
                 const double rho = Mp[i] / Dp[i];
-                const float o = st.ok ? (float)(st.tc + p.sigma_r * rho) : __builtin_nanf("");
+                const float o = st.ok ? (float)fma(p.sigma_r, rho, st.tc) : __builtin_nanf("");
                 p.out[(size_t)gy * p.pitch + gx] = o;
                 if (SAVE) {
                     const size_t idx = (size_t)gy * p.W + gx;

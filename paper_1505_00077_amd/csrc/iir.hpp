@@ -32,7 +32,6 @@ struct IirCoef {
     float phiB[2][4];     // Phi^B, Phi = [[-d1, -d2], [1, 0]], row-major
     float phiL[2][6][4];  // Phi^(L 2^j), j = 0..5
     float phiW[2][4];     // Phi^(64 L)
-    float fix1[2][kIirMaxL], fix2[2][kIirMaxL];  // (Phi^(i+1))[0][0], [0][1]
 };
 
 // Centred intensity of column `col`, row `row`, or 0 outside the image.
@@ -72,7 +71,7 @@ __device__ __forceinline__ void vband(const GPParams &p, const IirCoef &c, const
         const float x = xval(p, st, row, col);
         xv[i] = x;
         double lu = -0.5 * (double)x * (double)x;
-        if (BIG) lu += (double)big_shift(x) * 0.69314718055994531;
+        if (BIG) lu = fma((double)big_shift(x), 0.69314718055994531, lu);
         u[i] = inimg(p, row, col) ? (float)exp(lu) : 0.f;
     }
     const size_t cstride = (size_t)p.W;
@@ -85,27 +84,38 @@ __device__ __forceinline__ void vband(const GPParams &p, const IirCoef &c, const
         // channel value of sample i (undoing the range shift of BIG images)
         auto V = [&](int i) -> float { return BIG ? ldexpf(u[i], -big_shift(xv[i])) : u[i]; };
         float *cp = carry + ((size_t)(band * p.C + n) * 8) * cstride + col;
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const float n0 = c.n0[s], n1 = c.n1[s], d1 = c.d1[s], d2 = c.d2[s];
-            float y1 = 0.f, y2 = 0.f;
+        // causal: both sections advance together; the sum is staged in LDS
+        {
+            float y1[2] = {0.f, 0.f}, y2[2] = {0.f, 0.f};
             if (!AGG && col < p.W) {
-                y1 = cp[(2 * s) * cstride];
-                y2 = cp[(2 * s + 1) * cstride];
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    y1[s] = cp[(2 * s) * cstride];
+                    y2[s] = cp[(2 * s + 1) * cstride];
+                }
             }
             float xp = V(0);
 #pragma unroll
             for (int i = 0; i < B; ++i) {
                 const float vi = V(i + 1);
-                const float y = fmaf(n0, vi, fmaf(n1, xp, fmaf(-d1, y1, -d2 * y2)));
-                y2 = y1;
-                y1 = y;
+                float tot = 0.f;
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    const float b = fmaf(c.n0[s], vi, fmaf(c.n1[s], xp, -c.d2[s] * y2[s]));
+                    const float y = fmaf(-c.d1[s], y1[s], b);
+                    y2[s] = y1[s];
+                    y1[s] = y;
+                    tot += y;
+                }
                 xp = vi;
-                if (!AGG) sacc[i * 64 + lane] = (s == 0) ? y : sacc[i * 64 + lane] + y;
+                if (!AGG) sacc[i * 64 + lane] = tot;
             }
             if (AGG && col < p.W) {
-                cp[(2 * s) * cstride] = y1;
-                cp[(2 * s + 1) * cstride] = y2;
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    cp[(2 * s) * cstride] = y1[s];
+                    cp[(2 * s + 1) * cstride] = y2[s];
+                }
             }
         }
         // anticausal: both sections advance together, and the finished
@@ -126,7 +136,8 @@ __device__ __forceinline__ void vband(const GPParams &p, const IirCoef &c, const
                 float tot = 0.f;
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
-                    const float z = fmaf(c.m1[s], xn1, fmaf(c.m2[s], xn2, fmaf(-c.d1[s], z1[s], -c.d2[s] * z2[s])));
+                    const float b = fmaf(c.m1[s], xn1, fmaf(c.m2[s], xn2, -c.d2[s] * z2[s]));
+                    const float z = fmaf(-c.d1[s], z1[s], b);
                     z2[s] = z1[s];
                     z1[s] = z;
                     tot += z;
@@ -163,8 +174,8 @@ __device__ __forceinline__ void vresolve(const GPParams &p, const IirCoef &c, in
         for (int s = 0; s < 2; ++s) {
             const float *P = c.phiB[s];
             const float a0 = sc[2 * s], a1 = sc[2 * s + 1];
-            sc[2 * s] = l[2 * s] + P[0] * a0 + P[1] * a1;
-            sc[2 * s + 1] = l[2 * s + 1] + P[2] * a0 + P[3] * a1;
+            sc[2 * s] = fmaf(P[0], a0, fmaf(P[1], a1, l[2 * s]));
+            sc[2 * s + 1] = fmaf(P[2], a0, fmaf(P[3], a1, l[2 * s + 1]));
         }
     }
     float sa[4] = {0.f, 0.f, 0.f, 0.f};
@@ -179,16 +190,18 @@ __device__ __forceinline__ void vresolve(const GPParams &p, const IirCoef &c, in
         for (int s = 0; s < 2; ++s) {
             const float *P = c.phiB[s];
             const float a0 = sa[2 * s], a1 = sa[2 * s + 1];
-            sa[2 * s] = l[2 * s] + P[0] * a0 + P[1] * a1;
-            sa[2 * s + 1] = l[2 * s + 1] + P[2] * a0 + P[3] * a1;
+            sa[2 * s] = fmaf(P[0], a0, fmaf(P[1], a1, l[2 * s]));
+            sa[2 * s + 1] = fmaf(P[2], a0, fmaf(P[3], a1, l[2 * s + 1]));
         }
     }
 }
 
 // 2x2 helpers (row-major)
+// (explicit fmaf throughout the shared kernels: the result must not depend on
+// how the compiler contracts multiply-adds in different calling kernels)
 __device__ __forceinline__ void mat_mul(const float *A, const float *B, float *C) {
-    const float c0 = A[0] * B[0] + A[1] * B[2], c1 = A[0] * B[1] + A[1] * B[3];
-    const float c2 = A[2] * B[0] + A[3] * B[2], c3 = A[2] * B[1] + A[3] * B[3];
+    const float c0 = fmaf(A[0], B[0], A[1] * B[2]), c1 = fmaf(A[0], B[1], A[1] * B[3]);
+    const float c2 = fmaf(A[2], B[0], A[3] * B[2]), c3 = fmaf(A[2], B[1], A[3] * B[3]);
     C[0] = c0; C[1] = c1; C[2] = c2; C[3] = c3;
 }
 __device__ __forceinline__ void mat_pow_chunks(const IirCoef &c, int s, int m, float *G) {
@@ -204,48 +217,85 @@ __device__ __forceinline__ void mat_pow_chunks(const IirCoef &c, int s, int m, f
 
 // LDS floats used by hrow for a workgroup of nw waves.
 __host__ __device__ constexpr int hrow_smem_floats(int nw) {
-    return 2 * 2 * nw * 4 + 4 * kIirMaxL + 16 * 64;
+    return 2 * 2 * nw * 4 + 16 * 64;
+}
+
+// Lane shifts through DPP (no LDS round trip).  Lanes whose source is outside
+// the row (or wave) read 0.
+constexpr int kDppRowShl = 0x100, kDppRowShr = 0x110, kDppWaveShl1 = 0x130, kDppWaveShr1 = 0x138;
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float lane_f(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+// s[0..1] += P * (v0, v1), P 2x2 row-major
+__device__ __forceinline__ void acc2(float *s, const float *P, float v0, float v1) {
+    s[0] = fmaf(P[0], v0, fmaf(P[1], v1, s[0]));
+    s[1] = fmaf(P[2], v0, fmaf(P[3], v1, s[1]));
+}
+// r = v + P * w (2-vectors)
+__device__ __forceinline__ void affine2(float *r, const float *v, const float *P, const float *w) {
+    const float a = w[0], b = w[1];
+    r[0] = fmaf(P[0], a, fmaf(P[1], b, v[0]));
+    r[1] = fmaf(P[2], a, fmaf(P[3], b, v[1]));
 }
 
 // One image row: row pass of eq. (8) on every channel of the column-filtered
 // stack, fused with the recombination of eqs. (9)-(11).  Workgroup of T
 // threads (T a multiple of 64, T * L >= W); thread t owns samples
-// [t L, t L + L).  sm: hrow_smem_floats(T / 64) floats.
+// [t L, t L + L).  Per channel:
+//   1. each chunk runs causally and anticausally from rest (true halo inputs),
+//      giving local outputs and its end states;
+//   2. the chunk states are combined in order: a DPP scan inside each row of
+//      16 lanes, the row totals across the wave by readlane, the wave totals
+//      across the workgroup through LDS;
+//   3. each chunk adds the homogeneous response of its true incoming states.
+// Channels are visited from N+1 down to 0 so that the recombination is a
+// Horner evaluation in tau with two FP64 accumulators per pixel:
+//   bD <- Ubar_n + bD tau / sqrt(n+1)  (n <= N),
+//   bM <- sqrt(n) Ubar_n + bM tau / sqrt(n)  (n >= 1),
+// ending with bD = D exp(tau^2/2) and bM = M exp(tau^2/2).
+// sm: hrow_smem_floats(T / 64) floats.
 template <int L>
 __device__ __forceinline__ void hrow(const GPParams &p, const IirCoef &c, const Stats &st, int y,
                                      const float *__restrict__ S, float *sm) {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, nw = blockDim.x >> 6;
+    const int r16 = lane >> 4, j16 = lane & 15;
     const int x0 = t * L;
-    float *tot = sm;                          // wave totals, double-buffered
-    float *fix = sm + 2 * 2 * nw * 4;         // fix[(2 s + k) * L + i]
-    float *G = fix + 4 * kIirMaxL;            // G[k * 64 + lane], k = 0..15
-    for (int i = t; i < 4 * L; i += blockDim.x) {
-        const int s = i / (2 * L), k = (i / L) & 1, j = i % L;
-        fix[i] = k == 0 ? c.fix1[s][j] : c.fix2[s][j];
-    }
-    if (wave == 0) {
-        // carry-in multipliers Phi^((lane+1) L) (causal) and Phi^((64-lane) L)
+    float *tot = sm;                 // wave totals, double-buffered
+    float *G64 = sm + 2 * 2 * nw * 4;  // G64[k * 64 + lane], k = 0..15
+    if (nw > 1) {
+        if (wave == 0) {
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            float g[4];
-            mat_pow_chunks(c, s, lane + 1, g);
-            for (int q = 0; q < 4; ++q) G[(4 * s + q) * 64 + lane] = g[q];
-            mat_pow_chunks(c, s, 64 - lane, g);
-            for (int q = 0; q < 4; ++q) G[(8 + 4 * s + q) * 64 + lane] = g[q];
+            for (int s = 0; s < 2; ++s) {
+                float g[4];
+                mat_pow_chunks(c, s, lane + 1, g);
+                for (int q = 0; q < 4; ++q) G64[(4 * s + q) * 64 + lane] = g[q];
+                mat_pow_chunks(c, s, 64 - lane, g);
+                for (int q = 0; q < 4; ++q) G64[(8 + 4 * s + q) * 64 + lane] = g[q];
+            }
         }
+        __syncthreads();
     }
-    __syncthreads();
+    // per-lane multipliers across a row of 16 chunks
+    float G16c[2][4], G16a[2][4];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        mat_pow_chunks(c, s, j16 + 1, G16c[s]);
+        mat_pow_chunks(c, s, 16 - j16, G16a[s]);
+    }
 
     float tau[L];
-    double D[L], M[L], P[L];
+    double bD[L], bM[L];
 #pragma unroll
     for (int i = 0; i < L; ++i) {
         tau[i] = xval(p, st, y, x0 + i);
-        D[i] = 0.0;
-        M[i] = 0.0;
-        P[i] = 0.0;
+        bD[i] = 0.0;
+        bM[i] = 0.0;
     }
-    for (int n = 0; n < p.C; ++n) {
+    for (int n = p.C - 1; n >= 0; --n) {
         const float *row = S + ((size_t)n * p.H + y) * p.W;
         float z[L + 3];
         z[0] = (x0 - 1 >= 0 && x0 - 1 < p.W) ? row[x0 - 1] : 0.f;
@@ -262,108 +312,144 @@ __device__ __forceinline__ void hrow(const GPParams &p, const IirCoef &c, const 
         z[L + 1] = (x0 + L < p.W) ? row[x0 + L] : 0.f;
         z[L + 2] = (x0 + L + 1 < p.W) ? row[x0 + L + 1] : 0.f;
 
-        // chunk from rest: causal and anticausal, both sections together
+        // 1. chunk from rest
         float o[L];
         float sc[4], sa[4];
         {
             float y1[2] = {0.f, 0.f}, y2[2] = {0.f, 0.f};
-            float xp = z[0];
 #pragma unroll
             for (int i = 0; i < L; ++i) {
                 float acc = 0.f;
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
-                    const float v = fmaf(c.n0[s], z[i + 1], fmaf(c.n1[s], xp, fmaf(-c.d1[s], y1[s], -c.d2[s] * y2[s])));
+                    const float b = fmaf(c.n0[s], z[i + 1], fmaf(c.n1[s], z[i], -c.d2[s] * y2[s]));
+                    const float v = fmaf(-c.d1[s], y1[s], b);
                     y2[s] = y1[s];
                     y1[s] = v;
                     acc += v;
                 }
-                xp = z[i + 1];
                 o[i] = acc;
             }
             sc[0] = y1[0]; sc[1] = y2[0]; sc[2] = y1[1]; sc[3] = y2[1];
         }
         {
             float z1[2] = {0.f, 0.f}, z2[2] = {0.f, 0.f};
-            float xn1 = z[L + 1], xn2 = z[L + 2];
 #pragma unroll
             for (int i = L - 1; i >= 0; --i) {
                 float acc = 0.f;
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
-                    const float v = fmaf(c.m1[s], xn1, fmaf(c.m2[s], xn2, fmaf(-c.d1[s], z1[s], -c.d2[s] * z2[s])));
+                    const float b = fmaf(c.m1[s], z[i + 2], fmaf(c.m2[s], z[i + 3], -c.d2[s] * z2[s]));
+                    const float v = fmaf(-c.d1[s], z1[s], b);
                     z2[s] = z1[s];
                     z1[s] = v;
                     acc += v;
                 }
-                xn2 = xn1;
-                xn1 = z[i + 1];
                 o[i] += acc;
             }
             sa[0] = z1[0]; sa[1] = z2[0]; sa[2] = z1[1]; sa[3] = z2[1];
         }
-        // wave-level scans: causal prefix, anticausal suffix
-#pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            const int d = 1 << j;
-            float pc[4], pa[4];
+        // 2a. scans inside each row of 16 lanes (distances 1, 2, 4, 8 chunks)
+#define BF_ROWSTEP(J, D)                                                                   \
+        {                                                                                  \
+            float pc[4], pa[4];                                                            \
+            _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                \
+                pc[q] = dpp_f<kDppRowShr + D>(sc[q]);                                      \
+                pa[q] = dpp_f<kDppRowShl + D>(sa[q]);                                      \
+            }                                                                              \
+            _Pragma("unroll") for (int s = 0; s < 2; ++s) {                                \
+                acc2(&sc[2 * s], c.phiL[s][J], pc[2 * s], pc[2 * s + 1]);                  \
+                acc2(&sa[2 * s], c.phiL[s][J], pa[2 * s], pa[2 * s + 1]);                  \
+            }                                                                              \
+        }
+        BF_ROWSTEP(0, 1)
+        BF_ROWSTEP(1, 2)
+        BF_ROWSTEP(2, 4)
+        BF_ROWSTEP(3, 8)
+#undef BF_ROWSTEP
+        // 2b. across the four rows of the wave
+        {
+            float C1[4], C2[4], C3[4], A0[4], A1[4], A2[4];
+            float t0[4], t1[4], t2[4], h1[4], h2[4], h3[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                pc[q] = __shfl_up(sc[q], d, 64);
-                pa[q] = __shfl_down(sa[q], d, 64);
+                t0[q] = lane_f(sc[q], 15);
+                t1[q] = lane_f(sc[q], 31);
+                t2[q] = lane_f(sc[q], 47);
+                h1[q] = lane_f(sa[q], 16);
+                h2[q] = lane_f(sa[q], 32);
+                h3[q] = lane_f(sa[q], 48);
             }
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
-                const float *Pm = c.phiL[s][j];
-                if (lane >= d) {
-                    sc[2 * s] += Pm[0] * pc[2 * s] + Pm[1] * pc[2 * s + 1];
-                    sc[2 * s + 1] += Pm[2] * pc[2 * s] + Pm[3] * pc[2 * s + 1];
-                }
-                if (lane + d < 64) {
-                    sa[2 * s] += Pm[0] * pa[2 * s] + Pm[1] * pa[2 * s + 1];
-                    sa[2 * s + 1] += Pm[2] * pa[2 * s] + Pm[3] * pa[2 * s + 1];
-                }
+                const float *P16 = c.phiL[s][4];
+                C1[2 * s] = t0[2 * s];
+                C1[2 * s + 1] = t0[2 * s + 1];
+                affine2(&C2[2 * s], &t1[2 * s], P16, &C1[2 * s]);
+                affine2(&C3[2 * s], &t2[2 * s], P16, &C2[2 * s]);
+                A2[2 * s] = h3[2 * s];
+                A2[2 * s + 1] = h3[2 * s + 1];
+                affine2(&A1[2 * s], &h2[2 * s], P16, &A2[2 * s]);
+                affine2(&A0[2 * s], &h1[2 * s], P16, &A1[2 * s]);
+            }
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                float cr0 = 0.f, cr1 = 0.f, ar0 = 0.f, ar1 = 0.f;
+                if (r16 == 1) { cr0 = C1[2 * s]; cr1 = C1[2 * s + 1]; }
+                if (r16 == 2) { cr0 = C2[2 * s]; cr1 = C2[2 * s + 1]; }
+                if (r16 == 3) { cr0 = C3[2 * s]; cr1 = C3[2 * s + 1]; }
+                if (r16 == 0) { ar0 = A0[2 * s]; ar1 = A0[2 * s + 1]; }
+                if (r16 == 1) { ar0 = A1[2 * s]; ar1 = A1[2 * s + 1]; }
+                if (r16 == 2) { ar0 = A2[2 * s]; ar1 = A2[2 * s + 1]; }
+                acc2(&sc[2 * s], G16c[s], cr0, cr1);
+                acc2(&sa[2 * s], G16a[s], ar0, ar1);
             }
         }
-        // cross-wave carries
+        // 2c. across the waves of the workgroup
         float cc[4] = {0.f, 0.f, 0.f, 0.f}, ca[4] = {0.f, 0.f, 0.f, 0.f};
         if (nw > 1) {
             float *buf = tot + (n & 1) * (2 * nw * 4);
-            if (lane == 63)
-                for (int q = 0; q < 4; ++q) buf[wave * 4 + q] = sc[q];
-            if (lane == 0)
-                for (int q = 0; q < 4; ++q) buf[(nw + wave) * 4 + q] = sa[q];
+            float wc[4], wa[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                wc[q] = lane_f(sc[q], 63);
+                wa[q] = lane_f(sa[q], 0);
+            }
+            if (lane == 0) {
+                for (int q = 0; q < 4; ++q) {
+                    buf[wave * 4 + q] = wc[q];
+                    buf[(nw + wave) * 4 + q] = wa[q];
+                }
+            }
             __syncthreads();
             for (int w2 = 0; w2 < wave; ++w2) {
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
-                    const float *Pm = c.phiW[s];
-                    const float a0 = cc[2 * s], a1 = cc[2 * s + 1];
-                    cc[2 * s] = buf[w2 * 4 + 2 * s] + Pm[0] * a0 + Pm[1] * a1;
-                    cc[2 * s + 1] = buf[w2 * 4 + 2 * s + 1] + Pm[2] * a0 + Pm[3] * a1;
+                    float r[2];
+                    affine2(r, &buf[w2 * 4 + 2 * s], c.phiW[s], &cc[2 * s]);
+                    cc[2 * s] = r[0];
+                    cc[2 * s + 1] = r[1];
                 }
             }
             for (int w2 = nw - 1; w2 > wave; --w2) {
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
-                    const float *Pm = c.phiW[s];
-                    const float a0 = ca[2 * s], a1 = ca[2 * s + 1];
-                    ca[2 * s] = buf[(nw + w2) * 4 + 2 * s] + Pm[0] * a0 + Pm[1] * a1;
-                    ca[2 * s + 1] = buf[(nw + w2) * 4 + 2 * s + 1] + Pm[2] * a0 + Pm[3] * a1;
+                    float r[2];
+                    affine2(r, &buf[(nw + w2) * 4 + 2 * s], c.phiW[s], &ca[2 * s]);
+                    ca[2 * s] = r[0];
+                    ca[2 * s + 1] = r[1];
                 }
             }
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
-                const float g0 = G[(4 * s + 0) * 64 + lane], g1 = G[(4 * s + 1) * 64 + lane];
-                const float g2 = G[(4 * s + 2) * 64 + lane], g3 = G[(4 * s + 3) * 64 + lane];
-                const float a0 = cc[2 * s], a1 = cc[2 * s + 1];
-                sc[2 * s] += g0 * a0 + g1 * a1;
-                sc[2 * s + 1] += g2 * a0 + g3 * a1;
-                const float h0 = G[(8 + 4 * s + 0) * 64 + lane], h1 = G[(8 + 4 * s + 1) * 64 + lane];
-                const float h2 = G[(8 + 4 * s + 2) * 64 + lane], h3 = G[(8 + 4 * s + 3) * 64 + lane];
-                const float b0 = ca[2 * s], b1 = ca[2 * s + 1];
-                sa[2 * s] += h0 * b0 + h1 * b1;
-                sa[2 * s + 1] += h2 * b0 + h3 * b1;
+                float g[4], h[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    g[q] = G64[(4 * s + q) * 64 + lane];
+                    h[q] = G64[(8 + 4 * s + q) * 64 + lane];
+                }
+                acc2(&sc[2 * s], g, cc[2 * s], cc[2 * s + 1]);
+                acc2(&sa[2 * s], h, ca[2 * s], ca[2 * s + 1]);
             }
         }
         // exclusive states: incoming causal from the previous chunk, incoming
@@ -371,31 +457,41 @@ __device__ __forceinline__ void hrow(const GPParams &p, const IirCoef &c, const 
         float ic[4], ia[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const float up = __shfl_up(sc[q], 1, 64);
-            const float dn = __shfl_down(sa[q], 1, 64);
+            const float up = dpp_f<kDppWaveShr1>(sc[q]);
+            const float dn = dpp_f<kDppWaveShl1>(sa[q]);
             ic[q] = lane == 0 ? cc[q] : up;
             ia[q] = lane == 63 ? ca[q] : dn;
         }
-        // homogeneous responses of the incoming states, then the recombination
-        // in double precision
-        const double sqn = p.sq[n], isqn = p.isq[n];
+        // 3. homogeneous responses of the incoming states (by recursion)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const float d1 = c.d1[s], d2 = c.d2[s];
+            float a1 = ic[2 * s], a2 = ic[2 * s + 1];
+#pragma unroll
+            for (int i = 0; i < L; ++i) {
+                const float h = fmaf(-d1, a1, -d2 * a2);
+                o[i] += h;
+                a2 = a1;
+                a1 = h;
+            }
+            float b1 = ia[2 * s], b2 = ia[2 * s + 1];
+#pragma unroll
+            for (int i = L - 1; i >= 0; --i) {
+                const float h = fmaf(-d1, b1, -d2 * b2);
+                o[i] += h;
+                b2 = b1;
+                b1 = h;
+            }
+        }
+        // recombination: Horner in tau, double precision
         const bool inD = n <= p.N;
+        const double rD = p.isq[n + 1], rM = p.isq[n], sqn = p.sq[n];
 #pragma unroll
         for (int i = 0; i < L; ++i) {
-            float v = o[i];
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                v = fmaf(fix[(2 * s) * L + i], ic[2 * s], v);
-                v = fmaf(fix[(2 * s + 1) * L + i], ic[2 * s + 1], v);
-                v = fmaf(fix[(2 * s) * L + (L - 1 - i)], ia[2 * s], v);
-                v = fmaf(fix[(2 * s + 1) * L + (L - 1 - i)], ia[2 * s + 1], v);
-            }
-            const double ub = (double)v;
-            if (n >= 1) M[i] = fma(P[i] * sqn, ub, M[i]);
-            if (inD) {
-                P[i] = (n == 0) ? 1.0 : P[i] * (double)tau[i] * isqn;
-                D[i] = fma(P[i], ub, D[i]);
-            }
+            const double ub = (double)o[i];
+            const double tv = (double)tau[i];
+            if (inD) bD[i] = fma(bD[i], tv * rD, ub);
+            if (n >= 1) bM[i] = fma(bM[i], tv * rM, sqn * ub);
         }
     }
     if (y < p.H) {
@@ -403,8 +499,8 @@ __device__ __forceinline__ void hrow(const GPParams &p, const IirCoef &c, const 
         for (int i = 0; i < L; ++i) {
             const int x = x0 + i;
             if (x < p.W) {
-                const double rho = M[i] / D[i];
-                p.out[(size_t)y * p.pitch + x] = st.ok ? (float)(st.tc + p.sigma_r * rho) : __builtin_nanf("");
+                const double rho = bM[i] / bD[i];
+                p.out[(size_t)y * p.pitch + x] = st.ok ? (float)fma(p.sigma_r, rho, st.tc) : __builtin_nanf("");
             }
         }
     }

@@ -8,7 +8,6 @@ template <int R>
 __global__ __launch_bounds__(kBlock) void k_bwd(GPParams p, BwdParams b, FirTaps2 taps) {
     extern __shared__ float smem[];
     const Stats st = load_stats(p);
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *p.status = st.ok ? 0 : -3;
     bwd_tile<R>(p, b, taps, st, blockIdx.y * BwdShape<R>::TY, blockIdx.x * BwdShape<R>::TX,
                 blockIdx.y * gridDim.x + blockIdx.x, smem);
 }

@@ -11,11 +11,12 @@ __global__ __launch_bounds__(kBlock) void k_stats(const float *img, int H, int W
     stats_rows(img, H, W, pitch, blockIdx.x, gridDim.x, parts);
 }
 
+__global__ __launch_bounds__(kBlock) void k_stats_final(GPParams p) { stats_final(p); }
+
 template <int R, bool SAVE>
 __global__ __launch_bounds__(kBlock) void k_fir(GPParams p, FirTaps taps) {
     extern __shared__ float smem[];
     const Stats st = load_stats(p);
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *p.status = st.ok ? 0 : -3;
     fir_tile<R, SAVE>(p, taps, st, blockIdx.y * FirShape<R>::TY, blockIdx.x * FirShape<R>::TX, smem);
 }
 
@@ -34,7 +35,6 @@ template <int B, bool AGG, bool BIG>
 __global__ __launch_bounds__(64, 2) void k_vband(GPParams p, IirCoef c, float *carry, float *S) {
     __shared__ float sacc[AGG ? 1 : B * 64];
     const Stats st = load_stats(p);
-    if (AGG && !BIG && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *p.status = st.ok ? 0 : -3;
     if (!st.ok || ((st.xmax > 12.0) != BIG)) return;
     const int col = blockIdx.x * 64 + threadIdx.x;
     vband<B, AGG, BIG>(p, c, st, col, blockIdx.y, carry, S, sacc);
@@ -58,8 +58,10 @@ __global__ __launch_bounds__(512, 1) void k_hrow(GPParams p, IirCoef c, const fl
 
 // ---- host launchers ----------------------------------------------------------
 
-hipError_t launch_stats(const float *img, int H, int W, int pitch, Partial *parts, int nparts, hipStream_t s) {
-    BF_LAUNCH("k_stats", k_stats, dim3(nparts), dim3(kBlock), 0, s, img, H, W, pitch, parts);
+hipError_t launch_stats(const GPParams &p, hipStream_t s) {
+    BF_LAUNCH("k_stats", k_stats, dim3(p.nparts), dim3(kBlock), 0, s, p.img, p.H, p.W, p.pitch,
+              const_cast<Partial *>(p.parts));
+    BF_LAUNCH("k_stats_final", k_stats_final, dim3(1), dim3(kBlock), 0, s, p);
     return hipGetLastError();
 }
 
