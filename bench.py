@@ -121,7 +121,8 @@ def main():
         step()
     e.record()
     torch.cuda.synchronize()
-    stage = bf.profile_collect()
+    stage_t = bf.profile_collect(with_threads=True)
+    stage = {k: v[:2] for k, v in stage_t.items()}
     bf.profile_enable(False)
     ms_step = s.elapsed_time(e) / K
     px_step = len(SWEEP) * H * W
@@ -136,8 +137,15 @@ def main():
     # pixels per launch: every kernel of a forward covers the whole image
     bpp = bytes_per_pixel(kname, C)
     achieved = bpp * H * W / (avg_ms * 1e-3) / 1e9 if bpp else None
+    # measured HBM traffic of the same kernel (rocprofv3 FETCH_SIZE + WRITE_SIZE,
+    # calibrated by a device copy), valid only for the sources it was taken with
+    from paper_1505_00077_amd import profiling
+    traffic = profiling.traffic_for(os.path.join(ROOT, "profiles", "traffic_counters.json"), kname,
+                                    stage_t[kname][2])
     roofline = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                "traffic": (traffic / (avg_ms * 1e-3) / 1e9) if traffic else None,
+                "traffic_bytes_per_launch": traffic, "algorithmic_bytes_per_launch": bpp * H * W if bpp else None,
                 "avg_launch_ms": avg_ms, "launches": kcount, "bytes_per_px": bpp,
                 "share_of_step": kms / (ms_step * K)}
     modes["stages_ms_per_step"] = {k: v[1] / K for k, v in sorted(stage.items())}
@@ -261,6 +269,18 @@ def main():
                                    "fwd_only_mpix_s": npx / (ms_f * 1e-3) / 1e6, "plan": "fir",
                                    "grad_log_sigma_s_sum": float(gls.sum()), "grad_log_sigma_r_sum": float(glr.sum())}
         log(f"fwd+bwd: {ms_fb:.3f} ms (fwd only {ms_f:.3f} ms)")
+
+    # ---------------- copy calibration for the traffic counters ----------------
+    if want("calib"):
+        # a plain device-to-device copy of 256 MiB: its FETCH_SIZE / WRITE_SIZE
+        # counters give the scale between counter readings and bytes moved
+        nbytes = 256 << 20
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        ms = timed(lambda: dst.copy_(src), max(1, K // 2), 1, torch)
+        modes["copy_calibration"] = {"bytes_each_way": nbytes, "ms": ms,
+                                     "gbs_read_plus_write": 2 * nbytes / (ms * 1e-3) / 1e9}
+        del src, dst
 
     # ---------------- accuracy on the small configuration ----------------
     if want("accuracy"):

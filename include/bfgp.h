@@ -157,10 +157,11 @@ int bf_direct_forward(const float *img, float *out, int H, int W, int pitch,
  * on its stream around each kernel it launches.  bf_profile_enable(1) (re)starts
  * the record, bf_profile_enable(0) stops recording.  bf_profile_collect waits for
  * the recorded events and fills, for up to `max` distinct kernel names, the
- * number of launches and the summed duration in milliseconds; it returns the
- * number of names filled (or a negative status).  Name strings are static. */
+ * number of launches, the summed duration in milliseconds and the grid size
+ * (in threads) of the last launch; it returns the number of names filled (or a
+ * negative status).  Name strings are static. */
 int bf_profile_enable(int on);
-int bf_profile_collect(int max, const char **names, int *counts, double *total_ms);
+int bf_profile_collect(int max, const char **names, int *counts, double *total_ms, long long *threads);
 
 #ifdef __cplusplus
 }

@@ -62,7 +62,7 @@ bf_gp_plan_free = _sig("bf_gp_plan_free", None, _vp)
 bf_direct_forward = _sig("bf_direct_forward", _i, _vp, _vp, _i, _i, _i, _d, _d, _i, _vp)
 bf_profile_enable = _sig("bf_profile_enable", _i, _i)
 bf_profile_collect = _sig("bf_profile_collect", _i, _i, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(_i),
-                          ctypes.POINTER(_d))
+                          ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_longlong))
 
 
 class BfError(RuntimeError):
@@ -177,14 +177,18 @@ def profile_enable(on=True):
     _check(bf_profile_enable(1 if on else 0), "bf_profile_enable")
 
 
-def profile_collect(max_names=64):
-    """{kernel name: (launches, total ms)} for the launches recorded so far."""
+def profile_collect(max_names=64, with_threads=False):
+    """{kernel name: (launches, total ms)} for the launches recorded so far
+    (with_threads: (launches, total ms, grid size in threads of the last launch))."""
     names = (ctypes.c_char_p * max_names)()
     counts = (ctypes.c_int * max_names)()
     total = (ctypes.c_double * max_names)()
-    n = bf_profile_collect(max_names, names, counts, total)
+    threads = (ctypes.c_longlong * max_names)()
+    n = bf_profile_collect(max_names, names, counts, total, threads)
     if n < 0:
         raise BfError(n, "bf_profile_collect")
+    if with_threads:
+        return {names[i].decode(): (counts[i], total[i], threads[i]) for i in range(n)}
     return {names[i].decode(): (counts[i], total[i]) for i in range(n)}
 
 

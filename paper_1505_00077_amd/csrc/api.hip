@@ -253,6 +253,18 @@ BwdLayout bwd_layout(int H, int W) {
 
 // Helpers shared with the batched path (batched.hip).
 namespace bfgp {
+int column_groups(int H, int W, int C) {
+    // one 64-column group of one band is one wave; small images are split by
+    // channel until about 2048 waves exist (each split repeats the band's
+    // channel generation, which large images cannot afford), at most 4 groups
+    const long waves = (long)((W + 63) / 64) * ((H + kBand - 1) / kBand);
+    const long target = 2048;
+    int g = (int)((target + waves - 1) / waves);
+    if (g < 1) g = 1;
+    if (g > 4) g = 4;
+    if (g > C) g = C;
+    return g;
+}
 GPParams gp_params_for(const float *img, float *out, int H, int W, int pitch, double sigma_r, int N, unsigned flags,
                        const Partial *parts, int nparts, int *status, Stats *stats) {
     Layout L;
@@ -319,7 +331,8 @@ int bf_gp_forward(const float *img, float *out, int H, int W, int pitch, double 
     } else {
         int Lc, T;
         row_shape(W, &Lc, &T);
-        e = launch_iir(p, make_iir(sigma_s, kBand, Lc), kBand, Lc, T, (float *)(w + L.carry), (float *)(w + L.stack), s);
+        e = launch_iir(p, make_iir(sigma_s, kBand, Lc), kBand, Lc, T, column_groups(H, W, N + 2), (float *)(w + L.carry),
+                       (float *)(w + L.stack), s);
         if (e != hipSuccess) return hip_fail(e, "IIR launch");
     }
     return BF_OK;

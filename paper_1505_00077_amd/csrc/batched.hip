@@ -40,6 +40,7 @@ struct BatchImage {
     int R;         // FIR radius
     int L;         // IIR row chunk
     int nb;        // IIR bands
+    int G;         // channel groups of the column passes
     float *carry;
     float *S;
 };
@@ -78,7 +79,8 @@ __global__ __launch_bounds__(kBlock) void k_bfir(const BatchImage *imgs, const B
     }
 }
 
-// One item = one band of four 64-column groups (one per wave).
+// One item = one channel group of one band of four 64-column groups (one
+// per wave).
 template <bool AGG, bool BIG>
 __global__ __launch_bounds__(kBlock, 2) void k_bband(const BatchImage *imgs, const BatchItem *items) {
     __shared__ float sacc[AGG ? 1 : 4 * kBatchBand * 64];
@@ -88,17 +90,21 @@ __global__ __launch_bounds__(kBlock, 2) void k_bband(const BatchImage *imgs, con
     if (!st.ok || ((st.xmax > 12.0) != BIG)) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int ncg = (B.p.W + 63) / 64, ncg4 = (ncg + 3) / 4;
-    const int band = w.idx / ncg4, cg = (w.idx % ncg4) * 4 + wave;
+    const int g = w.idx % B.G, rest = w.idx / B.G;
+    const int band = rest / ncg4, cg = (rest % ncg4) * 4 + wave;
     if (cg >= ncg) return;
-    vband<kBatchBand, AGG, BIG>(B.p, B.c, st, cg * 64 + lane, band, B.carry, B.S, sacc + (AGG ? 0 : wave * kBatchBand * 64));
+    const int cb = (B.p.C * g) / B.G, ce = (B.p.C * (g + 1)) / B.G;
+    vband<kBatchBand, AGG, BIG>(B.p, B.c, st, cg * 64 + lane, band, B.carry, B.S,
+                                sacc + (AGG ? 0 : wave * kBatchBand * 64), cb, ce);
 }
 
 __global__ __launch_bounds__(kBlock) void k_bresolve(const BatchImage *imgs, const BatchItem *items) {
     const BatchItem w = items[blockIdx.x];
     const BatchImage &B = imgs[w.img];
     const int ng = (B.p.W + kBlock - 1) / kBlock;
-    const int n = w.idx / ng, col = (w.idx % ng) * kBlock + threadIdx.x;
-    if (col < B.p.W) vresolve(B.p, B.c, B.nb, col, n, B.carry);
+    const int dir = w.idx & 1, rest = w.idx >> 1;
+    const int n = rest / ng, col = (rest % ng) * kBlock + threadIdx.x;
+    if (col < B.p.W) vresolve(B.p, B.c, B.nb, col, n, dir, B.carry);
 }
 
 __global__ __launch_bounds__(kBlock) void k_brow(const BatchImage *imgs, const BatchItem *items) {
@@ -123,7 +129,7 @@ struct Plan {
     std::vector<BatchImage> imgs;
     std::vector<BatchItem> work;           // all stages, concatenated
     int first[kNumStages + 1];             // stage s items: work[first[s] .. first[s+1])
-    std::vector<int> iir, R, L;
+    std::vector<int> iir, R, L, G;
     size_t off_imgs, off_items, total;
     std::vector<size_t> off_parts, off_status, off_stats, off_carry, off_S;
     size_t fir_smem;
@@ -193,6 +199,7 @@ int bf_gp_plan_batched(const bf_gp_item *items, int count, unsigned flags, void 
     P->iir.resize(count);
     P->R.resize(count);
     P->L.resize(count);
+    P->G.assign(count, 1);
     for (int i = 0; i < count; ++i) {
         const bf_gp_item &it = items[i];
         unsigned m = flags & BF_SPATIAL_MASK;
@@ -223,10 +230,12 @@ int bf_gp_plan_batched(const bf_gp_item *items, int count, unsigned flags, void 
             P->off_S[i] = off;
             off = al(off + sizeof(float) * C * (size_t)it.H * it.W);
             const int ncg4 = ((it.W + 63) / 64 + 3) / 4;
-            for (int t = 0; t < nb * ncg4; ++t) per[kStAgg].push_back({i, t});
+            const int G = column_groups(it.H, it.W, (int)C);
+            P->G[i] = G;
+            for (int t = 0; t < nb * ncg4 * G; ++t) per[kStAgg].push_back({i, t});
             const int ng = (it.W + kBlock - 1) / kBlock;
-            for (int t = 0; t < (int)C * ng; ++t) per[kStResolve].push_back({i, t});
-            for (int t = 0; t < nb * ncg4; ++t) per[kStBand].push_back({i, t});
+            for (int t = 0; t < (int)C * ng * 2; ++t) per[kStResolve].push_back({i, t});
+            for (int t = 0; t < nb * ncg4 * G; ++t) per[kStBand].push_back({i, t});
             for (int y = 0; y < it.H; ++y) per[kStRow].push_back({i, y});
         }
     }
@@ -266,6 +275,7 @@ int bf_gp_plan_upload(void *plan, void *ws, size_t ws_bytes, void *stream) {
         B.R = P->R[i];
         B.L = P->L[i];
         B.nb = (it.H + kBatchBand - 1) / kBatchBand;
+        B.G = P->G[i];
         if (B.iir) {
             B.c = iir_coef_for(it.sigma_s, kBatchBand, B.L);
             B.carry = (float *)(w + P->off_carry[i]);

@@ -74,17 +74,31 @@ __device__ __forceinline__ void stats_rows(const float *__restrict__ img, int H,
                                            int b, int G, Partial *__restrict__ parts) {
     __shared__ double s_sum[kBlock / 64];
     __shared__ float s_lo[kBlock / 64], s_hi[kBlock / 64];
-    double s = 0.0;
+    double s = 0.0, s2 = 0.0;
     float lo = __builtin_inff(), hi = -__builtin_inff();
     for (int y = b; y < H; y += G) {
         const float *row = img + (size_t)y * pitch;
-        for (int x = threadIdx.x; x < W; x += kBlock) {
+        int x0 = 0;
+        if ((((size_t)row) & 15) == 0) {
+            // four columns per load; two independent double accumulators
+            const int W4 = W & ~3;
+            for (int x = 4 * (int)threadIdx.x; x < W4; x += 4 * kBlock) {
+                const float4 v = *(const float4 *)(row + x);
+                s += (double)v.x + (double)v.y;
+                s2 += (double)v.z + (double)v.w;
+                lo = fminf(lo, fminf(fminf(v.x, v.y), fminf(v.z, v.w)));
+                hi = fmaxf(hi, fmaxf(fmaxf(v.x, v.y), fmaxf(v.z, v.w)));
+            }
+            x0 = W4;
+        }
+        for (int x = x0 + threadIdx.x; x < W; x += kBlock) {
             const float v = row[x];
             s += (double)v;
             lo = fminf(lo, v);
             hi = fmaxf(hi, v);
         }
     }
+    s += s2;
     s = wave_sum(s);
     lo = wave_min(lo);
     hi = wave_max(hi);
@@ -160,6 +174,15 @@ __device__ __forceinline__ void stats_final(const GPParams &p) {
 
 // The statistics of the image (written earlier in the same stream).
 __device__ __forceinline__ Stats load_stats(const GPParams &p) { return *p.stats; }
+
+// exp(-x^2/2) * 2^shift as float, to about one ulp: the base-2 exponent is
+// formed in double and split into an integer part (applied by ldexp) and a
+// fraction in [-1/2, 1/2] (exp2 in float).  Much cheaper than a double exp.
+__device__ __forceinline__ float gauss_u0(float x, int shift) {
+    const double a = fma(-0.72134752044448170, (double)x * (double)x, (double)shift);  // log2(e)/2
+    const double ah = rint(a);
+    return ldexpf(exp2f((float)(a - ah)), (int)ah);
+}
 
 // x = (f - t_c) / sigma_r, computed in double and rounded once to float.
 __device__ __forceinline__ float centred(float f, const Stats &st, double inv_sr) {

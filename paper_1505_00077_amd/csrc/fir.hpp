@@ -56,7 +56,7 @@ __device__ __forceinline__ void fir_tile(const GPParams &p, const FirTaps &taps,
             if (gy >= 0 && gy < p.H && gx >= 0 && gx < p.W) {
                 const float x = centred(p.img[(size_t)gy * p.pitch + gx], st, p.inv_sigma_r);
                 xr[i] = x;
-                u[i] = exp(-0.5 * (double)x * (double)x);
+                u[i] = (double)gauss_u0(x, 0);
             }
         }
     }

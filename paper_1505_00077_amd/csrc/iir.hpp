@@ -59,9 +59,12 @@ __device__ __forceinline__ int big_shift(float x) {
 // (section 0: z_a, z_{a+1}; section 1: same).
 // sacc: LDS scratch of B * 64 floats (the causal outputs of the wave's 64
 // columns while the anticausal pass runs), used only when !AGG.
+// Channels [cb, ce) only: the channel recurrence still starts from u_0, so the
+// values do not depend on how the channels are split across workgroups.
 template <int B, bool AGG, bool BIG>
 __device__ __forceinline__ void vband(const GPParams &p, const IirCoef &c, const Stats &st, int col, int band,
-                                      float *__restrict__ carry, float *__restrict__ S, float *sacc) {
+                                      float *__restrict__ carry, float *__restrict__ S, float *sacc, int cb,
+                                      int ce) {
     const int lane = threadIdx.x & 63;
     const int a = band * B;
     float xv[B + 3], u[B + 3];
@@ -70,12 +73,15 @@ __device__ __forceinline__ void vband(const GPParams &p, const IirCoef &c, const
         const int row = a - 1 + i;
         const float x = xval(p, st, row, col);
         xv[i] = x;
-        double lu = -0.5 * (double)x * (double)x;
-        if (BIG) lu = fma((double)big_shift(x), 0.69314718055994531, lu);
-        u[i] = inimg(p, row, col) ? (float)exp(lu) : 0.f;
+        u[i] = inimg(p, row, col) ? gauss_u0(x, BIG ? big_shift(x) : 0) : 0.f;
     }
     const size_t cstride = (size_t)p.W;
-    for (int n = 0; n < p.C; ++n) {
+    for (int n = 1; n < cb; ++n) {
+        const float isq = (float)p.isq[n];
+#pragma unroll
+        for (int i = 0; i < B + 3; ++i) u[i] *= xv[i] * isq;
+    }
+    for (int n = cb; n < ce; ++n) {
         const float isq = (float)p.isq[n];
         if (n > 0) {
 #pragma unroll
@@ -157,41 +163,27 @@ __device__ __forceinline__ void vband(const GPParams &p, const IirCoef &c, const
     }
 }
 
-// Resolves, for one (column, channel), the true incoming states of every band
-// from the band end states, in place.
-__device__ __forceinline__ void vresolve(const GPParams &p, const IirCoef &c, int nb, int col, int n,
+// Resolves, for one (column, channel) and one direction (dir 0 causal, top to
+// bottom; dir 1 anticausal, bottom to top), the true incoming states of every
+// band from the band end states, in place.
+__device__ __forceinline__ void vresolve(const GPParams &p, const IirCoef &c, int nb, int col, int n, int dir,
                                          float *__restrict__ carry) {
     const size_t cs = (size_t)p.W;
-    float sc[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int k = 0; k < nb; ++k) {
-        float *cp = carry + ((size_t)(k * p.C + n) * 8) * cs + col;
+    float st4[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int kk = 0; kk < nb; ++kk) {
+        const int k = dir == 0 ? kk : nb - 1 - kk;
+        float *cp = carry + ((size_t)(k * p.C + n) * 8 + 4 * dir) * cs + col;
         float l[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) l[j] = cp[j * cs];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) cp[j * cs] = sc[j];
+        for (int j = 0; j < 4; ++j) cp[j * cs] = st4[j];
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             const float *P = c.phiB[s];
-            const float a0 = sc[2 * s], a1 = sc[2 * s + 1];
-            sc[2 * s] = fmaf(P[0], a0, fmaf(P[1], a1, l[2 * s]));
-            sc[2 * s + 1] = fmaf(P[2], a0, fmaf(P[3], a1, l[2 * s + 1]));
-        }
-    }
-    float sa[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int k = nb - 1; k >= 0; --k) {
-        float *cp = carry + ((size_t)(k * p.C + n) * 8 + 4) * cs + col;
-        float l[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) l[j] = cp[j * cs];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) cp[j * cs] = sa[j];
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const float *P = c.phiB[s];
-            const float a0 = sa[2 * s], a1 = sa[2 * s + 1];
-            sa[2 * s] = fmaf(P[0], a0, fmaf(P[1], a1, l[2 * s]));
-            sa[2 * s + 1] = fmaf(P[2], a0, fmaf(P[3], a1, l[2 * s + 1]));
+            const float a0 = st4[2 * s], a1 = st4[2 * s + 1];
+            st4[2 * s] = fmaf(P[0], a0, fmaf(P[1], a1, l[2 * s]));
+            st4[2 * s + 1] = fmaf(P[2], a0, fmaf(P[3], a1, l[2 * s + 1]));
         }
     }
 }
@@ -255,8 +247,9 @@ __device__ __forceinline__ void affine2(float *r, const float *v, const float *P
 // Channels are visited from N+1 down to 0 so that the recombination is a
 // Horner evaluation in tau with two FP64 accumulators per pixel:
 //   bD <- Ubar_n + bD tau / sqrt(n+1)  (n <= N),
-//   bM <- sqrt(n) Ubar_n + bM tau / sqrt(n)  (n >= 1),
-// ending with bD = D exp(tau^2/2) and bM = M exp(tau^2/2).
+//   bM <- Ubar_n + bM tau sqrt(n+1) / n  (n >= 1),
+// ending with bD = D exp(tau^2/2) and bM = M exp(tau^2/2) (the second is the
+// Horner form of sum_k sqrt(k) p_{k-1} Ubar_k with sqrt(k) divided out).
 // sm: hrow_smem_floats(T / 64) floats.
 template <int L>
 __device__ __forceinline__ void hrow(const GPParams &p, const IirCoef &c, const Stats &st, int y,
@@ -483,15 +476,17 @@ __device__ __forceinline__ void hrow(const GPParams &p, const IirCoef &c, const 
                 b1 = h;
             }
         }
-        // recombination: Horner in tau, double precision
+        // recombination: Horner in tau, double precision.  With
+        // m_k = bM_k / sqrt(k): m_k = Ubar_k + m_{k+1} tau sqrt(k+1) / k.
         const bool inD = n <= p.N;
-        const double rD = p.isq[n + 1], rM = p.isq[n], sqn = p.sq[n];
+        const double rD = p.isq[n + 1];
+        const double rM = n >= 1 ? p.sq[n + 1] / (double)n : 0.0;
 #pragma unroll
         for (int i = 0; i < L; ++i) {
             const double ub = (double)o[i];
             const double tv = (double)tau[i];
             if (inD) bD[i] = fma(bD[i], tv * rD, ub);
-            if (n >= 1) bM[i] = fma(bM[i], tv * rM, sqn * ub);
+            if (n >= 1) bM[i] = fma(bM[i], tv * rM, ub);
         }
     }
     if (y < p.H) {

@@ -32,17 +32,19 @@ __global__ __launch_bounds__(kBlock) void k_direct(DirectArgs a) {
 // that its register allocation does not burden the common case; both are
 // launched and the one that does not match the image's range returns at once.
 template <int B, bool AGG, bool BIG>
-__global__ __launch_bounds__(64, 2) void k_vband(GPParams p, IirCoef c, float *carry, float *S) {
+__global__ __launch_bounds__(64, 2) void k_vband(GPParams p, IirCoef c, float *carry, float *S, int groups) {
     __shared__ float sacc[AGG ? 1 : B * 64];
     const Stats st = load_stats(p);
     if (!st.ok || ((st.xmax > 12.0) != BIG)) return;
     const int col = blockIdx.x * 64 + threadIdx.x;
-    vband<B, AGG, BIG>(p, c, st, col, blockIdx.y, carry, S, sacc);
+    // channel group blockIdx.z of `groups` nearly equal groups
+    const int cb = (p.C * (int)blockIdx.z) / groups, ce = (p.C * ((int)blockIdx.z + 1)) / groups;
+    vband<B, AGG, BIG>(p, c, st, col, blockIdx.y, carry, S, sacc, cb, ce);
 }
 
 __global__ __launch_bounds__(kBlock) void k_vresolve(GPParams p, IirCoef c, int nb, float *carry) {
     const int col = blockIdx.x * kBlock + threadIdx.x;
-    if (col < p.W) vresolve(p, c, nb, col, blockIdx.y, carry);
+    if (col < p.W) vresolve(p, c, nb, col, blockIdx.y, blockIdx.z, carry);
 }
 
 template <int L>
@@ -89,13 +91,14 @@ hipError_t launch_fir(const GPParams &p, const FirTaps &t, int R, bool save, hip
 }
 
 
-hipError_t launch_iir(const GPParams &p, const IirCoef &c, int B, int L, int T, float *carry, float *S, hipStream_t s) {
+hipError_t launch_iir(const GPParams &p, const IirCoef &c, int B, int L, int T, int G, float *carry, float *S,
+                      hipStream_t s) {
     const int nb = (p.H + B - 1) / B;
-    dim3 gv((p.W + 63) / 64, nb);
-#define BF_VB(b, agg)                                                                        \
-    do {                                                                                     \
-        BF_LAUNCH(agg ? "k_vband_agg" : "k_vband", (k_vband<b, agg, false>), gv, dim3(64), 0, s, p, c, carry, S);    \
-        BF_LAUNCH(agg ? "k_vband_agg_big" : "k_vband_big", (k_vband<b, agg, true>), gv, dim3(64), 0, s, p, c, carry, S);     \
+    dim3 gv((p.W + 63) / 64, nb, G);
+#define BF_VB(b, agg)                                                                                      \
+    do {                                                                                                   \
+        BF_LAUNCH(agg ? "k_vband_agg" : "k_vband", (k_vband<b, agg, false>), gv, dim3(64), 0, s, p, c, carry, S, G); \
+        BF_LAUNCH(agg ? "k_vband_agg_big" : "k_vband_big", (k_vband<b, agg, true>), gv, dim3(64), 0, s, p, c, carry, S, G); \
     } while (0)
     if (B == 64)
         BF_VB(64, true);
@@ -103,7 +106,7 @@ hipError_t launch_iir(const GPParams &p, const IirCoef &c, int B, int L, int T, 
         BF_VB(32, true);
     else
         return hipErrorInvalidValue;
-    BF_LAUNCH("k_vresolve", k_vresolve, dim3((p.W + kBlock - 1) / kBlock, p.C), dim3(kBlock), 0, s, p, c, nb, carry);
+    BF_LAUNCH("k_vresolve", k_vresolve, dim3((p.W + kBlock - 1) / kBlock, p.C, 2), dim3(kBlock), 0, s, p, c, nb, carry);
     if (B == 64)
         BF_VB(64, false);
     else

@@ -19,6 +19,7 @@ struct Prof {
     bool on = false;
     std::vector<hipEvent_t> ev;        // 2 * kMaxPairs events, created once
     std::vector<const char *> name;    // per recorded pair
+    std::vector<long long> threads;    // per recorded pair: grid size in threads
     int used = 0;
     bool open = false;
 };
@@ -30,13 +31,14 @@ Prof &prof() {
 
 }  // namespace
 
-void prof_begin(hipStream_t s, const char *name) {
+void prof_begin(hipStream_t s, const char *name, long long threads) {
     Prof &p = prof();
     if (!p.on) return;
     std::lock_guard<std::mutex> g(p.mu);
     if (!p.on || p.used >= kMaxPairs) return;
     if (hipEventRecord(p.ev[2 * p.used], s) != hipSuccess) return;
     p.name[p.used] = name;
+    p.threads[p.used] = threads;
     p.open = true;
 }
 
@@ -61,6 +63,7 @@ int bf_profile_enable(int on) {
     if (on && p.ev.empty()) {
         p.ev.resize(2 * kMaxPairs);
         p.name.resize(kMaxPairs);
+        p.threads.resize(kMaxPairs);
         for (auto &e : p.ev)
             if (hipEventCreate(&e) != hipSuccess) {
                 p.ev.clear();
@@ -73,10 +76,10 @@ int bf_profile_enable(int on) {
     return BF_OK;
 }
 
-int bf_profile_collect(int max, const char **names, int *counts, double *total_ms) {
+int bf_profile_collect(int max, const char **names, int *counts, double *total_ms, long long *threads) {
     Prof &p = prof();
     std::lock_guard<std::mutex> g(p.mu);
-    if (max < 0 || (max > 0 && (!names || !counts || !total_ms))) return BF_EINVAL;
+    if (max < 0 || (max > 0 && (!names || !counts || !total_ms || !threads))) return BF_EINVAL;
     int n = 0;
     for (int i = 0; i < p.used; ++i) {
         if (hipEventSynchronize(p.ev[2 * i + 1]) != hipSuccess) return BF_EHIP;
@@ -93,6 +96,7 @@ int bf_profile_collect(int max, const char **names, int *counts, double *total_m
         }
         counts[j] += 1;
         total_ms[j] += ms;
+        threads[j] = p.threads[i];
     }
     return n;
 }
