@@ -101,6 +101,23 @@ unsigned bf_gp_resolve_spatial(double sigma_s, unsigned flags);
 int bf_gp_set_fir_crossover(int radius);
 int bf_gp_get_fir_crossover(void);
 
+/* Launch-shape overrides of the IIR mode, process-wide, for tuning (0 restores
+ * the automatic choice):
+ *   band_rows   0, 32 or 64: rows per band of the column passes;
+ *   col_groups  0..8: channel groups of the column passes;
+ *   row_groups  0..8: channel groups of the row pass (capped by the row width
+ *               and by the channel count).
+ * They change how the passes split the work, hence the rounding of the
+ * result (never its mathematics), and the workspace size of the IIR mode:
+ * size the workspace after setting them.  The batched plan reads them when it
+ * is built.  Returns BF_EINVAL for values outside the ranges. */
+int bf_gp_set_iir_tuning(int band_rows, int col_groups, int row_groups);
+/* The IIR launch shape an H x W image of degree N gets under the current
+ * settings: shape[0] band rows, [1] column channel groups, [2] samples per row
+ * thread, [3] row threads per channel group, [4] row channel groups.
+ * W up to 8192. */
+int bf_gp_iir_shape(int H, int W, int N, int *shape /* 5 ints, host */);
+
 /* ---- GP backward -------------------------------------------------------------
  * Adjoint of bf_gp_forward for a scalar loss L with upstream gradient
  * grad_out = dL/dout.  Derived by the chain rule through eqs. (7)-(11) and the

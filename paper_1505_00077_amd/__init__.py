@@ -52,6 +52,8 @@ bf_gp_status = _sig("bf_gp_status", _i, _vp, _vp, ctypes.POINTER(_i))
 bf_gp_resolve_spatial = _sig("bf_gp_resolve_spatial", _u, _d, _u)
 bf_gp_set_fir_crossover = _sig("bf_gp_set_fir_crossover", _i, _i)
 bf_gp_get_fir_crossover = _sig("bf_gp_get_fir_crossover", _i)
+bf_gp_set_iir_tuning = _sig("bf_gp_set_iir_tuning", _i, _i, _i, _i)
+bf_gp_iir_shape = _sig("bf_gp_iir_shape", _i, _i, _i, _i, ctypes.POINTER(_i))
 bf_gp_backward_workspace_bytes = _sig("bf_gp_backward_workspace_bytes", _sz, _i, _i, _i, _d, _u)
 bf_gp_backward = _sig("bf_gp_backward", _i, _vp, _vp, _vp, _i, _i, _i, _d, _d, _i, _u, _vp, _vp, _vp, _vp, _sz, _vp)
 bf_gp_plan_batched = _sig("bf_gp_plan_batched", _i, ctypes.POINTER(BfGpItem), _i, _u, ctypes.POINTER(_vp))
@@ -170,6 +172,18 @@ def set_fir_crossover(radius):
 
 def get_fir_crossover():
     return int(bf_gp_get_fir_crossover())
+
+
+def set_iir_tuning(band_rows=0, col_groups=0, row_groups=0):
+    """Overrides the IIR launch shape process-wide (0 = automatic)."""
+    _check(bf_gp_set_iir_tuning(int(band_rows), int(col_groups), int(row_groups)), "bf_gp_set_iir_tuning")
+
+
+def iir_shape(H, W, N=20):
+    """dict(band_rows, col_groups, row_chunk, row_threads, row_groups) for an image."""
+    v = (ctypes.c_int * 5)()
+    _check(bf_gp_iir_shape(int(H), int(W), int(N), v), "bf_gp_iir_shape")
+    return dict(zip(("band_rows", "col_groups", "row_chunk", "row_threads", "row_groups"), list(v)))
 
 
 def profile_enable(on=True):

@@ -82,15 +82,10 @@ double range_limit(int N) {
     return lo;
 }
 
-// IIR band height and row chunking for an image.
-constexpr int kBand = 64;
-void row_shape(int W, int *L, int *T) {
-    int l = W <= 1024 ? 4 : (W <= 2048 ? 8 : 16);
-    int t = (W + l - 1) / l;
-    t = ((t + 63) / 64) * 64;
-    *L = l;
-    *T = t;
-}
+// Launch-shape overrides of the IIR passes (0 = automatic), for tuning.
+std::atomic<int> g_band_rows{0}, g_col_groups{0}, g_row_groups{0};
+// Waves the column passes aim for: a few per SIMD of the 1024 on the device.
+constexpr long kTargetWaves = 2048;
 constexpr int kIirMaxW = 8192;
 
 struct Layout {
@@ -109,11 +104,12 @@ Layout gp_layout(int H, int W, int N, unsigned spatial) {
     L.carry = L.stack = off;
     if (spatial == BF_SPATIAL_IIR) {
         const size_t C = (size_t)N + 2;
-        const size_t nb = ((size_t)H + kBand - 1) / kBand;
+        const IirShape sh = iir_shape(H, W, (int)C);
+        const size_t nb = ((size_t)H + sh.B - 1) / sh.B;
         L.carry = off;
         off = align256(off + sizeof(float) * nb * C * 8 * (size_t)W);
         L.stack = off;
-        off = align256(off + sizeof(float) * C * (size_t)H * (size_t)W);
+        off = align256(off + sizeof(float) * C * (size_t)sh.Hs * (size_t)sh.P);
     }
     L.total = off;
     return L;
@@ -166,6 +162,7 @@ GPParams make_params(const float *img, float *out, int H, int W, int pitch, doub
     for (int n = 0; n < kMaxC + 3; ++n) {
         p.sq[n] = sqrt((double)n);
         p.isq[n] = n > 0 ? 1.0 / sqrt((double)n) : 0.0;
+        p.rm[n] = n > 0 ? sqrt((double)n + 1.0) / (double)n : 0.0;
     }
     return p;
 }
@@ -224,6 +221,7 @@ IirCoef make_iir(double sigma_s, int B, int L) {
         }
         mat2_pow(Phi, 64L * L, M);
         for (int q = 0; q < 4; ++q) c.phiW[s][q] = (float)M[q];
+
     }
     return c;
 }
@@ -253,17 +251,53 @@ BwdLayout bwd_layout(int H, int W) {
 
 // Helpers shared with the batched path (batched.hip).
 namespace bfgp {
-int column_groups(int H, int W, int C) {
-    // one 64-column group of one band is one wave; small images are split by
-    // channel until about 2048 waves exist (each split repeats the band's
-    // channel generation, which large images cannot afford), at most 4 groups
-    const long waves = (long)((W + 63) / 64) * ((H + kBand - 1) / kBand);
-    const long target = 2048;
-    int g = (int)((target + waves - 1) / waves);
-    if (g < 1) g = 1;
-    if (g > 4) g = 4;
-    if (g > C) g = C;
-    return g;
+IirShape iir_shape(int H, int W, int C) {
+    IirShape sh;
+    const long cols = (W + 63) / 64;  // one wave per 64 columns of one band
+    // band height: 32 rows (measured faster than 64 at every size: more waves
+    // for the same work, and fewer registers per wave)
+    int B = g_band_rows.load();
+    if (B != 32 && B != 64) B = 32;
+    sh.B = B;
+    // channel groups of the column passes: each repeats the band's channel
+    // generation up to its first channel, so only images with too few waves
+    // are split
+    int G = g_col_groups.load();
+    if (G < 1) {
+        const long waves = cols * ((H + B - 1) / B);
+        G = (int)((kTargetWaves + waves - 1) / waves);
+        if (G > 8) G = 8;
+    }
+    if (G < 1) G = 1;
+    if (G > C) G = C;
+    sh.G = G;
+    // row pass: the fewest waves that hold the row at 16 samples per thread,
+    // then the shortest chunk (4, 8, 12 or 16 samples) that still covers it
+    // (fewer idle lanes), and channel groups until the rows give enough waves
+    // (each group adds an LDS hand-over, so no more than needed)
+    sh.T = (((W + 15) / 16 + 63) / 64) * 64;
+    sh.L = 16;
+    for (int l = 4; l < 16; l += 4)
+        if (sh.T * l >= W) {
+            sh.L = l;
+            break;
+        }
+    int Gr = g_row_groups.load();
+    if (Gr < 1) {
+        const long waves = (long)H * (sh.T / 64);
+        Gr = (int)((kTargetWaves + waves - 1) / waves);
+        if (Gr > 4) Gr = 4;
+    }
+    if (Gr > 512 / sh.T) Gr = 512 / sh.T;
+    if (Gr > C) Gr = C;
+    if (Gr < 1) Gr = 1;
+    while (Gr > 1 && hrow_smem_bytes(sh.T, Gr, sh.L) > 65536) --Gr;
+    sh.Gr = Gr;
+    // stack pitch: past the last chunk's right halo (two samples), rounded up
+    // to a 128-byte line so that every stack row starts on a line
+    sh.P = ((sh.T * sh.L + 2 + 31) / 32) * 32;
+    sh.Hs = ((H + B - 1) / B) * B;
+    return sh;
 }
 GPParams gp_params_for(const float *img, float *out, int H, int W, int pitch, double sigma_r, int N, unsigned flags,
                        const Partial *parts, int nparts, int *status, Stats *stats) {
@@ -299,6 +333,28 @@ int bf_gp_set_fir_crossover(int radius) {
 
 int bf_gp_get_fir_crossover(void) { return g_fir_crossover.load(); }
 
+int bf_gp_set_iir_tuning(int band_rows, int col_groups, int row_groups) {
+    if (band_rows != 0 && band_rows != 32 && band_rows != 64) return fail(BF_EINVAL, "band rows %d not 0, 32 or 64", band_rows);
+    if (col_groups < 0 || col_groups > 8) return fail(BF_EINVAL, "column groups %d outside 0..8", col_groups);
+    if (row_groups < 0 || row_groups > 8) return fail(BF_EINVAL, "row groups %d outside 0..8", row_groups);
+    g_band_rows.store(band_rows);
+    g_col_groups.store(col_groups);
+    g_row_groups.store(row_groups);
+    return BF_OK;
+}
+
+int bf_gp_iir_shape(int H, int W, int N, int *shape) {
+    if (!shape) return fail(BF_EINVAL, "null shape");
+    if (H < 1 || W < 1 || W > kIirMaxW || N < 0 || N > BF_MAX_DEGREE) return fail(BF_EINVAL, "bad image size or degree");
+    const IirShape sh = iir_shape(H, W, N + 2);
+    shape[0] = sh.B;
+    shape[1] = sh.G;
+    shape[2] = sh.L;
+    shape[3] = sh.T;
+    shape[4] = sh.Gr;
+    return BF_OK;
+}
+
 size_t bf_gp_workspace_bytes(int H, int W, int N, double sigma_s, unsigned flags) {
     if (H < 1 || W < 1 || N < 0 || N > BF_MAX_DEGREE || !finite_pos(sigma_s)) return 0;
     return gp_layout(H, W, N, resolve_spatial(sigma_s, flags)).total;
@@ -322,17 +378,15 @@ int bf_gp_forward(const float *img, float *out, int H, int W, int pitch, double 
     hipStream_t s = (hipStream_t)stream;
     char *w = (char *)ws;
     GPParams p = make_params(img, out, H, W, pitch, sigma_r, N, flags, w, L, saved);
-    hipError_t e = launch_stats(p, s);
+    hipError_t e = launch_stats(p, false, s);
     if (e != hipSuccess) return hip_fail(e, "statistics launch");
     if (spatial == BF_SPATIAL_FIR) {
         const int R = fir_radius(sigma_s);
         e = launch_fir(p, make_taps(sigma_s, R), R, saved != nullptr, s);
         if (e != hipSuccess) return hip_fail(e, "FIR launch");
     } else {
-        int Lc, T;
-        row_shape(W, &Lc, &T);
-        e = launch_iir(p, make_iir(sigma_s, kBand, Lc), kBand, Lc, T, column_groups(H, W, N + 2), (float *)(w + L.carry),
-                       (float *)(w + L.stack), s);
+        const IirShape sh = iir_shape(H, W, N + 2);
+        e = launch_iir(p, make_iir(sigma_s, sh.B, sh.L), sh, (float *)(w + L.carry), (float *)(w + L.stack), s);
         if (e != hipSuccess) return hip_fail(e, "IIR launch");
     }
     return BF_OK;
@@ -383,7 +437,7 @@ int bf_gp_backward(const float *img, const float *grad_out, const void *saved, i
     fl.status = L.status;
     fl.stats = L.stats;
     GPParams p = make_params(img, nullptr, H, W, pitch, sigma_r, N, flags, w, fl, const_cast<void *>(saved));
-    hipError_t e = launch_stats(p, s);
+    hipError_t e = launch_stats(p, true, s);
     if (e != hipSuccess) return hip_fail(e, "statistics launch");
     const int R = fir_radius(sigma_s);
     FirTaps2 t;

@@ -25,12 +25,13 @@
 
 namespace bfgp {
 
-enum { kStStats = 0, kStFir, kStAgg, kStResolve, kStBand, kStRow, kNumStages };
+// kStRow + k: row items whose workgroup has 64 << k threads (k = 0..3)
+enum { kStStats = 0, kStFir, kStAgg, kStResolve, kStBand, kStRow, kNumStages = kStRow + 4 };
 // same partial count as the single-image path, so that both reduce the image
 // sum in the same order and produce bit-identical centres and outputs
 constexpr int kBatchStatsParts = kMaxParts;
 constexpr int kBatchFirMaxR = 12;
-constexpr int kBatchBand = 64;
+constexpr int kBatchMaxW = 8192;
 
 struct BatchImage {
     GPParams p;
@@ -38,9 +39,14 @@ struct BatchImage {
     FirTaps taps;
     int iir;       // 0 FIR, 1 IIR
     int R;         // FIR radius
-    int L;         // IIR row chunk
+    int Bh;        // IIR band rows (32 or 64)
     int nb;        // IIR bands
     int G;         // channel groups of the column passes
+    int L;         // IIR row chunk
+    int T;         // row threads per channel group
+    int Gr;        // channel groups of the row pass
+    int Sp;        // row pitch of the channel stack
+    int Sr;        // rows per channel of the stack
     float *carry;
     float *S;
 };
@@ -55,8 +61,6 @@ __global__ __launch_bounds__(kBlock) void k_bstats(const BatchImage *imgs, const
     stats_rows(p.img, p.H, p.W, p.pitch, w.idx, p.nparts, const_cast<Partial *>(p.parts));
 }
 
-// one workgroup per image
-__global__ __launch_bounds__(kBlock) void k_bstats_final(const BatchImage *imgs) { stats_final(imgs[blockIdx.x].p); }
 
 template <int R>
 __device__ __forceinline__ void fir_item(const BatchImage &B, const Stats &st, int idx, float *smem) {
@@ -69,7 +73,9 @@ __global__ __launch_bounds__(kBlock) void k_bfir(const BatchImage *imgs, const B
     extern __shared__ float smem[];
     const BatchItem w = items[blockIdx.x];
     const BatchImage &B = imgs[w.img];
-    const Stats st = load_stats(B.p);
+    // first kernel after the statistics pass for FIR images
+    const Stats st = reduce_stats(B.p);
+    if (w.idx == 0 && threadIdx.x == 0) publish_stats(B.p, st);
     switch (B.R) {
 #define BF_CASE(r) case r: fir_item<r>(B, st, w.idx, smem); break;
         BF_CASE(1) BF_CASE(2) BF_CASE(3) BF_CASE(4) BF_CASE(5) BF_CASE(6)
@@ -79,23 +85,35 @@ __global__ __launch_bounds__(kBlock) void k_bfir(const BatchImage *imgs, const B
     }
 }
 
-// One item = one channel group of one band of four 64-column groups (one
-// per wave).
-template <bool AGG, bool BIG>
-__global__ __launch_bounds__(kBlock, 2) void k_bband(const BatchImage *imgs, const BatchItem *items) {
-    __shared__ float sacc[AGG ? 1 : 4 * kBatchBand * 64];
+// One item = one channel group of one band of one 64-column group (one wave,
+// as in the single-image launch).  The end-state pass is the first kernel
+// after the statistics pass for IIR images.  The band height is the same for
+// every image of a plan (it depends on no image property).
+template <int BH, bool AGG>
+__global__ __launch_bounds__(64, 3) void k_bband(const BatchImage *imgs, const BatchItem *items) {
+    __shared__ float sacc[AGG ? 1 : BH * 64];
     const BatchItem w = items[blockIdx.x];
     const BatchImage &B = imgs[w.img];
-    const Stats st = load_stats(B.p);
-    if (!st.ok || ((st.xmax > 12.0) != BIG)) return;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int ncg = (B.p.W + 63) / 64, ncg4 = (ncg + 3) / 4;
+    Stats st;
+    if (AGG) {
+        st = reduce_stats(B.p);
+        if (w.idx == 0 && threadIdx.x == 0) publish_stats(B.p, st);
+    } else {
+        st = load_stats(B.p);
+    }
+    if (!st.ok) return;
+    const bool big = st.xmax > 12.0;
+    const int lane = threadIdx.x & 63;
+    const int ncg = (B.Sp + 63) / 64;
     const int g = w.idx % B.G, rest = w.idx / B.G;
-    const int band = rest / ncg4, cg = (rest % ncg4) * 4 + wave;
-    if (cg >= ncg) return;
+    const int band = rest / ncg, cg = rest % ncg;
     const int cb = (B.p.C * g) / B.G, ce = (B.p.C * (g + 1)) / B.G;
-    vband<kBatchBand, AGG, BIG>(B.p, B.c, st, cg * 64 + lane, band, B.carry, B.S,
-                                sacc + (AGG ? 0 : wave * kBatchBand * 64), cb, ce);
+    float *sa = sacc;
+    const int col = cg * 64 + lane;
+    if (big)
+        vband<BH, AGG, true>(B.p, B.c, st, col, band, B.carry, B.S, B.Sp, sa, cb, ce);
+    else
+        vband<BH, AGG, false>(B.p, B.c, st, col, band, B.carry, B.S, B.Sp, sa, cb, ce);
 }
 
 __global__ __launch_bounds__(kBlock) void k_bresolve(const BatchImage *imgs, const BatchItem *items) {
@@ -107,19 +125,25 @@ __global__ __launch_bounds__(kBlock) void k_bresolve(const BatchImage *imgs, con
     if (col < B.p.W) vresolve(B.p, B.c, B.nb, col, n, dir, B.carry);
 }
 
-__global__ __launch_bounds__(kBlock) void k_brow(const BatchImage *imgs, const BatchItem *items) {
-    __shared__ float sm[hrow_smem_floats(kBlock / 64)];
+// blockDim: T * Gr of every image in the launch (images are launched in
+// classes of equal workgroup size).
+__global__ __launch_bounds__(512) void k_brow(const BatchImage *imgs, const BatchItem *items) {
+    extern __shared__ float sm[];
     const BatchItem w = items[blockIdx.x];
     const BatchImage &B = imgs[w.img];
     const Stats st = load_stats(B.p);
     if (!st.ok) {
-        for (int x = threadIdx.x; x < B.p.W; x += kBlock) B.p.out[(size_t)w.idx * B.p.pitch + x] = __builtin_nanf("");
+        for (int x = threadIdx.x; x < B.p.W; x += blockDim.x) B.p.out[(size_t)w.idx * B.p.pitch + x] = __builtin_nanf("");
         return;
     }
     if (B.L == 4)
-        hrow<4>(B.p, B.c, st, w.idx, B.S, sm);
+        hrow<4>(B.p, B.c, st, w.idx, B.S, B.Sr, B.Sp, sm, B.T, B.Gr);
+    else if (B.L == 8)
+        hrow<8>(B.p, B.c, st, w.idx, B.S, B.Sr, B.Sp, sm, B.T, B.Gr);
+    else if (B.L == 12)
+        hrow<12>(B.p, B.c, st, w.idx, B.S, B.Sr, B.Sp, sm, B.T, B.Gr);
     else
-        hrow<8>(B.p, B.c, st, w.idx, B.S, sm);
+        hrow<16>(B.p, B.c, st, w.idx, B.S, B.Sr, B.Sp, sm, B.T, B.Gr);
 }
 
 // ---- host side -------------------------------------------------------------
@@ -129,10 +153,12 @@ struct Plan {
     std::vector<BatchImage> imgs;
     std::vector<BatchItem> work;           // all stages, concatenated
     int first[kNumStages + 1];             // stage s items: work[first[s] .. first[s+1])
-    std::vector<int> iir, R, L, G;
+    std::vector<int> iir, R;
+    std::vector<IirShape> shape;
     size_t off_imgs, off_items, total;
     std::vector<size_t> off_parts, off_status, off_stats, off_carry, off_S;
-    size_t fir_smem;
+    size_t fir_smem, row_smem[4];
+    int band_rows;
     unsigned flags;
     bool uploaded;
     void *ws;
@@ -178,7 +204,7 @@ int bf_gp_plan_batched(const bf_gp_item *items, int count, unsigned flags, void 
             !std::isfinite((double)it.sigma_r))
             return set_error(BF_EINVAL, "bad sigma in the batch");
         if (it.N < 0 || it.N > BF_MAX_DEGREE) return set_error(BF_EINVAL, "bad degree in the batch");
-        if (it.W > 2048) return set_error(BF_EUNSUPPORTED, "batched images are limited to 2048 columns");
+        if (it.W > kBatchMaxW) return set_error(BF_EUNSUPPORTED, "batched images are limited to 8192 columns");
     }
     Plan *P = new (std::nothrow) Plan();
     if (!P) return set_error(BF_EHIP, "out of host memory");
@@ -198,8 +224,9 @@ int bf_gp_plan_batched(const bf_gp_item *items, int count, unsigned flags, void 
     P->off_S.resize(count);
     P->iir.resize(count);
     P->R.resize(count);
-    P->L.resize(count);
-    P->G.assign(count, 1);
+    P->shape.assign(count, IirShape{64, 1, 16, 64, 1});
+    size_t row_smem[4] = {0, 0, 0, 0};
+    P->band_rows = 32;
     for (int i = 0; i < count; ++i) {
         const bf_gp_item &it = items[i];
         unsigned m = flags & BF_SPATIAL_MASK;
@@ -208,7 +235,6 @@ int bf_gp_plan_batched(const bf_gp_item *items, int count, unsigned flags, void 
         const bool iir = (m == BF_SPATIAL_IIR) || R > kBatchFirMaxR;
         P->iir[i] = iir;
         P->R[i] = R;
-        P->L[i] = it.W <= 1024 ? 4 : 8;
         const int nparts = std::min(it.H, kBatchStatsParts);
         P->off_parts[i] = off;
         off = al(off + sizeof(Partial) * nparts);
@@ -224,19 +250,24 @@ int bf_gp_plan_batched(const bf_gp_item *items, int count, unsigned flags, void 
             P->off_carry[i] = P->off_S[i] = 0;
         } else {
             const size_t C = (size_t)it.N + 2;
-            const int nb = (it.H + kBatchBand - 1) / kBatchBand;
+            const IirShape sh = iir_shape(it.H, it.W, (int)C);
+            P->shape[i] = sh;
+            P->band_rows = sh.B;  // the same for every image
+            const int nb = (it.H + sh.B - 1) / sh.B;
             P->off_carry[i] = off;
             off = al(off + sizeof(float) * nb * C * 8 * (size_t)it.W);
             P->off_S[i] = off;
-            off = al(off + sizeof(float) * C * (size_t)it.H * it.W);
-            const int ncg4 = ((it.W + 63) / 64 + 3) / 4;
-            const int G = column_groups(it.H, it.W, (int)C);
-            P->G[i] = G;
-            for (int t = 0; t < nb * ncg4 * G; ++t) per[kStAgg].push_back({i, t});
+            off = al(off + sizeof(float) * C * (size_t)sh.Hs * sh.P);
+            const int ncg = (sh.P + 63) / 64;
+            const int G = sh.G;
+            int cls = 0;
+            while ((64 << cls) < sh.T * sh.Gr) ++cls;
+            row_smem[cls] = std::max(row_smem[cls], hrow_smem_bytes(sh.T, sh.Gr, sh.L));
+            for (int t = 0; t < nb * ncg * G; ++t) per[kStAgg].push_back({i, t});
             const int ng = (it.W + kBlock - 1) / kBlock;
             for (int t = 0; t < (int)C * ng * 2; ++t) per[kStResolve].push_back({i, t});
-            for (int t = 0; t < nb * ncg4 * G; ++t) per[kStBand].push_back({i, t});
-            for (int y = 0; y < it.H; ++y) per[kStRow].push_back({i, y});
+            for (int t = 0; t < nb * ncg * G; ++t) per[kStBand].push_back({i, t});
+            for (int y = 0; y < it.H; ++y) per[kStRow + cls].push_back({i, y});
         }
     }
     for (int s = 0; s < kNumStages; ++s) {
@@ -248,6 +279,7 @@ int bf_gp_plan_batched(const bf_gp_item *items, int count, unsigned flags, void 
     off = al(off + sizeof(BatchItem) * P->work.size());
     P->total = off;
     P->fir_smem = fir_smem;
+    for (int k = 0; k < 4; ++k) P->row_smem[k] = row_smem[k];
     P->imgs.resize(count);
     *plan_out = P;
     return BF_OK;
@@ -273,11 +305,17 @@ int bf_gp_plan_upload(void *plan, void *ws, size_t ws_bytes, void *stream) {
                             (Stats *)(w + P->off_stats[i]));
         B.iir = P->iir[i];
         B.R = P->R[i];
-        B.L = P->L[i];
-        B.nb = (it.H + kBatchBand - 1) / kBatchBand;
-        B.G = P->G[i];
+        const IirShape &sh = P->shape[i];
+        B.Bh = sh.B;
+        B.nb = (it.H + sh.B - 1) / sh.B;
+        B.G = sh.G;
+        B.L = sh.L;
+        B.T = sh.T;
+        B.Gr = sh.Gr;
+        B.Sp = sh.P;
+        B.Sr = sh.Hs;
         if (B.iir) {
-            B.c = iir_coef_for(it.sigma_s, kBatchBand, B.L);
+            B.c = iir_coef_for(it.sigma_s, sh.B, sh.L);
             B.carry = (float *)(w + P->off_carry[i]);
             B.S = (float *)(w + P->off_S[i]);
         } else {
@@ -309,15 +347,21 @@ int bf_gp_forward_batched(void *plan, void *ws, size_t ws_bytes, void *stream) {
     auto n = [P](int st) { return P->first[st + 1] - P->first[st]; };
     auto at = [P, work](int st) { return work + P->first[st]; };
     if (n(kStStats)) BF_LAUNCH("k_bstats", k_bstats, dim3(n(kStStats)), dim3(kBlock), 0, s, imgs, at(kStStats));
-    BF_LAUNCH("k_bstats_final", k_bstats_final, dim3((unsigned)P->items.size()), dim3(kBlock), 0, s, imgs);
     if (n(kStFir)) BF_LAUNCH("k_bfir", k_bfir, dim3(n(kStFir)), dim3(kBlock), P->fir_smem, s, imgs, at(kStFir));
     if (n(kStAgg)) {
-        BF_LAUNCH("k_bband_agg", (k_bband<true, false>), dim3(n(kStAgg)), dim3(kBlock), 0, s, imgs, at(kStAgg));
-        BF_LAUNCH("k_bband_agg_big", (k_bband<true, true>), dim3(n(kStAgg)), dim3(kBlock), 0, s, imgs, at(kStAgg));
+        if (P->band_rows == 32)
+            BF_LAUNCH("k_bband_agg", (k_bband<32, true>), dim3(n(kStAgg)), dim3(64), 0, s, imgs, at(kStAgg));
+        else
+            BF_LAUNCH("k_bband_agg", (k_bband<64, true>), dim3(n(kStAgg)), dim3(64), 0, s, imgs, at(kStAgg));
         BF_LAUNCH("k_bresolve", k_bresolve, dim3(n(kStResolve)), dim3(kBlock), 0, s, imgs, at(kStResolve));
-        BF_LAUNCH("k_bband", (k_bband<false, false>), dim3(n(kStBand)), dim3(kBlock), 0, s, imgs, at(kStBand));
-        BF_LAUNCH("k_bband_big", (k_bband<false, true>), dim3(n(kStBand)), dim3(kBlock), 0, s, imgs, at(kStBand));
-        BF_LAUNCH("k_brow", k_brow, dim3(n(kStRow)), dim3(kBlock), 0, s, imgs, at(kStRow));
+        if (P->band_rows == 32)
+            BF_LAUNCH("k_bband", (k_bband<32, false>), dim3(n(kStBand)), dim3(64), 0, s, imgs, at(kStBand));
+        else
+            BF_LAUNCH("k_bband", (k_bband<64, false>), dim3(n(kStBand)), dim3(64), 0, s, imgs, at(kStBand));
+        for (int k = 0; k < 4; ++k)
+            if (n(kStRow + k))
+                BF_LAUNCH("k_brow", k_brow, dim3(n(kStRow + k)), dim3(64 << k), P->row_smem[k], s, imgs,
+                          at(kStRow + k));
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(BF_EHIP, hipGetErrorString(e));

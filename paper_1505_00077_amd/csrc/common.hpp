@@ -9,7 +9,7 @@ constexpr int kBlock = 256;          // threads per workgroup for every GP kerne
 constexpr int kMaxN = 64;            // largest Gauss-polynomial degree
 constexpr int kMaxC = kMaxN + 2;     // channels u_0..u_{N+1}
 constexpr int kFirMaxR = 24;         // largest FIR radius compiled
-constexpr int kMaxParts = 1024;      // partial sums of the statistics pass
+constexpr int kMaxParts = 256;       // partial sums of the statistics pass
 constexpr int kDirectMaxW = 64;      // largest direct-filter window
 
 // One workgroup's share of the image statistics.
@@ -41,10 +41,11 @@ struct GPParams {
     const Partial *parts;
     int nparts;
     int *status;         // device status word (BF_OK / BF_ERANGE)
-    Stats *stats;        // written by stats_final
+    Stats *stats;        // written by the first kernel after the statistics pass
     void *saved;         // nullable, 16 B per pixel (see bf_gp_forward)
     double sq[kMaxC + 3];   // sqrt(n)
     double isq[kMaxC + 3];  // 1 / sqrt(n)
+    double rm[kMaxC + 3];   // sqrt(n + 1) / n (n >= 1; 0 at n = 0)
 };
 
 // Spatial taps of the FIR mode: k[d] = exp(-d^2 / 2 sigma_s^2), d = 0..R.
@@ -69,33 +70,50 @@ __device__ __forceinline__ float wave_max(float v) {
 }
 
 // Statistics pass: workgroup b reduces rows b, b + G, ... into parts[b].
-// The sum is accumulated in double, in a fixed order (deterministic).
+// The sum is accumulated in double, in a fixed order (deterministic).  Loads
+// are issued eight at a time (four rows by two 4-column groups per thread,
+// from clamped addresses, masked afterwards) so that enough are in flight.
 __device__ __forceinline__ void stats_rows(const float *__restrict__ img, int H, int W, int pitch,
                                            int b, int G, Partial *__restrict__ parts) {
     __shared__ double s_sum[kBlock / 64];
     __shared__ float s_lo[kBlock / 64], s_hi[kBlock / 64];
     double s = 0.0, s2 = 0.0;
     float lo = __builtin_inff(), hi = -__builtin_inff();
-    for (int y = b; y < H; y += G) {
-        const float *row = img + (size_t)y * pitch;
-        int x0 = 0;
-        if ((((size_t)row) & 15) == 0) {
-            // four columns per load; two independent double accumulators
-            const int W4 = W & ~3;
-            for (int x = 4 * (int)threadIdx.x; x < W4; x += 4 * kBlock) {
-                const float4 v = *(const float4 *)(row + x);
-                s += (double)v.x + (double)v.y;
-                s2 += (double)v.z + (double)v.w;
-                lo = fminf(lo, fminf(fminf(v.x, v.y), fminf(v.z, v.w)));
-                hi = fmaxf(hi, fmaxf(fmaxf(v.x, v.y), fmaxf(v.z, v.w)));
+    const int nr = (H - b + G - 1) / G;  // rows of this workgroup
+    const bool vec = ((((size_t)img) & 15) == 0) && (pitch & 3) == 0;
+    const int W4 = vec ? (W & ~3) : 0;
+    const int nch = (W4 + 4 * kBlock - 1) / (4 * kBlock);  // 4-column groups per thread and row
+    for (int r0 = 0; r0 < nr; r0 += 4) {
+        for (int j0 = 0; j0 < nch; j0 += 2) {
+            float4 v[8];
+            bool ok[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int r = r0 + (k >> 1), x = 4 * ((int)threadIdx.x + (j0 + (k & 1)) * kBlock);
+                ok[k] = r < nr && x < W4;
+                const int y = b + (ok[k] ? r : 0) * G;
+                v[k] = *(const float4 *)(img + (size_t)y * pitch + (ok[k] ? x : 0));
             }
-            x0 = W4;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (ok[k]) {
+                    s += (double)v[k].x + (double)v[k].y;
+                    s2 += (double)v[k].z + (double)v[k].w;
+                    lo = fminf(lo, fminf(fminf(v[k].x, v[k].y), fminf(v[k].z, v[k].w)));
+                    hi = fmaxf(hi, fmaxf(fmaxf(v[k].x, v[k].y), fmaxf(v[k].z, v[k].w)));
+                }
+            }
         }
-        for (int x = x0 + threadIdx.x; x < W; x += kBlock) {
-            const float v = row[x];
-            s += (double)v;
-            lo = fminf(lo, v);
-            hi = fmaxf(hi, v);
+    }
+    // columns W4 .. W-1 (all of them when rows are not 16-byte aligned)
+    const int tw = W - W4;
+    for (int r = 0; r < nr; ++r) {
+        const float *row = img + (size_t)(b + r * G) * pitch + W4;
+        for (int x = threadIdx.x; x < tw; x += kBlock) {
+            const float f = row[x];
+            s += (double)f;
+            lo = fminf(lo, f);
+            hi = fmaxf(hi, f);
         }
     }
     s += s2;
@@ -124,52 +142,53 @@ __device__ __forceinline__ void stats_rows(const float *__restrict__ img, int H,
     __syncthreads();
 }
 
-// Reduces the partials in a fixed order (one workgroup), derives the centre and
-// the range check, and stores them with the status word.
-__device__ __forceinline__ void stats_final(const GPParams &p) {
-    __shared__ double s_sum[kBlock / 64];
-    __shared__ float s_lo[kBlock / 64], s_hi[kBlock / 64];
+// Reduces the partials of the statistics pass inside one wave, in a fixed
+// order (the sum is the one lane 0 forms, so every wave that calls this gets
+// the same bits), and derives the centre and the range check.  The first
+// kernel after the statistics pass calls it in every wave instead of reading
+// a result, which saves a launch; its first workgroup publishes the result.
+__device__ __forceinline__ Stats reduce_stats(const GPParams &p) {
+    const int lane = threadIdx.x & 63;
     double s = 0.0;
     float lo = __builtin_inff(), hi = -__builtin_inff();
-    for (int i = threadIdx.x; i < p.nparts; i += kBlock) {
-        s += p.parts[i].sum;
-        lo = fminf(lo, p.parts[i].lo);
-        hi = fmaxf(hi, p.parts[i].hi);
+    for (int i = lane; i < p.nparts; i += 64) {
+        const Partial q = p.parts[i];
+        s += q.sum;
+        lo = fminf(lo, q.lo);
+        hi = fmaxf(hi, q.hi);
     }
-    s = wave_sum(s);
+    s = __shfl(wave_sum(s), 0, 64);
     lo = wave_min(lo);
     hi = wave_max(hi);
-    if ((threadIdx.x & 63) == 0) {
-        s_sum[threadIdx.x >> 6] = s;
-        s_lo[threadIdx.x >> 6] = lo;
-        s_hi[threadIdx.x >> 6] = hi;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        float l = __builtin_inff(), h = -__builtin_inff();
-        for (int i = 0; i < kBlock / 64; ++i) {
-            t += s_sum[i];
-            l = fminf(l, s_lo[i]);
-            h = fmaxf(h, s_hi[i]);
-        }
-        double tc;
-        if (p.center == 1)
-            tc = 0.5 * ((double)l + (double)h);
-        else if (p.center == 2)
-            tc = 0.0;
-        else
-            tc = t / ((double)p.H * (double)p.W);
-        const double a = fabs((double)l - tc) * p.inv_sigma_r;
-        const double b = fabs((double)h - tc) * p.inv_sigma_r;
-        Stats st;
-        st.tc = tc;
-        st.xmax = a > b ? a : b;
-        st.ok = (st.xmax <= p.xlim) ? 1 : 0;
-        st.pad = 0;
-        *p.stats = st;
-        *p.status = st.ok ? 0 : -3;
-    }
+    double tc;
+    if (p.center == 1)
+        tc = 0.5 * ((double)lo + (double)hi);
+    else if (p.center == 2)
+        tc = 0.0;
+    else
+        tc = s / ((double)p.H * (double)p.W);
+    const double a = fabs((double)lo - tc) * p.inv_sigma_r;
+    const double b = fabs((double)hi - tc) * p.inv_sigma_r;
+    Stats st;
+    st.tc = tc;
+    st.xmax = a > b ? a : b;
+    st.ok = (st.xmax <= p.xlim) ? 1 : 0;
+    st.pad = 0;
+    return st;
+}
+
+// Stores the statistics and the status word for the kernels and calls that
+// follow (one thread).
+__device__ __forceinline__ void publish_stats(const GPParams &p, const Stats &st) {
+    *p.stats = st;
+    *p.status = st.ok ? 0 : -3;
+}
+
+// Statistics of an image as a kernel of its own (one wave publishes).
+__device__ __forceinline__ void stats_final(const GPParams &p) {
+    if (threadIdx.x >= 64) return;
+    const Stats st = reduce_stats(p);
+    if (threadIdx.x == 0) publish_stats(p, st);
 }
 
 // The statistics of the image (written earlier in the same stream).

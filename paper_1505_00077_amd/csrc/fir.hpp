@@ -43,22 +43,29 @@ __device__ __forceinline__ void fir_tile(const GPParams &p, const FirTaps &taps,
     const int tid = threadIdx.x;
 
     // ---- region: centred intensities and u_0 = exp(-x^2/2) ----
+    // every load is issued unconditionally from a clamped address, so that
+    // all of them are in flight together; samples outside the image (or past
+    // the region) are zeroed afterwards
     float xr[S::PER];
     double u[S::PER];
 #pragma unroll
     for (int i = 0; i < S::PER; ++i) {
         const int e = tid + i * kBlock;
-        xr[i] = 0.f;
-        u[i] = 0.0;
-        if (e < S::REG) {
-            const int gy = ty0 - R + e / S::RX;
-            const int gx = tx0 - R + e % S::RX;
-            if (gy >= 0 && gy < p.H && gx >= 0 && gx < p.W) {
-                const float x = centred(p.img[(size_t)gy * p.pitch + gx], st, p.inv_sigma_r);
-                xr[i] = x;
-                u[i] = (double)gauss_u0(x, 0);
-            }
-        }
+        const int gy = ty0 - R + e / S::RX;
+        const int gx = tx0 - R + e % S::RX;
+        const int yc = gy < 0 ? 0 : (gy >= p.H ? p.H - 1 : gy);
+        const int xc = gx < 0 ? 0 : (gx >= p.W ? p.W - 1 : gx);
+        xr[i] = p.img[(size_t)yc * p.pitch + xc];
+    }
+#pragma unroll
+    for (int i = 0; i < S::PER; ++i) {
+        const int e = tid + i * kBlock;
+        const int gy = ty0 - R + e / S::RX;
+        const int gx = tx0 - R + e % S::RX;
+        const bool in = e < S::REG && gy >= 0 && gy < p.H && gx >= 0 && gx < p.W;
+        const float x = in ? centred(xr[i], st, p.inv_sigma_r) : 0.f;
+        xr[i] = x;
+        u[i] = in ? (double)gauss_u0(x, 0) : 0.0;
     }
 
     // ---- output ownership: row y, 8 consecutive columns from x0 ----
@@ -69,11 +76,17 @@ __device__ __forceinline__ void fir_tile(const GPParams &p, const FirTaps &taps,
     double Dt[SAVE ? S::PX : 1], Mt[SAVE ? S::PX : 1], pm[SAVE ? S::PX : 1];
     {
         const int gy = ty0 + oy;
+        const int yc = gy < p.H ? gy : p.H - 1;
+        float f[S::PX];
 #pragma unroll
         for (int i = 0; i < S::PX; ++i) {
             const int gx = tx0 + ox0 + i;
-            float x = 0.f;
-            if (gy < p.H && gx < p.W) x = centred(p.img[(size_t)gy * p.pitch + gx], st, p.inv_sigma_r);
+            f[i] = p.img[(size_t)yc * p.pitch + (gx < p.W ? gx : p.W - 1)];
+        }
+#pragma unroll
+        for (int i = 0; i < S::PX; ++i) {
+            const int gx = tx0 + ox0 + i;
+            const float x = (gy < p.H && gx < p.W) ? centred(f[i], st, p.inv_sigma_r) : 0.f;
             tau[i] = (double)x;
             Dp[i] = 0.0;
             Mp[i] = 0.0;

@@ -34,15 +34,6 @@ struct IirCoef {
     float phiW[2][4];     // Phi^(64 L)
 };
 
-// Centred intensity of column `col`, row `row`, or 0 outside the image.
-__device__ __forceinline__ float xval(const GPParams &p, const Stats &st, int row, int col) {
-    if (row < 0 || row >= p.H || col >= p.W) return 0.f;
-    return centred(p.img[(size_t)row * p.pitch + col], st, p.inv_sigma_r);
-}
-__device__ __forceinline__ bool inimg(const GPParams &p, int row, int col) {
-    return row >= 0 && row < p.H && col < p.W;
-}
-
 // Scale exponent used when exp(-x^2/2) would leave the FP32 range: the channel
 // is carried as uh = u * 2^s and stored as u = uh * 2^-s.
 __device__ __forceinline__ int big_shift(float x) {
@@ -63,17 +54,54 @@ __device__ __forceinline__ int big_shift(float x) {
 // values do not depend on how the channels are split across workgroups.
 template <int B, bool AGG, bool BIG>
 __device__ __forceinline__ void vband(const GPParams &p, const IirCoef &c, const Stats &st, int col, int band,
-                                      float *__restrict__ carry, float *__restrict__ S, float *sacc, int cb,
-                                      int ce) {
+                                      float *__restrict__ carry, float *__restrict__ S, int sp_pitch, float *sacc,
+                                      int cb, int ce) {
     const int lane = threadIdx.x & 63;
     const int a = band * B;
+    // the stack holds every channel as rows(H) = H rounded up to a whole band
+    // of rows with pitch sp_pitch, so every band stores all of its rows
+    const int srows = ((p.H + B - 1) / B) * B;
+    // lanes own columns and never exchange data.  Lanes on the stack's pad
+    // columns [W, sp_pitch) store zeros there (the row pass reads them as the
+    // zero extension of the image), lanes past the pad leave at once.
+    if (col >= p.W) {
+        if (!AGG && col < sp_pitch) {
+            for (int n = cb; n < ce; ++n) {
+                float *sp = S + ((size_t)n * srows + a) * sp_pitch + col;
+#pragma unroll
+                for (int i = 0; i < B; ++i) sp[(size_t)i * sp_pitch] = 0.f;
+            }
+        }
+        return;
+    }
+    // rows a-1 .. a+B+1: every load is issued unconditionally from a clamped
+    // row (so that all of them are in flight together), and samples outside
+    // the image are zeroed afterwards
     float xv[B + 3], u[B + 3];
 #pragma unroll
     for (int i = 0; i < B + 3; ++i) {
         const int row = a - 1 + i;
-        const float x = xval(p, st, row, col);
-        xv[i] = x;
-        u[i] = inimg(p, row, col) ? gauss_u0(x, BIG ? big_shift(x) : 0) : 0.f;
+        const int rc = row < 0 ? 0 : (row >= p.H ? p.H - 1 : row);
+        xv[i] = p.img[(size_t)rc * p.pitch + col];
+    }
+#pragma unroll
+    for (int i = 0; i < B + 3; ++i) {
+        xv[i] = centred(xv[i], st, p.inv_sigma_r);
+        u[i] = gauss_u0(xv[i], BIG ? big_shift(xv[i]) : 0);
+    }
+    // rows outside the image (a uniform test per row: only the first and the
+    // last bands have any)
+    if (a == 0) {
+        xv[0] = 0.f;
+        u[0] = 0.f;
+    }
+    if (a + B + 2 > p.H) {
+#pragma unroll
+        for (int i = 1; i < B + 3; ++i)
+            if (a - 1 + i >= p.H) {
+                xv[i] = 0.f;
+                u[i] = 0.f;
+            }
     }
     const size_t cstride = (size_t)p.W;
     for (int n = 1; n < cb; ++n) {
@@ -90,33 +118,38 @@ __device__ __forceinline__ void vband(const GPParams &p, const IirCoef &c, const
         // channel value of sample i (undoing the range shift of BIG images)
         auto V = [&](int i) -> float { return BIG ? ldexpf(u[i], -big_shift(xv[i])) : u[i]; };
         float *cp = carry + ((size_t)(band * p.C + n) * 8) * cstride + col;
+        // incoming states of both directions
+        float in8[8];
+        if (!AGG) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) in8[k] = cp[k * cstride];
+        }
         // causal: both sections advance together; the sum is staged in LDS
         {
             float y1[2] = {0.f, 0.f}, y2[2] = {0.f, 0.f};
-            if (!AGG && col < p.W) {
+            if (!AGG) {
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
-                    y1[s] = cp[(2 * s) * cstride];
-                    y2[s] = cp[(2 * s + 1) * cstride];
+                    y1[s] = in8[2 * s];
+                    y2[s] = in8[2 * s + 1];
                 }
             }
             float xp = V(0);
 #pragma unroll
             for (int i = 0; i < B; ++i) {
                 const float vi = V(i + 1);
-                float tot = 0.f;
+                float yv[2];
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
                     const float b = fmaf(c.n0[s], vi, fmaf(c.n1[s], xp, -c.d2[s] * y2[s]));
-                    const float y = fmaf(-c.d1[s], y1[s], b);
+                    yv[s] = fmaf(-c.d1[s], y1[s], b);
                     y2[s] = y1[s];
-                    y1[s] = y;
-                    tot += y;
+                    y1[s] = yv[s];
                 }
                 xp = vi;
-                if (!AGG) sacc[i * 64 + lane] = tot;
+                if (!AGG) sacc[i * 64 + lane] = yv[0] + yv[1];
             }
-            if (AGG && col < p.W) {
+            if (AGG) {
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
                     cp[(2 * s) * cstride] = y1[s];
@@ -128,31 +161,30 @@ __device__ __forceinline__ void vband(const GPParams &p, const IirCoef &c, const
         // sample (causal + anticausal) is stored as soon as it is known
         {
             float z1[2] = {0.f, 0.f}, z2[2] = {0.f, 0.f};
-            if (!AGG && col < p.W) {
+            if (!AGG) {
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
-                    z1[s] = cp[(4 + 2 * s) * cstride];
-                    z2[s] = cp[(5 + 2 * s) * cstride];
+                    z1[s] = in8[4 + 2 * s];
+                    z2[s] = in8[5 + 2 * s];
                 }
             }
             float xn1 = V(B + 1), xn2 = V(B + 2);
-            float *sp = S + ((size_t)n * p.H + a) * p.W + col;
+            float *sp = S + ((size_t)n * srows + a) * sp_pitch + col;
 #pragma unroll
             for (int i = B - 1; i >= 0; --i) {
-                float tot = 0.f;
+                float zv[2];
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
                     const float b = fmaf(c.m1[s], xn1, fmaf(c.m2[s], xn2, -c.d2[s] * z2[s]));
-                    const float z = fmaf(-c.d1[s], z1[s], b);
+                    zv[s] = fmaf(-c.d1[s], z1[s], b);
                     z2[s] = z1[s];
-                    z1[s] = z;
-                    tot += z;
+                    z1[s] = zv[s];
                 }
                 xn2 = xn1;
                 xn1 = V(i + 1);
-                if (!AGG && col < p.W && a + i < p.H) sp[(size_t)i * p.W] = sacc[i * 64 + lane] + tot;
+                if (!AGG) sp[(size_t)i * sp_pitch] = sacc[i * 64 + lane] + (zv[0] + zv[1]);
             }
-            if (AGG && col < p.W) {
+            if (AGG) {
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
                     cp[(4 + 2 * s) * cstride] = z1[s];
@@ -165,25 +197,40 @@ __device__ __forceinline__ void vband(const GPParams &p, const IirCoef &c, const
 
 // Resolves, for one (column, channel) and one direction (dir 0 causal, top to
 // bottom; dir 1 anticausal, bottom to top), the true incoming states of every
-// band from the band end states, in place.
+// band from the band end states, in place.  The end states are read 16 bands
+// at a time so that the loads overlap.
 __device__ __forceinline__ void vresolve(const GPParams &p, const IirCoef &c, int nb, int col, int n, int dir,
                                          float *__restrict__ carry) {
+    constexpr int K = 16;
     const size_t cs = (size_t)p.W;
     float st4[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int kk = 0; kk < nb; ++kk) {
-        const int k = dir == 0 ? kk : nb - 1 - kk;
-        float *cp = carry + ((size_t)(k * p.C + n) * 8 + 4 * dir) * cs + col;
-        float l[4];
+    for (int k0 = 0; k0 < nb; k0 += K) {
+        float l[K][4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) l[j] = cp[j * cs];
+        for (int q = 0; q < K; ++q) {
+            const int kk = k0 + q;
+            const int k = dir == 0 ? kk : nb - 1 - kk;
+            if (kk < nb) {
+                const float *cp = carry + ((size_t)(k * p.C + n) * 8 + 4 * dir) * cs + col;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) cp[j * cs] = st4[j];
+                for (int j = 0; j < 4; ++j) l[q][j] = cp[j * cs];
+            }
+        }
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const float *P = c.phiB[s];
-            const float a0 = st4[2 * s], a1 = st4[2 * s + 1];
-            st4[2 * s] = fmaf(P[0], a0, fmaf(P[1], a1, l[2 * s]));
-            st4[2 * s + 1] = fmaf(P[2], a0, fmaf(P[3], a1, l[2 * s + 1]));
+        for (int q = 0; q < K; ++q) {
+            const int kk = k0 + q;
+            if (kk >= nb) break;
+            const int k = dir == 0 ? kk : nb - 1 - kk;
+            float *cp = carry + ((size_t)(k * p.C + n) * 8 + 4 * dir) * cs + col;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) cp[j * cs] = st4[j];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const float *P = c.phiB[s];
+                const float a0 = st4[2 * s], a1 = st4[2 * s + 1];
+                st4[2 * s] = fmaf(P[0], a0, fmaf(P[1], a1, l[q][2 * s]));
+                st4[2 * s + 1] = fmaf(P[2], a0, fmaf(P[3], a1, l[q][2 * s + 1]));
+            }
         }
     }
 }
@@ -207,9 +254,23 @@ __device__ __forceinline__ void mat_pow_chunks(const IirCoef &c, int s, int m, f
         if (m & (1 << j)) mat_mul(G, c.phiL[s][j], G);
 }
 
-// LDS floats used by hrow for a workgroup of nw waves.
-__host__ __device__ constexpr int hrow_smem_floats(int nw) {
-    return 2 * 2 * nw * 4 + 16 * 64;
+// LDS bytes used by hrow for rows of T threads split into `groups` channel
+// groups: the per-lane chunk-power tables, the wave totals of every group
+// (double-buffered), and the FP64 partial sums that groups 1.. hand to group 0.
+__host__ __device__ constexpr size_t hrow_smem_bytes(int T, int groups, int L) {
+    return sizeof(float) * (size_t)(16 * 64 + groups * 16 * (T / 64)) +
+           sizeof(double) * 2 * (size_t)(groups - 1) * (size_t)T * (size_t)L;
+}
+
+// x^e for a small non-negative integer e (binary powering)
+__device__ __forceinline__ double ipow(double x, int e) {
+    double r = 1.0;
+    while (e > 0) {
+        if (e & 1) r *= x;
+        x *= x;
+        e >>= 1;
+    }
+    return r;
 }
 
 // Lane shifts through DPP (no LDS round trip).  Lanes whose source is outside
@@ -235,39 +296,55 @@ __device__ __forceinline__ void affine2(float *r, const float *v, const float *P
 }
 
 // One image row: row pass of eq. (8) on every channel of the column-filtered
-// stack, fused with the recombination of eqs. (9)-(11).  Workgroup of T
-// threads (T a multiple of 64, T * L >= W); thread t owns samples
-// [t L, t L + L).  Per channel:
+// stack, fused with the recombination of eqs. (9)-(11).  The workgroup holds
+// `groups` channel groups of T threads each (T a multiple of 64, T * L >= W);
+// thread t of a group owns samples [t L, t L + L), and group g filters the
+// channels [C g / groups, C (g + 1) / groups).  Threads past the last group
+// only take part in the barriers.  Per channel:
 //   1. each chunk runs causally and anticausally from rest (true halo inputs),
 //      giving local outputs and its end states;
 //   2. the chunk states are combined in order: a DPP scan inside each row of
 //      16 lanes, the row totals across the wave by readlane, the wave totals
-//      across the workgroup through LDS;
+//      across the group through LDS;
 //   3. each chunk adds the homogeneous response of its true incoming states.
-// Channels are visited from N+1 down to 0 so that the recombination is a
-// Horner evaluation in tau with two FP64 accumulators per pixel:
+// Channels are visited from the top of the group's range down, so that the
+// recombination is a Horner evaluation in tau with two FP64 accumulators per
+// pixel:
 //   bD <- Ubar_n + bD tau / sqrt(n+1)  (n <= N),
 //   bM <- Ubar_n + bM tau sqrt(n+1) / n  (n >= 1),
-// ending with bD = D exp(tau^2/2) and bM = M exp(tau^2/2) (the second is the
-// Horner form of sum_k sqrt(k) p_{k-1} Ubar_k with sqrt(k) divided out).
-// sm: hrow_smem_floats(T / 64) floats.
+// which over all channels ends with bD = D exp(tau^2/2) and bM = M exp(tau^2/2)
+// (the second is the Horner form of sum_k sqrt(k) p_{k-1} Ubar_k with sqrt(k)
+// divided out).  A group that starts at channel cb > 0 holds the tail of both
+// Horner sums; its share of the full sums is its value times
+//   tau^cb / sqrt(cb!)                                  (bD),
+//   prod_{j=1}^{cb-1} tau sqrt(j+1) / j = tau^(cb-1) sqrt(cb!) / (cb-1)!  (bM),
+// and group 0 adds the shares of groups 1, 2, ... in that order.
+// sm: hrow_smem_bytes(T, groups, L) bytes.
 template <int L>
 __device__ __forceinline__ void hrow(const GPParams &p, const IirCoef &c, const Stats &st, int y,
-                                     const float *__restrict__ S, float *sm) {
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, nw = blockDim.x >> 6;
+                                     const float *__restrict__ S, int sp_rows, int sp_pitch, float *sm, int T,
+                                     int groups) {
+    const int g = __builtin_amdgcn_readfirstlane((int)threadIdx.x / T);  // whole waves share a group
+    const int t = threadIdx.x - g * T;
+    const int lane = threadIdx.x & 63, wave = t >> 6, nw = T >> 6;
     const int r16 = lane >> 4, j16 = lane & 15;
     const int x0 = t * L;
-    float *tot = sm;                 // wave totals, double-buffered
-    float *G64 = sm + 2 * 2 * nw * 4;  // G64[k * 64 + lane], k = 0..15
+    const bool member = g < groups;
+    const int cb = member ? (p.C * g) / groups : p.C;
+    const int ce = member ? (p.C * (g + 1)) / groups : p.C;
+    const int steps = (p.C + groups - 1) / groups;  // largest group
+    float *G64 = sm;                                // G64[k * 64 + lane], k = 0..15
+    float *tot = sm + 16 * 64 + (member ? g : 0) * (16 * nw);  // wave totals, double-buffered
+    double *comb = (double *)(sm + 16 * 64 + groups * 16 * nw);
     if (nw > 1) {
-        if (wave == 0) {
+        if (threadIdx.x < 64) {
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
-                float g[4];
-                mat_pow_chunks(c, s, lane + 1, g);
-                for (int q = 0; q < 4; ++q) G64[(4 * s + q) * 64 + lane] = g[q];
-                mat_pow_chunks(c, s, 64 - lane, g);
-                for (int q = 0; q < 4; ++q) G64[(8 + 4 * s + q) * 64 + lane] = g[q];
+                float gm[4];
+                mat_pow_chunks(c, s, lane + 1, gm);
+                for (int q = 0; q < 4; ++q) G64[(4 * s + q) * 64 + lane] = gm[q];
+                mat_pow_chunks(c, s, 64 - lane, gm);
+                for (int q = 0; q < 4; ++q) G64[(8 + 4 * s + q) * 64 + lane] = gm[q];
             }
         }
         __syncthreads();
@@ -282,169 +359,182 @@ __device__ __forceinline__ void hrow(const GPParams &p, const IirCoef &c, const 
 
     float tau[L];
     double bD[L], bM[L];
+    {
+        // unconditional loads from clamped columns, zeroed past the row end
+        const float *irow = p.img + (size_t)y * p.pitch;
 #pragma unroll
-    for (int i = 0; i < L; ++i) {
-        tau[i] = xval(p, st, y, x0 + i);
-        bD[i] = 0.0;
-        bM[i] = 0.0;
+        for (int i = 0; i < L; ++i) tau[i] = irow[x0 + i < p.W ? x0 + i : p.W - 1];
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            tau[i] = x0 + i < p.W ? centred(tau[i], st, p.inv_sigma_r) : 0.f;
+            bD[i] = 0.0;
+            bM[i] = 0.0;
+        }
     }
-    for (int n = p.C - 1; n >= 0; --n) {
-        const float *row = S + ((size_t)n * p.H + y) * p.W;
-        float z[L + 3];
-        z[0] = (x0 - 1 >= 0 && x0 - 1 < p.W) ? row[x0 - 1] : 0.f;
-        if (x0 + L <= p.W && ((((size_t)(row + x0)) & 15) == 0) && (L % 4) == 0) {
+    for (int it = 0; it < steps; ++it) {
+        const int n = ce - 1 - it;
+        const bool act = n >= cb;  // uniform over the group
+        float o[L];
+        float sc[4], sa[4];
+        if (act) {
+            // samples x0-1 .. x0+L+1 of the stack row: columns W .. pitch-1
+            // are zero pad, so only the sample left of the row start needs a
+            // mask (the pitch is a multiple of 4 and the rows 16-byte aligned)
+            const float *row = S + ((size_t)n * sp_rows + y) * sp_pitch;
+            float z[L + 3];
+            z[0] = row[x0 > 0 ? x0 - 1 : 0];
 #pragma unroll
             for (int i = 0; i < L; i += 4) {
                 const float4 q = *(const float4 *)(row + x0 + i);
                 z[1 + i] = q.x; z[2 + i] = q.y; z[3 + i] = q.z; z[4 + i] = q.w;
             }
-        } else {
-#pragma unroll
-            for (int i = 0; i < L; ++i) z[1 + i] = (x0 + i < p.W) ? row[x0 + i] : 0.f;
-        }
-        z[L + 1] = (x0 + L < p.W) ? row[x0 + L] : 0.f;
-        z[L + 2] = (x0 + L + 1 < p.W) ? row[x0 + L + 1] : 0.f;
+            z[L + 1] = row[x0 + L];
+            z[L + 2] = row[x0 + L + 1];
+            z[0] = x0 > 0 ? z[0] : 0.f;
 
-        // 1. chunk from rest
-        float o[L];
-        float sc[4], sa[4];
-        {
-            float y1[2] = {0.f, 0.f}, y2[2] = {0.f, 0.f};
+            // 1. chunk from rest
+            {
+                float y1[2] = {0.f, 0.f}, y2[2] = {0.f, 0.f};
 #pragma unroll
-            for (int i = 0; i < L; ++i) {
-                float acc = 0.f;
+                for (int i = 0; i < L; ++i) {
+                    float v[2];
 #pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    const float b = fmaf(c.n0[s], z[i + 1], fmaf(c.n1[s], z[i], -c.d2[s] * y2[s]));
-                    const float v = fmaf(-c.d1[s], y1[s], b);
-                    y2[s] = y1[s];
-                    y1[s] = v;
-                    acc += v;
+                    for (int s = 0; s < 2; ++s) {
+                        const float b = fmaf(c.n0[s], z[i + 1], fmaf(c.n1[s], z[i], -c.d2[s] * y2[s]));
+                        v[s] = fmaf(-c.d1[s], y1[s], b);
+                        y2[s] = y1[s];
+                        y1[s] = v[s];
+                    }
+                    o[i] = v[0] + v[1];
                 }
-                o[i] = acc;
+                sc[0] = y1[0]; sc[1] = y2[0]; sc[2] = y1[1]; sc[3] = y2[1];
             }
-            sc[0] = y1[0]; sc[1] = y2[0]; sc[2] = y1[1]; sc[3] = y2[1];
-        }
-        {
-            float z1[2] = {0.f, 0.f}, z2[2] = {0.f, 0.f};
+            {
+                float z1[2] = {0.f, 0.f}, z2[2] = {0.f, 0.f};
 #pragma unroll
-            for (int i = L - 1; i >= 0; --i) {
-                float acc = 0.f;
+                for (int i = L - 1; i >= 0; --i) {
+                    float v[2];
 #pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    const float b = fmaf(c.m1[s], z[i + 2], fmaf(c.m2[s], z[i + 3], -c.d2[s] * z2[s]));
-                    const float v = fmaf(-c.d1[s], z1[s], b);
-                    z2[s] = z1[s];
-                    z1[s] = v;
-                    acc += v;
+                    for (int s = 0; s < 2; ++s) {
+                        const float b = fmaf(c.m1[s], z[i + 2], fmaf(c.m2[s], z[i + 3], -c.d2[s] * z2[s]));
+                        v[s] = fmaf(-c.d1[s], z1[s], b);
+                        z2[s] = z1[s];
+                        z1[s] = v[s];
+                    }
+                    o[i] += v[0] + v[1];
                 }
-                o[i] += acc;
+                sa[0] = z1[0]; sa[1] = z2[0]; sa[2] = z1[1]; sa[3] = z2[1];
             }
-            sa[0] = z1[0]; sa[1] = z2[0]; sa[2] = z1[1]; sa[3] = z2[1];
-        }
-        // 2a. scans inside each row of 16 lanes (distances 1, 2, 4, 8 chunks)
+            // 2a. scans inside each row of 16 lanes (distances 1, 2, 4, 8 chunks)
 #define BF_ROWSTEP(J, D)                                                                   \
-        {                                                                                  \
-            float pc[4], pa[4];                                                            \
-            _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                \
-                pc[q] = dpp_f<kDppRowShr + D>(sc[q]);                                      \
-                pa[q] = dpp_f<kDppRowShl + D>(sa[q]);                                      \
-            }                                                                              \
-            _Pragma("unroll") for (int s = 0; s < 2; ++s) {                                \
-                acc2(&sc[2 * s], c.phiL[s][J], pc[2 * s], pc[2 * s + 1]);                  \
-                acc2(&sa[2 * s], c.phiL[s][J], pa[2 * s], pa[2 * s + 1]);                  \
-            }                                                                              \
-        }
-        BF_ROWSTEP(0, 1)
-        BF_ROWSTEP(1, 2)
-        BF_ROWSTEP(2, 4)
-        BF_ROWSTEP(3, 8)
+            {                                                                              \
+                float pc[4], pa[4];                                                        \
+                _Pragma("unroll") for (int q = 0; q < 4; ++q) {                            \
+                    pc[q] = dpp_f<kDppRowShr + D>(sc[q]);                                  \
+                    pa[q] = dpp_f<kDppRowShl + D>(sa[q]);                                  \
+                }                                                                          \
+                _Pragma("unroll") for (int s = 0; s < 2; ++s) {                            \
+                    acc2(&sc[2 * s], c.phiL[s][J], pc[2 * s], pc[2 * s + 1]);              \
+                    acc2(&sa[2 * s], c.phiL[s][J], pa[2 * s], pa[2 * s + 1]);              \
+                }                                                                          \
+            }
+            BF_ROWSTEP(0, 1)
+            BF_ROWSTEP(1, 2)
+            BF_ROWSTEP(2, 4)
+            BF_ROWSTEP(3, 8)
 #undef BF_ROWSTEP
-        // 2b. across the four rows of the wave
-        {
-            float C1[4], C2[4], C3[4], A0[4], A1[4], A2[4];
-            float t0[4], t1[4], t2[4], h1[4], h2[4], h3[4];
+            // 2b. across the four rows of the wave
+            {
+                float C1[4], C2[4], C3[4], A0[4], A1[4], A2[4];
+                float t0[4], t1[4], t2[4], h1[4], h2[4], h3[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                t0[q] = lane_f(sc[q], 15);
-                t1[q] = lane_f(sc[q], 31);
-                t2[q] = lane_f(sc[q], 47);
-                h1[q] = lane_f(sa[q], 16);
-                h2[q] = lane_f(sa[q], 32);
-                h3[q] = lane_f(sa[q], 48);
-            }
+                for (int q = 0; q < 4; ++q) {
+                    t0[q] = lane_f(sc[q], 15);
+                    t1[q] = lane_f(sc[q], 31);
+                    t2[q] = lane_f(sc[q], 47);
+                    h1[q] = lane_f(sa[q], 16);
+                    h2[q] = lane_f(sa[q], 32);
+                    h3[q] = lane_f(sa[q], 48);
+                }
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                const float *P16 = c.phiL[s][4];
-                C1[2 * s] = t0[2 * s];
-                C1[2 * s + 1] = t0[2 * s + 1];
-                affine2(&C2[2 * s], &t1[2 * s], P16, &C1[2 * s]);
-                affine2(&C3[2 * s], &t2[2 * s], P16, &C2[2 * s]);
-                A2[2 * s] = h3[2 * s];
-                A2[2 * s + 1] = h3[2 * s + 1];
-                affine2(&A1[2 * s], &h2[2 * s], P16, &A2[2 * s]);
-                affine2(&A0[2 * s], &h1[2 * s], P16, &A1[2 * s]);
-            }
+                for (int s = 0; s < 2; ++s) {
+                    const float *P16 = c.phiL[s][4];
+                    C1[2 * s] = t0[2 * s];
+                    C1[2 * s + 1] = t0[2 * s + 1];
+                    affine2(&C2[2 * s], &t1[2 * s], P16, &C1[2 * s]);
+                    affine2(&C3[2 * s], &t2[2 * s], P16, &C2[2 * s]);
+                    A2[2 * s] = h3[2 * s];
+                    A2[2 * s + 1] = h3[2 * s + 1];
+                    affine2(&A1[2 * s], &h2[2 * s], P16, &A2[2 * s]);
+                    affine2(&A0[2 * s], &h1[2 * s], P16, &A1[2 * s]);
+                }
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                float cr0 = 0.f, cr1 = 0.f, ar0 = 0.f, ar1 = 0.f;
-                if (r16 == 1) { cr0 = C1[2 * s]; cr1 = C1[2 * s + 1]; }
-                if (r16 == 2) { cr0 = C2[2 * s]; cr1 = C2[2 * s + 1]; }
-                if (r16 == 3) { cr0 = C3[2 * s]; cr1 = C3[2 * s + 1]; }
-                if (r16 == 0) { ar0 = A0[2 * s]; ar1 = A0[2 * s + 1]; }
-                if (r16 == 1) { ar0 = A1[2 * s]; ar1 = A1[2 * s + 1]; }
-                if (r16 == 2) { ar0 = A2[2 * s]; ar1 = A2[2 * s + 1]; }
-                acc2(&sc[2 * s], G16c[s], cr0, cr1);
-                acc2(&sa[2 * s], G16a[s], ar0, ar1);
+                for (int s = 0; s < 2; ++s) {
+                    float cr0 = 0.f, cr1 = 0.f, ar0 = 0.f, ar1 = 0.f;
+                    if (r16 == 1) { cr0 = C1[2 * s]; cr1 = C1[2 * s + 1]; }
+                    if (r16 == 2) { cr0 = C2[2 * s]; cr1 = C2[2 * s + 1]; }
+                    if (r16 == 3) { cr0 = C3[2 * s]; cr1 = C3[2 * s + 1]; }
+                    if (r16 == 0) { ar0 = A0[2 * s]; ar1 = A0[2 * s + 1]; }
+                    if (r16 == 1) { ar0 = A1[2 * s]; ar1 = A1[2 * s + 1]; }
+                    if (r16 == 2) { ar0 = A2[2 * s]; ar1 = A2[2 * s + 1]; }
+                    acc2(&sc[2 * s], G16c[s], cr0, cr1);
+                    acc2(&sa[2 * s], G16a[s], ar0, ar1);
+                }
             }
         }
-        // 2c. across the waves of the workgroup
+        // 2c. across the waves of the group (every wave of the workgroup meets
+        // the barrier, active or not)
         float cc[4] = {0.f, 0.f, 0.f, 0.f}, ca[4] = {0.f, 0.f, 0.f, 0.f};
         if (nw > 1) {
-            float *buf = tot + (n & 1) * (2 * nw * 4);
-            float wc[4], wa[4];
+            float *buf = tot + (it & 1) * (2 * nw * 4);
+            if (act) {
+                float wc[4], wa[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                wc[q] = lane_f(sc[q], 63);
-                wa[q] = lane_f(sa[q], 0);
-            }
-            if (lane == 0) {
                 for (int q = 0; q < 4; ++q) {
-                    buf[wave * 4 + q] = wc[q];
-                    buf[(nw + wave) * 4 + q] = wa[q];
+                    wc[q] = lane_f(sc[q], 63);
+                    wa[q] = lane_f(sa[q], 0);
+                }
+                if (lane == 0) {
+                    for (int q = 0; q < 4; ++q) {
+                        buf[wave * 4 + q] = wc[q];
+                        buf[(nw + wave) * 4 + q] = wa[q];
+                    }
                 }
             }
             __syncthreads();
-            for (int w2 = 0; w2 < wave; ++w2) {
+            if (act) {
+                for (int w2 = 0; w2 < wave; ++w2) {
+#pragma unroll
+                    for (int s = 0; s < 2; ++s) {
+                        float r[2];
+                        affine2(r, &buf[w2 * 4 + 2 * s], c.phiW[s], &cc[2 * s]);
+                        cc[2 * s] = r[0];
+                        cc[2 * s + 1] = r[1];
+                    }
+                }
+                for (int w2 = nw - 1; w2 > wave; --w2) {
+#pragma unroll
+                    for (int s = 0; s < 2; ++s) {
+                        float r[2];
+                        affine2(r, &buf[(nw + w2) * 4 + 2 * s], c.phiW[s], &ca[2 * s]);
+                        ca[2 * s] = r[0];
+                        ca[2 * s + 1] = r[1];
+                    }
+                }
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
-                    float r[2];
-                    affine2(r, &buf[w2 * 4 + 2 * s], c.phiW[s], &cc[2 * s]);
-                    cc[2 * s] = r[0];
-                    cc[2 * s + 1] = r[1];
-                }
-            }
-            for (int w2 = nw - 1; w2 > wave; --w2) {
+                    float gm[4], hm[4];
 #pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    float r[2];
-                    affine2(r, &buf[(nw + w2) * 4 + 2 * s], c.phiW[s], &ca[2 * s]);
-                    ca[2 * s] = r[0];
-                    ca[2 * s + 1] = r[1];
+                    for (int q = 0; q < 4; ++q) {
+                        gm[q] = G64[(4 * s + q) * 64 + lane];
+                        hm[q] = G64[(8 + 4 * s + q) * 64 + lane];
+                    }
+                    acc2(&sc[2 * s], gm, cc[2 * s], cc[2 * s + 1]);
+                    acc2(&sa[2 * s], hm, ca[2 * s], ca[2 * s + 1]);
                 }
-            }
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                float g[4], h[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    g[q] = G64[(4 * s + q) * 64 + lane];
-                    h[q] = G64[(8 + 4 * s + q) * 64 + lane];
-                }
-                acc2(&sc[2 * s], g, cc[2 * s], cc[2 * s + 1]);
-                acc2(&sa[2 * s], h, ca[2 * s], ca[2 * s + 1]);
             }
         }
+        if (!act) continue;
         // exclusive states: incoming causal from the previous chunk, incoming
         // anticausal from the next chunk
         float ic[4], ia[4];
@@ -478,18 +568,52 @@ __device__ __forceinline__ void hrow(const GPParams &p, const IirCoef &c, const 
         }
         // recombination: Horner in tau, double precision.  With
         // m_k = bM_k / sqrt(k): m_k = Ubar_k + m_{k+1} tau sqrt(k+1) / k.
-        const bool inD = n <= p.N;
+        // (channel N+1 enters only bM, channel 0 only bD: uniform branches,
+        // so that the common case carries no per-sample selects)
         const double rD = p.isq[n + 1];
-        const double rM = n >= 1 ? p.sq[n + 1] / (double)n : 0.0;
+        const double rM = p.rm[n];
+        if (n <= p.N && n >= 1) {
 #pragma unroll
-        for (int i = 0; i < L; ++i) {
-            const double ub = (double)o[i];
-            const double tv = (double)tau[i];
-            if (inD) bD[i] = fma(bD[i], tv * rD, ub);
-            if (n >= 1) bM[i] = fma(bM[i], tv * rM, ub);
+            for (int i = 0; i < L; ++i) {
+                const double ub = (double)o[i];
+                const double tv = (double)tau[i];
+                bD[i] = fma(bD[i], tv * rD, ub);
+                bM[i] = fma(bM[i], tv * rM, ub);
+            }
+        } else if (n >= 1) {
+#pragma unroll
+            for (int i = 0; i < L; ++i) bM[i] = fma(bM[i], (double)tau[i] * rM, (double)o[i]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < L; ++i) bD[i] = fma(bD[i], (double)tau[i] * rD, (double)o[i]);
         }
     }
-    if (y < p.H) {
+    if (groups > 1) {
+        // shares of groups 1.. in the full Horner sums, through LDS
+        if (member && g > 0) {
+            double kD = 1.0, kM = 1.0;
+            for (int j = 0; j < cb; ++j) kD *= p.isq[j + 1];
+            for (int j = 1; j < cb; ++j) kM *= p.rm[j];
+#pragma unroll
+            for (int i = 0; i < L; ++i) {
+                const double tv = (double)tau[i];
+                const double tp = ipow(tv, cb - 1);
+                comb[((size_t)(g - 1) * 2 * L + 2 * i) * T + t] = bD[i] * (tp * tv * kD);
+                comb[((size_t)(g - 1) * 2 * L + 2 * i + 1) * T + t] = bM[i] * (tp * kM);
+            }
+        }
+        __syncthreads();
+        if (g == 0) {
+            for (int gg = 1; gg < groups; ++gg) {
+#pragma unroll
+                for (int i = 0; i < L; ++i) {
+                    bD[i] += comb[((size_t)(gg - 1) * 2 * L + 2 * i) * T + t];
+                    bM[i] += comb[((size_t)(gg - 1) * 2 * L + 2 * i + 1) * T + t];
+                }
+            }
+        }
+    }
+    if (g == 0 && y < p.H) {
 #pragma unroll
         for (int i = 0; i < L; ++i) {
             const int x = x0 + i;

@@ -16,7 +16,8 @@ __global__ __launch_bounds__(kBlock) void k_stats_final(GPParams p) { stats_fina
 template <int R, bool SAVE>
 __global__ __launch_bounds__(kBlock) void k_fir(GPParams p, FirTaps taps) {
     extern __shared__ float smem[];
-    const Stats st = load_stats(p);
+    const Stats st = reduce_stats(p);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) publish_stats(p, st);
     fir_tile<R, SAVE>(p, taps, st, blockIdx.y * FirShape<R>::TY, blockIdx.x * FirShape<R>::TX, smem);
 }
 
@@ -28,18 +29,29 @@ __global__ __launch_bounds__(kBlock) void k_direct(DirectArgs a) {
 
 // ---- recursive (IIR) passes ----------------------------------------------------
 
-// The BIG variant (channels carried with a range shift) is a separate kernel so
-// that its register allocation does not burden the common case; both are
-// launched and the one that does not match the image's range returns at once.
-template <int B, bool AGG, bool BIG>
-__global__ __launch_bounds__(64, 2) void k_vband(GPParams p, IirCoef c, float *carry, float *S, int groups) {
+// One kernel per pass covers both channel representations: images whose
+// range needs the per-sample shift (xmax > 12) take the BIG branch, which is
+// uniform over the launch.  The launch bound keeps the common branch at three
+// waves per SIMD (the rare BIG branch may spill).  The end-state pass is the
+// first kernel after the statistics pass: it reduces the partials itself.
+template <int B, bool AGG>
+__global__ __launch_bounds__(64, 3) void k_vband(GPParams p, IirCoef c, float *carry, float *S, int sp, int groups) {
     __shared__ float sacc[AGG ? 1 : B * 64];
-    const Stats st = load_stats(p);
-    if (!st.ok || ((st.xmax > 12.0) != BIG)) return;
+    Stats st;
+    if (AGG) {
+        st = reduce_stats(p);
+        if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) publish_stats(p, st);
+    } else {
+        st = load_stats(p);
+    }
+    if (!st.ok) return;
     const int col = blockIdx.x * 64 + threadIdx.x;
     // channel group blockIdx.z of `groups` nearly equal groups
     const int cb = (p.C * (int)blockIdx.z) / groups, ce = (p.C * ((int)blockIdx.z + 1)) / groups;
-    vband<B, AGG, BIG>(p, c, st, col, blockIdx.y, carry, S, sacc, cb, ce);
+    if (st.xmax > 12.0)
+        vband<B, AGG, true>(p, c, st, col, blockIdx.y, carry, S, sp, sacc, cb, ce);
+    else
+        vband<B, AGG, false>(p, c, st, col, blockIdx.y, carry, S, sp, sacc, cb, ce);
 }
 
 __global__ __launch_bounds__(kBlock) void k_vresolve(GPParams p, IirCoef c, int nb, float *carry) {
@@ -48,22 +60,23 @@ __global__ __launch_bounds__(kBlock) void k_vresolve(GPParams p, IirCoef c, int 
 }
 
 template <int L>
-__global__ __launch_bounds__(512, 1) void k_hrow(GPParams p, IirCoef c, const float *S) {
-    __shared__ float sm[hrow_smem_floats(8)];
+__global__ __launch_bounds__(512, 1) void k_hrow(GPParams p, IirCoef c, const float *S, int srows, int sp, int T,
+                                                 int groups) {
+    extern __shared__ float sm[];
     const Stats st = load_stats(p);
     if (!st.ok) {
         for (int x = threadIdx.x; x < p.W; x += blockDim.x) p.out[(size_t)blockIdx.x * p.pitch + x] = __builtin_nanf("");
         return;
     }
-    hrow<L>(p, c, st, blockIdx.x, S, sm);
+    hrow<L>(p, c, st, blockIdx.x, S, srows, sp, sm, T, groups);
 }
 
 // ---- host launchers ----------------------------------------------------------
 
-hipError_t launch_stats(const GPParams &p, hipStream_t s) {
+hipError_t launch_stats(const GPParams &p, bool final_kernel, hipStream_t s) {
     BF_LAUNCH("k_stats", k_stats, dim3(p.nparts), dim3(kBlock), 0, s, p.img, p.H, p.W, p.pitch,
               const_cast<Partial *>(p.parts));
-    BF_LAUNCH("k_stats_final", k_stats_final, dim3(1), dim3(kBlock), 0, s, p);
+    if (final_kernel) BF_LAUNCH("k_stats_final", k_stats_final, dim3(1), dim3(64), 0, s, p);
     return hipGetLastError();
 }
 
@@ -91,31 +104,28 @@ hipError_t launch_fir(const GPParams &p, const FirTaps &t, int R, bool save, hip
 }
 
 
-hipError_t launch_iir(const GPParams &p, const IirCoef &c, int B, int L, int T, int G, float *carry, float *S,
+hipError_t launch_iir(const GPParams &p, const IirCoef &c, const IirShape &sh, float *carry, float *S,
                       hipStream_t s) {
-    const int nb = (p.H + B - 1) / B;
-    dim3 gv((p.W + 63) / 64, nb, G);
-#define BF_VB(b, agg)                                                                                      \
-    do {                                                                                                   \
-        BF_LAUNCH(agg ? "k_vband_agg" : "k_vband", (k_vband<b, agg, false>), gv, dim3(64), 0, s, p, c, carry, S, G); \
-        BF_LAUNCH(agg ? "k_vband_agg_big" : "k_vband_big", (k_vband<b, agg, true>), gv, dim3(64), 0, s, p, c, carry, S, G); \
-    } while (0)
-    if (B == 64)
-        BF_VB(64, true);
-    else if (B == 32)
-        BF_VB(32, true);
+    const int nb = (p.H + sh.B - 1) / sh.B;
+    dim3 gv((sh.P + 63) / 64, nb, sh.G);
+    if (sh.B == 64)
+        BF_LAUNCH("k_vband_agg", (k_vband<64, true>), gv, dim3(64), 0, s, p, c, carry, S, sh.P, sh.G);
+    else if (sh.B == 32)
+        BF_LAUNCH("k_vband_agg", (k_vband<32, true>), gv, dim3(64), 0, s, p, c, carry, S, sh.P, sh.G);
     else
         return hipErrorInvalidValue;
     BF_LAUNCH("k_vresolve", k_vresolve, dim3((p.W + kBlock - 1) / kBlock, p.C, 2), dim3(kBlock), 0, s, p, c, nb, carry);
-    if (B == 64)
-        BF_VB(64, false);
+    if (sh.B == 64)
+        BF_LAUNCH("k_vband", (k_vband<64, false>), gv, dim3(64), 0, s, p, c, carry, S, sh.P, sh.G);
     else
-        BF_VB(32, false);
-#undef BF_VB
-    switch (L) {
-        case 4: BF_LAUNCH("k_hrow", (k_hrow<4>), dim3(p.H), dim3(T), 0, s, p, c, S); break;
-        case 8: BF_LAUNCH("k_hrow", (k_hrow<8>), dim3(p.H), dim3(T), 0, s, p, c, S); break;
-        case 16: BF_LAUNCH("k_hrow", (k_hrow<16>), dim3(p.H), dim3(T), 0, s, p, c, S); break;
+        BF_LAUNCH("k_vband", (k_vband<32, false>), gv, dim3(64), 0, s, p, c, carry, S, sh.P, sh.G);
+    const dim3 rb(sh.T * sh.Gr);
+    const size_t sm = hrow_smem_bytes(sh.T, sh.Gr, sh.L);
+    switch (sh.L) {
+        case 4: BF_LAUNCH("k_hrow", (k_hrow<4>), dim3(p.H), rb, sm, s, p, c, S, sh.Hs, sh.P, sh.T, sh.Gr); break;
+        case 8: BF_LAUNCH("k_hrow", (k_hrow<8>), dim3(p.H), rb, sm, s, p, c, S, sh.Hs, sh.P, sh.T, sh.Gr); break;
+        case 12: BF_LAUNCH("k_hrow", (k_hrow<12>), dim3(p.H), rb, sm, s, p, c, S, sh.Hs, sh.P, sh.T, sh.Gr); break;
+        case 16: BF_LAUNCH("k_hrow", (k_hrow<16>), dim3(p.H), rb, sm, s, p, c, S, sh.Hs, sh.P, sh.T, sh.Gr); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -22,13 +22,25 @@ void prof_end(hipStream_t s);
         ::bfgp::prof_end(stream);                                                  \
     } while (0)
 
-hipError_t launch_stats(const GPParams &p, hipStream_t s);
+// Statistics partials; with final_kernel also a kernel that reduces them
+// (otherwise the next kernel reduces them itself).
+hipError_t launch_stats(const GPParams &p, bool final_kernel, hipStream_t s);
 hipError_t launch_fir(const GPParams &p, const FirTaps &t, int R, bool save, hipStream_t s);
-hipError_t launch_iir(const GPParams &p, const IirCoef &c, int B, int L, int T, int G, float *carry, float *S,
+// Launch shape of the IIR passes for one image.  The single-image and the
+// batched path take it from the same function, so both round identically.
+struct IirShape {
+    int B;   // band height of the column passes (32 or 64 rows)
+    int G;   // channel groups of the column passes
+    int L;   // samples per thread in the row pass (4, 8, 12 or 16)
+    int T;   // threads per channel group of the row pass (T L >= W)
+    int Gr;  // channel groups of the row pass
+    int P;   // row pitch of the channel stack, >= T L + 2, a multiple of 32
+             // (columns W .. P-1 are zero)
+    int Hs;  // rows per channel of the stack: H rounded up to a multiple of B
+};
+IirShape iir_shape(int H, int W, int C);
+hipError_t launch_iir(const GPParams &p, const IirCoef &c, const IirShape &sh, float *carry, float *S,
                       hipStream_t s);
-// Channel groups of the column passes for an image (enough workgroups to fill
-// the device several times over).
-int column_groups(int H, int W, int C);
 hipError_t launch_direct(const DirectArgs &a, hipStream_t s);
 int bwd_tiles(int H, int W);
 hipError_t launch_bwd(const GPParams &p, const BwdParams &b, const FirTaps2 &t, int R, double *corr, double *g_lss,

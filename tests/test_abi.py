@@ -114,3 +114,48 @@ def test_fir_radius_rule():
     import numpy as np
     assert bf.fir_radius(math.exp(float(np.float32(math.log(2.0))))) == 6
     assert bf.fir_radius(2.0 * (1 + 1e-5)) == 7
+
+
+def test_iir_shape_rule_and_overrides():
+    # automatic shapes: small images split the channels over more waves
+    assert bf.iir_shape(1024, 1024, 20) == dict(band_rows=32, col_groups=4, row_chunk=16, row_threads=64,
+                                                row_groups=2)
+    assert bf.iir_shape(4096, 4096, 20) == dict(band_rows=32, col_groups=1, row_chunk=16, row_threads=256,
+                                                row_groups=1)
+    assert bf.iir_shape(512, 512, 20)["col_groups"] == 8
+    assert bf.iir_shape(512, 512, 20)["row_groups"] == 4
+    assert bf.iir_shape(2048, 2048, 20)["row_groups"] == 1
+    assert bf.iir_shape(100, 200, 20)["row_chunk"] == 4
+    assert bf.iir_shape(100, 500, 20)["row_chunk"] == 8
+    assert bf.iir_shape(100, 640, 20)["row_chunk"] == 12
+    assert bf.iir_shape(100, 1500, 20)["row_threads"] == 128
+    assert bf.iir_shape(100, 1500, 20)["row_chunk"] == 12
+    # every width is covered, with fewer than one chunk of idle samples per wave
+    for W in (1, 63, 64, 65, 255, 256, 257, 700, 1023, 1025, 2047, 3000, 4097, 8192):
+        s = bf.iir_shape(8, W, 20)
+        assert s["row_threads"] % 64 == 0 and s["row_threads"] * s["row_chunk"] >= W
+        assert s["row_chunk"] == 4 or s["row_threads"] * (s["row_chunk"] - 4) < W
+    # never more channel groups than channels (N = 0: two channels)
+    s = bf.iir_shape(64, 64, 0)
+    assert s["col_groups"] <= 2 and s["row_groups"] <= 2
+    ws_auto = bf.workspace_bytes(1024, 1024, 20, 8.0, "iir")
+    try:
+        bf.set_iir_tuning(64, 2, 1)
+        s = bf.iir_shape(1024, 1024, 20)
+        assert (s["band_rows"], s["col_groups"], s["row_groups"]) == (64, 2, 1)
+        # half as many bands: half the carry space
+        assert bf.workspace_bytes(1024, 1024, 20, 8.0, "iir") < ws_auto
+        bf.set_iir_tuning(0, 2, 0)
+        assert bf.iir_shape(512, 512, 20)["col_groups"] == 2
+        # row groups are capped by the threads a workgroup can hold and its LDS
+        bf.set_iir_tuning(0, 0, 8)
+        s = bf.iir_shape(1024, 4096, 20)
+        assert s["row_threads"] * s["row_groups"] <= 512
+        for bad in ((16, 0, 0), (0, 9, 0), (0, 0, -1)):
+            with pytest.raises(bf.BfError):
+                bf.set_iir_tuning(*bad)
+    finally:
+        bf.set_iir_tuning(0, 0, 0)
+    assert bf.workspace_bytes(1024, 1024, 20, 8.0, "iir") == ws_auto
+    with pytest.raises(bf.BfError):
+        bf.iir_shape(10, 9000, 20)

@@ -25,9 +25,9 @@ def singles(bf, imgs, ss, sr, N=20):
 
 
 def test_small_uneven_batch(bf):
-    shapes = [(37, 70), (128, 200), (300, 129), (1, 64), (64, 1), (513, 777), (90, 2048)]
-    ss = [1.0, 2.5, 6.0, 3.0, 1.5, 11.0, 4.5]
-    sr = [30.0, 20.0, 45.0, 25.0, 30.0, 15.0, 35.0]
+    shapes = [(37, 70), (128, 200), (300, 129), (1, 64), (64, 1), (513, 777), (90, 2048), (40, 3000), (20, 300)]
+    ss = [1.0, 2.5, 6.0, 3.0, 1.5, 11.0, 4.5, 7.0, 5.0]
+    sr = [30.0, 20.0, 45.0, 25.0, 30.0, 15.0, 35.0, 30.0, 30.0]
     host = [synthimg.voronoi_image(H, W, max(1, H * W // 400), seed=300 + i) for i, (H, W) in enumerate(shapes)]
     imgs = [to_dev(h) for h in host]
     note(f"batched plan {len(imgs)} images, modes {[bf.resolve_spatial(s) for s in ss]}")

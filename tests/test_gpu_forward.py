@@ -65,6 +65,28 @@ def test_iir_scales(bf, ss):
     assert np.max(np.abs(got - oracle_gp(img, ss, 25.0, 20, "iir"))) <= TOL
 
 
+@pytest.mark.parametrize("shape", [(300, 700), (70, 1500)])
+def test_iir_launch_shapes(bf, shape):
+    # every split of the IIR passes (band height, channel groups of the column
+    # and row passes) computes the same filter: each matches the oracle, and
+    # they agree with one another to rounding
+    H, W = shape
+    img = synthimg.voronoi_image(H, W, 60, seed=H + W)
+    ref = oracle_gp(img, 6.0, 25.0, 20, "iir")
+    outs = {}
+    try:
+        for tune in [(0, 0, 0), (32, 1, 1), (64, 3, 2), (64, 8, 4), (32, 2, 8)]:
+            bf.set_iir_tuning(*tune)
+            note(f"iir tuning {tune} shape {bf.iir_shape(H, W, 20)}")
+            outs[tune] = run(bf, img, 6.0, 25.0, 20, "iir")
+            assert np.max(np.abs(outs[tune] - ref)) <= TOL, (tune, np.max(np.abs(outs[tune] - ref)))
+    finally:
+        bf.set_iir_tuning(0, 0, 0)
+    base = outs[(0, 0, 0)]
+    for tune, o in outs.items():
+        assert np.max(np.abs(o - base)) <= 1e-4, tune
+
+
 @pytest.mark.parametrize("N", [0, 2, 8, 40, 64])
 @pytest.mark.parametrize("spatial", ["fir", "iir"])
 def test_degrees(bf, N, spatial):
