@@ -59,18 +59,26 @@ def timed(fn, steps, warmup, torch):
     return s.elapsed_time(e) / steps  # ms per call
 
 
-def bytes_per_pixel(kernel, C):
-    """Algorithmic HBM bytes per pixel of one launch of each kernel."""
-    band = 64
-    return {
-        "k_hrow": 4 * C + 4 + 4,                   # stack read, image read, output write
-        "k_vband": 4 + 4 * C + 32 * C / band,      # image read, stack write, band states read
-        "k_vband_agg": 4 + 32 * C / band,          # image read, band end states written
-        "k_vresolve": 2 * 32 * C / band,           # band states read and rewritten
-        "k_fir": 4 + 4,                            # image read, output write
-        "k_stats": 4,
-        "k_direct": 4 + 4,
+FP32_VALU_PEAK_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x FMA (2 flops) x 2.4 GHz, unpacked
+
+
+def step_model(kernel, C, band, fir_radii, n_iir, n_calls, HW):
+    """Algorithmic HBM bytes and FP32 flops of one step of the sweep for one
+    kernel: every kernel of a forward covers the whole image; fir_radii lists
+    the FIR radii of the step, n_iir counts its recursive forwards."""
+    rec = 32 * C  # 2 directions x 2 second-order sections x (2 input + 2 feedback taps) x 2 flops
+    per = {
+        "k_stats": (4 * n_calls, 0),
+        "k_fir": ((4 + 4) * len(fir_radii), sum(4 * (2 * r + 1) * C for r in fir_radii)),
+        "k_vband_agg": ((4 + 32 * C / band) * n_iir, rec * n_iir),
+        "k_vresolve": (2 * 32 * C / band * n_iir, 0),
+        "k_vband": ((4 + 4 * C + 32 * C / band) * n_iir, rec * n_iir),
+        "k_hrow": ((4 * C + 4 + 4) * n_iir, rec * n_iir),
+        "k_direct": (8 * n_calls, 0),
     }.get(kernel)
+    if per is None:
+        return None, None
+    return per[0] * HW, per[1] * HW
 
 
 def main():
@@ -102,8 +110,14 @@ def main():
     img = torch.from_numpy(synthimg.mid_1024()).to(dev)
     H, W = img.shape
     outs = {ss: torch.empty_like(img) for ss in SWEEP}
+    # AUTO mode: FIR/IIR crossover measured on this device (cached per device)
+    from paper_1505_00077_amd import autotune
+    t0 = time.time()
+    crossover = autotune.ensure(DEGREE, log=log)
+    log(f"crossover table {crossover} ({time.time() - t0:.1f} s)")
     wss = {ss: bf.workspace(H, W, DEGREE, ss, "auto") for ss in SWEEP}
-    plan = {ss: bf.resolve_spatial(ss) for ss in SWEEP}
+    plan = {ss: bf.resolve_spatial(ss, shape=(H, W)) for ss in SWEEP}
+    band = bf.iir_shape(H, W, DEGREE)["band_rows"]
 
     def step():
         for ss in SWEEP:
@@ -113,9 +127,22 @@ def main():
     for _ in range(Wm):
         step()
     torch.cuda.synchronize()
-    bf.profile_enable(True)
     s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(K):
+        step()
+    e.record()
     torch.cuda.synchronize()
+    ms_step = s.elapsed_time(e) / K
+    px_step = len(SWEEP) * H * W
+    value = px_step / (ms_step * 1e-3) / 1e6
+    for ss in SWEEP:
+        if bf.status(wss[ss]) != bf.BF_OK:
+            raise RuntimeError(f"device status not OK at sigma_s={ss}")
+    # the same K steps again with a HIP event pair around every kernel launch
+    # (recorded by the library on the stream it launches on); the events
+    # themselves slow the step, so the headline above is taken without them
+    bf.profile_enable(True)
     s.record()
     for _ in range(K):
         step()
@@ -124,31 +151,38 @@ def main():
     stage_t = bf.profile_collect(with_threads=True)
     stage = {k: v[:2] for k, v in stage_t.items()}
     bf.profile_enable(False)
-    ms_step = s.elapsed_time(e) / K
-    px_step = len(SWEEP) * H * W
-    value = px_step / (ms_step * 1e-3) / 1e6
-    for ss in SWEEP:
-        if bf.status(wss[ss]) != bf.BF_OK:
-            raise RuntimeError(f"device status not OK at sigma_s={ss}")
+    ms_step_profiled = s.elapsed_time(e) / K
 
-    # dominant kernel of the timed region
+    # dominant kernel of the step, against the roofline that binds it: the
+    # higher of its algorithmic HBM-byte and FP32-flop fractions
     kname, (kcount, kms) = max(stage.items(), key=lambda kv: kv[1][1])
     avg_ms = kms / kcount
-    # pixels per launch: every kernel of a forward covers the whole image
-    bpp = bytes_per_pixel(kname, C)
-    achieved = bpp * H * W / (avg_ms * 1e-3) / 1e9 if bpp else None
+    fir_radii = [bf.fir_radius(ss) for ss in SWEEP if plan[ss] == "fir"]
+    n_iir = sum(1 for ss in SWEEP if plan[ss] == "iir")
+    bytes_step, flops_step = step_model(kname, C, band, fir_radii, n_iir, len(SWEEP), H * W)
+    per_launch = K / kcount  # launches of this kernel per step, inverted
+    gbs = bytes_step * per_launch / (avg_ms * 1e-3) / 1e9 if bytes_step else None
+    tflops = flops_step * per_launch / (avg_ms * 1e-3) / 1e12 if flops_step else None
+    f_hbm = gbs / HBM_PEAK_GBS if gbs else 0.0
+    f_alu = tflops / FP32_VALU_PEAK_TFLOPS if tflops else 0.0
     # measured HBM traffic of the same kernel (rocprofv3 FETCH_SIZE + WRITE_SIZE,
     # calibrated by a device copy), valid only for the sources it was taken with
     from paper_1505_00077_amd import profiling
     traffic = profiling.traffic_for(os.path.join(ROOT, "profiles", "traffic_counters.json"), kname,
                                     stage_t[kname][2])
-    roofline = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                "traffic": (traffic / (avg_ms * 1e-3) / 1e9) if traffic else None,
-                "traffic_bytes_per_launch": traffic, "algorithmic_bytes_per_launch": bpp * H * W if bpp else None,
-                "avg_launch_ms": avg_ms, "launches": kcount, "bytes_per_px": bpp,
-                "share_of_step": kms / (ms_step * K)}
+    common = {"kernel": kname, "traffic": (traffic / (avg_ms * 1e-3) / 1e9) if traffic else None,
+              "traffic_bytes_per_launch": traffic,
+              "algorithmic_bytes_per_launch": bytes_step * per_launch if bytes_step else None,
+              "algorithmic_fp32_flops_per_launch": flops_step * per_launch if flops_step else None,
+              "avg_launch_ms": avg_ms, "launches": kcount, "share_of_profiled_step": kms / (ms_step_profiled * K),
+              "hbm_frac": f_hbm, "fp32_valu_frac": f_alu}
+    if f_alu > f_hbm:
+        roofline = {"bound": "alu", "achieved": tflops, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": f_alu, **common}
+    else:
+        roofline = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": f_hbm, **common}
     modes["stages_ms_per_step"] = {k: v[1] / K for k, v in sorted(stage.items())}
+    modes["profiled_ms_per_step"] = ms_step_profiled
 
     # ---------------- per-sigma_s forward and direct ----------------
     if want("sweep"):
@@ -177,19 +211,21 @@ def main():
         big = torch.from_numpy(synthimg.large_4096()).to(dev)
         bws = bf.workspace(4096, 4096, DEGREE, 10.0, "auto")
         bout = torch.empty_like(big)
-        bf.profile_enable(True)
         ms = timed(lambda: bf.gp_forward(big, 10.0, 20.0, DEGREE, out=bout, ws=bws), K, Wm, torch)
+        bf.profile_enable(True)  # a second pass with per-launch events
+        timed(lambda: bf.gp_forward(big, 10.0, 20.0, DEGREE, out=bout, ws=bws), K, 0, torch)
         bstage = bf.profile_collect()
         bf.profile_enable(False)
         if bf.status(bws) != bf.BF_OK:
             raise RuntimeError("device status not OK on the 16-MP image")
         mp = 4096 * 4096
         kn, (kc, kt) = max(bstage.items(), key=lambda kv: kv[1][1])
-        # launches recorded include warm-up calls; average per launch
-        kb = bytes_per_pixel(kn, C)
+        # average per launch
+        kb, _ = step_model(kn, C, bf.iir_shape(4096, 4096, DEGREE)["band_rows"], [], 1, 1, 1)
         model_bytes = (12 + 8 * C) * mp
         modes["gp_forward_4096"] = {
-            "plan": bf.resolve_spatial(10.0), "ms": ms, "mpix_s": mp / (ms * 1e-3) / 1e6,
+            "plan": bf.resolve_spatial(10.0, shape=(4096, 4096)), "ms": ms, "mpix_s": mp / (ms * 1e-3) / 1e6,
+            "iir_shape": bf.iir_shape(4096, 4096, DEGREE),
             "model_bytes_per_px": 12 + 8 * C,
             "model_frac_of_hbm_peak": model_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "stages_ms_per_call": {k: v[1] / v[0] for k, v in sorted(bstage.items())},
@@ -228,7 +264,8 @@ def main():
                                "mpix_s_graph": npx / (ms_graph * 1e-3) / 1e6, "ms_sequential": ms_seq,
                                "mpix_s_sequential": npx / (ms_seq * 1e-3) / 1e6,
                                "max_abs_diff_vs_sequential": worst,
-                               "plans": {m: sum(1 for s_ in bss if bf.resolve_spatial(s_) == m) for m in ("fir", "iir")}}
+                               "plans": {m: sum(1 for x, s_ in zip(bimgs, bss)
+                                                if bf.resolve_spatial(s_, shape=x.shape) == m) for m in ("fir", "iir")}}
         log(f"batched: graph {ms_graph:.3f} ms, sequential {ms_seq:.3f} ms")
         del plan_b, graph, bimgs, souts, swss
 
@@ -324,6 +361,7 @@ def main():
         "config": {"workload": "gp_forward 1024x1024 voronoi-200+noise10, sigma_s sweep {2,5,10,20}, sigma_r 30, "
                                "N 20 (one step = the four forwards)",
                    "global_batch": 1, "image": [H, W], "plan": {str(k): v for k, v in plan.items()},
+                   "fir_crossover_table": crossover, "iir_shape": bf.iir_shape(H, W, DEGREE),
                    "recombination": "f64", "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -93,13 +93,28 @@ int bf_gp_forward(const float *img, float *out, int H, int W, int pitch,
  * backward that used `ws` in *status (BF_OK or BF_ERANGE). */
 int bf_gp_status(const void *ws, void *stream, int *status);
 
-/* The spatial mode BF_SPATIAL_AUTO resolves to for this sigma_s (FIR or IIR). */
+/* The spatial mode BF_SPATIAL_AUTO resolves to for this sigma_s (FIR or IIR)
+ * under the process-wide crossover radius. */
 unsigned bf_gp_resolve_spatial(double sigma_s, unsigned flags);
+/* The same for an H x W image: the size-dependent crossover table, when set,
+ * takes precedence (bf_gp_forward, the workspace size and the batched plan
+ * resolve AUTO this way). */
+unsigned bf_gp_resolve_spatial_for(int H, int W, double sigma_s, unsigned flags);
 
 /* Sets the AUTO crossover: FIR is used while ceil(3 sigma_s) <= radius.
  * radius in 0..BF_FIR_MAX_RADIUS (0 = always IIR).  Process-wide. */
 int bf_gp_set_fir_crossover(int radius);
 int bf_gp_get_fir_crossover(void);
+
+/* Size-dependent AUTO crossover, as a tuner measures it on a device: an image
+ * of H * W pixels takes radius[k] of the first k with H * W <= max_pixels[k];
+ * larger images take the process-wide radius.  max_pixels strictly increasing
+ * and positive, radius in 0..BF_FIR_MAX_RADIUS, count in 0..8 (0 clears the
+ * table).  Host arrays, copied.  Process-wide.  Returns BF_EINVAL on bad
+ * input, leaving the table unchanged. */
+int bf_gp_set_fir_crossover_table(const long long *max_pixels, const int *radius, int count);
+/* Copies up to `max` entries of the table; returns the number of entries. */
+int bf_gp_get_fir_crossover_table(long long *max_pixels, int *radius, int max);
 
 /* Launch-shape overrides of the IIR mode, process-wide, for tuning (0 restores
  * the automatic choice):
@@ -146,7 +161,10 @@ int bf_gp_backward(const float *img, const float *grad_out, const void *saved,
  * bf_gp_plan_upload copies the plan's descriptors into the workspace (once,
  * outside any graph capture, synchronising `stream`); bf_gp_forward_batched
  * then only launches kernels and may be captured into a hipGraph and replayed.
- * Images are limited to 2048 columns; FIR is used up to radius 12. */
+ * Each image gets the spatial mode and launch shape a single bf_gp_forward
+ * call would give it (the AUTO crossover table and the IIR tuning overrides
+ * are read when the plan is built), and its output is bit-identical to that
+ * call's.  Images are limited to 8192 columns (the IIR limit). */
 typedef struct bf_gp_item {
     const float *img; /* device, H x W, row pitch `pitch` elements */
     float *out;       /* device, same shape and pitch */

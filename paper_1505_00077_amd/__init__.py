@@ -50,6 +50,11 @@ bf_gp_workspace_bytes = _sig("bf_gp_workspace_bytes", _sz, _i, _i, _i, _d, _u)
 bf_gp_forward = _sig("bf_gp_forward", _i, _vp, _vp, _i, _i, _i, _d, _d, _i, _u, _vp, _vp, _sz, _vp)
 bf_gp_status = _sig("bf_gp_status", _i, _vp, _vp, ctypes.POINTER(_i))
 bf_gp_resolve_spatial = _sig("bf_gp_resolve_spatial", _u, _d, _u)
+bf_gp_resolve_spatial_for = _sig("bf_gp_resolve_spatial_for", _u, _i, _i, _d, _u)
+bf_gp_set_fir_crossover_table = _sig("bf_gp_set_fir_crossover_table", _i, ctypes.POINTER(ctypes.c_longlong),
+                                     ctypes.POINTER(_i), _i)
+bf_gp_get_fir_crossover_table = _sig("bf_gp_get_fir_crossover_table", _i, ctypes.POINTER(ctypes.c_longlong),
+                                     ctypes.POINTER(_i), _i)
 bf_gp_set_fir_crossover = _sig("bf_gp_set_fir_crossover", _i, _i)
 bf_gp_get_fir_crossover = _sig("bf_gp_get_fir_crossover", _i)
 bf_gp_set_iir_tuning = _sig("bf_gp_set_iir_tuning", _i, _i, _i, _i)
@@ -103,9 +108,31 @@ def fir_radius(sigma_s):
     return max(1, int(math.ceil(3.0 * sigma_s * (1.0 - 1e-6))))
 
 
-def resolve_spatial(sigma_s, spatial="auto"):
-    m = bf_gp_resolve_spatial(float(sigma_s), SPATIAL[spatial])
+def resolve_spatial(sigma_s, spatial="auto", shape=None):
+    """"fir" or "iir" for this sigma_s (for an image of `shape` = (H, W) when
+    given, which honours the size-dependent crossover table)."""
+    if shape is None:
+        m = bf_gp_resolve_spatial(float(sigma_s), SPATIAL[spatial])
+    else:
+        m = bf_gp_resolve_spatial_for(int(shape[0]), int(shape[1]), float(sigma_s), SPATIAL[spatial])
     return {1: "fir", 2: "iir"}[m]
+
+
+def set_fir_crossover_table(table):
+    """table: [(max_pixels, radius), ...] with increasing max_pixels ([] clears)."""
+    n = len(table)
+    px = (ctypes.c_longlong * max(n, 1))(*[int(a) for a, _ in table])
+    rr = (ctypes.c_int * max(n, 1))(*[int(b) for _, b in table])
+    _check(bf_gp_set_fir_crossover_table(px, rr, n), "bf_gp_set_fir_crossover_table")
+
+
+def get_fir_crossover_table():
+    px = (ctypes.c_longlong * 8)()
+    rr = (ctypes.c_int * 8)()
+    n = bf_gp_get_fir_crossover_table(px, rr, 8)
+    if n < 0:
+        raise BfError(n, "bf_gp_get_fir_crossover_table")
+    return [(int(px[k]), int(rr[k])) for k in range(n)]
 
 
 def workspace_bytes(H, W, N, sigma_s, spatial="auto", center="mean"):

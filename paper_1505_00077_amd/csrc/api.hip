@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <atomic>
+#include <mutex>
 #include <string>
 
 #include "../../include/bfgp.h"
@@ -48,10 +49,29 @@ int fir_radius(double sigma_s) {
     return r < 1 ? 1 : r;
 }
 
-unsigned resolve_spatial(double sigma_s, unsigned flags) {
+// Size-dependent crossover (set by a tuner): the first entry whose pixel
+// count bounds the image gives the radius; larger images use the process-wide
+// radius.
+constexpr int kMaxCrossTable = 8;
+std::mutex g_cross_mu;
+int g_cross_n = 0;
+long long g_cross_px[kMaxCrossTable];
+int g_cross_r[kMaxCrossTable];
+
+int crossover_for(long long px) {
+    if (px > 0) {
+        std::lock_guard<std::mutex> g(g_cross_mu);
+        for (int k = 0; k < g_cross_n; ++k)
+            if (px <= g_cross_px[k]) return g_cross_r[k];
+    }
+    return g_fir_crossover.load();
+}
+
+// px = H * W of the image, or 0 when unknown (the process-wide radius).
+unsigned resolve_spatial(long long px, double sigma_s, unsigned flags) {
     unsigned m = flags & BF_SPATIAL_MASK;
     if (m == BF_SPATIAL_FIR || m == BF_SPATIAL_IIR) return m;
-    return fir_radius(sigma_s) <= g_fir_crossover.load() ? BF_SPATIAL_FIR : BF_SPATIAL_IIR;
+    return fir_radius(sigma_s) <= crossover_for(px) ? BF_SPATIAL_FIR : BF_SPATIAL_IIR;
 }
 
 int center_code(unsigned flags) {
@@ -323,7 +343,40 @@ int bf_version(void) { return 10000; }
 
 const char *bf_last_error(void) { return g_err.c_str(); }
 
-unsigned bf_gp_resolve_spatial(double sigma_s, unsigned flags) { return resolve_spatial(sigma_s, flags); }
+unsigned bf_gp_resolve_spatial(double sigma_s, unsigned flags) { return resolve_spatial(0, sigma_s, flags); }
+
+unsigned bf_gp_resolve_spatial_for(int H, int W, double sigma_s, unsigned flags) {
+    return resolve_spatial(H > 0 && W > 0 ? (long long)H * W : 0, sigma_s, flags);
+}
+
+int bf_gp_set_fir_crossover_table(const long long *max_pixels, const int *radius, int count) {
+    if (count < 0 || count > kMaxCrossTable) return fail(BF_EINVAL, "crossover table of %d entries (0..%d)", count, kMaxCrossTable);
+    if (count > 0 && (!max_pixels || !radius)) return fail(BF_EINVAL, "null crossover table");
+    for (int k = 0; k < count; ++k) {
+        if (max_pixels[k] < 1 || (k > 0 && max_pixels[k] <= max_pixels[k - 1]))
+            return fail(BF_EINVAL, "crossover table pixel counts must be positive and increasing");
+        if (radius[k] < 0 || radius[k] > BF_FIR_MAX_RADIUS)
+            return fail(BF_EINVAL, "crossover radius %d outside 0..%d", radius[k], BF_FIR_MAX_RADIUS);
+    }
+    std::lock_guard<std::mutex> g(g_cross_mu);
+    for (int k = 0; k < count; ++k) {
+        g_cross_px[k] = max_pixels[k];
+        g_cross_r[k] = radius[k];
+    }
+    g_cross_n = count;
+    return BF_OK;
+}
+
+int bf_gp_get_fir_crossover_table(long long *max_pixels, int *radius, int max) {
+    if (max < 0 || (max > 0 && (!max_pixels || !radius))) return fail(BF_EINVAL, "bad table buffers");
+    std::lock_guard<std::mutex> g(g_cross_mu);
+    const int n = g_cross_n < max ? g_cross_n : max;
+    for (int k = 0; k < n; ++k) {
+        max_pixels[k] = g_cross_px[k];
+        radius[k] = g_cross_r[k];
+    }
+    return g_cross_n;
+}
 
 int bf_gp_set_fir_crossover(int radius) {
     if (radius < 0 || radius > BF_FIR_MAX_RADIUS) return fail(BF_EINVAL, "crossover radius %d outside 0..%d", radius, BF_FIR_MAX_RADIUS);
@@ -357,7 +410,7 @@ int bf_gp_iir_shape(int H, int W, int N, int *shape) {
 
 size_t bf_gp_workspace_bytes(int H, int W, int N, double sigma_s, unsigned flags) {
     if (H < 1 || W < 1 || N < 0 || N > BF_MAX_DEGREE || !finite_pos(sigma_s)) return 0;
-    return gp_layout(H, W, N, resolve_spatial(sigma_s, flags)).total;
+    return gp_layout(H, W, N, resolve_spatial((long long)H * W, sigma_s, flags)).total;
 }
 
 int bf_gp_forward(const float *img, float *out, int H, int W, int pitch, double sigma_s, double sigma_r, int N,
@@ -368,7 +421,7 @@ int bf_gp_forward(const float *img, float *out, int H, int W, int pitch, double 
     if (!ws) return fail(BF_EINVAL, "null workspace");
     if (flags & ~(BF_SPATIAL_MASK | BF_CENTER_MASK)) return fail(BF_EINVAL, "unknown flag bits 0x%x", flags);
     if ((flags & BF_SPATIAL_MASK) == 3u || (flags & BF_CENTER_MASK) == 12u) return fail(BF_EINVAL, "invalid flag combination");
-    const unsigned spatial = resolve_spatial(sigma_s, flags);
+    const unsigned spatial = resolve_spatial((long long)H * W, sigma_s, flags);
     if ((rc = check_spatial(spatial, sigma_s, W))) return rc;
     if ((const void *)img == (const void *)out) return fail(BF_EINVAL, "img and out must not alias");
     const Layout L = gp_layout(H, W, N, spatial);
@@ -421,7 +474,7 @@ int bf_gp_backward(const float *img, const float *grad_out, const void *saved, i
     if (!ws) return fail(BF_EINVAL, "null workspace");
     if (flags & ~(BF_SPATIAL_MASK | BF_CENTER_MASK)) return fail(BF_EINVAL, "unknown flag bits 0x%x", flags);
     if ((flags & BF_SPATIAL_MASK) == 3u || (flags & BF_CENTER_MASK) == 12u) return fail(BF_EINVAL, "invalid flag combination");
-    if (resolve_spatial(sigma_s, flags) != BF_SPATIAL_FIR)
+    if (resolve_spatial((long long)H * W, sigma_s, flags) != BF_SPATIAL_FIR)
         return fail(BF_EUNSUPPORTED, "the backward pass is implemented for the FIR spatial mode");
     if ((rc = check_spatial(BF_SPATIAL_FIR, sigma_s, W))) return rc;
     if ((flags & BF_CENTER_MASK) == BF_CENTER_MIDRANGE)

@@ -26,11 +26,15 @@
 namespace bfgp {
 
 // kStRow + k: row items whose workgroup has 64 << k threads (k = 0..3)
-enum { kStStats = 0, kStFir, kStAgg, kStResolve, kStBand, kStRow, kNumStages = kStRow + 4 };
+// kStFir: FIR images with radius up to kBatchFirSplit; kStFirWide: the rest
+// (separate launches, so that wide radii do not set the register budget of
+// narrow ones)
+enum { kStStats = 0, kStFir, kStFirWide, kStAgg, kStResolve, kStBand, kStRow, kNumStages = kStRow + 4 };
+constexpr int kBatchFirSplit = 12;
 // same partial count as the single-image path, so that both reduce the image
 // sum in the same order and produce bit-identical centres and outputs
 constexpr int kBatchStatsParts = kMaxParts;
-constexpr int kBatchFirMaxR = 12;
+constexpr int kBatchFirMaxR = kFirMaxR;
 constexpr int kBatchMaxW = 8192;
 
 struct BatchImage {
@@ -69,6 +73,7 @@ __device__ __forceinline__ void fir_item(const BatchImage &B, const Stats &st, i
     fir_tile<R, false>(B.p, B.taps, st, (idx / tx) * S::TY, (idx % tx) * S::TX, smem);
 }
 
+template <bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_bfir(const BatchImage *imgs, const BatchItem *items) {
     extern __shared__ float smem[];
     const BatchItem w = items[blockIdx.x];
@@ -76,13 +81,21 @@ __global__ __launch_bounds__(kBlock) void k_bfir(const BatchImage *imgs, const B
     // first kernel after the statistics pass for FIR images
     const Stats st = reduce_stats(B.p);
     if (w.idx == 0 && threadIdx.x == 0) publish_stats(B.p, st);
-    switch (B.R) {
 #define BF_CASE(r) case r: fir_item<r>(B, st, w.idx, smem); break;
-        BF_CASE(1) BF_CASE(2) BF_CASE(3) BF_CASE(4) BF_CASE(5) BF_CASE(6)
-        BF_CASE(7) BF_CASE(8) BF_CASE(9) BF_CASE(10) BF_CASE(11) BF_CASE(12)
-#undef BF_CASE
-        default: break;
+    if (!WIDE) {
+        switch (B.R) {
+            BF_CASE(1) BF_CASE(2) BF_CASE(3) BF_CASE(4) BF_CASE(5) BF_CASE(6)
+            BF_CASE(7) BF_CASE(8) BF_CASE(9) BF_CASE(10) BF_CASE(11) BF_CASE(12)
+            default: break;
+        }
+    } else {
+        switch (B.R) {
+            BF_CASE(13) BF_CASE(14) BF_CASE(15) BF_CASE(16) BF_CASE(17) BF_CASE(18)
+            BF_CASE(19) BF_CASE(20) BF_CASE(21) BF_CASE(22) BF_CASE(23) BF_CASE(24)
+            default: break;
+        }
     }
+#undef BF_CASE
 }
 
 // One item = one channel group of one band of one 64-column group (one wave,
@@ -157,7 +170,7 @@ struct Plan {
     std::vector<IirShape> shape;
     size_t off_imgs, off_items, total;
     std::vector<size_t> off_parts, off_status, off_stats, off_carry, off_S;
-    size_t fir_smem, row_smem[4];
+    size_t fir_smem[2], row_smem[4];
     int band_rows;
     unsigned flags;
     bool uploaded;
@@ -215,7 +228,7 @@ int bf_gp_plan_batched(const bf_gp_item *items, int count, unsigned flags, void 
     size_t off = 0;
     P->off_imgs = off;
     off = al(off + sizeof(BatchImage) * count);
-    size_t fir_smem = 0;
+    size_t fir_smem[2] = {0, 0};
     std::vector<std::vector<BatchItem>> per(kNumStages);
     P->off_parts.resize(count);
     P->off_status.resize(count);
@@ -230,7 +243,7 @@ int bf_gp_plan_batched(const bf_gp_item *items, int count, unsigned flags, void 
     for (int i = 0; i < count; ++i) {
         const bf_gp_item &it = items[i];
         unsigned m = flags & BF_SPATIAL_MASK;
-        if (m == BF_SPATIAL_AUTO) m = bf_gp_resolve_spatial(it.sigma_s, flags);
+        if (m == BF_SPATIAL_AUTO) m = bf_gp_resolve_spatial_for(it.H, it.W, it.sigma_s, flags);
         const int R = fir_radius_b(it.sigma_s);
         const bool iir = (m == BF_SPATIAL_IIR) || R > kBatchFirMaxR;
         P->iir[i] = iir;
@@ -245,8 +258,9 @@ int bf_gp_plan_batched(const bf_gp_item *items, int count, unsigned flags, void 
         for (int b = 0; b < nparts; ++b) per[kStStats].push_back({i, b});
         if (!iir) {
             const int tiles = ((it.W + 63) / 64) * ((it.H + 31) / 32);
-            for (int t = 0; t < tiles; ++t) per[kStFir].push_back({i, t});
-            fir_smem = std::max(fir_smem, sizeof(float) * (size_t)fir_smem_floats(R));
+            const int wide = R > kBatchFirSplit;
+            for (int t = 0; t < tiles; ++t) per[wide ? kStFirWide : kStFir].push_back({i, t});
+            fir_smem[wide] = std::max(fir_smem[wide], sizeof(float) * (size_t)fir_smem_floats(R));
             P->off_carry[i] = P->off_S[i] = 0;
         } else {
             const size_t C = (size_t)it.N + 2;
@@ -278,7 +292,8 @@ int bf_gp_plan_batched(const bf_gp_item *items, int count, unsigned flags, void 
     P->off_items = off;
     off = al(off + sizeof(BatchItem) * P->work.size());
     P->total = off;
-    P->fir_smem = fir_smem;
+    P->fir_smem[0] = fir_smem[0];
+    P->fir_smem[1] = fir_smem[1];
     for (int k = 0; k < 4; ++k) P->row_smem[k] = row_smem[k];
     P->imgs.resize(count);
     *plan_out = P;
@@ -347,7 +362,10 @@ int bf_gp_forward_batched(void *plan, void *ws, size_t ws_bytes, void *stream) {
     auto n = [P](int st) { return P->first[st + 1] - P->first[st]; };
     auto at = [P, work](int st) { return work + P->first[st]; };
     if (n(kStStats)) BF_LAUNCH("k_bstats", k_bstats, dim3(n(kStStats)), dim3(kBlock), 0, s, imgs, at(kStStats));
-    if (n(kStFir)) BF_LAUNCH("k_bfir", k_bfir, dim3(n(kStFir)), dim3(kBlock), P->fir_smem, s, imgs, at(kStFir));
+    if (n(kStFir))
+        BF_LAUNCH("k_bfir", k_bfir<false>, dim3(n(kStFir)), dim3(kBlock), P->fir_smem[0], s, imgs, at(kStFir));
+    if (n(kStFirWide))
+        BF_LAUNCH("k_bfir", k_bfir<true>, dim3(n(kStFirWide)), dim3(kBlock), P->fir_smem[1], s, imgs, at(kStFirWide));
     if (n(kStAgg)) {
         if (P->band_rows == 32)
             BF_LAUNCH("k_bband_agg", (k_bband<32, true>), dim3(n(kStAgg)), dim3(64), 0, s, imgs, at(kStAgg));

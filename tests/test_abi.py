@@ -159,3 +159,28 @@ def test_iir_shape_rule_and_overrides():
     assert bf.workspace_bytes(1024, 1024, 20, 8.0, "iir") == ws_auto
     with pytest.raises(bf.BfError):
         bf.iir_shape(10, 9000, 20)
+
+
+def test_crossover_table():
+    old = bf.get_fir_crossover()
+    try:
+        bf.set_fir_crossover(9)
+        bf.set_fir_crossover_table([(300 * 300, 20), (1100 * 1100, 12), (2100 * 2100, 4)])
+        assert bf.get_fir_crossover_table() == [(90000, 20), (1210000, 12), (4410000, 4)]
+        # sigma_s = 5 -> radius 15
+        assert bf.resolve_spatial(5.0, shape=(256, 256)) == "fir"
+        assert bf.resolve_spatial(5.0, shape=(1024, 1024)) == "iir"
+        assert bf.resolve_spatial(4.0, shape=(1024, 1024)) == "fir"      # radius 12
+        assert bf.resolve_spatial(2.0, shape=(2048, 2048)) == "iir"      # radius 6 > 4
+        assert bf.resolve_spatial(2.0, shape=(4096, 4096)) == "fir"      # past the table: radius 9
+        assert bf.resolve_spatial(5.0) == "iir"                          # no shape: process-wide radius
+        # the workspace follows the size-dependent choice
+        assert bf.workspace_bytes(256, 256, 20, 5.0) < bf.workspace_bytes(256, 256, 20, 5.0, "iir")
+        for bad in ([(100, 3), (100, 4)], [(0, 3)], [(100, 25)], [(100, 1)] * 9):
+            with pytest.raises(bf.BfError):
+                bf.set_fir_crossover_table(bad)
+        assert len(bf.get_fir_crossover_table()) == 3  # unchanged by the rejected calls
+    finally:
+        bf.set_fir_crossover_table([])
+        bf.set_fir_crossover(old)
+    assert bf.get_fir_crossover_table() == []

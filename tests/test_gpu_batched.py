@@ -18,10 +18,26 @@ def bf():
     return m
 
 
-def singles(bf, imgs, ss, sr, N=20):
+def singles(bf, imgs, ss, sr, N=20, spatial="auto"):
     # the batch descriptor holds the sigmas as float32: use the same values
     f32 = lambda v: float(np.float32(v))
-    return [to_np(bf.gp_forward(x, f32(s), f32(r), N, check=True)) for x, s, r in zip(imgs, ss, sr)]
+    return [to_np(bf.gp_forward(x, f32(s), f32(r), N, spatial=spatial, check=True)) for x, s, r in zip(imgs, ss, sr)]
+
+
+def test_forced_fir_wide_radii(bf):
+    # FIR at every radius class the batched plan launches separately
+    shapes = [(70, 90), (200, 333), (128, 64)]
+    ss = [1.0, 4.5, 8.0]  # radii 3, 14, 24
+    sr = [30.0, 25.0, 40.0]
+    host = [synthimg.voronoi_image(H, W, 30, seed=700 + i) for i, (H, W) in enumerate(shapes)]
+    imgs = [to_dev(h) for h in host]
+    note("batched forced FIR, radii 3/14/24")
+    plan = bf.BatchPlan(imgs, ss, sr, 20, spatial="fir")
+    outs = [to_np(o) for o in plan.run()]
+    ref = singles(bf, imgs, ss, sr, spatial="fir")
+    for i in range(len(imgs)):
+        assert np.array_equal(outs[i], ref[i]), i
+        assert np.max(np.abs(outs[i] - oracle_gp(host[i], ss[i], sr[i], 20, "fir"))) <= 1e-3
 
 
 def test_small_uneven_batch(bf):
@@ -37,7 +53,7 @@ def test_small_uneven_batch(bf):
     for i in range(len(imgs)):
         assert np.array_equal(outs[i], ref[i]), (i, np.max(np.abs(outs[i] - ref[i])))
     for i in (0, 1, 3, 4):
-        mode = bf.resolve_spatial(ss[i]) if bf.fir_radius(ss[i]) <= 12 else "iir"
+        mode = bf.resolve_spatial(ss[i], shape=host[i].shape)
         assert np.max(np.abs(outs[i] - oracle_gp(host[i], ss[i], sr[i], 20, mode))) <= 1e-3
 
 
@@ -62,7 +78,7 @@ def test_uneven_batch_64(bf):
     # sampled oracle check on three images
     for i in (0, 17, 40):
         H, W = host[i].shape
-        mode = bf.resolve_spatial(ss[i]) if bf.fir_radius(ss[i]) <= 12 else "iir"
+        mode = bf.resolve_spatial(ss[i], shape=host[i].shape)
         for (y, x) in [(0, 0), (H // 2, W // 3)]:
             ref1 = oracle_gp_at(host[i], y, x, ss[i], sr[i], 20, mode)
             assert abs(outs[i][y, x] - ref1) <= 1e-3, (i, y, x)
