@@ -257,7 +257,7 @@ int bf_gp_plan_batched(const bf_gp_item *items, int count, unsigned flags, void 
         off = al(off + sizeof(Stats));
         for (int b = 0; b < nparts; ++b) per[kStStats].push_back({i, b});
         if (!iir) {
-            const int tiles = ((it.W + 63) / 64) * ((it.H + 31) / 32);
+            const int tiles = ((it.W + kFirTX - 1) / kFirTX) * ((it.H + fir_ty(R) - 1) / fir_ty(R));
             const int wide = R > kBatchFirSplit;
             for (int t = 0; t < tiles; ++t) per[wide ? kStFirWide : kStFir].push_back({i, t});
             fir_smem[wide] = std::max(fir_smem[wide], sizeof(float) * (size_t)fir_smem_floats(R));

@@ -203,6 +203,14 @@ __device__ __forceinline__ float gauss_u0(float x, int shift) {
     return ldexpf(exp2f((float)(a - ah)), (int)ah);
 }
 
+// Scale exponent used when exp(-x^2/2) would leave the FP32 range (|x| > 12):
+// the channel is carried as uh = u * 2^s (u_0 = gauss_u0(x, s) stays near
+// 2^-60) and u is recovered as uh * 2^-s.
+__device__ __forceinline__ int big_shift(float x) {
+    const float t = x * x;
+    return t > 144.f ? (int)(t * 0.72134752f) - 60 : 0;
+}
+
 // x = (f - t_c) / sigma_r, computed in double and rounded once to float.
 __device__ __forceinline__ float centred(float f, const Stats &st, double inv_sr) {
     return (float)(((double)f - st.tc) * inv_sr);

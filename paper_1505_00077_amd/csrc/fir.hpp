@@ -17,27 +17,37 @@
 
 namespace bfgp {
 
-template <int R>
+// Output tile of the FIR kernels: 64 columns by fir_ty(R, save) rows.
+// 16-row tiles give twice the workgroups and fewer registers per thread; they
+// were measured faster except for radii 10..17 without the saved terms, where
+// the halo rows of a 16-row tile cost more than the extra parallelism gains.
+// With the saved terms (more accumulators) 16 rows keep two waves per SIMD.
+constexpr int kFirTX = 64;
+__host__ __device__ constexpr int fir_ty(int R, bool save = false) {
+    return (!save && R >= 10 && R <= 17) ? 32 : 16;
+}
+
+template <int R, bool SAVE = false>
 struct FirShape {
-    static constexpr int TY = 32, TX = 64;       // output tile
+    static constexpr int TY = fir_ty(R, SAVE), TX = kFirTX;  // output tile
     static constexpr int RY = TY + 2 * R, RX = TX + 2 * R;
     static constexpr int REG = RY * RX;           // region elements
     static constexpr int PER = (REG + kBlock - 1) / kBlock;
     static constexpr int SV = 4;                  // column-pass outputs per item
     static constexpr int BP = RX + 1;             // odd pitch of the row-pass input
-    static constexpr int PX = 8;                  // output pixels per thread
+    static constexpr int PX = TY * TX / kBlock;   // output pixels per thread (one row segment)
     static constexpr int SMEM_FLOATS = REG + TY * BP;
 };
 
 // Number of LDS floats needed by fir_tile<R>.
-__host__ __device__ constexpr int fir_smem_floats(int R) {
-    return (32 + 2 * R) * (64 + 2 * R) + 32 * (64 + 2 * R + 1);
+__host__ __device__ constexpr int fir_smem_floats(int R, bool save = false) {
+    return (fir_ty(R, save) + 2 * R) * (kFirTX + 2 * R) + fir_ty(R, save) * (kFirTX + 2 * R + 1);
 }
 
 template <int R, bool SAVE>
 __device__ __forceinline__ void fir_tile(const GPParams &p, const FirTaps &taps, const Stats &st,
                                          int ty0, int tx0, float *smem) {
-    using S = FirShape<R>;
+    using S = FirShape<R, SAVE>;
     float *A = smem;             // region, RY x RX
     float *B = smem + S::REG;    // column-pass output, TY x BP
     const int tid = threadIdx.x;
@@ -65,13 +75,15 @@ __device__ __forceinline__ void fir_tile(const GPParams &p, const FirTaps &taps,
         const bool in = e < S::REG && gy >= 0 && gy < p.H && gx >= 0 && gx < p.W;
         const float x = in ? centred(xr[i], st, p.inv_sigma_r) : 0.f;
         xr[i] = x;
-        u[i] = in ? (double)gauss_u0(x, 0) : 0.0;
+        // exp(-x^2/2) formed with a range shift and taken to double exactly,
+        // so that it does not underflow where |x| > 13 (double carries it)
+        const int sh = big_shift(x);
+        u[i] = in ? ldexp((double)gauss_u0(x, sh), -sh) : 0.0;
     }
 
-    // ---- output ownership: row y, 8 consecutive columns from x0 ----
-    const int lane = tid & 63, wave = tid >> 6;
-    const int oy = lane & 31;
-    const int ox0 = ((lane >> 5) + 2 * wave) * S::PX;
+    // ---- output ownership: row oy, PX consecutive columns from ox0 ----
+    const int oy = tid % S::TY;
+    const int ox0 = (tid / S::TY) * S::PX;
     double tau[S::PX], Dp[S::PX], Mp[S::PX], pw[S::PX];
     double Dt[SAVE ? S::PX : 1], Mt[SAVE ? S::PX : 1], pm[SAVE ? S::PX : 1];
     {
@@ -147,25 +159,38 @@ __device__ __forceinline__ void fir_tile(const GPParams &p, const FirTaps &taps,
                 }
             }
         }
-        // 4. recombination, double precision
+        // 4. recombination, double precision.  Channel 0 only starts D'
+        // (p_0 = 1) and channel N+1 only enters M': uniform branches, so that
+        // the common case carries no per-pixel selects.
         const double sqn = p.sq[n];
         const double sqm = n >= 1 ? p.sq[n - 1] : 0.0;
-        const bool inD = n <= p.N;
+        if (n >= 1 && n <= p.N) {
 #pragma unroll
-        for (int i = 0; i < S::PX; ++i) {
-            const double ub = (double)h[i];
-            if (n >= 1) {
+            for (int i = 0; i < S::PX; ++i) {
+                const double ub = (double)h[i];
                 const double q = pw[i] * sqn;  // sqrt(n) p_{n-1}
                 Mp[i] = fma(q, ub, Mp[i]);
                 if (SAVE) {
-                    if (inD) Dt[i] = fma(q, ub, Dt[i]);
+                    Dt[i] = fma(q, ub, Dt[i]);
                     Mt[i] = fma(sqn * sqm * pm[i], ub, Mt[i]);
+                    pm[i] = pw[i];
                 }
-            }
-            if (inD) {
-                if (SAVE) pm[i] = pw[i];
-                pw[i] = (n == 0) ? 1.0 : pw[i] * tau[i] * isq;
+                pw[i] = pw[i] * tau[i] * isq;
                 Dp[i] = fma(pw[i], ub, Dp[i]);
+            }
+        } else if (n == 0) {
+#pragma unroll
+            for (int i = 0; i < S::PX; ++i) {
+                if (SAVE) pm[i] = pw[i];
+                pw[i] = 1.0;
+                Dp[i] = fma(pw[i], (double)h[i], Dp[i]);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < S::PX; ++i) {
+                const double ub = (double)h[i];
+                Mp[i] = fma(pw[i] * sqn, ub, Mp[i]);
+                if (SAVE) Mt[i] = fma(sqn * sqm * pm[i], ub, Mt[i]);
             }
         }
     }

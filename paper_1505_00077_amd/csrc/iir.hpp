@@ -34,13 +34,6 @@ struct IirCoef {
     float phiW[2][4];     // Phi^(64 L)
 };
 
-// Scale exponent used when exp(-x^2/2) would leave the FP32 range: the channel
-// is carried as uh = u * 2^s and stored as u = uh * 2^-s.
-__device__ __forceinline__ int big_shift(float x) {
-    const float t = x * x;
-    return t > 144.f ? (int)(t * 0.72134752f) - 60 : 0;
-}
-
 // One band of B rows in one column.  AGG: run from rest, write the band's end
 // states (causal end, anticausal start).  !AGG: run from the resolved
 // incoming states and write the column-filtered channel stack S[n][row][col].

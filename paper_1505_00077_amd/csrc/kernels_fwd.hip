@@ -18,7 +18,7 @@ __global__ __launch_bounds__(kBlock) void k_fir(GPParams p, FirTaps taps) {
     extern __shared__ float smem[];
     const Stats st = reduce_stats(p);
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) publish_stats(p, st);
-    fir_tile<R, SAVE>(p, taps, st, blockIdx.y * FirShape<R>::TY, blockIdx.x * FirShape<R>::TX, smem);
+    fir_tile<R, SAVE>(p, taps, st, blockIdx.y * FirShape<R, SAVE>::TY, blockIdx.x * FirShape<R, SAVE>::TX, smem);
 }
 
 __global__ __launch_bounds__(kBlock) void k_direct(DirectArgs a) {
@@ -80,16 +80,17 @@ hipError_t launch_stats(const GPParams &p, bool final_kernel, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int R, bool SAVE>
+static hipError_t fir_launch_rs(const GPParams &p, const FirTaps &t, hipStream_t s) {
+    using S = FirShape<R, SAVE>;
+    dim3 grid((p.W + S::TX - 1) / S::TX, (p.H + S::TY - 1) / S::TY);
+    BF_LAUNCH("k_fir", (k_fir<R, SAVE>), grid, dim3(kBlock), sizeof(float) * S::SMEM_FLOATS, s, p, t);
+    return hipGetLastError();
+}
+
 template <int R>
 static hipError_t fir_launch_r(const GPParams &p, const FirTaps &t, bool save, hipStream_t s) {
-    using S = FirShape<R>;
-    dim3 grid((p.W + S::TX - 1) / S::TX, (p.H + S::TY - 1) / S::TY);
-    const size_t sm = sizeof(float) * S::SMEM_FLOATS;
-    if (save)
-        BF_LAUNCH("k_fir", (k_fir<R, true>), grid, dim3(kBlock), sm, s, p, t);
-    else
-        BF_LAUNCH("k_fir", (k_fir<R, false>), grid, dim3(kBlock), sm, s, p, t);
-    return hipGetLastError();
+    return save ? fir_launch_rs<R, true>(p, t, s) : fir_launch_rs<R, false>(p, t, s);
 }
 
 hipError_t launch_fir(const GPParams &p, const FirTaps &t, int R, bool save, hipStream_t s) {
