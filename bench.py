@@ -81,6 +81,30 @@ def step_model(kernel, C, band, fir_radii, n_iir, n_calls, HW):
     return per[0] * HW, per[1] * HW
 
 
+def launch_ids(stage, bf, H, W, C, fir_radii):
+    """(kernel instantiation, grid threads) of every launch of `stage` in one
+    step, as the counter files name them."""
+    if stage == "k_fir":
+        return [(f"k_fir<{r}, false>", ((W + 63) // 64) * ((H + fir_ty(r) - 1) // fir_ty(r)) * 256)
+                for r in fir_radii]
+    sh = bf.iir_shape(H, W, C - 2)
+    B, G, L, T, Gr = sh["band_rows"], sh["col_groups"], sh["row_chunk"], sh["row_threads"], sh["row_groups"]
+    P = ((T * L + 2 + 31) // 32) * 32
+    nb = (H + B - 1) // B
+    return {
+        "k_hrow": [(f"k_hrow<{L}>", H * T * Gr)],
+        "k_vband": [(f"k_vband<{B}, false>", ((P + 63) // 64) * nb * G * 64)],
+        "k_vband_agg": [(f"k_vband<{B}, true>", ((P + 63) // 64) * nb * G * 64)],
+        "k_vresolve": [("k_vresolve", ((W + 255) // 256) * 256 * C * 2)],
+        "k_stats": [("k_stats", min(H, 256) * 256)],
+    }.get(stage, [])
+
+
+def fir_ty(r):
+    """Rows of the FIR output tile for radius r (forward without saved terms)."""
+    return 32 if 10 <= r <= 17 else 16
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -168,8 +192,8 @@ def main():
     # measured HBM traffic of the same kernel (rocprofv3 FETCH_SIZE + WRITE_SIZE,
     # calibrated by a device copy), valid only for the sources it was taken with
     from paper_1505_00077_amd import profiling
-    traffic = profiling.traffic_for(os.path.join(ROOT, "profiles", "traffic_counters.json"), kname,
-                                    stage_t[kname][2])
+    traffic = profiling.traffic_for(os.path.join(ROOT, "profiles", "traffic_counters.json"),
+                                    launch_ids(kname, bf, H, W, C, fir_radii))
     common = {"kernel": kname, "traffic": (traffic / (avg_ms * 1e-3) / 1e9) if traffic else None,
               "traffic_bytes_per_launch": traffic,
               "algorithmic_bytes_per_launch": bytes_step * per_launch if bytes_step else None,

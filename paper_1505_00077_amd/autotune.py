@@ -11,7 +11,7 @@ for a given radius therefore depends on the image size and the device.
 each size the largest radius at which FIR is still faster (the FIR time rises
 with the radius, so a bisection over radii suffices), installs the result in
 the library as its size-dependent crossover table and stores it in a JSON
-cache keyed by device name and degree.  `ensure()` loads the cached table, or
+cache keyed by device architecture, compute-unit count and degree.  `ensure()` loads the cached table, or
 tunes once when there is none.  Timing uses synthetic images on the device;
 the filter's cost does not depend on the pixel values.
 """
@@ -32,7 +32,11 @@ def cache_path():
 
 
 def _key(device, N):
-    return f"{torch.cuda.get_device_name(device)}|N={N}"
+    # architecture and compute-unit count identify the device class (the
+    # marketing name is not always reported, e.g. under a profiler)
+    props = torch.cuda.get_device_properties(device)
+    arch = getattr(props, "gcnArchName", "") or props.name
+    return f"{arch}|{props.multi_processor_count}CU|N={N}"
 
 
 def _time_ms(fn, reps, warmup=2):

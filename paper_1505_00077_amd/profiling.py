@@ -63,27 +63,72 @@ def counter_summary(fetch_csv, write_csv, copy_bytes, copy_kernel="__amd_rocclr_
             "per_dispatch": out}
 
 
-# profiling stage name -> kernel instantiation name prefix in counter files
-STAGE_KERNELS = {
-    "k_vband_agg": "k_vband<64, true, false>", "k_vband_agg_big": "k_vband<64, true, true>",
-    "k_vband": "k_vband<64, false, false>", "k_vband_big": "k_vband<64, false, true>",
-    "k_hrow": "k_hrow<", "k_fir": "k_fir<", "k_bwd": "k_bwd<",
-}
-
-
-def traffic_for(summary_path, stage, grid):
-    """Calibrated HBM bytes (fetch + write) per dispatch of the kernel behind
-    profiling stage `stage` launched with `grid` threads, or None when absent
-    or taken with other kernel sources."""
+def traffic_for(summary_path, launches):
+    """Mean calibrated HBM bytes (fetch + write) per dispatch over `launches`,
+    a list of (kernel instantiation name as in the counter files, grid size in
+    threads); None when any of them is absent or the summary was taken with
+    other kernel sources."""
     try:
-        s = json.load(open(summary_path))
+        with open(summary_path) as f:
+            s = json.load(f)
     except (OSError, ValueError):
         return None
-    if s.get("fingerprint") != source_fingerprint():
+    if s.get("fingerprint") != source_fingerprint() or not launches:
         return None
-    want = STAGE_KERNELS.get(stage, stage)
-    for key, v in s["per_dispatch"].items():
-        name, g = key.rsplit("@", 1)
-        if int(g) == grid and (name == want or name.startswith(want)):
-            return v["fetch_bytes"] + v["write_bytes"]
-    return None
+    vals = []
+    for name, grid in launches:
+        v = s["per_dispatch"].get(f"{name}@{int(grid)}")
+        if v is None:
+            return None
+        vals.append(v["fetch_bytes"] + v["write_bytes"])
+    return sum(vals) / len(vals)
+
+
+def kernel_stats_table(stats_csv, top=12):
+    """Markdown table of a rocprofv3 `--stats` kernel summary (name, calls,
+    average and total duration), the `top` kernels by total time."""
+    rows = list(csv.DictReader(open(stats_csv)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = ["| kernel | calls | avg us | total us | share |", "|---|---:|---:|---:|---:|"]
+    for r in rows[:top]:
+        out.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                   f"{float(r['TotalDurationNs']) / 1e3:.1f} | {float(r['Percentage']):.1f}% |")
+    return "\n".join(out)
+
+
+def kernel_trace_table(trace_csv, top=16):
+    """Markdown table of a rocprofv3 `--kernel-trace` CSV grouped by kernel
+    and grid size (calls, average and total duration), by total time."""
+    per = defaultdict(list)
+    for r in csv.DictReader(open(trace_csv)):
+        grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+        per[(_short(r["Kernel_Name"]), grid)].append(
+            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    total = sum(sum(v) for v in per.values())
+    rows = sorted(per.items(), key=lambda kv: -sum(kv[1]))
+    out = ["| kernel | grid | calls | avg us | total us | share |", "|---|---:|---:|---:|---:|---:|"]
+    for (name, grid), v in rows[:top]:
+        out.append(f"| `{name}` | {grid} | {len(v)} | {sum(v) / len(v):.2f} | {sum(v):.1f} | "
+                   f"{100 * sum(v) / total:.1f}% |")
+    return "\n".join(out)
+
+
+def main(argv):
+    """python -m paper_1505_00077_amd.profiling counters FETCH.csv WRITE.csv COPY_BYTES
+       python -m paper_1505_00077_amd.profiling stats KERNEL_STATS.csv
+       python -m paper_1505_00077_amd.profiling trace KERNEL_TRACE.csv"""
+    if len(argv) >= 4 and argv[0] == "counters":
+        print(json.dumps(counter_summary(argv[1], argv[2], int(argv[3])), indent=1))
+    elif len(argv) >= 2 and argv[0] == "stats":
+        print(kernel_stats_table(argv[1]))
+    elif len(argv) >= 2 and argv[0] == "trace":
+        print(kernel_trace_table(argv[1]))
+    else:
+        print(main.__doc__)
+        return 2
+    return 0
+
+
+if __name__ == "__main__":
+    import sys
+    sys.exit(main(sys.argv[1:]))
