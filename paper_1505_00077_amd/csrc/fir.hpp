@@ -5,13 +5,14 @@
 //   1. every thread updates its share of the (TY+2R) x (TX+2R) input region,
 //      u_n = u_{n-1} * x / sqrt(n) (double), and stores it to LDS as float;
 //   2. the column pass of eq. (8): B = k (*) A along y, (TY) x (TX+2R);
-//   3. the row pass of eq. (8): Ubar_n at the thread's 8 output pixels;
+//   3. the row pass of eq. (8): Ubar_n at the thread's PX output pixels;
 //   4. the recombination of eqs. (9)-(11) as power sums in tau (double):
 //        D' += p_n Ubar_n (n <= N),  M' += sqrt(n) p_{n-1} Ubar_n (n >= 1),
 //      p_n = tau^n / sqrt(n!).  D' = exp(tau^2/2) D and M' = exp(tau^2/2) M,
 //      so M'/D' = M/D.
-// The channel buffer never leaves the chip: HBM traffic is the input region
-// and the output tile.
+// Steps 1-2 and 3-4 each run for CH channels between barriers.  The channel
+// buffer never leaves the chip: HBM traffic is the input region and the
+// output tile.
 #pragma once
 #include "common.hpp"
 
@@ -27,6 +28,13 @@ __host__ __device__ constexpr int fir_ty(int R, bool save = false) {
     return (!save && R >= 10 && R <= 17) ? 32 : 16;
 }
 
+// Channels processed between two barrier pairs: two (twice the independent
+// work per barrier) where the LDS stages of two channels fit in 64 KB.
+__host__ __device__ constexpr int fir_ch(int R, bool save = false) {
+    return (!save && 2 * ((fir_ty(R) + 2 * R) * (kFirTX + 2 * R) + fir_ty(R) * (kFirTX + 2 * R + 1)) <= 16384)
+               ? 2 : 1;
+}
+
 template <int R, bool SAVE = false>
 struct FirShape {
     static constexpr int TY = fir_ty(R, SAVE), TX = kFirTX;  // output tile
@@ -36,20 +44,25 @@ struct FirShape {
     static constexpr int SV = 4;                  // column-pass outputs per item
     static constexpr int BP = RX + 1;             // odd pitch of the row-pass input
     static constexpr int PX = TY * TX / kBlock;   // output pixels per thread (one row segment)
-    static constexpr int SMEM_FLOATS = REG + TY * BP;
+    static constexpr int CH = fir_ch(R, SAVE);    // channels per barrier pair
+    static constexpr int STAGE = REG + TY * BP;   // LDS floats per channel
+    static constexpr int SMEM_FLOATS = CH * STAGE;
 };
 
 // Number of LDS floats needed by fir_tile<R>.
 __host__ __device__ constexpr int fir_smem_floats(int R, bool save = false) {
-    return (fir_ty(R, save) + 2 * R) * (kFirTX + 2 * R) + fir_ty(R, save) * (kFirTX + 2 * R + 1);
+    return fir_ch(R, save) *
+           ((fir_ty(R, save) + 2 * R) * (kFirTX + 2 * R) + fir_ty(R, save) * (kFirTX + 2 * R + 1));
 }
 
 template <int R, bool SAVE>
 __device__ __forceinline__ void fir_tile(const GPParams &p, const FirTaps &taps, const Stats &st,
                                          int ty0, int tx0, float *smem) {
     using S = FirShape<R, SAVE>;
-    float *A = smem;             // region, RY x RX
-    float *B = smem + S::REG;    // column-pass output, TY x BP
+    // stage c (one per channel in flight): region A_c (RY x RX), then the
+    // column-pass output B_c (TY x BP)
+    auto A = [&](int c) { return smem + c * S::STAGE; };
+    auto Bc = [&](int c) { return smem + c * S::STAGE + S::REG; };
     const int tid = threadIdx.x;
 
     // ---- region: centred intensities and u_0 = exp(-x^2/2) ----
@@ -111,86 +124,107 @@ __device__ __forceinline__ void fir_tile(const GPParams &p, const FirTaps &taps,
         }
     }
 
-    for (int n = 0; n < p.C; ++n) {
-        // 1. channel n on the region
-        const double isq = p.isq[n];
+    for (int n0 = 0; n0 < p.C; n0 += S::CH) {
+        const int nc = p.C - n0 < S::CH ? p.C - n0 : S::CH;  // channels this round
+        // 1. channels n0 .. n0+nc-1 on the region
 #pragma unroll
-        for (int i = 0; i < S::PER; ++i) {
-            const int e = tid + i * kBlock;
-            if (e < S::REG) {
-                if (n > 0) u[i] *= (double)xr[i] * isq;
-                A[e] = (float)u[i];
+        for (int c = 0; c < S::CH; ++c) {
+            if (c < nc) {
+                const int n = n0 + c;
+                const double isq = p.isq[n];
+                float *Ac = A(c);
+#pragma unroll
+                for (int i = 0; i < S::PER; ++i) {
+                    const int e = tid + i * kBlock;
+                    if (e < S::REG) {
+                        if (n > 0) u[i] *= (double)xr[i] * isq;
+                        Ac[e] = (float)u[i];
+                    }
+                }
             }
         }
         __syncthreads();
         // 2. column pass
         for (int it = tid; it < S::RX * (S::TY / S::SV); it += kBlock) {
             const int xx = it % S::RX, sy = it / S::RX;
-            const float *col = A + sy * S::SV * S::RX + xx;
-            float acc[S::SV];
 #pragma unroll
-            for (int i = 0; i < S::SV; ++i) acc[i] = 0.f;
+            for (int c = 0; c < S::CH; ++c) {
+                if (c < nc) {
+                    const float *col = A(c) + sy * S::SV * S::RX + xx;
+                    float acc[S::SV];
 #pragma unroll
-            for (int j = 0; j < S::SV + 2 * R; ++j) {
-                const float v = col[j * S::RX];
+                    for (int i = 0; i < S::SV; ++i) acc[i] = 0.f;
 #pragma unroll
-                for (int i = 0; i < S::SV; ++i) {
-                    const int d = j - i;
-                    if (d >= 0 && d <= 2 * R) acc[i] = fmaf(taps.k[d >= R ? d - R : R - d], v, acc[i]);
+                    for (int j = 0; j < S::SV + 2 * R; ++j) {
+                        const float v = col[j * S::RX];
+#pragma unroll
+                        for (int i = 0; i < S::SV; ++i) {
+                            const int d = j - i;
+                            if (d >= 0 && d <= 2 * R) acc[i] = fmaf(taps.k[d >= R ? d - R : R - d], v, acc[i]);
+                        }
+                    }
+                    float *Bo = Bc(c);
+#pragma unroll
+                    for (int i = 0; i < S::SV; ++i) Bo[(sy * S::SV + i) * S::BP + xx] = acc[i];
                 }
             }
-#pragma unroll
-            for (int i = 0; i < S::SV; ++i) B[(sy * S::SV + i) * S::BP + xx] = acc[i];
         }
         __syncthreads();
-        // 3. row pass at the owned pixels
-        float h[S::PX];
+        // 3. row pass at the owned pixels, 4. recombination per channel
 #pragma unroll
-        for (int i = 0; i < S::PX; ++i) h[i] = 0.f;
-        {
-            const float *row = B + oy * S::BP + ox0;
+        for (int c = 0; c < S::CH; ++c) {
+            if (c < nc) {
+                const int n = n0 + c;
+                float h[S::PX];
 #pragma unroll
-            for (int j = 0; j < S::PX + 2 * R; ++j) {
-                const float v = row[j];
+                for (int i = 0; i < S::PX; ++i) h[i] = 0.f;
+                {
+                    const float *row = Bc(c) + oy * S::BP + ox0;
 #pragma unroll
-                for (int i = 0; i < S::PX; ++i) {
-                    const int d = j - i;
-                    if (d >= 0 && d <= 2 * R) h[i] = fmaf(taps.k[d >= R ? d - R : R - d], v, h[i]);
+                    for (int j = 0; j < S::PX + 2 * R; ++j) {
+                        const float v = row[j];
+#pragma unroll
+                        for (int i = 0; i < S::PX; ++i) {
+                            const int d = j - i;
+                            if (d >= 0 && d <= 2 * R) h[i] = fmaf(taps.k[d >= R ? d - R : R - d], v, h[i]);
+                        }
+                    }
                 }
-            }
-        }
-        // 4. recombination, double precision.  Channel 0 only starts D'
-        // (p_0 = 1) and channel N+1 only enters M': uniform branches, so that
-        // the common case carries no per-pixel selects.
-        const double sqn = p.sq[n];
-        const double sqm = n >= 1 ? p.sq[n - 1] : 0.0;
-        if (n >= 1 && n <= p.N) {
+                // recombination, double precision.  Channel 0 only starts D'
+                // (p_0 = 1) and channel N+1 only enters M': uniform branches,
+                // so that the common case carries no per-pixel selects.
+                const double isq = p.isq[n];
+                const double sqn = p.sq[n];
+                const double sqm = n >= 1 ? p.sq[n - 1] : 0.0;
+                if (n >= 1 && n <= p.N) {
 #pragma unroll
-            for (int i = 0; i < S::PX; ++i) {
-                const double ub = (double)h[i];
-                const double q = pw[i] * sqn;  // sqrt(n) p_{n-1}
-                Mp[i] = fma(q, ub, Mp[i]);
-                if (SAVE) {
-                    Dt[i] = fma(q, ub, Dt[i]);
-                    Mt[i] = fma(sqn * sqm * pm[i], ub, Mt[i]);
-                    pm[i] = pw[i];
+                    for (int i = 0; i < S::PX; ++i) {
+                        const double ub = (double)h[i];
+                        const double q = pw[i] * sqn;  // sqrt(n) p_{n-1}
+                        Mp[i] = fma(q, ub, Mp[i]);
+                        if (SAVE) {
+                            Dt[i] = fma(q, ub, Dt[i]);
+                            Mt[i] = fma(sqn * sqm * pm[i], ub, Mt[i]);
+                            pm[i] = pw[i];
+                        }
+                        pw[i] = pw[i] * tau[i] * isq;
+                        Dp[i] = fma(pw[i], ub, Dp[i]);
+                    }
+                } else if (n == 0) {
+#pragma unroll
+                    for (int i = 0; i < S::PX; ++i) {
+                        if (SAVE) pm[i] = pw[i];
+                        pw[i] = 1.0;
+                        Dp[i] = fma(pw[i], (double)h[i], Dp[i]);
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < S::PX; ++i) {
+                        const double ub = (double)h[i];
+                        Mp[i] = fma(pw[i] * sqn, ub, Mp[i]);
+                        if (SAVE) Mt[i] = fma(sqn * sqm * pm[i], ub, Mt[i]);
+                    }
                 }
-                pw[i] = pw[i] * tau[i] * isq;
-                Dp[i] = fma(pw[i], ub, Dp[i]);
-            }
-        } else if (n == 0) {
-#pragma unroll
-            for (int i = 0; i < S::PX; ++i) {
-                if (SAVE) pm[i] = pw[i];
-                pw[i] = 1.0;
-                Dp[i] = fma(pw[i], (double)h[i], Dp[i]);
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < S::PX; ++i) {
-                const double ub = (double)h[i];
-                Mp[i] = fma(pw[i] * sqn, ub, Mp[i]);
-                if (SAVE) Mt[i] = fma(sqn * sqm * pm[i], ub, Mt[i]);
             }
         }
     }
