@@ -283,11 +283,15 @@ def main():
                 bf.gp_forward(x, s_, r_, DEGREE, out=o, ws=w)
 
         ms_seq = timed(seq, K, Wm, torch)
+        bf.profile_enable(True)  # per-stage durations of the batched launches (eager, with events)
+        timed(plan_b.run, K, 0, torch)
+        bstages = {k: v[1] / K for k, v in sorted(bf.profile_collect().items())}
+        bf.profile_enable(False)
         worst = max(float((a - b).abs().max()) for a, b in zip(plan_b.outs, souts))
         modes["batched_64"] = {"images": len(bimgs), "megapixels": npx / 1e6, "ms_graph": ms_graph,
                                "mpix_s_graph": npx / (ms_graph * 1e-3) / 1e6, "ms_sequential": ms_seq,
                                "mpix_s_sequential": npx / (ms_seq * 1e-3) / 1e6,
-                               "max_abs_diff_vs_sequential": worst,
+                               "max_abs_diff_vs_sequential": worst, "stages_ms": bstages,
                                "plans": {m: sum(1 for x, s_ in zip(bimgs, bss)
                                                 if bf.resolve_spatial(s_, shape=x.shape) == m) for m in ("fir", "iir")}}
         log(f"batched: graph {ms_graph:.3f} ms, sequential {ms_seq:.3f} ms")

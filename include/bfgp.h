@@ -161,10 +161,13 @@ int bf_gp_backward(const float *img, const float *grad_out, const void *saved,
  * bf_gp_plan_upload copies the plan's descriptors into the workspace (once,
  * outside any graph capture, synchronising `stream`); bf_gp_forward_batched
  * then only launches kernels and may be captured into a hipGraph and replayed.
- * Each image gets the spatial mode and launch shape a single bf_gp_forward
- * call would give it (the AUTO crossover table and the IIR tuning overrides
- * are read when the plan is built), and its output is bit-identical to that
- * call's.  Images are limited to 8192 columns (the IIR limit). */
+ * Each image gets the spatial mode a single bf_gp_forward call would give it
+ * (the AUTO crossover table is read when the plan is built).  The batch fills
+ * the device by itself, so its IIR images are not split into channel groups:
+ * each image's output is bit-identical to a single call made under
+ * bf_gp_set_iir_tuning(0, 1, 1) (with other tuning overrides, under the same
+ * overrides), and differs from a default single call only in rounding.
+ * Images are limited to 8192 columns (the IIR limit). */
 typedef struct bf_gp_item {
     const float *img; /* device, H x W, row pitch `pitch` elements */
     float *out;       /* device, same shape and pitch */

@@ -271,7 +271,7 @@ BwdLayout bwd_layout(int H, int W) {
 
 // Helpers shared with the batched path (batched.hip).
 namespace bfgp {
-IirShape iir_shape(int H, int W, int C) {
+IirShape iir_shape(int H, int W, int C, bool batch) {
     IirShape sh;
     const long cols = (W + 63) / 64;  // one wave per 64 columns of one band
     // band height: 32 rows (measured faster than 64 at every size: more waves
@@ -283,6 +283,7 @@ IirShape iir_shape(int H, int W, int C) {
     // generation up to its first channel, so only images with too few waves
     // are split
     int G = g_col_groups.load();
+    if (G < 1 && batch) G = 1;
     if (G < 1) {
         const long waves = cols * ((H + B - 1) / B);
         G = (int)((kTargetWaves + waves - 1) / waves);
@@ -303,6 +304,7 @@ IirShape iir_shape(int H, int W, int C) {
             break;
         }
     int Gr = g_row_groups.load();
+    if (Gr < 1 && batch) Gr = 1;
     if (Gr < 1) {
         const long waves = (long)H * (sh.T / 64);
         Gr = (int)((kTargetWaves + waves - 1) / waves);

@@ -25,11 +25,11 @@
 
 namespace bfgp {
 
-// kStRow + k: row items whose workgroup has 64 << k threads (k = 0..3)
+// kStRow + k: row items whose workgroup has 64 (k + 1) threads (k = 0..7)
 // kStFir: FIR images with radius up to kBatchFirSplit; kStFirWide: the rest
 // (separate launches, so that wide radii do not set the register budget of
 // narrow ones)
-enum { kStStats = 0, kStFir, kStFirWide, kStAgg, kStResolve, kStBand, kStRow, kNumStages = kStRow + 4 };
+enum { kStStats = 0, kStFir, kStFirWide, kStAgg, kStResolve, kStBand, kStRow, kNumStages = kStRow + 8 };
 constexpr int kBatchFirSplit = 12;
 // same partial count as the single-image path, so that both reduce the image
 // sum in the same order and produce bit-identical centres and outputs
@@ -170,7 +170,7 @@ struct Plan {
     std::vector<IirShape> shape;
     size_t off_imgs, off_items, total;
     std::vector<size_t> off_parts, off_status, off_stats, off_carry, off_S;
-    size_t fir_smem[2], row_smem[4];
+    size_t fir_smem[2], row_smem[8];
     int band_rows;
     unsigned flags;
     bool uploaded;
@@ -238,7 +238,7 @@ int bf_gp_plan_batched(const bf_gp_item *items, int count, unsigned flags, void 
     P->iir.resize(count);
     P->R.resize(count);
     P->shape.assign(count, IirShape{64, 1, 16, 64, 1});
-    size_t row_smem[4] = {0, 0, 0, 0};
+    size_t row_smem[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     P->band_rows = 32;
     for (int i = 0; i < count; ++i) {
         const bf_gp_item &it = items[i];
@@ -264,7 +264,7 @@ int bf_gp_plan_batched(const bf_gp_item *items, int count, unsigned flags, void 
             P->off_carry[i] = P->off_S[i] = 0;
         } else {
             const size_t C = (size_t)it.N + 2;
-            const IirShape sh = iir_shape(it.H, it.W, (int)C);
+            const IirShape sh = iir_shape(it.H, it.W, (int)C, true);
             P->shape[i] = sh;
             P->band_rows = sh.B;  // the same for every image
             const int nb = (it.H + sh.B - 1) / sh.B;
@@ -274,8 +274,7 @@ int bf_gp_plan_batched(const bf_gp_item *items, int count, unsigned flags, void 
             off = al(off + sizeof(float) * C * (size_t)sh.Hs * sh.P);
             const int ncg = (sh.P + 63) / 64;
             const int G = sh.G;
-            int cls = 0;
-            while ((64 << cls) < sh.T * sh.Gr) ++cls;
+            const int cls = sh.T * sh.Gr / 64 - 1;  // T * Gr is a multiple of 64, at most 512
             row_smem[cls] = std::max(row_smem[cls], hrow_smem_bytes(sh.T, sh.Gr, sh.L));
             for (int t = 0; t < nb * ncg * G; ++t) per[kStAgg].push_back({i, t});
             const int ng = (it.W + kBlock - 1) / kBlock;
@@ -294,7 +293,7 @@ int bf_gp_plan_batched(const bf_gp_item *items, int count, unsigned flags, void 
     P->total = off;
     P->fir_smem[0] = fir_smem[0];
     P->fir_smem[1] = fir_smem[1];
-    for (int k = 0; k < 4; ++k) P->row_smem[k] = row_smem[k];
+    for (int k = 0; k < 8; ++k) P->row_smem[k] = row_smem[k];
     P->imgs.resize(count);
     *plan_out = P;
     return BF_OK;
@@ -376,9 +375,9 @@ int bf_gp_forward_batched(void *plan, void *ws, size_t ws_bytes, void *stream) {
             BF_LAUNCH("k_bband", (k_bband<32, false>), dim3(n(kStBand)), dim3(64), 0, s, imgs, at(kStBand));
         else
             BF_LAUNCH("k_bband", (k_bband<64, false>), dim3(n(kStBand)), dim3(64), 0, s, imgs, at(kStBand));
-        for (int k = 0; k < 4; ++k)
+        for (int k = 0; k < 8; ++k)
             if (n(kStRow + k))
-                BF_LAUNCH("k_brow", k_brow, dim3(n(kStRow + k)), dim3(64 << k), P->row_smem[k], s, imgs,
+                BF_LAUNCH("k_brow", k_brow, dim3(n(kStRow + k)), dim3(64 * (k + 1)), P->row_smem[k], s, imgs,
                           at(kStRow + k));
     }
     hipError_t e = hipGetLastError();

@@ -38,7 +38,9 @@ struct IirShape {
              // (columns W .. P-1 are zero)
     int Hs;  // rows per channel of the stack: H rounded up to a multiple of B
 };
-IirShape iir_shape(int H, int W, int C);
+// batch: the image is one of many filtered together, which fill the device by
+// themselves: no channel groups unless the tuning overrides ask for them.
+IirShape iir_shape(int H, int W, int C, bool batch = false);
 hipError_t launch_iir(const GPParams &p, const IirCoef &c, const IirShape &sh, float *carry, float *S,
                       hipStream_t s);
 hipError_t launch_direct(const DirectArgs &a, hipStream_t s);

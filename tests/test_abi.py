@@ -184,3 +184,15 @@ def test_crossover_table():
         bf.set_fir_crossover_table([])
         bf.set_fir_crossover(old)
     assert bf.get_fir_crossover_table() == []
+
+
+def test_workspace_follows_tuning_overrides():
+    # a batch plan and a workspace sized under one set of overrides: the
+    # forward refuses a workspace sized for fewer bands
+    try:
+        bf.set_iir_tuning(64, 0, 0)
+        small = bf.workspace_bytes(1000, 700, 20, 8.0, "iir")
+        bf.set_iir_tuning(32, 0, 0)
+        assert bf.workspace_bytes(1000, 700, 20, 8.0, "iir") > small
+    finally:
+        bf.set_iir_tuning(0, 0, 0)
