@@ -79,7 +79,8 @@ const char *bf_last_error(void);
  *  flags        BF_SPATIAL_* | BF_CENTER_*.
  *  saved        NULL, or a device buffer of 16*H*W bytes that receives what
  *               bf_gp_backward needs (per pixel: M/D and its tau-derivative as
- *               float, the rescaled denominator as double), planar.
+ *               float, the rescaled denominator as double), planar.  Either
+ *               spatial mode; the backward must use the same mode.
  *  ws, ws_bytes device workspace of at least bf_gp_workspace_bytes(...) bytes.
  * Intensities whose |x| is so large that the channels leave the FP32 range make
  * the output NaN and set BF_ERANGE in the workspace status (bf_gp_status). */
@@ -136,15 +137,20 @@ int bf_gp_iir_shape(int H, int W, int N, int *shape /* 5 ints, host */);
 /* ---- GP backward -------------------------------------------------------------
  * Adjoint of bf_gp_forward for a scalar loss L with upstream gradient
  * grad_out = dL/dout.  Derived by the chain rule through eqs. (7)-(11) and the
- * mean of Algorithm 1's first step; the spatial radius is held fixed when
- * differentiating in sigma_s.
+ * mean of Algorithm 1's first step.  The spatial filter is symmetric with
+ * zero extension, so its adjoint is itself: the adjoint channels are filtered
+ * by the forward's own kernel.  FIR mode: the radius ceil(3 sigma_s) is held
+ * fixed when differentiating in sigma_s.  IIR mode: the recursion is
+ * differentiated exactly in log sigma_s (a tangent recursion beside each
+ * section); the workspace then holds two transposed channel stacks
+ * (2 * (N+2) * W * ceil64(H) floats) and the band carries.
  *  saved              the buffer filled by bf_gp_forward with the same
- *                     image and parameters.
+ *                     image, parameters and spatial mode.
  *  grad_img           NULL or device H x W (pitch) float: dL/dimg.
  *  grad_log_sigma_s   NULL or device double: dL/d(log sigma_s) (overwritten).
  *  grad_log_sigma_r   NULL or device double: dL/d(log sigma_r) (overwritten).
- * Supported for BF_SPATIAL_FIR (and AUTO resolving to FIR) with centre mean or
- * none; other modes return BF_EUNSUPPORTED. */
+ * Supported for both spatial modes (AUTO resolves as in bf_gp_forward) with
+ * centre mean or none; the midrange centre returns BF_EUNSUPPORTED. */
 size_t bf_gp_backward_workspace_bytes(int H, int W, int N, double sigma_s, unsigned flags);
 
 int bf_gp_backward(const float *img, const float *grad_out, const void *saved,

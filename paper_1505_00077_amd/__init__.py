@@ -242,15 +242,16 @@ def saved_buffer(H, W, device="cuda"):
     return torch.empty(16 * H * W, dtype=torch.uint8, device=device)
 
 
-def backward_workspace(H, W, N, sigma_s, spatial="fir", device="cuda"):
+def backward_workspace(H, W, N, sigma_s, spatial="auto", device="cuda"):
     n = int(bf_gp_backward_workspace_bytes(int(H), int(W), int(N), float(sigma_s), _flags(spatial)))
     return torch.empty(max(n, 256), dtype=torch.uint8, device=device)
 
 
-def gp_backward(img, grad_out, saved, sigma_s, sigma_r, N=20, spatial="fir", center="mean", grad_img=True,
+def gp_backward(img, grad_out, saved, sigma_s, sigma_r, N=20, spatial="auto", center="mean", grad_img=True,
                 ws=None):
     """Adjoint of gp_forward.  Returns (dL/dimg or None, dL/dlog sigma_s, dL/dlog sigma_r) with the scalar
-    gradients as float64 CUDA tensors of shape (1,)."""
+    gradients as float64 CUDA tensors of shape (1,).  ``saved`` must come from a gp_forward call in the same
+    spatial mode (FIR or IIR; AUTO resolves the same way for the same image size and sigma_s)."""
     H, W, pitch = _image(img)
     gh, gw, gp = _image(grad_out, "grad_out")
     if (gh, gw, gp) != (H, W, pitch):
@@ -271,16 +272,20 @@ class GPFilterFn(torch.autograd.Function):
     """GP bilateral filter with learnable log sigma_s and log sigma_r.
 
     forward(img (H, W) or (B, H, W) float32 CUDA, log_ss, log_sr, N, spatial, center).
-    Both passes run in the library's kernels; the spatial radius ceil(3
-    sigma_s) is held fixed when differentiating in sigma_s.  The sigmas are read
-    on the host (one device-to-host copy when they are tensors)."""
+    Both passes run in the library's kernels.  The spatial mode is resolved
+    once per call (AUTO: by image size and sigma_s) and used by both passes;
+    in the FIR mode the radius ceil(3 sigma_s) is held fixed when
+    differentiating in sigma_s, in the IIR mode the recursive kernel is
+    differentiated exactly.  The sigmas are read on the host (one
+    device-to-host copy when they are tensors)."""
 
     @staticmethod
-    def forward(ctx, img, log_ss, log_sr, N=20, spatial="fir", center="mean"):
+    def forward(ctx, img, log_ss, log_sr, N=20, spatial="auto", center="mean"):
         ss = math.exp(float(log_ss))
         sr = math.exp(float(log_sr))
         batch = img if img.dim() == 3 else img.unsqueeze(0)
         B, H, W = batch.shape
+        spatial = resolve_spatial(ss, spatial, shape=(H, W))
         out = torch.empty_like(batch)
         saved = torch.empty(B, 16 * H * W, dtype=torch.uint8, device=img.device)
         ws = workspace(H, W, N, ss, spatial, img.device)
@@ -313,7 +318,7 @@ class GPFilterFn(torch.autograd.Function):
         return gimg, gss, gsr, None, None, None
 
 
-def gp_filter(img, log_ss, log_sr, N=20, spatial="fir", center="mean"):
+def gp_filter(img, log_ss, log_sr, N=20, spatial="auto", center="mean"):
     """Differentiable GP bilateral filter (see GPFilterFn)."""
     return GPFilterFn.apply(img, log_ss, log_sr, N, spatial, center)
 

@@ -15,6 +15,7 @@
 #include "iir.hpp"
 #include "direct.hpp"
 #include "bwd.hpp"
+#include "iir_bwd.hpp"
 
 using namespace bfgp;
 
@@ -246,12 +247,67 @@ IirCoef make_iir(double sigma_s, int B, int L) {
     return c;
 }
 
+// The same recursion differentiated in log sigma_s (theta = w / s and
+// r = e^{-l / s} give theta' = -theta, r' = r l / s), and the band transfer
+// blocks of the tangent system [[Phi, 0], [Phi', Phi]] over the band lengths of
+// the backward passes (Phi' = [[-d1', -d2'], [0, 0]]).
+IirTan make_iir_tan(double sigma_s) {
+    static const double al[2] = {1.680, -0.6803}, be[2] = {3.735, -0.2598};
+    static const double la[2] = {1.783, 1.723}, om[2] = {0.6318, 1.997};
+    IirTan c;
+    memset(&c, 0, sizeof c);
+    for (int s = 0; s < 2; ++s) {
+        const double th = om[s] / sigma_s, r = exp(-la[s] / sigma_s);
+        const double dth = -th, dr = r * la[s] / sigma_s;
+        const double cs = cos(th), sn = sin(th);
+        const double n0 = al[s], n1 = r * (be[s] * sn - al[s] * cs);
+        const double d1 = -2.0 * r * cs, d2 = r * r;
+        const double dn1 = dr * (be[s] * sn - al[s] * cs) + r * dth * (be[s] * cs + al[s] * sn);
+        const double dd1 = -2.0 * dr * cs + 2.0 * r * sn * dth;
+        const double dd2 = 2.0 * r * dr;
+        c.n0[s] = (float)n0;
+        c.n1[s] = (float)n1;
+        c.d1[s] = (float)d1;
+        c.d2[s] = (float)d2;
+        c.m1[s] = (float)(n1 - n0 * d1);
+        c.m2[s] = (float)(-n0 * d2);
+        c.tn1[s] = (float)dn1;
+        c.td1[s] = (float)dd1;
+        c.td2[s] = (float)dd2;
+        c.tm1[s] = (float)(dn1 - n0 * dd1);
+        c.tm2[s] = (float)(-n0 * dd2);
+        const double A[16] = {-d1, -d2, 0, 0, 1, 0, 0, 0, -dd1, -dd2, -d1, -d2, 0, 0, 1, 0};
+        for (int which = 0; which < 2; ++which) {
+            const int B = which == 0 ? kBwdBV : kBwdBH;
+            double M[16] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1};
+            for (int k = 0; k < B; ++k) {
+                double T[16];
+                for (int i = 0; i < 4; ++i)
+                    for (int j = 0; j < 4; ++j) {
+                        double v = 0.0;
+                        for (int q = 0; q < 4; ++q) v += A[4 * i + q] * M[4 * q + j];
+                        T[4 * i + j] = v;
+                    }
+                memcpy(M, T, sizeof M);
+            }
+            float *phi = which == 0 ? c.phiV[s] : c.phiH[s];
+            float *psi = which == 0 ? c.psiV[s] : c.psiH[s];
+            phi[0] = (float)M[0]; phi[1] = (float)M[1]; phi[2] = (float)M[4]; phi[3] = (float)M[5];
+            psi[0] = (float)M[8]; psi[1] = (float)M[9]; psi[2] = (float)M[12]; psi[3] = (float)M[13];
+        }
+    }
+    return c;
+}
+
 struct BwdLayout {
-    size_t parts, status, stats, bparts, corr, total;
+    size_t parts, status, stats, bparts, corr, cv, pt, qt, chz, total;
+    int Hp;
 };
 
-BwdLayout bwd_layout(int H, int W) {
+BwdLayout bwd_layout(int H, int W, int N, unsigned spatial) {
     BwdLayout L;
+    memset(&L, 0, sizeof L);
+    const bool iir = spatial == BF_SPATIAL_IIR;
     size_t off = 0;
     L.parts = off;
     off = align256(off + sizeof(Partial) * kMaxParts);
@@ -260,9 +316,22 @@ BwdLayout bwd_layout(int H, int W) {
     L.stats = off;
     off = align256(off + sizeof(Stats));
     L.bparts = off;
-    off = align256(off + sizeof(BwdPartial) * (size_t)bwd_tiles(H, W));
+    off = align256(off + sizeof(BwdPartial) * (size_t)(iir ? bwd_iir_parts(H, W) : bwd_tiles(H, W)));
     L.corr = off;
     off = align256(off + sizeof(double));
+    if (iir) {
+        const size_t C = (size_t)N + 2;
+        L.Hp = ((H + 63) / 64) * 64;
+        const size_t nbv = ((size_t)H + kBwdBV - 1) / kBwdBV, nbh = ((size_t)W + kBwdBH - 1) / kBwdBH;
+        L.cv = off;
+        off = align256(off + sizeof(float) * nbv * C * 16 * (size_t)W);
+        L.pt = off;
+        off = align256(off + sizeof(float) * C * (size_t)W * (size_t)L.Hp);
+        L.qt = off;
+        off = align256(off + sizeof(float) * C * (size_t)W * (size_t)L.Hp);
+        L.chz = off;
+        off = align256(off + sizeof(float) * nbh * C * 16 * (size_t)L.Hp);
+    }
     L.total = off;
     return L;
 }
@@ -428,8 +497,6 @@ int bf_gp_forward(const float *img, float *out, int H, int W, int pitch, double 
     if ((const void *)img == (const void *)out) return fail(BF_EINVAL, "img and out must not alias");
     const Layout L = gp_layout(H, W, N, spatial);
     if (ws_bytes < L.total) return fail(BF_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
-    if (saved && spatial != BF_SPATIAL_FIR)
-        return fail(BF_EUNSUPPORTED, "saving for the backward pass needs the FIR spatial mode");
     hipStream_t s = (hipStream_t)stream;
     char *w = (char *)ws;
     GPParams p = make_params(img, out, H, W, pitch, sigma_r, N, flags, w, L, saved);
@@ -441,7 +508,8 @@ int bf_gp_forward(const float *img, float *out, int H, int W, int pitch, double 
         if (e != hipSuccess) return hip_fail(e, "FIR launch");
     } else {
         const IirShape sh = iir_shape(H, W, N + 2);
-        e = launch_iir(p, make_iir(sigma_s, sh.B, sh.L), sh, (float *)(w + L.carry), (float *)(w + L.stack), s);
+        e = launch_iir(p, make_iir(sigma_s, sh.B, sh.L), sh, (float *)(w + L.carry), (float *)(w + L.stack),
+                       saved != nullptr, s);
         if (e != hipSuccess) return hip_fail(e, "IIR launch");
     }
     return BF_OK;
@@ -462,8 +530,7 @@ int bf_gp_status(const void *ws, void *stream, int *status) {
 
 size_t bf_gp_backward_workspace_bytes(int H, int W, int N, double sigma_s, unsigned flags) {
     if (H < 1 || W < 1 || N < 0 || N > BF_MAX_DEGREE || !finite_pos(sigma_s)) return 0;
-    (void)flags;
-    return bwd_layout(H, W).total;
+    return bwd_layout(H, W, N, resolve_spatial((long long)H * W, sigma_s, flags)).total;
 }
 
 int bf_gp_backward(const float *img, const float *grad_out, const void *saved, int H, int W, int pitch,
@@ -476,14 +543,13 @@ int bf_gp_backward(const float *img, const float *grad_out, const void *saved, i
     if (!ws) return fail(BF_EINVAL, "null workspace");
     if (flags & ~(BF_SPATIAL_MASK | BF_CENTER_MASK)) return fail(BF_EINVAL, "unknown flag bits 0x%x", flags);
     if ((flags & BF_SPATIAL_MASK) == 3u || (flags & BF_CENTER_MASK) == 12u) return fail(BF_EINVAL, "invalid flag combination");
-    if (resolve_spatial((long long)H * W, sigma_s, flags) != BF_SPATIAL_FIR)
-        return fail(BF_EUNSUPPORTED, "the backward pass is implemented for the FIR spatial mode");
-    if ((rc = check_spatial(BF_SPATIAL_FIR, sigma_s, W))) return rc;
+    const unsigned spatial = resolve_spatial((long long)H * W, sigma_s, flags);
+    if ((rc = check_spatial(spatial, sigma_s, W))) return rc;
     if ((flags & BF_CENTER_MASK) == BF_CENTER_MIDRANGE)
         return fail(BF_EUNSUPPORTED, "the backward pass supports the mean centre or no centring");
     if (grad_img && ((const void *)grad_img == (const void *)img || (const void *)grad_img == (const void *)grad_out))
         return fail(BF_EINVAL, "grad_img must not alias img or grad_out");
-    const BwdLayout L = bwd_layout(H, W);
+    const BwdLayout L = bwd_layout(H, W, N, spatial);
     if (ws_bytes < L.total) return fail(BF_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
     hipStream_t s = (hipStream_t)stream;
     char *w = (char *)ws;
@@ -494,6 +560,25 @@ int bf_gp_backward(const float *img, const float *grad_out, const void *saved, i
     GPParams p = make_params(img, nullptr, H, W, pitch, sigma_r, N, flags, w, fl, const_cast<void *>(saved));
     hipError_t e = launch_stats(p, true, s);
     if (e != hipSuccess) return hip_fail(e, "statistics launch");
+    if (spatial == BF_SPATIAL_IIR) {
+        const size_t npx = (size_t)H * W;
+        BwdIir b;
+        memset(&b, 0, sizeof b);
+        b.grad_out = grad_out;
+        b.rho = (const float *)saved;
+        b.drho = (const float *)saved + npx;
+        b.Dp = (const double *)((const float *)saved + 2 * npx);
+        b.grad_img = grad_img;
+        b.cv = (float *)(w + L.cv);
+        b.PT = (float *)(w + L.pt);
+        b.QT = (float *)(w + L.qt);
+        b.chz = (float *)(w + L.chz);
+        b.bparts = (BwdPartial *)(w + L.bparts);
+        b.Hp = L.Hp;
+        e = launch_bwd_iir(p, b, make_iir_tan(sigma_s), (double *)(w + L.corr), grad_log_sigma_s, grad_log_sigma_r, s);
+        if (e != hipSuccess) return hip_fail(e, "backward launch");
+        return BF_OK;
+    }
     const int R = fir_radius(sigma_s);
     FirTaps2 t;
     memset(&t, 0, sizeof t);

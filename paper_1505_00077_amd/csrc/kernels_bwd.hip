@@ -1,6 +1,7 @@
 // __global__ entry points of the backward pass and their launchers.
 #include "launch.hpp"
 #include "bwd.hpp"
+#include "iir_bwd.hpp"
 
 namespace bfgp {
 
@@ -62,6 +63,58 @@ hipError_t launch_bwd(const GPParams &p, const BwdParams &b, const FirTaps2 &t, 
     }
     if (e != hipSuccess) return e;
     BF_LAUNCH("k_bwd_finalize", k_bwd_finalize, dim3(1), dim3(64), 0, s, p, b.bparts, bwd_tiles(p.H, p.W), corr,
+              g_lss, g_lsr);
+    if (b.grad_img && p.center == 0) {
+        const int g = p.H < 1024 ? p.H : 1024;
+        BF_LAUNCH("k_bwd_apply", k_bwd_apply, dim3(g), dim3(kBlock), 0, s, b.grad_img, p.H, p.W, p.pitch, corr);
+    }
+    return hipGetLastError();
+}
+
+// ---- recursive (IIR) mode ------------------------------------------------------
+
+template <bool AGG>
+__global__ __launch_bounds__(64) void k_bvband(GPParams p, BwdIir b, IirTan c) {
+    __shared__ float tile[AGG ? 1 : 2 * kBwdBV * 65];
+    const Stats st = load_stats(p);
+    bvband<kBwdBV, AGG>(p, b, c, st, blockIdx.x * 64, blockIdx.y, tile);
+}
+
+// lines: lines to resolve; stride: line stride of the carry array; horiz
+// selects the band transfer blocks of the row pass.
+__global__ __launch_bounds__(kBlock) void k_bresolve(GPParams p, IirTan c, float *carry, int nb, int lines, int stride,
+                                                     int horiz) {
+    const int line = blockIdx.x * kBlock + threadIdx.x;
+    if (line < lines)
+        bresolve(horiz ? c.phiH : c.phiV, horiz ? c.psiH : c.psiV, nb, p.C, blockIdx.y, blockIdx.z, (size_t)stride,
+                 (size_t)line, carry);
+}
+
+template <bool AGG>
+__global__ __launch_bounds__(64) void k_bhband(GPParams p, BwdIir b, IirTan c) {
+    const Stats st = load_stats(p);
+    bhband<kBwdBH, AGG>(p, b, c, st, blockIdx.x * 64 + threadIdx.x, blockIdx.y,
+                        b.bparts + (size_t)blockIdx.y * gridDim.x + blockIdx.x);
+}
+
+static int iir_hp(int H) { return ((H + 63) / 64) * 64; }
+int bwd_iir_parts(int H, int W) { return (iir_hp(H) / 64) * ((W + kBwdBH - 1) / kBwdBH); }
+
+hipError_t launch_bwd_iir(const GPParams &p, const BwdIir &b, const IirTan &c, double *corr, double *g_lss,
+                          double *g_lsr, hipStream_t s) {
+    if (b.Hp != iir_hp(p.H)) return hipErrorInvalidValue;
+    const int nbv = (p.H + kBwdBV - 1) / kBwdBV, nbh = (p.W + kBwdBH - 1) / kBwdBH;
+    const dim3 gv((p.W + 63) / 64, nbv);
+    BF_LAUNCH("k_bvband_agg", k_bvband<true>, gv, dim3(64), 0, s, p, b, c);
+    BF_LAUNCH("k_bresolve", k_bresolve, dim3((p.W + kBlock - 1) / kBlock, p.C, 2), dim3(kBlock), 0, s, p, c, b.cv,
+              nbv, p.W, p.W, 0);
+    BF_LAUNCH("k_bvband", k_bvband<false>, gv, dim3(64), 0, s, p, b, c);
+    const dim3 gh(b.Hp / 64, nbh);
+    BF_LAUNCH("k_bhband_agg", k_bhband<true>, gh, dim3(64), 0, s, p, b, c);
+    BF_LAUNCH("k_bresolve", k_bresolve, dim3((p.H + kBlock - 1) / kBlock, p.C, 2), dim3(kBlock), 0, s, p, c, b.chz,
+              nbh, p.H, b.Hp, 1);
+    BF_LAUNCH("k_bhband", k_bhband<false>, gh, dim3(64), 0, s, p, b, c);
+    BF_LAUNCH("k_bwd_finalize", k_bwd_finalize, dim3(1), dim3(64), 0, s, p, b.bparts, bwd_iir_parts(p.H, p.W), corr,
               g_lss, g_lsr);
     if (b.grad_img && p.center == 0) {
         const int g = p.H < 1024 ? p.H : 1024;

@@ -59,7 +59,7 @@ __global__ __launch_bounds__(kBlock) void k_vresolve(GPParams p, IirCoef c, int 
     if (col < p.W) vresolve(p, c, nb, col, blockIdx.y, blockIdx.z, carry);
 }
 
-template <int L>
+template <int L, bool SAVE>
 __global__ __launch_bounds__(512, 1) void k_hrow(GPParams p, IirCoef c, const float *S, int srows, int sp, int T,
                                                  int groups) {
     extern __shared__ float sm[];
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(512, 1) void k_hrow(GPParams p, IirCoef c, const fl
         for (int x = threadIdx.x; x < p.W; x += blockDim.x) p.out[(size_t)blockIdx.x * p.pitch + x] = __builtin_nanf("");
         return;
     }
-    hrow<L>(p, c, st, blockIdx.x, S, srows, sp, sm, T, groups);
+    hrow<L, SAVE>(p, c, st, blockIdx.x, S, srows, sp, sm, T, groups);
 }
 
 // ---- host launchers ----------------------------------------------------------
@@ -105,8 +105,21 @@ hipError_t launch_fir(const GPParams &p, const FirTaps &t, int R, bool save, hip
 }
 
 
-hipError_t launch_iir(const GPParams &p, const IirCoef &c, const IirShape &sh, float *carry, float *S,
+template <int L>
+static void hrow_launch(const GPParams &p, const IirCoef &c, const IirShape &sh, const float *S, bool save,
+                        hipStream_t s) {
+    const dim3 rb(sh.T * sh.Gr);
+    const size_t sm = hrow_smem_bytes(sh.T, sh.Gr, sh.L);
+    if (save)
+        BF_LAUNCH("k_hrow", (k_hrow<L, true>), dim3(p.H), rb, sm, s, p, c, S, sh.Hs, sh.P, sh.T, sh.Gr);
+    else
+        BF_LAUNCH("k_hrow", (k_hrow<L, false>), dim3(p.H), rb, sm, s, p, c, S, sh.Hs, sh.P, sh.T, sh.Gr);
+}
+
+hipError_t launch_iir(const GPParams &p, const IirCoef &c, const IirShape &shape, float *carry, float *S, bool save,
                       hipStream_t s) {
+    IirShape sh = shape;
+    if (save) sh.Gr = 1;  // the saved terms need the whole Horner sums in one group
     const int nb = (p.H + sh.B - 1) / sh.B;
     dim3 gv((sh.P + 63) / 64, nb, sh.G);
     if (sh.B == 64)
@@ -120,13 +133,11 @@ hipError_t launch_iir(const GPParams &p, const IirCoef &c, const IirShape &sh, f
         BF_LAUNCH("k_vband", (k_vband<64, false>), gv, dim3(64), 0, s, p, c, carry, S, sh.P, sh.G);
     else
         BF_LAUNCH("k_vband", (k_vband<32, false>), gv, dim3(64), 0, s, p, c, carry, S, sh.P, sh.G);
-    const dim3 rb(sh.T * sh.Gr);
-    const size_t sm = hrow_smem_bytes(sh.T, sh.Gr, sh.L);
     switch (sh.L) {
-        case 4: BF_LAUNCH("k_hrow", (k_hrow<4>), dim3(p.H), rb, sm, s, p, c, S, sh.Hs, sh.P, sh.T, sh.Gr); break;
-        case 8: BF_LAUNCH("k_hrow", (k_hrow<8>), dim3(p.H), rb, sm, s, p, c, S, sh.Hs, sh.P, sh.T, sh.Gr); break;
-        case 12: BF_LAUNCH("k_hrow", (k_hrow<12>), dim3(p.H), rb, sm, s, p, c, S, sh.Hs, sh.P, sh.T, sh.Gr); break;
-        case 16: BF_LAUNCH("k_hrow", (k_hrow<16>), dim3(p.H), rb, sm, s, p, c, S, sh.Hs, sh.P, sh.T, sh.Gr); break;
+        case 4: hrow_launch<4>(p, c, sh, S, save, s); break;
+        case 8: hrow_launch<8>(p, c, sh, S, save, s); break;
+        case 12: hrow_launch<12>(p, c, sh, S, save, s); break;
+        case 16: hrow_launch<16>(p, c, sh, S, save, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -41,11 +41,18 @@ struct IirShape {
 // batch: the image is one of many filtered together, which fill the device by
 // themselves: no channel groups unless the tuning overrides ask for them.
 IirShape iir_shape(int H, int W, int C, bool batch = false);
-hipError_t launch_iir(const GPParams &p, const IirCoef &c, const IirShape &sh, float *carry, float *S,
+// save: also store the terms bf_gp_backward needs (p.saved), with the row pass
+// in one channel group.
+hipError_t launch_iir(const GPParams &p, const IirCoef &c, const IirShape &sh, float *carry, float *S, bool save,
                       hipStream_t s);
 hipError_t launch_direct(const DirectArgs &a, hipStream_t s);
 int bwd_tiles(int H, int W);
 hipError_t launch_bwd(const GPParams &p, const BwdParams &b, const FirTaps2 &t, int R, double *corr, double *g_lss,
                       double *g_lsr, hipStream_t s);
+struct BwdIir;
+struct IirTan;
+int bwd_iir_parts(int H, int W);
+hipError_t launch_bwd_iir(const GPParams &p, const BwdIir &b, const IirTan &c, double *corr, double *g_lss,
+                          double *g_lsr, hipStream_t s);
 
 }  // namespace bfgp

@@ -57,10 +57,38 @@ def test_forward_rejects_small_workspace():
 def test_forward_rejects_unsupported_modes():
     # FIR radius ceil(3 * 9) = 27 > 24
     assert fwd(ss=9.0, flags=bf.SPATIAL["fir"]) == bf.BF_EUNSUPPORTED
-    # saving for the backward pass needs the FIR mode
-    assert fwd(flags=bf.SPATIAL["iir"], saved=FAKE + 65536) == bf.BF_EUNSUPPORTED
     # IIR width limit
     assert fwd(H=4, W=9000, pitch=9000, flags=bf.SPATIAL["iir"]) == bf.BF_EUNSUPPORTED
+
+
+def bwd(img=FAKE, g=FAKE + 4096, saved=FAKE + 8192, H=8, W=8, pitch=8, ss=2.0, sr=30.0, N=20, flags=0,
+        gi=FAKE + 65536, ws=FAKE + 131072, ws_bytes=1 << 30):
+    return bf.bf_gp_backward(img, g, saved, H, W, pitch, ss, sr, N, flags, gi, None, None, ws, ws_bytes, None)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(img=None), dict(g=None), dict(saved=None), dict(ws=None), dict(H=0), dict(pitch=7), dict(ss=0.0),
+    dict(sr=float("inf")), dict(N=65), dict(flags=3), dict(flags=16), dict(gi=FAKE), dict(gi=FAKE + 4096),
+    dict(flags=2, gi=FAKE), dict(flags=2, N=-1),
+])
+def test_backward_rejects_invalid_arguments(kw):
+    assert bwd(**kw) == bf.BF_EINVAL
+
+
+def test_backward_modes_and_workspace():
+    fir, iir = bf.SPATIAL["fir"], bf.SPATIAL["iir"]
+    # FIR radius limit and the unsupported midrange centre, in both modes
+    assert bwd(ss=9.0, flags=fir) == bf.BF_EUNSUPPORTED
+    assert bwd(flags=fir | bf.CENTER["midrange"]) == bf.BF_EUNSUPPORTED
+    assert bwd(flags=iir | bf.CENTER["midrange"]) == bf.BF_EUNSUPPORTED
+    # the recursive backward holds two transposed channel stacks and carries
+    need_iir = bf.bf_gp_backward_workspace_bytes(512, 512, 20, 12.0, iir)
+    need_fir = bf.bf_gp_backward_workspace_bytes(512, 512, 20, 2.0, fir)
+    assert need_iir >= 2 * 22 * 512 * 512 * 4 > need_fir > 0
+    assert bwd(H=512, W=512, pitch=512, ss=12.0, flags=iir, ws_bytes=need_iir - 1) == bf.BF_ENOMEM
+    # AUTO resolves as the forward does (radius 36 is past any crossover)
+    assert bf.bf_gp_backward_workspace_bytes(512, 512, 20, 12.0, 0) == need_iir
+    assert bf.bf_gp_backward_workspace_bytes(0, 512, 20, 12.0, iir) == 0
 
 
 def test_workspace_sizes():

@@ -24,20 +24,23 @@ def bf():
     return m
 
 
-def gpu_grads(bf, img, target, ss, sr, N, center="mean"):
-    note(f"backward {img.shape} ss={ss} sr={sr} N={N} {center}")
+def gpu_grads(bf, img, target, ss, sr, N, center="mean", spatial="fir"):
+    note(f"backward {spatial} {img.shape} ss={ss} sr={sr} N={N} {center}")
     x = to_dev(img)
     saved = bf.saved_buffer(*img.shape)
-    out = bf.gp_forward(x, ss, sr, N, spatial="fir", center=center, saved=saved, check=True)
+    out = bf.gp_forward(x, ss, sr, N, spatial=spatial, center=center, saved=saved, check=True)
     g = out - to_dev(target)
-    gi, gs, gr = bf.gp_backward(x, g.contiguous(), saved, ss, sr, N, spatial="fir", center=center)
+    gi, gs, gr = bf.gp_backward(x, g.contiguous(), saved, ss, sr, N, spatial=spatial, center=center)
     return to_np(out), to_np(gi), float(gs.item()), float(gr.item())
 
 
-def oracle_grads(img, target, ss, sr, N, center=oracle.CENTER_MEAN):
+def oracle_grads(img, target, ss, sr, N, center=oracle.CENTER_MEAN, mode="fir"):
+    """The oracle's analytic gradient with the spatial kernel of the mode: the
+    sampled Gaussian over ceil(3 sigma_s) (FIR), or Deriche's kernel over the
+    whole image and its exact log sigma_s derivative (IIR)."""
     f = img.astype(np.float64)
-    R = oracle.fir_radius(ss)
-    k, kt = oracle.gauss_table(ss, R), oracle.gauss_dtable(ss, R)
+    k, _ = oracle.spatial_table(mode, ss, *f.shape)
+    kt, _ = oracle.spatial_dtable(mode, ss, *f.shape)
     out = oracle.gp_alg1(f, sr, N, k, center)
     return oracle.gp_grad(f, out - target, sr, N, k, kt, center)
 
@@ -124,7 +127,7 @@ def test_autograd_function(bf):
     loss.backward()
     gx = to_np(x.grad)
     # the filter sees the sigmas that the float32 parameters hold
-    ss, sr = math.exp(float(lss)), math.exp(float(lsr))
+    ss, sr = math.exp(float(lss.detach())), math.exp(float(lsr.detach()))
     tot_s = tot_r = 0.0
     for i in range(3):
         rgi, rgs, rgr = oracle_grads(imgs[i], target.astype(np.float64), ss, sr, 20)
@@ -141,3 +144,107 @@ def test_backward_deterministic(bf):
     a = gpu_grads(bf, img, tgt, 2.0, 30.0, 20)
     b = gpu_grads(bf, img, tgt, 2.0, 30.0, 20)
     assert np.array_equal(a[1], b[1]) and a[2] == b[2] and a[3] == b[3]
+
+
+# ---- recursive (IIR) mode ------------------------------------------------------
+# Shapes cover several column bands (32 rows) and row bands (16 columns) with
+# ragged ends, single rows and columns, and sigma_s past the FIR limit.  Every
+# case is well conditioned (cond = sum |h| w / |sum h w| below 1.2; at low
+# degree and sigma_s below 1, Deriche's negative lobes can cancel the
+# denominator, where FP32 and FP64 legitimately part, as the forward tests show).
+
+@pytest.mark.parametrize("shape,ss,N", [((37, 45), 1.3, 8), ((64, 40), 2.5, 20), ((70, 101), 4.0, 20),
+                                         ((33, 97), 0.8, 6), ((48, 48), 6.0, 20), ((65, 33), 12.0, 20),
+                                         ((130, 47), 20.0, 20), ((1, 50), 3.0, 6), ((50, 1), 3.0, 6)])
+def test_iir_gradients_match_oracle(bf, shape, ss, N):
+    H, W = shape
+    img = synthimg.voronoi_image(H, W, 12, seed=H + W + 7)
+    target = synthimg.voronoi_image(H, W, 12, seed=H * W + 7)
+    out, gi, gs, gr = gpu_grads(bf, img, target, ss, 25.0, N, spatial="iir")
+    rgi, rgs, rgr = oracle_grads(img, target.astype(np.float64), ss, 25.0, N, mode="iir")
+    ref = oracle.gp_alg1(img.astype(np.float64), 25.0, N, oracle.spatial_table("iir", ss, H, W)[0])
+    assert np.max(np.abs(out - ref)) <= 1e-3
+    scale = np.max(np.abs(rgi))
+    assert np.max(np.abs(gi - rgi)) <= 1e-3 * scale
+    assert gs == pytest.approx(rgs, rel=1e-3, abs=1e-6 * scale * img.size)
+    assert gr == pytest.approx(rgr, rel=1e-3, abs=1e-6 * scale * img.size)
+
+
+def test_iir_no_centring_gradient(bf):
+    img = (synthimg.voronoi_image(40, 52, 10, seed=19) * 0.5 + 60.0).astype(np.float32)
+    target = synthimg.voronoi_image(40, 52, 10, seed=20) * 0.5 + 60.0
+    _, gi, gs, gr = gpu_grads(bf, img, target, 5.0, 40.0, 20, center="none", spatial="iir")
+    rgi, rgs, rgr = oracle_grads(img, target.astype(np.float64), 5.0, 40.0, 20, oracle.CENTER_NONE, mode="iir")
+    scale = np.max(np.abs(rgi))
+    assert np.max(np.abs(gi - rgi)) <= 1e-3 * scale
+    assert gs == pytest.approx(rgs, rel=1e-3)
+    assert gr == pytest.approx(rgr, rel=1e-3)
+
+
+def test_iir_finite_differences_on_crop(bf):
+    # 32x32 crop of a 512x512 training image, sigma_s 10 (past the FIR limit),
+    # sigma_r 25, L2 loss; FP64 central differences, h = 1e-4, of the oracle
+    # forward with Deriche's kernel over the whole crop
+    imgs, target = synthimg.grad_batch(count=1)
+    img = imgs[0][300:332, 40:72].copy()
+    tgt = target[300:332, 40:72].astype(np.float64)
+    ss, sr, N = 10.0, 25.0, 20
+    _, gi, gs, gr = gpu_grads(bf, img, tgt, ss, sr, N, spatial="iir")
+    f = img.astype(np.float64)
+
+    def loss(fimg, s, r):
+        o = oracle.gp(fimg, s, r, N, mode="iir")
+        return 0.5 * float(np.sum((o - tgt) ** 2))
+
+    h = 1e-4
+    fd = np.empty_like(f)
+    for idx in np.ndindex(f.shape):
+        fp = f.copy(); fp[idx] += h
+        fm = f.copy(); fm[idx] -= h
+        fd[idx] = (loss(fp, ss, sr) - loss(fm, ss, sr)) / (2 * h)
+    fs = (loss(f, ss * math.exp(h), sr) - loss(f, ss * math.exp(-h), sr)) / (2 * h)
+    fr = (loss(f, ss, sr * math.exp(h)) - loss(f, ss, sr * math.exp(-h))) / (2 * h)
+    scale = np.max(np.abs(fd))
+    print(f"IIR FD crop: max|grad - fd| / max|fd| = {np.max(np.abs(gi - fd)) / scale:.2e}; "
+          f"log ss {gs:.6g} vs {fs:.6g}; log sr {gr:.6g} vs {fr:.6g}")
+    assert np.max(np.abs(gi - fd)) <= 1e-3 * scale
+    assert gs == pytest.approx(fs, rel=1e-3)
+    assert gr == pytest.approx(fr, rel=1e-3)
+
+
+def test_iir_autograd_function_large_sigma(bf):
+    # sigma_s 12 is past the FIR radius limit: AUTO resolves to the recursive
+    # mode for both passes
+    imgs, target = synthimg.grad_batch(count=2, H=72, W=90)
+    x = to_dev(imgs).requires_grad_(True)
+    lss = torch.tensor(math.log(12.0), device="cuda", requires_grad=True)
+    lsr = torch.tensor(math.log(30.0), device="cuda", requires_grad=True)
+    note("autograd IIR batch of 2")
+    assert bf.resolve_spatial(12.0, "auto", shape=(72, 90)) == "iir"
+    out = bf.gp_filter(x, lss, lsr, 20)
+    loss = 0.5 * ((out - to_dev(target)[None]) ** 2).sum()
+    loss.backward()
+    gx = to_np(x.grad)
+    ss, sr = math.exp(float(lss.detach())), math.exp(float(lsr.detach()))
+    tot_s = tot_r = 0.0
+    for i in range(2):
+        rgi, rgs, rgr = oracle_grads(imgs[i], target.astype(np.float64), ss, sr, 20, mode="iir")
+        assert np.max(np.abs(gx[i] - rgi)) <= 1e-3 * np.max(np.abs(rgi))
+        tot_s += rgs
+        tot_r += rgr
+    assert float(lss.grad) == pytest.approx(tot_s, rel=1e-3)
+    assert float(lsr.grad) == pytest.approx(tot_r, rel=1e-3)
+
+
+def test_iir_backward_deterministic_and_full_size(bf):
+    # one 512x512 training image at sigma_s 10: twice, bit-identical, and
+    # against the oracle on the full image
+    imgs, target = synthimg.grad_batch(count=1)
+    a = gpu_grads(bf, imgs[0], target, 10.0, 25.0, 20, spatial="iir")
+    b = gpu_grads(bf, imgs[0], target, 10.0, 25.0, 20, spatial="iir")
+    assert np.array_equal(a[1], b[1]) and a[2] == b[2] and a[3] == b[3]
+    rgi, rgs, rgr = oracle_grads(imgs[0], target.astype(np.float64), 10.0, 25.0, 20, mode="iir")
+    scale = np.max(np.abs(rgi))
+    assert np.max(np.abs(a[1] - rgi)) <= 1e-3 * scale
+    assert a[2] == pytest.approx(rgs, rel=1e-3)
+    assert a[3] == pytest.approx(rgr, rel=1e-3)
