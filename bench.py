@@ -85,14 +85,14 @@ def launch_ids(stage, bf, H, W, C, fir_radii):
     """(kernel instantiation, grid threads) of every launch of `stage` in one
     step, as the counter files name them."""
     if stage == "k_fir":
-        return [(f"k_fir<{r}, false>", ((W + 63) // 64) * ((H + fir_ty(r) - 1) // fir_ty(r)) * 256)
+        return [(f"k_fir<{r}, false>", ((W + fir_tx(r) - 1) // fir_tx(r)) * ((H + fir_ty(r) - 1) // fir_ty(r)) * 256)
                 for r in fir_radii]
     sh = bf.iir_shape(H, W, C - 2)
     B, G, L, T, Gr = sh["band_rows"], sh["col_groups"], sh["row_chunk"], sh["row_threads"], sh["row_groups"]
     P = ((T * L + 2 + 31) // 32) * 32
     nb = (H + B - 1) // B
     return {
-        "k_hrow": [(f"k_hrow<{L}>", H * T * Gr)],
+        "k_hrow": [(f"k_hrow<{L}, false>", H * T * Gr)],
         "k_vband": [(f"k_vband<{B}, false>", ((P + 63) // 64) * nb * G * 64)],
         "k_vband_agg": [(f"k_vband<{B}, true>", ((P + 63) // 64) * nb * G * 64)],
         "k_vresolve": [("k_vresolve", ((W + 255) // 256) * 256 * C * 2)],
@@ -100,9 +100,14 @@ def launch_ids(stage, bf, H, W, C, fir_radii):
     }.get(stage, [])
 
 
+def fir_tx(r):
+    """Columns of the FIR output tile for radius r (forward without saved terms)."""
+    return 128 if r <= 16 else 64
+
+
 def fir_ty(r):
     """Rows of the FIR output tile for radius r (forward without saved terms)."""
-    return 32 if 10 <= r <= 17 else 16
+    return 32 if r == 17 else 16
 
 
 def main():

@@ -184,6 +184,7 @@ GPParams make_params(const float *img, float *out, int H, int W, int pitch, doub
         p.sq[n] = sqrt((double)n);
         p.isq[n] = n > 0 ? 1.0 / sqrt((double)n) : 0.0;
         p.rm[n] = n > 0 ? sqrt((double)n + 1.0) / (double)n : 0.0;
+        p.inv[n] = n > 0 ? 1.0 / (double)n : 0.0;
     }
     return p;
 }

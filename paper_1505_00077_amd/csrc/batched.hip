@@ -68,9 +68,8 @@ __global__ __launch_bounds__(kBlock) void k_bstats(const BatchImage *imgs, const
 
 template <int R>
 __device__ __forceinline__ void fir_item(const BatchImage &B, const Stats &st, int idx, float *smem) {
-    using S = FirShape<R>;
-    const int tx = (B.p.W + S::TX - 1) / S::TX;
-    fir_tile<R, false>(B.p, B.taps, st, (idx / tx) * S::TY, (idx % tx) * S::TX, smem);
+    const int tx = (B.p.W + fir_tx(R) - 1) / fir_tx(R);
+    fir_tile_auto<R, false>(B.p, B.taps, st, (idx / tx) * fir_ty(R), (idx % tx) * fir_tx(R), smem);
 }
 
 template <bool WIDE>
@@ -257,7 +256,7 @@ int bf_gp_plan_batched(const bf_gp_item *items, int count, unsigned flags, void 
         off = al(off + sizeof(Stats));
         for (int b = 0; b < nparts; ++b) per[kStStats].push_back({i, b});
         if (!iir) {
-            const int tiles = ((it.W + kFirTX - 1) / kFirTX) * ((it.H + fir_ty(R) - 1) / fir_ty(R));
+            const int tiles = ((it.W + fir_tx(R) - 1) / fir_tx(R)) * ((it.H + fir_ty(R) - 1) / fir_ty(R));
             const int wide = R > kBatchFirSplit;
             for (int t = 0; t < tiles; ++t) per[wide ? kStFirWide : kStFir].push_back({i, t});
             fir_smem[wide] = std::max(fir_smem[wide], sizeof(float) * (size_t)fir_smem_floats(R));

@@ -46,6 +46,7 @@ struct GPParams {
     double sq[kMaxC + 3];   // sqrt(n)
     double isq[kMaxC + 3];  // 1 / sqrt(n)
     double rm[kMaxC + 3];   // sqrt(n + 1) / n (n >= 1; 0 at n = 0)
+    double inv[kMaxC + 3];  // 1 / n (n >= 1; 0 at n = 0)
 };
 
 // Spatial taps of the FIR mode: k[d] = exp(-d^2 / 2 sigma_s^2), d = 0..R.

@@ -18,26 +18,44 @@
 
 namespace bfgp {
 
-// Output tile of the FIR kernels: 64 columns by fir_ty(R, save) rows.
-// 16-row tiles give twice the workgroups and fewer registers per thread; they
-// were measured faster except for radii 10..17 without the saved terms, where
-// the halo rows of a 16-row tile cost more than the extra parallelism gains.
-// With the saved terms (more accumulators) 16 rows keep two waves per SIMD.
-constexpr int kFirTX = 64;
-__host__ __device__ constexpr int fir_ty(int R, bool save = false) {
-    return (!save && R >= 10 && R <= 17) ? 32 : 16;
-}
+// Two variants share each kernel.  The register-column variant (radii up to
+// kFirRegMaxR, forward without the saved terms) gives every thread one column
+// of the input region: its channel values stay in registers and its column
+// pass runs from them, so LDS only carries the column-filtered rows to the row
+// pass.  The region variant (below) stages the region in LDS; it serves wider
+// radii, the saved terms, and images the register variant cannot represent
+// (|x| > 12, degree above kFirRegMaxN), with the same tile shape.
+constexpr int kFirRegMaxR = 16;
+constexpr int kFirRegMaxN = 46;
+__host__ __device__ constexpr bool fir_reg(int R, bool save) { return !save && R <= kFirRegMaxR; }
 
-// Channels processed between two barrier pairs: two (twice the independent
-// work per barrier) where the LDS stages of two channels fit in 64 KB.
+// Output tile of a FIR launch: fir_tx(R, save) columns by fir_ty(R, save)
+// rows.  Kernels that can take the register variant use 16 x 128 tiles (the
+// region's 128 + 2R columns fill at least two waves); the region variant then
+// covers such a tile as two 16 x 64 halves.  Other kernels use the region
+// variant's own tile, 64 columns wide: 16-row tiles give twice the workgroups
+// and fewer registers per thread; they were measured faster except for radii
+// 10..17 without the saved terms, where the halo rows of a 16-row tile cost
+// more than the extra parallelism gains.  With the saved terms (more
+// accumulators) 16 rows keep two waves per SIMD.
+__host__ __device__ constexpr int fir_region_ty(int R, bool save = false) {
+    return (!fir_reg(R, save) && !save && R >= 10 && R <= 17) ? 32 : 16;
+}
+__host__ __device__ constexpr int fir_tx(int R, bool save = false) { return fir_reg(R, save) ? 128 : 64; }
+__host__ __device__ constexpr int fir_ty(int R, bool save = false) { return fir_region_ty(R, save); }
+
+// Channels processed between two barrier pairs by the region variant: two
+// (twice the independent work per barrier) where the LDS stages of two
+// channels fit in 64 KB.
 __host__ __device__ constexpr int fir_ch(int R, bool save = false) {
-    return (!save && 2 * ((fir_ty(R) + 2 * R) * (kFirTX + 2 * R) + fir_ty(R) * (kFirTX + 2 * R + 1)) <= 16384)
+    return (!save && 2 * ((fir_region_ty(R) + 2 * R) * (64 + 2 * R) + fir_region_ty(R) * (64 + 2 * R + 1)) <= 16384)
                ? 2 : 1;
 }
 
+// Shape of the region variant's tile (64 columns).
 template <int R, bool SAVE = false>
 struct FirShape {
-    static constexpr int TY = fir_ty(R, SAVE), TX = kFirTX;  // output tile
+    static constexpr int TY = fir_region_ty(R, SAVE), TX = 64;  // output tile
     static constexpr int RY = TY + 2 * R, RX = TX + 2 * R;
     static constexpr int REG = RY * RX;           // region elements
     static constexpr int PER = (REG + kBlock - 1) / kBlock;
@@ -49,10 +67,14 @@ struct FirShape {
     static constexpr int SMEM_FLOATS = CH * STAGE;
 };
 
-// Number of LDS floats needed by fir_tile<R>.
+// Number of LDS floats needed by fir_tile_auto<R, save> (either variant).
 __host__ __device__ constexpr int fir_smem_floats(int R, bool save = false) {
-    return fir_ch(R, save) *
-           ((fir_ty(R, save) + 2 * R) * (kFirTX + 2 * R) + fir_ty(R, save) * (kFirTX + 2 * R + 1));
+    return fir_ch(R, save) * ((fir_region_ty(R, save) + 2 * R) * (64 + 2 * R) +
+                              fir_region_ty(R, save) * (64 + 2 * R + 1)) >
+                   (fir_reg(R, save) ? 2 * 16 * (128 + 2 * R + 1) : 0)
+               ? fir_ch(R, save) * ((fir_region_ty(R, save) + 2 * R) * (64 + 2 * R) +
+                                    fir_region_ty(R, save) * (64 + 2 * R + 1))
+               : 2 * 16 * (128 + 2 * R + 1);
 }
 
 template <int R, bool SAVE>
@@ -249,6 +271,160 @@ __device__ __forceinline__ void fir_tile(const GPParams &p, const FirTaps &taps,
                 }
             }
         }
+    }
+}
+
+// Register-column variant (16 x 128 tile, radius R <= kFirRegMaxR).  The
+// channels are carried unnormalised, w_n = exp(-x^2/2) x^n = sqrt(n!) u_n
+// (one multiply per sample and channel); the 1/sqrt(n!) goes into the
+// recombination weights: with q_n = tau^n / n!,
+//   D' = sum_{n<=N} q_n (k * w_n),   M' = sum_{n=1}^{N+1} q_{n-1} (k * w_n),
+// the same D' = exp(tau^2/2) D and M' = exp(tau^2/2) M as the region variant.
+// w_n stays in the FP32 range for |x| <= 12 and n <= kFirRegMaxN + 1.
+// Per channel: threads 0 .. 127+2R update their region column and run its
+// column pass from registers into LDS (two buffers, one barrier per channel),
+// then every thread runs the row pass at its 8 pixels and accumulates D', M'
+// in double.
+template <int R>
+__device__ __forceinline__ void fir_tile_reg(const GPParams &p, const FirTaps &taps, const Stats &st, int ty0,
+                                             int tx0, float *smem) {
+    constexpr int TY = 16, TX = 128, RX = TX + 2 * R, RY = TY + 2 * R, BP = RX + 1;
+    constexpr int PX = TY * TX / kBlock;
+    static_assert(RX <= kBlock, "one region column per thread");
+    const int tid = threadIdx.x;
+    const bool colt = tid < RX;
+
+    // ---- region column tid: centred x and w_0 = exp(-x^2/2) ----
+    float w[RY], xc[RY];
+    {
+        const int gx = tx0 - R + tid;
+        const int xcl = gx < 0 ? 0 : (gx >= p.W ? p.W - 1 : gx);
+        const bool inx = colt && gx >= 0 && gx < p.W;
+        float f[RY];
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const int gy = ty0 - R + j;
+            const int yc = gy < 0 ? 0 : (gy >= p.H ? p.H - 1 : gy);
+            f[j] = p.img[(size_t)yc * p.pitch + xcl];
+        }
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const int gy = ty0 - R + j;
+            const bool in = inx && gy >= 0 && gy < p.H;
+            const float x = in ? centred(f[j], st, p.inv_sigma_r) : 0.f;
+            xc[j] = x;
+            w[j] = in ? gauss_u0(x, 0) : 0.f;
+        }
+    }
+
+    // ---- output ownership: row oy, PX consecutive columns from ox0 ----
+    const int oy = tid % TY;
+    const int ox0 = (tid / TY) * PX;
+    double tau[PX], Dp[PX], Mp[PX], q[PX];
+    {
+        const int gy = ty0 + oy;
+        const int yc = gy < p.H ? gy : p.H - 1;
+        float f[PX];
+#pragma unroll
+        for (int i = 0; i < PX; ++i) {
+            const int gx = tx0 + ox0 + i;
+            f[i] = p.img[(size_t)yc * p.pitch + (gx < p.W ? gx : p.W - 1)];
+        }
+#pragma unroll
+        for (int i = 0; i < PX; ++i) {
+            const int gx = tx0 + ox0 + i;
+            tau[i] = (gy < p.H && gx < p.W) ? (double)centred(f[i], st, p.inv_sigma_r) : 0.0;
+            Dp[i] = 0.0;
+            Mp[i] = 0.0;
+            q[i] = 1.0;
+        }
+    }
+
+    for (int n = 0; n < p.C; ++n) {
+        float *Bn = smem + (n & 1) * (TY * BP);
+        // column pass of channel n from registers
+        if (colt) {
+            if (n > 0) {
+#pragma unroll
+                for (int j = 0; j < RY; ++j) w[j] *= xc[j];
+            }
+            float acc[TY];
+#pragma unroll
+            for (int i = 0; i < TY; ++i) {
+                float a = 0.f;
+#pragma unroll
+                for (int d = -R; d <= R; ++d) a = fmaf(taps.k[d < 0 ? -d : d], w[i + R + d], a);
+                acc[i] = a;
+            }
+#pragma unroll
+            for (int i = 0; i < TY; ++i) Bn[i * BP + tid] = acc[i];
+        }
+        __syncthreads();
+        // row pass at the owned pixels
+        float h[PX];
+#pragma unroll
+        for (int i = 0; i < PX; ++i) h[i] = 0.f;
+        {
+            const float *row = Bn + oy * BP + ox0;
+#pragma unroll
+            for (int j = 0; j < PX + 2 * R; ++j) {
+                const float v = row[j];
+#pragma unroll
+                for (int i = 0; i < PX; ++i) {
+                    const int d = j - i;
+                    if (d >= 0 && d <= 2 * R) h[i] = fmaf(taps.k[d >= R ? d - R : R - d], v, h[i]);
+                }
+            }
+        }
+        // recombination (double): M' takes q_{n-1}, D' takes q_n; channel 0
+        // only starts D', channel N+1 only ends M' (uniform branches)
+        if (n == 0) {
+#pragma unroll
+            for (int i = 0; i < PX; ++i) Dp[i] = (double)h[i];
+        } else {
+            const double rn = p.inv[n];
+            if (n <= p.N) {
+#pragma unroll
+                for (int i = 0; i < PX; ++i) {
+                    const double hd = (double)h[i];
+                    Mp[i] = fma(q[i], hd, Mp[i]);
+                    q[i] *= tau[i] * rn;
+                    Dp[i] = fma(q[i], hd, Dp[i]);
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < PX; ++i) Mp[i] = fma(q[i], (double)h[i], Mp[i]);
+            }
+        }
+    }
+
+    const int gy = ty0 + oy;
+    if (gy < p.H) {
+#pragma unroll
+        for (int i = 0; i < PX; ++i) {
+            const int gx = tx0 + ox0 + i;
+            if (gx < p.W) {
+                const double rho = Mp[i] / Dp[i];
+                p.out[(size_t)gy * p.pitch + gx] = st.ok ? (float)fma(p.sigma_r, rho, st.tc) : __builtin_nanf("");
+            }
+        }
+    }
+}
+
+// The FIR tile with the variant this image can take (the choice is uniform
+// over the launch: it depends on the image statistics and the degree only).
+template <int R, bool SAVE>
+__device__ __forceinline__ void fir_tile_auto(const GPParams &p, const FirTaps &taps, const Stats &st, int ty0,
+                                              int tx0, float *smem) {
+    if constexpr (fir_reg(R, SAVE)) {
+        if (st.xmax <= 12.0 && p.N <= kFirRegMaxN) {
+            fir_tile_reg<R>(p, taps, st, ty0, tx0, smem);
+        } else {
+            fir_tile<R, SAVE>(p, taps, st, ty0, tx0, smem);
+            fir_tile<R, SAVE>(p, taps, st, ty0, tx0 + 64, smem);
+        }
+    } else {
+        fir_tile<R, SAVE>(p, taps, st, ty0, tx0, smem);
     }
 }
 

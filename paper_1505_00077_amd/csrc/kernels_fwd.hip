@@ -18,7 +18,7 @@ __global__ __launch_bounds__(kBlock) void k_fir(GPParams p, FirTaps taps) {
     extern __shared__ float smem[];
     const Stats st = reduce_stats(p);
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) publish_stats(p, st);
-    fir_tile<R, SAVE>(p, taps, st, blockIdx.y * FirShape<R, SAVE>::TY, blockIdx.x * FirShape<R, SAVE>::TX, smem);
+    fir_tile_auto<R, SAVE>(p, taps, st, blockIdx.y * fir_ty(R, SAVE), blockIdx.x * fir_tx(R, SAVE), smem);
 }
 
 __global__ __launch_bounds__(kBlock) void k_direct(DirectArgs a) {
@@ -82,9 +82,8 @@ hipError_t launch_stats(const GPParams &p, bool final_kernel, hipStream_t s) {
 
 template <int R, bool SAVE>
 static hipError_t fir_launch_rs(const GPParams &p, const FirTaps &t, hipStream_t s) {
-    using S = FirShape<R, SAVE>;
-    dim3 grid((p.W + S::TX - 1) / S::TX, (p.H + S::TY - 1) / S::TY);
-    BF_LAUNCH("k_fir", (k_fir<R, SAVE>), grid, dim3(kBlock), sizeof(float) * S::SMEM_FLOATS, s, p, t);
+    dim3 grid((p.W + fir_tx(R, SAVE) - 1) / fir_tx(R, SAVE), (p.H + fir_ty(R, SAVE) - 1) / fir_ty(R, SAVE));
+    BF_LAUNCH("k_fir", (k_fir<R, SAVE>), grid, dim3(kBlock), sizeof(float) * fir_smem_floats(R, SAVE), s, p, t);
     return hipGetLastError();
 }
 
