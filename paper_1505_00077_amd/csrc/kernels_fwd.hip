@@ -34,8 +34,13 @@ __global__ __launch_bounds__(kBlock) void k_direct(DirectArgs a) {
 // uniform over the launch.  The launch bound keeps the common branch at three
 // waves per SIMD (the rare BIG branch may spill).  The end-state pass is the
 // first kernel after the statistics pass: it reduces the partials itself.
+// One-dimensional grid: the workgroups of the image's column groups (cgr of
+// them per band and channel group) come first, those of the stack's pad-only
+// column groups (cgp, column pass only: they store zeros) last, so that the
+// light pad workgroups fill in behind the full ones.
 template <int B, bool AGG>
-__global__ __launch_bounds__(64, 3) void k_vband(GPParams p, IirCoef c, float *carry, float *S, int sp, int groups) {
+__global__ __launch_bounds__(64, 3) void k_vband(GPParams p, IirCoef c, float *carry, float *S, int sp, int groups,
+                                                 int cgr, int cgp) {
     __shared__ float sacc[AGG ? 1 : B * 64];
     Stats st;
     if (AGG) {
@@ -45,17 +50,29 @@ __global__ __launch_bounds__(64, 3) void k_vband(GPParams p, IirCoef c, float *c
         st = load_stats(p);
     }
     if (!st.ok) return;
-    const int col = blockIdx.x * 64 + threadIdx.x;
-    // channel group blockIdx.z of `groups` nearly equal groups
-    const int cb = (p.C * (int)blockIdx.z) / groups, ce = (p.C * ((int)blockIdx.z + 1)) / groups;
+    const int nb = (p.H + B - 1) / B;
+    const int nreal = cgr * nb * groups;
+    int idx = blockIdx.x, cg;
+    if (idx < nreal) {
+        cg = idx % cgr;
+        idx /= cgr;
+    } else {
+        idx -= nreal;
+        cg = cgr + idx % cgp;
+        idx /= cgp;
+    }
+    const int band = idx % nb, grp = idx / nb;
+    const int col = cg * 64 + threadIdx.x;
+    // channel group grp of `groups` nearly equal groups
+    const int cb = (p.C * grp) / groups, ce = (p.C * (grp + 1)) / groups;
     if (st.xmax > 12.0)
-        vband<B, AGG, true>(p, c, st, col, blockIdx.y, carry, S, sp, sacc, cb, ce);
+        vband<B, AGG, true>(p, c, st, col, band, carry, S, sp, sacc, cb, ce);
     else
-        vband<B, AGG, false>(p, c, st, col, blockIdx.y, carry, S, sp, sacc, cb, ce);
+        vband<B, AGG, false>(p, c, st, col, band, carry, S, sp, sacc, cb, ce);
 }
 
-__global__ __launch_bounds__(kBlock) void k_vresolve(GPParams p, IirCoef c, int nb, float *carry) {
-    const int col = blockIdx.x * kBlock + threadIdx.x;
+__global__ __launch_bounds__(64) void k_vresolve(GPParams p, IirCoef c, int nb, float *carry) {
+    const int col = blockIdx.x * 64 + threadIdx.x;
     if (col < p.W) vresolve(p, c, nb, col, blockIdx.y, blockIdx.z, carry);
 }
 
@@ -120,18 +137,22 @@ hipError_t launch_iir(const GPParams &p, const IirCoef &c, const IirShape &shape
     IirShape sh = shape;
     if (save) sh.Gr = 1;  // the saved terms need the whole Horner sums in one group
     const int nb = (p.H + sh.B - 1) / sh.B;
-    dim3 gv((sh.P + 63) / 64, nb, sh.G);
+    // the end-state pass has nothing to do on the stack's pad columns: its
+    // grid covers the image columns only (an even number of waves per SIMD
+    // where the column pass has one extra, nearly empty, column group)
+    const int cgr = (p.W + 63) / 64, cgp = (sh.P + 63) / 64 - cgr;
+    const dim3 ga(cgr * nb * sh.G), gv((cgr + cgp) * nb * sh.G);
     if (sh.B == 64)
-        BF_LAUNCH("k_vband_agg", (k_vband<64, true>), gv, dim3(64), 0, s, p, c, carry, S, sh.P, sh.G);
+        BF_LAUNCH("k_vband_agg", (k_vband<64, true>), ga, dim3(64), 0, s, p, c, carry, S, sh.P, sh.G, cgr, cgp);
     else if (sh.B == 32)
-        BF_LAUNCH("k_vband_agg", (k_vband<32, true>), gv, dim3(64), 0, s, p, c, carry, S, sh.P, sh.G);
+        BF_LAUNCH("k_vband_agg", (k_vband<32, true>), ga, dim3(64), 0, s, p, c, carry, S, sh.P, sh.G, cgr, cgp);
     else
         return hipErrorInvalidValue;
-    BF_LAUNCH("k_vresolve", k_vresolve, dim3((p.W + kBlock - 1) / kBlock, p.C, 2), dim3(kBlock), 0, s, p, c, nb, carry);
+    BF_LAUNCH("k_vresolve", k_vresolve, dim3((p.W + 63) / 64, p.C, 2), dim3(64), 0, s, p, c, nb, carry);
     if (sh.B == 64)
-        BF_LAUNCH("k_vband", (k_vband<64, false>), gv, dim3(64), 0, s, p, c, carry, S, sh.P, sh.G);
+        BF_LAUNCH("k_vband", (k_vband<64, false>), gv, dim3(64), 0, s, p, c, carry, S, sh.P, sh.G, cgr, cgp);
     else
-        BF_LAUNCH("k_vband", (k_vband<32, false>), gv, dim3(64), 0, s, p, c, carry, S, sh.P, sh.G);
+        BF_LAUNCH("k_vband", (k_vband<32, false>), gv, dim3(64), 0, s, p, c, carry, S, sh.P, sh.G, cgr, cgp);
     switch (sh.L) {
         case 4: hrow_launch<4>(p, c, sh, S, save, s); break;
         case 8: hrow_launch<8>(p, c, sh, S, save, s); break;
