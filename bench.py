@@ -302,15 +302,16 @@ def main():
         log(f"batched: graph {ms_graph:.3f} ms, sequential {ms_seq:.3f} ms")
         del plan_b, graph, bimgs, souts, swss
 
-    # ---------------- forward + backward: 16 x 512^2, sigma_s 4, sigma_r 25 ----------------
+    # ---------------- forward + backward: 16 x 512^2, sigma_r 25 ----------------
+    # sigma_s 4 (the gradient workload; FIR, radius 12) and sigma_s 10 (past the
+    # FIR radius limit: the recursive mode, whose backward differentiates
+    # Deriche's recursion exactly)
     if want("fwdbwd"):
         imgs_np, tgt_np = synthimg.grad_batch()
         gimgs = torch.from_numpy(imgs_np).to(dev)
         tgt = torch.from_numpy(tgt_np).to(dev)
         B_, H_, W_ = gimgs.shape
-        ss_g, sr_g = 4.0, 25.0
-        fws = bf.workspace(H_, W_, DEGREE, ss_g, "fir")
-        bws = bf.backward_workspace(H_, W_, DEGREE, ss_g, "fir")
+        sr_g = 25.0
         saved = torch.empty(B_, 16 * H_ * W_, dtype=torch.uint8, device=dev)
         fout = torch.empty_like(gimgs)
         gout = torch.empty_like(gimgs)
@@ -318,27 +319,32 @@ def main():
         gls = torch.zeros(B_, dtype=torch.float64, device=dev)
         glr = torch.zeros(B_, dtype=torch.float64, device=dev)
         stream = bf._stream(dev)
-        flags = bf._flags("fir")
-
-        def fwd_bwd():
-            for i in range(B_):
-                bf.gp_forward(gimgs[i], ss_g, sr_g, DEGREE, spatial="fir", out=fout[i], ws=fws, saved=saved[i])
-                torch.sub(fout[i], tgt, out=gout[i])
-                bf._check(bf.bf_gp_backward(gimgs[i].data_ptr(), gout[i].data_ptr(), saved[i].data_ptr(), H_, W_, W_,
-                                            ss_g, sr_g, DEGREE, flags, gimg[i].data_ptr(), gls[i:].data_ptr(),
-                                            glr[i:].data_ptr(), bws.data_ptr(), bws.numel(), stream), "backward")
-
-        def fwd_only():
-            for i in range(B_):
-                bf.gp_forward(gimgs[i], ss_g, sr_g, DEGREE, spatial="fir", out=fout[i], ws=fws)
-
-        ms_fb = timed(fwd_bwd, K, Wm, torch)
-        ms_f = timed(fwd_only, K, Wm, torch)
         npx = B_ * H_ * W_
-        modes["fwd_bwd_16x512"] = {"ms": ms_fb, "mpix_s": npx / (ms_fb * 1e-3) / 1e6, "fwd_only_ms": ms_f,
-                                   "fwd_only_mpix_s": npx / (ms_f * 1e-3) / 1e6, "plan": "fir",
-                                   "grad_log_sigma_s_sum": float(gls.sum()), "grad_log_sigma_r_sum": float(glr.sum())}
-        log(f"fwd+bwd: {ms_fb:.3f} ms (fwd only {ms_f:.3f} ms)")
+        for key, ss_g, mode in (("fwd_bwd_16x512", 4.0, "fir"), ("fwd_bwd_16x512_sigma_s10_iir", 10.0, "iir")):
+            fws = bf.workspace(H_, W_, DEGREE, ss_g, mode)
+            bws = bf.backward_workspace(H_, W_, DEGREE, ss_g, mode)
+            flags = bf._flags(mode)
+
+            def fwd_bwd():
+                for i in range(B_):
+                    bf.gp_forward(gimgs[i], ss_g, sr_g, DEGREE, spatial=mode, out=fout[i], ws=fws, saved=saved[i])
+                    torch.sub(fout[i], tgt, out=gout[i])
+                    bf._check(bf.bf_gp_backward(gimgs[i].data_ptr(), gout[i].data_ptr(), saved[i].data_ptr(), H_,
+                                                W_, W_, ss_g, sr_g, DEGREE, flags, gimg[i].data_ptr(),
+                                                gls[i:].data_ptr(), glr[i:].data_ptr(), bws.data_ptr(), bws.numel(),
+                                                stream), "backward")
+
+            def fwd_only():
+                for i in range(B_):
+                    bf.gp_forward(gimgs[i], ss_g, sr_g, DEGREE, spatial=mode, out=fout[i], ws=fws)
+
+            ms_fb = timed(fwd_bwd, K, Wm, torch)
+            ms_f = timed(fwd_only, K, Wm, torch)
+            modes[key] = {"ms": ms_fb, "mpix_s": npx / (ms_fb * 1e-3) / 1e6, "fwd_only_ms": ms_f,
+                          "fwd_only_mpix_s": npx / (ms_f * 1e-3) / 1e6, "plan": mode, "sigma_s": ss_g,
+                          "grad_log_sigma_s_sum": float(gls.sum()), "grad_log_sigma_r_sum": float(glr.sum())}
+            log(f"fwd+bwd {mode} sigma_s {ss_g}: {ms_fb:.3f} ms (fwd only {ms_f:.3f} ms)")
+            del fws, bws
 
     # ---------------- copy calibration for the traffic counters ----------------
     if want("calib"):
