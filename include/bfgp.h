@@ -126,7 +126,8 @@ int bf_gp_get_fir_crossover_table(long long *max_pixels, int *radius, int max);
  * They change how the passes split the work, hence the rounding of the
  * result (never its mathematics), and the workspace size of the IIR mode:
  * size the workspace after setting them.  The batched plan reads them when it
- * is built.  Returns BF_EINVAL for values outside the ranges. */
+ * is built.  The IIR backward takes col_groups and row_groups (capped at 4)
+ * as its channel groups.  Returns BF_EINVAL for values outside the ranges. */
 int bf_gp_set_iir_tuning(int band_rows, int col_groups, int row_groups);
 /* The IIR launch shape an H x W image of degree N gets under the current
  * settings: shape[0] band rows, [1] column channel groups, [2] samples per row

@@ -576,6 +576,13 @@ int bf_gp_backward(const float *img, const float *grad_out, const void *saved, i
         b.chz = (float *)(w + L.chz);
         b.bparts = (BwdPartial *)(w + L.bparts);
         b.Hp = L.Hp;
+        bwd_iir_groups(H, W, N + 2, &b.Gv, &b.Gh);
+        // the tuning overrides of the column and row channel groups apply here too
+        if (g_col_groups.load() > 0) b.Gv = g_col_groups.load() < N + 2 ? g_col_groups.load() : N + 2;
+        if (g_row_groups.load() > 0) {
+            const int gr = g_row_groups.load() < 4 ? g_row_groups.load() : 4;
+            b.Gh = gr < N + 2 ? gr : N + 2;
+        }
         e = launch_bwd_iir(p, b, make_iir_tan(sigma_s), (double *)(w + L.corr), grad_log_sigma_s, grad_log_sigma_r, s);
         if (e != hipSuccess) return hip_fail(e, "backward launch");
         return BF_OK;

@@ -152,11 +152,21 @@ __device__ __forceinline__ Stats reduce_stats(const GPParams &p) {
     const int lane = threadIdx.x & 63;
     double s = 0.0;
     float lo = __builtin_inff(), hi = -__builtin_inff();
-    for (int i = lane; i < p.nparts; i += 64) {
-        const Partial q = p.parts[i];
-        s += q.sum;
-        lo = fminf(lo, q.lo);
-        hi = fmaxf(hi, q.hi);
+    // all of a lane's partials (at most kMaxParts / 64) are loaded at once from
+    // clamped indices, then summed in index order
+    Partial q[kMaxParts / 64];
+#pragma unroll
+    for (int k = 0; k < kMaxParts / 64; ++k) {
+        const int i = lane + 64 * k;
+        q[k] = p.parts[i < p.nparts ? i : 0];
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxParts / 64; ++k) {
+        if (lane + 64 * k < p.nparts) {
+            s += q[k].sum;
+            lo = fminf(lo, q[k].lo);
+            hi = fmaxf(hi, q[k].hi);
+        }
     }
     s = __shfl(wave_sum(s), 0, 64);
     lo = wave_min(lo);

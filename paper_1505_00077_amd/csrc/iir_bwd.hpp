@@ -24,19 +24,24 @@
 // lane per line, so the column pass writes P and Q transposed (PT[n][x][y])
 // and the row pass reads them with lanes along y, coalesced.
 //
-// The contraction runs over the channels in descending order as Horner
-// evaluations in tau (double):
-//   sum_n W_n u_n' = e^{-tau^2/2} sum_{m=0}^{N+2} c_m p_m,
-//       c_m = sqrt(m+1) W_{m+1} - sqrt(m) W_{m-1}   (W_n = 0 outside 0..N+1),
-//   sum_n Z_n u_n  = e^{-tau^2/2} sum_n Z_n p_n,
-// using u_n' = sqrt(n) u_{n-1} - sqrt(n+1) u_{n+1}.
+// The contraction uses u_n' = sqrt(n) u_{n-1} - sqrt(n+1) u_{n+1}, u_n =
+// e^{-tau^2/2} p_n, so that
+//   sum_n W_n u_n' = e^{-tau^2/2} (S1 - tau S2),  sum_n Z_n u_n = e^{-tau^2/2} S3,
+//   S1 = sum_{n>=1} sqrt(n) W_n p_{n-1},  S2 = sum_n W_n p_n,  S3 = sum_n Z_n p_n,
+// three power series in tau, each evaluated by Horner (double) over the
+// channels of a group in descending order; group g (channels cb..ce-1) holds
+// its sums relative to p_cb (p_{cb-1} for S1) and is scaled by p_cb(tau) =
+// tau^cb / sqrt(cb!) before the groups are added in a fixed order.  Channel
+// groups split both passes when the image gives too few waves; the channel
+// recurrence of the column pass then starts from p_{cb-1} directly.
 #pragma once
 #include "common.hpp"
 #include "bwd.hpp"
+#include "iir.hpp"
 
 namespace bfgp {
 
-constexpr int kBwdBV = 32;  // band rows of the column pass
+constexpr int kBwdBV = 16;  // band rows of the column pass
 constexpr int kBwdBH = 16;  // band columns of the row pass
 
 // Section coefficients (as in IirCoef), their derivatives in log sigma_s, and
@@ -60,7 +65,22 @@ struct BwdIir {
     float *chz;             // row carries [nbh][C][16][Hp]
     BwdPartial *bparts;     // one per row-pass workgroup
     int Hp;                 // rows of the transposed stacks: H rounded up to 64
+    int Gv, Gh;             // channel groups of the column and the row passes
 };
+
+// 1 / sqrt(k!) (k uniform over the wave); p_k(x) = x^k / sqrt(k!) is
+// ipow(x, k) times it.
+__device__ __forceinline__ double inv_sqrt_fact(const GPParams &p, int k) {
+    double c = 1.0;
+    for (int j = 1; j <= k; ++j) c *= p.isq[j];
+    return c;
+}
+
+// LDS bytes of the row pass with G channel groups in one workgroup: the
+// scaled sums (S1, S2, S3) of groups 1..G-1 for every lane and sample.
+__host__ __device__ constexpr size_t bhband_smem_bytes(int G, int B) {
+    return sizeof(double) * 3 * (size_t)(G > 1 ? G - 1 : 0) * (size_t)B * 64;
+}
 
 // One step of a causal section with its tangent.  (y1, y2, t1, t2) is the
 // state; xc, xp are the current and previous inputs, tc, tp their tangents.
@@ -103,7 +123,7 @@ __device__ __forceinline__ void astep(const IirTan &c, int s, float x1, float x2
 // columns, used for the transposed store).
 template <int B, bool AGG>
 __device__ __forceinline__ void bvband(const GPParams &p, const BwdIir &b, const IirTan &c, const Stats &st, int col0,
-                                       int band, float *tile) {
+                                       int band, int cb, int ce, float *tile) {
     const int lane = threadIdx.x & 63;
     const int col = col0 + lane;
     const bool live = col < p.W;
@@ -127,8 +147,13 @@ __device__ __forceinline__ void bvband(const GPParams &p, const BwdIir &b, const
         rr[i] = in ? r : 0.f;
         s[i] = in ? (double)g * p.sigma_r / dp : 0.0;
     }
+    if (cb > 1) {
+        const double cf = inv_sqrt_fact(p, cb - 1);
+#pragma unroll
+        for (int i = 0; i < B + 3; ++i) s[i] *= ipow((double)xr[i], cb - 1) * cf;  // a p_{cb-1}
+    }
     float *tp = tile, *tq = tile + B * 65;
-    for (int n = 0; n < p.C; ++n) {
+    for (int n = cb; n < ce; ++n) {
         float v[B + 3];
         if (n == 0) {
 #pragma unroll
@@ -267,33 +292,35 @@ __device__ __forceinline__ void bresolve(const float (*phi)[4], const float (*ps
 }
 
 // Row pass over the transposed stacks for one band of B columns in one image
-// row y (lane).  AGG: end states from rest into b.chz.  !AGG: rerun from the
-// resolved states, contract with u_n' and u_n at every pixel (descending
-// channel order, Horner in tau), then form the image gradient and this
-// wave's partial sums (bp: its slot in b.bparts).
+// row y (lane), channels cb..ce-1.  AGG: end states from rest into b.chz.
+// !AGG: rerun from the resolved states and accumulate the group's Horner sums
+// (descending channels); the workgroup holds the G groups of the same rows and
+// band (wave g = group g), groups 1.. hand their scaled sums to group 0
+// through `red`, and group 0 forms the image gradient and this workgroup's
+// partial sums (bp).
 template <int B, bool AGG>
 __device__ __forceinline__ void bhband(const GPParams &p, const BwdIir &b, const IirTan &c, const Stats &st, int y,
-                                       int band, BwdPartial *bp) {
+                                       int band, int cb, int ce, int g, int G, BwdPartial *bp, double *red) {
+    const int lane = threadIdx.x & 63;
     const bool live = y < p.H;
     const int yl = live ? y : p.H - 1;  // rows past the image read a real row, results discarded
     const int a = band * B;
     const size_t Hp = (size_t)b.Hp;
-    double hg[AGG ? 1 : B], hz[AGG ? 1 : B], xd[AGG ? 1 : B];
-    float w1[AGG ? 1 : B], w2[AGG ? 1 : B];
+    double h1[AGG ? 1 : B], h2[AGG ? 1 : B], h3[AGG ? 1 : B];
+    float xf[AGG ? 1 : B];
     if constexpr (!AGG) {
 #pragma unroll
         for (int i = 0; i < B; ++i) {
             const int x = a + i;
             const float f = p.img[(size_t)yl * p.pitch + (x < p.W ? x : p.W - 1)];
-            xd[i] = x < p.W ? (double)centred(f, st, p.inv_sigma_r) : 0.0;
-            hg[i] = 0.0;
-            hz[i] = 0.0;
-            w1[i] = 0.f;
-            w2[i] = 0.f;
+            xf[i] = x < p.W ? centred(f, st, p.inv_sigma_r) : 0.f;
+            h1[i] = 0.0;
+            h2[i] = 0.0;
+            h3[i] = 0.0;
         }
     }
-    for (int it = 0; it < p.C; ++it) {
-        const int n = AGG ? it : p.C - 1 - it;
+    for (int it = 0; it < ce - cb; ++it) {
+        const int n = AGG ? cb + it : ce - 1 - it;
         // samples a-1 .. a+B+1 of stack row n (clamped loads, masked)
         float P[B + 3], Q[B + 3];
         const float *pt = b.PT + (size_t)n * p.W * Hp + yl;
@@ -384,54 +411,90 @@ __device__ __forceinline__ void bhband(const GPParams &p, const BwdIir &b, const
             }
         }
         if constexpr (!AGG) {
-            // Horner steps: m = n + 1 of the u_n' sum, n of the u_n sum
-            const double s2 = n + 2 <= p.C - 1 ? p.sq[n + 2] : 0.0;
-            const double s1 = p.sq[n + 1];
-            const double r2 = p.isq[n + 2], r1 = p.isq[n + 1];
+            // Horner steps of S2, S3 (ratio tau / sqrt(n+1)) and of S1 (ratio
+            // tau / sqrt(n), channels n >= 1)
+            const double r2 = p.isq[n + 1], r1 = p.isq[n], sq = p.sq[n];
 #pragma unroll
             for (int i = 0; i < B; ++i) {
-                const double cm = fma(s2, (double)w2[i], -s1 * (double)wc[i]);
-                hg[i] = fma(hg[i], xd[i] * r2, cm);
-                hz[i] = fma(hz[i], xd[i] * r1, (double)zc[i]);
-                w2[i] = w1[i];
-                w1[i] = wc[i];
+                const double xd = (double)xf[i], wd = (double)wc[i];
+                h2[i] = fma(h2[i], xd * r2, wd);
+                h3[i] = fma(h3[i], xd * r2, (double)zc[i]);
+                if (n >= 1) h1[i] = fma(h1[i], xd * r1, sq * wd);
             }
         }
     }
-    if constexpr (AGG) return;
-    // last Horner step of the u_n' sum (m = 0: c_0 = W_1), then per pixel
-    double s_gh = 0.0, s_xgH = 0.0, s_grho = 0.0, s_zu = 0.0, s_g = 0.0;
+    if constexpr (AGG) {
+        return;
+    } else {
+        // scale to the full sums: S1 by p_{cb-1}, S2 and S3 by p_cb
+        // (group 0 needs none: its S1 ran over n >= 1 relative to p_0 = 1)
+        if (cb > 0) {
+            const double c1 = inv_sqrt_fact(p, cb - 1);
 #pragma unroll
-    for (int i = 0; i < B; ++i) {
-        const int x = a + i;
-        const double hgi = fma(hg[i], xd[i] * p.isq[1], (double)w2[i]);
-        if (live && x < p.W) {
-            const double e = exp(-0.5 * xd[i] * xd[i]);
-            const size_t pi = (size_t)y * p.pitch + x, qi = (size_t)y * p.W + x;
-            const double g = (double)b.grad_out[pi];
-            const double h = fma(e, hgi, g * p.sigma_r * (double)b.drho[qi]);
-            const double gh = h * p.inv_sigma_r;
-            if (b.grad_img) b.grad_img[pi] = (float)gh;
-            s_gh += gh;
-            s_xgH += xd[i] * h;
-            s_grho += g * p.sigma_r * (double)b.rho[qi];
-            s_zu += e * hz[i];
-            s_g += g;
+            for (int i = 0; i < B; ++i) {
+                const double xd = (double)xf[i];
+                const double q1 = ipow(xd, cb - 1) * c1;  // p_{cb-1}
+                const double q2 = q1 * xd * p.isq[cb];    // p_cb
+                h1[i] *= q1;
+                h2[i] *= q2;
+                h3[i] *= q2;
+            }
         }
-    }
-    s_gh = wave_sum(s_gh);
-    s_xgH = wave_sum(s_xgH);
-    s_grho = wave_sum(s_grho);
-    s_zu = wave_sum(s_zu);
-    s_g = wave_sum(s_g);
-    if ((threadIdx.x & 63) == 0) {
-        BwdPartial o;
-        o.sum_gh = s_gh;
-        o.sum_xgH = s_xgH;
-        o.sum_grho = s_grho;
-        o.sum_zu = s_zu;
-        o.sum_g = s_g;
-        *bp = o;
+        if (G > 1) {
+            if (g > 0) {
+                double *r = red + (size_t)(g - 1) * 3 * B * 64;
+#pragma unroll
+                for (int i = 0; i < B; ++i) {
+                    r[(0 * B + i) * 64 + lane] = h1[i];
+                    r[(1 * B + i) * 64 + lane] = h2[i];
+                    r[(2 * B + i) * 64 + lane] = h3[i];
+                }
+            }
+            __syncthreads();
+            if (g > 0) return;
+            for (int gg = 1; gg < G; ++gg) {
+                const double *r = red + (size_t)(gg - 1) * 3 * B * 64;
+#pragma unroll
+                for (int i = 0; i < B; ++i) {
+                    h1[i] += r[(0 * B + i) * 64 + lane];
+                    h2[i] += r[(1 * B + i) * 64 + lane];
+                    h3[i] += r[(2 * B + i) * 64 + lane];
+                }
+            }
+        }
+        double s_gh = 0.0, s_xgH = 0.0, s_grho = 0.0, s_zu = 0.0, s_g = 0.0;
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            const int x = a + i;
+            if (live && x < p.W) {
+                const double xd = (double)xf[i];
+                const double e = exp(-0.5 * xd * xd);
+                const size_t pi = (size_t)y * p.pitch + x, qi = (size_t)y * p.W + x;
+                const double gv = (double)b.grad_out[pi];
+                const double h = fma(e, fma(-xd, h2[i], h1[i]), gv * p.sigma_r * (double)b.drho[qi]);
+                const double gh = h * p.inv_sigma_r;
+                if (b.grad_img) b.grad_img[pi] = (float)gh;
+                s_gh += gh;
+                s_xgH += xd * h;
+                s_grho += gv * p.sigma_r * (double)b.rho[qi];
+                s_zu += e * h3[i];
+                s_g += gv;
+            }
+        }
+        s_gh = wave_sum(s_gh);
+        s_xgH = wave_sum(s_xgH);
+        s_grho = wave_sum(s_grho);
+        s_zu = wave_sum(s_zu);
+        s_g = wave_sum(s_g);
+        if (lane == 0) {
+            BwdPartial o;
+            o.sum_gh = s_gh;
+            o.sum_xgH = s_xgH;
+            o.sum_grho = s_grho;
+            o.sum_zu = s_zu;
+            o.sum_g = s_g;
+            *bp = o;
+        }
     }
 }
 

@@ -74,46 +74,71 @@ hipError_t launch_bwd(const GPParams &p, const BwdParams &b, const FirTaps2 &t, 
 // ---- recursive (IIR) mode ------------------------------------------------------
 
 template <bool AGG>
-__global__ __launch_bounds__(64) void k_bvband(GPParams p, BwdIir b, IirTan c) {
+__global__ __launch_bounds__(64) void k_bwd_vband(GPParams p, BwdIir b, IirTan c) {
     __shared__ float tile[AGG ? 1 : 2 * kBwdBV * 65];
     const Stats st = load_stats(p);
-    bvband<kBwdBV, AGG>(p, b, c, st, blockIdx.x * 64, blockIdx.y, tile);
+    const int g = blockIdx.z;
+    bvband<kBwdBV, AGG>(p, b, c, st, blockIdx.x * 64, blockIdx.y, (p.C * g) / b.Gv, (p.C * (g + 1)) / b.Gv, tile);
 }
 
 // lines: lines to resolve; stride: line stride of the carry array; horiz
 // selects the band transfer blocks of the row pass.
-__global__ __launch_bounds__(kBlock) void k_bresolve(GPParams p, IirTan c, float *carry, int nb, int lines, int stride,
-                                                     int horiz) {
-    const int line = blockIdx.x * kBlock + threadIdx.x;
+__global__ __launch_bounds__(64) void k_bwd_resolve(GPParams p, IirTan c, float *carry, int nb, int lines, int stride,
+                                                    int horiz) {
+    const int line = blockIdx.x * 64 + threadIdx.x;
     if (line < lines)
         bresolve(horiz ? c.phiH : c.phiV, horiz ? c.psiH : c.psiV, nb, p.C, blockIdx.y, blockIdx.z, (size_t)stride,
                  (size_t)line, carry);
 }
 
-template <bool AGG>
-__global__ __launch_bounds__(64) void k_bhband(GPParams p, BwdIir b, IirTan c) {
+// End states: one wave per (64 rows, band, channel group).
+__global__ __launch_bounds__(64) void k_bwd_hband_agg(GPParams p, BwdIir b, IirTan c) {
     const Stats st = load_stats(p);
-    bhband<kBwdBH, AGG>(p, b, c, st, blockIdx.x * 64 + threadIdx.x, blockIdx.y,
-                        b.bparts + (size_t)blockIdx.y * gridDim.x + blockIdx.x);
+    const int g = blockIdx.z;
+    bhband<kBwdBH, true>(p, b, c, st, blockIdx.x * 64 + threadIdx.x, blockIdx.y, (p.C * g) / b.Gh,
+                         (p.C * (g + 1)) / b.Gh, g, b.Gh, nullptr, nullptr);
+}
+
+// Rerun and contraction: one workgroup of Gh waves per (64 rows, band).
+__global__ __launch_bounds__(256) void k_bwd_hband(GPParams p, BwdIir b, IirTan c) {
+    extern __shared__ double red[];
+    const Stats st = load_stats(p);
+    const int g = __builtin_amdgcn_readfirstlane((int)threadIdx.x / 64);
+    bhband<kBwdBH, false>(p, b, c, st, blockIdx.x * 64 + (threadIdx.x & 63), blockIdx.y, (p.C * g) / b.Gh,
+                          (p.C * (g + 1)) / b.Gh, g, b.Gh, b.bparts + (size_t)blockIdx.y * gridDim.x + blockIdx.x, red);
 }
 
 static int iir_hp(int H) { return ((H + 63) / 64) * 64; }
 int bwd_iir_parts(int H, int W) { return (iir_hp(H) / 64) * ((W + kBwdBH - 1) / kBwdBH); }
 
+// Channel groups of the backward passes: enough waves for the device (about
+// two per SIMD), at most 8 (column pass) and 4 (row pass, one workgroup).
+void bwd_iir_groups(int H, int W, int C, int *Gv, int *Gh) {
+    const long target = 2048;
+    const long wv = (long)((W + 63) / 64) * ((H + kBwdBV - 1) / kBwdBV);
+    const long wh = (long)(iir_hp(H) / 64) * ((W + kBwdBH - 1) / kBwdBH);
+    long gv = (target + wv - 1) / wv, gh = (target + wh - 1) / wh;
+    gv = gv < 1 ? 1 : (gv > 8 ? 8 : gv);
+    gh = gh < 1 ? 1 : (gh > 4 ? 4 : gh);
+    *Gv = (int)(gv > C ? C : gv);
+    *Gh = (int)(gh > C ? C : gh);
+}
+
 hipError_t launch_bwd_iir(const GPParams &p, const BwdIir &b, const IirTan &c, double *corr, double *g_lss,
                           double *g_lsr, hipStream_t s) {
-    if (b.Hp != iir_hp(p.H)) return hipErrorInvalidValue;
+    if (b.Hp != iir_hp(p.H) || b.Gv < 1 || b.Gv > p.C || b.Gh < 1 || b.Gh > 4 || b.Gh > p.C)
+        return hipErrorInvalidValue;
     const int nbv = (p.H + kBwdBV - 1) / kBwdBV, nbh = (p.W + kBwdBH - 1) / kBwdBH;
-    const dim3 gv((p.W + 63) / 64, nbv);
-    BF_LAUNCH("k_bvband_agg", k_bvband<true>, gv, dim3(64), 0, s, p, b, c);
-    BF_LAUNCH("k_bresolve", k_bresolve, dim3((p.W + kBlock - 1) / kBlock, p.C, 2), dim3(kBlock), 0, s, p, c, b.cv,
-              nbv, p.W, p.W, 0);
-    BF_LAUNCH("k_bvband", k_bvband<false>, gv, dim3(64), 0, s, p, b, c);
-    const dim3 gh(b.Hp / 64, nbh);
-    BF_LAUNCH("k_bhband_agg", k_bhband<true>, gh, dim3(64), 0, s, p, b, c);
-    BF_LAUNCH("k_bresolve", k_bresolve, dim3((p.H + kBlock - 1) / kBlock, p.C, 2), dim3(kBlock), 0, s, p, c, b.chz,
-              nbh, p.H, b.Hp, 1);
-    BF_LAUNCH("k_bhband", k_bhband<false>, gh, dim3(64), 0, s, p, b, c);
+    const dim3 gv((p.W + 63) / 64, nbv, b.Gv);
+    BF_LAUNCH("k_bwd_vband_agg", k_bwd_vband<true>, gv, dim3(64), 0, s, p, b, c);
+    BF_LAUNCH("k_bwd_resolve", k_bwd_resolve, dim3((p.W + 63) / 64, p.C, 2), dim3(64), 0, s, p, c, b.cv, nbv, p.W,
+              p.W, 0);
+    BF_LAUNCH("k_bwd_vband", k_bwd_vband<false>, gv, dim3(64), 0, s, p, b, c);
+    BF_LAUNCH("k_bwd_hband_agg", k_bwd_hband_agg, dim3(b.Hp / 64, nbh, b.Gh), dim3(64), 0, s, p, b, c);
+    BF_LAUNCH("k_bwd_resolve", k_bwd_resolve, dim3((p.H + 63) / 64, p.C, 2), dim3(64), 0, s, p, c, b.chz, nbh, p.H,
+              b.Hp, 1);
+    BF_LAUNCH("k_bwd_hband", k_bwd_hband, dim3(b.Hp / 64, nbh), dim3(64 * b.Gh), bhband_smem_bytes(b.Gh, kBwdBH), s,
+              p, b, c);
     BF_LAUNCH("k_bwd_finalize", k_bwd_finalize, dim3(1), dim3(64), 0, s, p, b.bparts, bwd_iir_parts(p.H, p.W), corr,
               g_lss, g_lsr);
     if (b.grad_img && p.center == 0) {

@@ -248,3 +248,24 @@ def test_iir_backward_deterministic_and_full_size(bf):
     assert np.max(np.abs(a[1] - rgi)) <= 1e-3 * scale
     assert a[2] == pytest.approx(rgs, rel=1e-3)
     assert a[3] == pytest.approx(rgr, rel=1e-3)
+
+
+@pytest.mark.parametrize("groups", [(1, 1), (3, 2), (8, 4)])
+def test_iir_backward_channel_groups(bf, groups):
+    # the channel-group split of both backward passes (set through the tuning
+    # overrides) changes only the rounding
+    H, W = 96, 130
+    img = synthimg.voronoi_image(H, W, 16, seed=77)
+    target = synthimg.voronoi_image(H, W, 16, seed=78)
+    try:
+        bf.set_iir_tuning(0, groups[0], groups[1])
+        note(f"backward iir channel groups {groups}")
+        _, gi, gs, gr = gpu_grads(bf, img, target, 9.0, 25.0, 20, spatial="iir")
+    finally:
+        bf.set_iir_tuning(0, 0, 0)
+    rgi, rgs, rgr = oracle_grads(img, target.astype(np.float64), 9.0, 25.0, 20, mode="iir")
+    scale = np.max(np.abs(rgi))
+    assert np.max(np.abs(gi - rgi)) <= 1e-3 * scale
+    assert gs == pytest.approx(rgs, rel=1e-3)
+    assert gr == pytest.approx(rgr, rel=1e-3)
+
