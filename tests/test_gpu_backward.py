@@ -269,3 +269,20 @@ def test_iir_backward_channel_groups(bf, groups):
     assert gs == pytest.approx(rgs, rel=1e-3)
     assert gr == pytest.approx(rgr, rel=1e-3)
 
+
+@pytest.mark.parametrize("spatial,ss", [("fir", 4.0), ("iir", 6.0)])
+def test_backward_large_x_range(bf, spatial, ss):
+    # every |x| in (13.3, 13.8) (no centring): exp(-x^2/2) is below the FP32
+    # normal range; the adjoint channels are formed in double in both modes
+    v = synthimg.voronoi_image(64, 90, 14, seed=93, noise=0)
+    img = (226.0 + 8.0 * (v.astype(np.float64) / 255.0)).astype(np.float32)
+    t = synthimg.voronoi_image(64, 90, 14, seed=94, noise=0)
+    target = 226.0 + 8.0 * (t.astype(np.float64) / 255.0)
+    _, gi, gs, gr = gpu_grads(bf, img, target, ss, 17.0, 20, center="none", spatial=spatial)
+    rgi, rgs, rgr = oracle_grads(img, target, ss, 17.0, 20, oracle.CENTER_NONE, mode=spatial)
+    assert np.isfinite(gi).all()
+    scale = np.max(np.abs(rgi))
+    assert np.max(np.abs(gi - rgi)) <= 1e-3 * scale
+    assert gs == pytest.approx(rgs, rel=1e-3, abs=1e-6 * scale * img.size)
+    assert gr == pytest.approx(rgr, rel=1e-3, abs=1e-6 * scale * img.size)
+

@@ -170,6 +170,28 @@ def test_large_x_range(bf, spatial, ss):
     assert np.max(np.abs(got - ref)) <= TOL, np.max(np.abs(got - ref))
 
 
+@pytest.mark.parametrize("N", [46, 47])
+def test_fir_degree_variant_boundary(bf, N):
+    # the register-column FIR carries unnormalised channels up to degree 46;
+    # above it the region variant (double channels) takes over
+    img = synthimg.voronoi_image(40, 150, 12, seed=91)
+    got = run(bf, img, 2.0, 40.0, N, "fir")
+    ref = oracle_gp(img, 2.0, 40.0, N, "fir")
+    assert np.max(np.abs(got - ref)) <= TOL
+
+
+@pytest.mark.parametrize("top", [11.9, 12.1])
+def test_fir_range_variant_boundary(bf, top):
+    # max |x| just below 12 (register-column variant) and just above it
+    # (region variant), no centring: |x| spans [top - 0.6, top]
+    v = synthimg.voronoi_image(48, 200, 16, seed=92, noise=0)
+    img = ((top - 0.6 + 0.6 * (v.astype(np.float64) / 255.0)) * 20.0).astype(np.float32)
+    got = run(bf, img, 3.0, 20.0, 20, "fir", center="none")
+    ref = oracle_gp(img, 3.0, 20.0, 20, "fir", center=oracle.CENTER_NONE)
+    assert np.isfinite(got).all()
+    assert np.max(np.abs(got - ref)) <= TOL, np.max(np.abs(got - ref))
+
+
 def test_out_of_range_reports_erange(bf):
     img = synthimg.voronoi_image(40, 40, 8, seed=83)
     img[0, 0], img[1, 1] = 0.0, 255.0
