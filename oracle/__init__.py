@@ -51,6 +51,8 @@ def _load():
     lib.or_gp_alg1.argtypes = [dp, dp, i, i, d, i, dp, i, i]
     lib.or_gp_rescaled.argtypes = [dp, dp, dp, dp, i, i, d, i, dp, i, i]
     lib.or_gp_grad.argtypes = [dp, dp, i, i, d, i, dp, dp, i, i, dp, dp, dp]
+    lib.or_joint_direct.argtypes = [dp, dp, dp, i, i, dp, i, d]
+    lib.or_joint_gp.argtypes = [dp, dp, dp, i, i, d, i, dp, i, i]
     lib.or_gauss_poly.argtypes = [d, d, d, i]
     lib.or_gauss_poly.restype = d
     _lib = lib
@@ -223,6 +225,59 @@ def gp_grad_mode(img, gout, sigma_s, sigma_r, N, mode="fir"):
     kt, R2 = spatial_dtable(mode, sigma_s, *f.shape)
     assert R == R2
     return gp_grad(f, gout, sigma_r, N, k, kt)
+
+
+def joint_direct(guide, data, sigma_r, k):
+    """Joint (cross) bilateral filter computed directly: eq. (1) with the range
+    argument taken from the guide and the average taken of the data."""
+    g, f = _img(guide), _img(data)
+    if g.shape != f.shape:
+        raise ValueError("guide and data shapes differ")
+    out = np.empty_like(g)
+    k = np.ascontiguousarray(k, np.float64)
+    _check(_load().or_joint_direct(_p(g), _p(f), _p(out), g.shape[0], g.shape[1], _p(k), len(k) - 1,
+                                   float(sigma_r)), "joint_direct")
+    return out
+
+
+def joint_gp(guide, data, sigma_r, N, k, center_mode=CENTER_MEAN):
+    """Gauss-polynomial approximation of the joint filter, Algorithm 1's steps
+    with the guide in every range term (see oracle.c)."""
+    g, f = _img(guide), _img(data)
+    if g.shape != f.shape:
+        raise ValueError("guide and data shapes differ")
+    out = np.empty_like(g)
+    k = np.ascontiguousarray(k, np.float64)
+    _check(_load().or_joint_gp(_p(g), _p(f), _p(out), g.shape[0], g.shape[1], float(sigma_r), int(N), _p(k),
+                               len(k) - 1, int(center_mode)), "joint_gp")
+    return out
+
+
+def brute_joint(guide, data, sigma_r, N, k, center_value=None):
+    """The joint GP filter as one explicit double sum per pixel (tiny images):
+    weights k(j) exp(-(t^2 + tau^2)/2) T_N(t tau) on the guide's centred
+    values, T_N the degree-N Taylor polynomial of exp (eq. (5))."""
+    g = np.asarray(guide, np.float64)
+    f = np.asarray(data, np.float64)
+    H, W = g.shape
+    tc = g.mean() if center_value is None else center_value
+    x = (g - tc) / sigma_r
+    R = len(k) - 1
+    out = np.empty_like(g)
+    fact = np.array([math.factorial(n) for n in range(N + 1)], np.float64)
+    for yi in range(H):
+        for xi in range(W):
+            tau = x[yi, xi]
+            num = den = 0.0
+            for yj in range(max(0, yi - R), min(H, yi + R + 1)):
+                for xj in range(max(0, xi - R), min(W, xi + R + 1)):
+                    t = x[yj, xj]
+                    w = k[abs(yi - yj)] * k[abs(xi - xj)] * math.exp(-(t * t + tau * tau) / 2) * \
+                        float(np.sum((t * tau) ** np.arange(N + 1) / fact))
+                    num += w * f[yj, xj]
+                    den += w
+            out[yi, xi] = num / den
+    return out
 
 
 def gauss_poly(t, tau, sigma_r, N):

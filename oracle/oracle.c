@@ -265,6 +265,101 @@ int or_gp_alg1(const double *f, double *out, int H, int W, double sigma_r, int N
 }
 
 /* ------------------------------------------------------------------------ */
+/* Joint (cross) bilateral filter                                            */
+/* ------------------------------------------------------------------------ */
+
+/* The extension the paper's conclusion names: the range kernel is evaluated
+ * on a guide image g and the average is taken of a data image f,
+ *   out(i) = sum_j k(j) g_r(g(i-j) - g(i)) f(i-j) / sum_j k(j) g_r(g(i-j) - g(i)),
+ * i.e. eq. (1) with the range argument taken from g (g = f gives eq. (1)). */
+int or_joint_direct(const double *g, const double *f, double *out, int H, int W, const double *k, int R,
+                    double sigma_r)
+{
+    if (!g || !f || !out || !k || H < 1 || W < 1 || R < 0 || !(sigma_r > 0))
+        return OR_EINVAL;
+    const double inv2r2 = 1.0 / (2.0 * sigma_r * sigma_r);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int y = 0; y < H; ++y) {
+        for (int x = 0; x < W; ++x) {
+            const double gi = g[(size_t)y * W + x];
+            double num = 0.0, den = 0.0;
+            for (int dy = -R; dy <= R; ++dy) {
+                int yy = y - dy;
+                if (yy < 0 || yy >= H)
+                    continue;
+                const double ky = k[dy < 0 ? -dy : dy];
+                for (int dx = -R; dx <= R; ++dx) {
+                    int xx = x - dx;
+                    if (xx < 0 || xx >= W)
+                        continue;
+                    const size_t j = (size_t)yy * W + xx;
+                    const double t = g[j] - gi;
+                    const double w = ky * k[dx < 0 ? -dx : dx] * exp(-t * t * inv2r2);
+                    num += w * f[j];
+                    den += w;
+                }
+            }
+            out[(size_t)y * W + x] = num / den;
+        }
+    }
+    return OR_OK;
+}
+
+/* The Gauss-polynomial approximation of the joint filter, in the steps and
+ * notation of Algorithm 1 with the guide in every range term: t_c is the
+ * centre of g, h = g - t_c, F = exp(-h^2 / 2 sigma_r^2), H = h / sigma_r, and
+ * for n = 0..N
+ *     Q += c G (F * g_s),   P += c G ((F f) * g_s),   F = H F,  G = H G,
+ *     c = c / (n + 1),
+ * from the factorisation g_r(g_j - g_i) = F_i F_j exp(H_i H_j) with the
+ * exponential truncated as in eqs. (4)-(5); out = P / Q (the F_i cancel).
+ * With g = f, (F f) = t_c F + sigma_r F H, so P = t_c Q + sigma_r P_alg1 and
+ * the output is Algorithm 1's. */
+int or_joint_gp(const double *g, const double *f, double *out, int H, int W, double sigma_r, int N,
+                const double *k, int R, int center_mode)
+{
+    if (!g || !f || !out || !k || H < 1 || W < 1 || R < 0 || !(sigma_r > 0) || N < 0)
+        return OR_EINVAL;
+    const size_t n = (size_t)H * W;
+    double *G = malloc(sizeof(double) * n), *F = malloc(sizeof(double) * n);
+    double *Fb = malloc(sizeof(double) * n), *P = malloc(sizeof(double) * n);
+    double *Q = malloc(sizeof(double) * n), *Hh = malloc(sizeof(double) * n);
+    double *Ff = malloc(sizeof(double) * n), *tmp = malloc(sizeof(double) * n);
+    if (!G || !F || !Fb || !P || !Q || !Hh || !Ff || !tmp) {
+        free(G); free(F); free(Fb); free(P); free(Q); free(Hh); free(Ff); free(tmp);
+        return OR_ENOMEM;
+    }
+    const double tc = or_center(g, H, W, center_mode);
+    for (size_t i = 0; i < n; ++i) {
+        const double h = g[i] - tc;
+        G[i] = 1.0;
+        F[i] = exp(-h * h / (2.0 * sigma_r * sigma_r));
+        P[i] = 0.0;
+        Q[i] = 0.0;
+        Hh[i] = h / sigma_r;
+    }
+    double c = 1.0;
+    for (int m = 0; m <= N; ++m) {
+        spatial_sep(F, Fb, tmp, H, W, k, k, R);
+        for (size_t i = 0; i < n; ++i) {
+            Q[i] += c * G[i] * Fb[i];
+            Ff[i] = F[i] * f[i];
+        }
+        spatial_sep(Ff, Fb, tmp, H, W, k, k, R);
+        for (size_t i = 0; i < n; ++i) {
+            P[i] += c * G[i] * Fb[i];
+            F[i] = Hh[i] * F[i];
+            G[i] = Hh[i] * G[i];
+        }
+        c = c / (double)(m + 1);
+    }
+    for (size_t i = 0; i < n; ++i)
+        out[i] = P[i] / Q[i];
+    free(G); free(F); free(Fb); free(P); free(Q); free(Hh); free(Ff); free(tmp);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* The same approximation in rescaled channels                               */
 /* ------------------------------------------------------------------------ */
 

@@ -342,3 +342,92 @@ def test_table1_trend_error_grows_with_sigma_s():
     for s in g["sigma_s"][:4]:
         db.append(oracle.mse_db(oracle.gp(f, s, g["sigma_r"], g["N"]), oracle.direct_gauss(f, s, g["sigma_r"])))
     assert all(b > a for a, b in zip(db, db[1:])), db
+
+
+# ---------------------------------------------------------------------------
+# joint (cross) bilateral filter: range kernel on a guide, average of data
+# ---------------------------------------------------------------------------
+
+def test_joint_direct_reduces_to_eq1_when_guide_is_data():
+    f = rand_img(9, 14, 21)
+    k = oracle.gauss_table(1.5, oracle.fir_radius(1.5))
+    assert np.allclose(oracle.joint_direct(f, f, 25.0, k), oracle.direct(f, 25.0, k), rtol=0, atol=1e-11)
+
+
+def test_joint_direct_matches_double_sum():
+    g, f = rand_img(6, 8, 22), rand_img(6, 8, 23)
+    k = oracle.gauss_table(1.2, 4)
+    ref = np.empty_like(g)
+    for yi in range(6):
+        for xi in range(8):
+            num = den = 0.0
+            for yj in range(6):
+                for xj in range(8):
+                    if abs(yi - yj) > 4 or abs(xi - xj) > 4:
+                        continue
+                    w = k[abs(yi - yj)] * k[abs(xi - xj)] * math.exp(-(g[yj, xj] - g[yi, xi]) ** 2 / (2 * 30.0 ** 2))
+                    num += w * f[yj, xj]
+                    den += w
+            ref[yi, xi] = num / den
+    assert np.allclose(oracle.joint_direct(g, f, 30.0, k), ref, rtol=0, atol=1e-10)
+
+
+@pytest.mark.parametrize("N", [0, 3, 8, 20])
+def test_joint_gp_reduces_to_alg1_when_guide_is_data(N):
+    # with g = f, F f = t_c F + sigma_r F H, so the joint numerator is
+    # t_c Q + sigma_r P of Algorithm 1 and the outputs agree exactly
+    f = voronoi_image(30, 44, 9, seed=24).astype(np.float64)
+    for mode, s in (("fir", 2.0), ("iir", 3.0)):
+        k, _ = oracle.spatial_table(mode, s, *f.shape)
+        assert np.max(np.abs(oracle.joint_gp(f, f, 30.0, N, k) - oracle.gp_alg1(f, 30.0, N, k))) < 1e-9
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_joint_gp_matches_explicit_double_sum(case):
+    rng = np.random.default_rng(300 + case)
+    H, W = int(rng.integers(5, 8)), int(rng.integers(6, 10))
+    g = rng.uniform(0, 255, size=(H, W))
+    f = rng.uniform(0, 255, size=(H, W))
+    s = float(rng.uniform(0.6, 1.6))
+    r = float(rng.uniform(30, 70))
+    N = [0, 4, 10, 20][case]
+    for kind in ("gauss", "deriche"):
+        R = oracle.fir_radius(s) if kind == "gauss" else 2 * oracle.fir_radius(s)
+        k = oracle.gauss_table(s, R) if kind == "gauss" else oracle.deriche_table(s, R)
+        ref = oracle.brute_joint(g, f, r, N, k)
+        assert np.allclose(oracle.joint_gp(g, f, r, N, k), ref, rtol=0, atol=1e-9), kind
+
+
+def test_joint_gp_linear_in_data_and_constant_data():
+    g = voronoi_image(20, 33, 7, seed=25).astype(np.float64)
+    f1, f2 = rand_img(20, 33, 26), rand_img(20, 33, 27)
+    k = oracle.gauss_table(2.0, 6)
+    a = oracle.joint_gp(g, 2.0 * f1 - 3.0 * f2, 25.0, 12, k)
+    b = 2.0 * oracle.joint_gp(g, f1, 25.0, 12, k) - 3.0 * oracle.joint_gp(g, f2, 25.0, 12, k)
+    assert np.max(np.abs(a - b)) < 1e-9
+    # constant data come back unchanged, whatever the guide (even degree)
+    assert np.max(np.abs(oracle.joint_gp(g, np.full_like(g, 42.5), 25.0, 12, k) - 42.5)) < 1e-11
+
+
+def test_joint_gp_wide_range_kernel_is_normalised_blur_of_data():
+    g, f = rand_img(17, 23, 28), rand_img(17, 23, 29)
+    k = oracle.gauss_table(1.5, 5)
+    w = np.concatenate([k[:0:-1], k])
+
+    def blur(a):
+        return ndimage.correlate1d(ndimage.correlate1d(a, w, axis=0, mode="constant"), w, axis=1, mode="constant")
+
+    assert np.allclose(oracle.joint_gp(g, f, 1e7, 2, k), blur(f) / blur(np.ones_like(f)), rtol=0, atol=1e-7)
+
+
+def test_joint_gp_converges_to_joint_direct_and_ignores_guide_offset():
+    g = voronoi_image(36, 50, 10, seed=30).astype(np.float64)
+    f = voronoi_image(36, 50, 10, seed=31).astype(np.float64)
+    k = oracle.gauss_table(2.0, oracle.fir_radius(2.0))
+    ref = oracle.joint_direct(g, f, 30.0, k)
+    errs = [np.max(np.abs(oracle.joint_gp(g, f, 30.0, N, k) - ref)) for N in (10, 20, 40, 60)]
+    assert errs[0] > errs[1] > errs[2] > errs[3] and errs[3] < 1e-6
+    # the range kernel sees guide differences only: with mean centring, a
+    # constant added to the guide changes nothing
+    assert np.max(np.abs(oracle.joint_gp(g + 37.0, f, 30.0, 20, k) - oracle.joint_gp(g, f, 30.0, 20, k))) < 1e-9
+
