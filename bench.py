@@ -346,6 +346,22 @@ def main():
             log(f"fwd+bwd {mode} sigma_s {ss_g}: {ms_fb:.3f} ms (fwd only {ms_f:.3f} ms)")
             del fws, bws
 
+    # ---------------- joint (cross) filter: 1024^2, guide and data images ----------------
+    if want("joint"):
+        guide = torch.from_numpy(synthimg.mid_1024()).to(dev)
+        jdata = torch.from_numpy(synthimg.voronoi_image(1024, 1024, 300, seed=12)).to(dev)
+        jout = torch.empty_like(guide)
+        jres = {}
+        for ss_j in (2.0, 10.0):
+            jws = bf.joint_workspace(1024, 1024, DEGREE, ss_j)
+            ms_j = timed(lambda: bf.gp_joint_forward(guide, jdata, ss_j, SIGMA_R, DEGREE, out=jout, ws=jws), K, Wm,
+                         torch)
+            jres[str(ss_j)] = {"ms": ms_j, "mpix_s": guide.numel() / (ms_j * 1e-3) / 1e6, "plan": "iir",
+                               "channels": 2 * (DEGREE + 1)}
+            del jws
+        modes["joint_1024"] = jres
+        log("joint 1024^2: " + ", ".join(f"sigma_s {k} {v['ms']:.3f} ms" for k, v in jres.items()))
+
     # ---------------- copy calibration for the traffic counters ----------------
     if want("calib"):
         # a plain device-to-device copy of 256 MiB: its FETCH_SIZE / WRITE_SIZE

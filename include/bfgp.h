@@ -90,6 +90,31 @@ int bf_gp_forward(const float *img, float *out, int H, int W, int pitch,
                   double sigma_s, double sigma_r, int N, unsigned flags,
                   void *saved, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- joint (cross) GP forward ------------------------------------------------
+ * The variant the Conclusion names as a direct extension: the range kernel is
+ * evaluated on a guide image g and the weighted average is taken of a data
+ * image f,
+ *     out(i) = sum_j k(j) g_r(g(i-j) - g(i)) f(i-j) / sum_j k(j) g_r(g(i-j) - g(i)),
+ * approximated as in Algorithm 1 with the guide in every range term: with
+ * x = (g - t_c)/sigma_r (t_c the guide's centre) and the channels u_n(x) and
+ * u_n(x) f, n = 0..N, each filtered spatially,
+ *     out = sum_n u_n(tau) Kbar[u_n f] / sum_n u_n(tau) Kbar[u_n],  tau = x(i).
+ * With g = f it equals bf_gp_forward.  2 (N + 1) channels.
+ *  guide, data, out  device, H x W with one row pitch `pitch`; out may alias
+ *                    neither input.
+ *  flags             BF_SPATIAL_AUTO or BF_SPATIAL_IIR (the recursive Gaussian,
+ *                    as in the paper's experiments; BF_SPATIAL_FIR returns
+ *                    BF_EUNSUPPORTED), | BF_CENTER_*.  W up to 8192.
+ *  ws, ws_bytes      device workspace of bf_gp_joint_workspace_bytes(...) bytes
+ *                    (0 for unsupported arguments).
+ * A guide too far from its centre for the FP32 channels makes the output NaN
+ * and sets BF_ERANGE in the workspace status, as bf_gp_forward does. */
+size_t bf_gp_joint_workspace_bytes(int H, int W, int N, double sigma_s, unsigned flags);
+
+int bf_gp_joint_forward(const float *guide, const float *data, float *out, int H, int W, int pitch,
+                        double sigma_s, double sigma_r, int N, unsigned flags,
+                        void *ws, size_t ws_bytes, void *stream);
+
 /* Blocking: waits for `stream`, then stores the status of the last forward or
  * backward that used `ws` in *status (BF_OK or BF_ERANGE). */
 int bf_gp_status(const void *ws, void *stream, int *status);

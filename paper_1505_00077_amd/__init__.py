@@ -48,6 +48,8 @@ bf_version = _sig("bf_version", _i)
 bf_last_error = _sig("bf_last_error", ctypes.c_char_p)
 bf_gp_workspace_bytes = _sig("bf_gp_workspace_bytes", _sz, _i, _i, _i, _d, _u)
 bf_gp_forward = _sig("bf_gp_forward", _i, _vp, _vp, _i, _i, _i, _d, _d, _i, _u, _vp, _vp, _sz, _vp)
+bf_gp_joint_workspace_bytes = _sig("bf_gp_joint_workspace_bytes", _sz, _i, _i, _i, _d, _u)
+bf_gp_joint_forward = _sig("bf_gp_joint_forward", _i, _vp, _vp, _vp, _i, _i, _i, _d, _d, _i, _u, _vp, _sz, _vp)
 bf_gp_status = _sig("bf_gp_status", _i, _vp, _vp, ctypes.POINTER(_i))
 bf_gp_resolve_spatial = _sig("bf_gp_resolve_spatial", _u, _d, _u)
 bf_gp_resolve_spatial_for = _sig("bf_gp_resolve_spatial_for", _u, _i, _i, _d, _u)
@@ -173,6 +175,39 @@ def gp_forward(img, sigma_s, sigma_r, N=20, spatial="auto", center="mean", out=N
         st = status(ws, img.device)
         if st != BF_OK:
             raise BfError(st, "bf_gp_forward (device status)")
+    return out
+
+
+def joint_workspace(H, W, N, sigma_s, spatial="auto", center="mean", device="cuda"):
+    n = int(bf_gp_joint_workspace_bytes(int(H), int(W), int(N), float(sigma_s), _flags(spatial, center)))
+    return torch.empty(max(n, 256), dtype=torch.uint8, device=device)
+
+
+def gp_joint_forward(guide, data, sigma_s, sigma_r, N=20, spatial="auto", center="mean", out=None, ws=None,
+                     check=False):
+    """Joint (cross) GP bilateral filter: the range kernel on ``guide``, the
+    average of ``data`` (float32 CUDA tensors of one shape and row stride).
+    Runs in the recursive spatial mode.  Returns ``out``."""
+    H, W, pitch = _image(guide)
+    dh, dw, dp = _image(data, "data")
+    if (dh, dw, dp) != (H, W, pitch):
+        raise ValueError("data must have the shape and row stride of the guide")
+    if out is None:
+        out = torch.empty_like(guide)
+    else:
+        oh, ow, opitch = _image(out, "out")
+        if (oh, ow, opitch) != (H, W, pitch):
+            raise ValueError("out must have the shape and row stride of the guide")
+    flags = _flags(spatial, center)
+    if ws is None:
+        ws = joint_workspace(H, W, N, sigma_s, spatial, center, guide.device)
+    _check(bf_gp_joint_forward(guide.data_ptr(), data.data_ptr(), out.data_ptr(), H, W, pitch, float(sigma_s),
+                               float(sigma_r), int(N), flags, ws.data_ptr(), ws.numel(), _stream(guide.device)),
+           "bf_gp_joint_forward")
+    if check:
+        st = status(ws, guide.device)
+        if st != BF_OK:
+            raise BfError(st, "bf_gp_joint_forward (device status)")
     return out
 
 

@@ -113,7 +113,9 @@ struct Layout {
     size_t parts, status, stats, carry, stack, total;
 };
 
-Layout gp_layout(int H, int W, int N, unsigned spatial) {
+// C: channels of the stack (N + 2 for the filter, 2 (N + 1) for the joint
+// filter).
+Layout gp_layout_c(int H, int W, int C, unsigned spatial) {
     Layout L;
     size_t off = 0;
     L.parts = off;
@@ -124,17 +126,18 @@ Layout gp_layout(int H, int W, int N, unsigned spatial) {
     off = align256(off + sizeof(Stats));
     L.carry = L.stack = off;
     if (spatial == BF_SPATIAL_IIR) {
-        const size_t C = (size_t)N + 2;
-        const IirShape sh = iir_shape(H, W, (int)C);
+        const IirShape sh = iir_shape(H, W, C);
         const size_t nb = ((size_t)H + sh.B - 1) / sh.B;
         L.carry = off;
-        off = align256(off + sizeof(float) * nb * C * 8 * (size_t)W);
+        off = align256(off + sizeof(float) * nb * (size_t)C * 8 * (size_t)W);
         L.stack = off;
-        off = align256(off + sizeof(float) * C * (size_t)sh.Hs * (size_t)sh.P);
+        off = align256(off + sizeof(float) * (size_t)C * (size_t)sh.Hs * (size_t)sh.P);
     }
     L.total = off;
     return L;
 }
+
+Layout gp_layout(int H, int W, int N, unsigned spatial) { return gp_layout_c(H, W, N + 2, spatial); }
 
 int check_image(const void *img, const void *out, int H, int W, int pitch) {
     if (!img || !out) return fail(BF_EINVAL, "null image pointer");
@@ -510,9 +513,48 @@ int bf_gp_forward(const float *img, float *out, int H, int W, int pitch, double 
     } else {
         const IirShape sh = iir_shape(H, W, N + 2);
         e = launch_iir(p, make_iir(sigma_s, sh.B, sh.L), sh, (float *)(w + L.carry), (float *)(w + L.stack),
-                       saved != nullptr, s);
+                       saved != nullptr, false, s);
         if (e != hipSuccess) return hip_fail(e, "IIR launch");
     }
+    return BF_OK;
+}
+
+size_t bf_gp_joint_workspace_bytes(int H, int W, int N, double sigma_s, unsigned flags) {
+    if (H < 1 || W < 1 || N < 0 || N > BF_MAX_DEGREE || !finite_pos(sigma_s)) return 0;
+    if ((flags & BF_SPATIAL_MASK) == BF_SPATIAL_FIR) return 0;
+    return gp_layout_c(H, W, 2 * (N + 1), BF_SPATIAL_IIR).total;
+}
+
+int bf_gp_joint_forward(const float *guide, const float *data, float *out, int H, int W, int pitch, double sigma_s,
+                        double sigma_r, int N, unsigned flags, void *ws, size_t ws_bytes, void *stream) {
+    int rc;
+    if ((rc = check_image(guide, out, H, W, pitch))) return rc;
+    if (!data) return fail(BF_EINVAL, "null data pointer");
+    if ((rc = check_params(sigma_s, sigma_r, N))) return rc;
+    if (!ws) return fail(BF_EINVAL, "null workspace");
+    if (flags & ~(BF_SPATIAL_MASK | BF_CENTER_MASK)) return fail(BF_EINVAL, "unknown flag bits 0x%x", flags);
+    if ((flags & BF_SPATIAL_MASK) == 3u || (flags & BF_CENTER_MASK) == 12u) return fail(BF_EINVAL, "invalid flag combination");
+    if ((const void *)out == (const void *)guide || (const void *)out == (const void *)data)
+        return fail(BF_EINVAL, "out must not alias the guide or the data");
+    if ((flags & BF_SPATIAL_MASK) == BF_SPATIAL_FIR)
+        return fail(BF_EUNSUPPORTED, "the joint filter runs in the recursive (IIR) spatial mode");
+    if ((rc = check_spatial(BF_SPATIAL_IIR, sigma_s, W))) return rc;
+    const int C = 2 * (N + 1);
+    const Layout L = gp_layout_c(H, W, C, BF_SPATIAL_IIR);
+    if (ws_bytes < L.total) return fail(BF_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    GPParams p = make_params(guide, out, H, W, pitch, sigma_r, N, flags, w, L, nullptr);
+    p.C = C;
+    p.data = data;
+    // the channels reach degree N only (not N + 1)
+    p.xlim = range_limit(N - 1);
+    hipError_t e = launch_stats(p, false, s);
+    if (e != hipSuccess) return hip_fail(e, "statistics launch");
+    const IirShape sh = iir_shape(H, W, C);
+    e = launch_iir(p, make_iir(sigma_s, sh.B, sh.L), sh, (float *)(w + L.carry), (float *)(w + L.stack), false, true,
+                   s);
+    if (e != hipSuccess) return hip_fail(e, "IIR launch");
     return BF_OK;
 }
 

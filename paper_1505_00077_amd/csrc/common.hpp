@@ -43,6 +43,7 @@ struct GPParams {
     int *status;         // device status word (BF_OK / BF_ERANGE)
     Stats *stats;        // written by the first kernel after the statistics pass
     void *saved;         // nullable, 16 B per pixel (see bf_gp_forward)
+    const float *data;   // joint filter: the image averaged (img is the guide); else null
     double sq[kMaxC + 3];   // sqrt(n)
     double isq[kMaxC + 3];  // 1 / sqrt(n)
     double rm[kMaxC + 3];   // sqrt(n + 1) / n (n >= 1; 0 at n = 0)

@@ -45,7 +45,10 @@ struct IirCoef {
 // columns while the anticausal pass runs), used only when !AGG.
 // Channels [cb, ce) only: the channel recurrence still starts from u_0, so the
 // values do not depend on how the channels are split across workgroups.
-template <int B, bool AGG, bool BIG>
+// JOINT (joint filter, range kernel on the guide p.img, average of p.data):
+// stack channel 2n holds u_n(x) of the guide and 2n+1 holds u_n(x) f of the
+// data, n = 0..N.
+template <int B, bool AGG, bool BIG, bool JOINT = false>
 __device__ __forceinline__ void vband(const GPParams &p, const IirCoef &c, const Stats &st, int col, int band,
                                       float *__restrict__ carry, float *__restrict__ S, int sp_pitch, float *sacc,
                                       int cb, int ce) {
@@ -70,12 +73,13 @@ __device__ __forceinline__ void vband(const GPParams &p, const IirCoef &c, const
     // rows a-1 .. a+B+1: every load is issued unconditionally from a clamped
     // row (so that all of them are in flight together), and samples outside
     // the image are zeroed afterwards
-    float xv[B + 3], u[B + 3];
+    float xv[B + 3], u[B + 3], dv[JOINT ? B + 3 : 1];
 #pragma unroll
     for (int i = 0; i < B + 3; ++i) {
         const int row = a - 1 + i;
         const int rc = row < 0 ? 0 : (row >= p.H ? p.H - 1 : row);
         xv[i] = p.img[(size_t)rc * p.pitch + col];
+        if constexpr (JOINT) dv[i] = p.data[(size_t)rc * p.pitch + col];
     }
 #pragma unroll
     for (int i = 0; i < B + 3; ++i) {
@@ -97,19 +101,29 @@ __device__ __forceinline__ void vband(const GPParams &p, const IirCoef &c, const
             }
     }
     const size_t cstride = (size_t)p.W;
-    for (int n = 1; n < cb; ++n) {
+    // advance u to the first channel's degree (the loop below advances it on
+    // entering every degree n > 0: channel n, or channel 2n of a joint stack)
+    const int pre = JOINT ? ((cb & 1) ? cb >> 1 : (cb >> 1) - 1) : cb - 1;
+    for (int n = 1; n <= pre; ++n) {
         const float isq = (float)p.isq[n];
 #pragma unroll
         for (int i = 0; i < B + 3; ++i) u[i] *= xv[i] * isq;
     }
     for (int n = cb; n < ce; ++n) {
-        const float isq = (float)p.isq[n];
-        if (n > 0) {
+        const int deg = JOINT ? n >> 1 : n;
+        const bool dat = JOINT && (n & 1);  // a joint data channel (uniform)
+        const float isq = (float)p.isq[deg];
+        if (deg > 0 && !dat) {
 #pragma unroll
             for (int i = 0; i < B + 3; ++i) u[i] *= xv[i] * isq;
         }
-        // channel value of sample i (undoing the range shift of BIG images)
-        auto V = [&](int i) -> float { return BIG ? ldexpf(u[i], -big_shift(xv[i])) : u[i]; };
+        // channel value of sample i (undoing the range shift of BIG images;
+        // times the data for a joint data channel)
+        auto V = [&](int i) -> float {
+            const float v = BIG ? ldexpf(u[i], -big_shift(xv[i])) : u[i];
+            if constexpr (JOINT) return dat ? v * dv[i] : v;
+            return v;
+        };
         float *cp = carry + ((size_t)(band * p.C + n) * 8) * cstride + col;
         // incoming states of both directions
         float in8[8];
@@ -317,7 +331,7 @@ __device__ __forceinline__ void affine2(float *r, const float *v, const float *P
 // and likewise for bM, and the terms the backward pass needs are stored:
 // rho = M/D, drho/dtau = (dM - rho dD) / bD and D' = bD = exp(tau^2/2) D.
 // sm: hrow_smem_bytes(T, groups, L) bytes.
-template <int L, bool SAVE = false>
+template <int L, bool SAVE = false, bool JOINT = false>
 __device__ __forceinline__ void hrow(const GPParams &p, const IirCoef &c, const Stats &st, int y,
                                      const float *__restrict__ S, int sp_rows, int sp_pitch, float *sm, int T,
                                      int groups) {
@@ -572,6 +586,20 @@ __device__ __forceinline__ void hrow(const GPParams &p, const IirCoef &c, const 
         // m_k = bM_k / sqrt(k): m_k = Ubar_k + m_{k+1} tau sqrt(k+1) / k.
         // (channel N+1 enters only bM, channel 0 only bD: uniform branches,
         // so that the common case carries no per-sample selects)
+        if constexpr (JOINT) {
+            // joint stack: channel 2k + 1 (data) into bM, channel 2k (guide)
+            // into bD, both with the Horner factor tau / sqrt(k + 1): bD ends
+            // as sum_k p_k(tau) Ubar_2k, bM as sum_k p_k(tau) Ubar_2k+1
+            const double r = p.isq[(n >> 1) + 1];
+            if (n & 1) {
+#pragma unroll
+                for (int i = 0; i < L; ++i) bM[i] = fma(bM[i], (double)tau[i] * r, (double)o[i]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < L; ++i) bD[i] = fma(bD[i], (double)tau[i] * r, (double)o[i]);
+            }
+            continue;
+        }
         const double rD = p.isq[n + 1];
         const double rM = p.rm[n];
         if (n <= p.N && n >= 1) {
@@ -600,7 +628,7 @@ __device__ __forceinline__ void hrow(const GPParams &p, const IirCoef &c, const 
             }
         }
     }
-    if (groups > 1) {
+    if (!JOINT && groups > 1) {
         // shares of groups 1.. in the full Horner sums, through LDS
         if (member && g > 0) {
             double kD = 1.0, kM = 1.0;
@@ -631,6 +659,10 @@ __device__ __forceinline__ void hrow(const GPParams &p, const IirCoef &c, const 
             const int x = x0 + i;
             if (x < p.W) {
                 const double rho = bM[i] / bD[i];
+                if constexpr (JOINT) {
+                    p.out[(size_t)y * p.pitch + x] = st.ok ? (float)rho : __builtin_nanf("");
+                    continue;
+                }
                 p.out[(size_t)y * p.pitch + x] = st.ok ? (float)fma(p.sigma_r, rho, st.tc) : __builtin_nanf("");
                 if constexpr (SAVE) {
                     const size_t npx = (size_t)p.H * p.W, idx = (size_t)y * p.W + x;

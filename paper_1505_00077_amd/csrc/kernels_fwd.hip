@@ -38,7 +38,7 @@ __global__ __launch_bounds__(kBlock) void k_direct(DirectArgs a) {
 // them per band and channel group) come first, those of the stack's pad-only
 // column groups (cgp, column pass only: they store zeros) last, so that the
 // light pad workgroups fill in behind the full ones.
-template <int B, bool AGG>
+template <int B, bool AGG, bool JOINT>
 __global__ __launch_bounds__(64, 3) void k_vband(GPParams p, IirCoef c, float *carry, float *S, int sp, int groups,
                                                  int cgr, int cgp) {
     __shared__ float sacc[AGG ? 1 : B * 64];
@@ -66,9 +66,9 @@ __global__ __launch_bounds__(64, 3) void k_vband(GPParams p, IirCoef c, float *c
     // channel group grp of `groups` nearly equal groups
     const int cb = (p.C * grp) / groups, ce = (p.C * (grp + 1)) / groups;
     if (st.xmax > 12.0)
-        vband<B, AGG, true>(p, c, st, col, band, carry, S, sp, sacc, cb, ce);
+        vband<B, AGG, true, JOINT>(p, c, st, col, band, carry, S, sp, sacc, cb, ce);
     else
-        vband<B, AGG, false>(p, c, st, col, band, carry, S, sp, sacc, cb, ce);
+        vband<B, AGG, false, JOINT>(p, c, st, col, band, carry, S, sp, sacc, cb, ce);
 }
 
 __global__ __launch_bounds__(64) void k_vresolve(GPParams p, IirCoef c, int nb, float *carry) {
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(64) void k_vresolve(GPParams p, IirCoef c, int nb, 
     if (col < p.W) vresolve(p, c, nb, col, blockIdx.y, blockIdx.z, carry);
 }
 
-template <int L, bool SAVE>
+template <int L, bool SAVE, bool JOINT>
 __global__ __launch_bounds__(512, 1) void k_hrow(GPParams p, IirCoef c, const float *S, int srows, int sp, int T,
                                                  int groups) {
     extern __shared__ float sm[];
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(512, 1) void k_hrow(GPParams p, IirCoef c, const fl
         for (int x = threadIdx.x; x < p.W; x += blockDim.x) p.out[(size_t)blockIdx.x * p.pitch + x] = __builtin_nanf("");
         return;
     }
-    hrow<L, SAVE>(p, c, st, blockIdx.x, S, srows, sp, sm, T, groups);
+    hrow<L, SAVE, JOINT>(p, c, st, blockIdx.x, S, srows, sp, sm, T, groups);
 }
 
 // ---- host launchers ----------------------------------------------------------
@@ -123,19 +123,33 @@ hipError_t launch_fir(const GPParams &p, const FirTaps &t, int R, bool save, hip
 
 template <int L>
 static void hrow_launch(const GPParams &p, const IirCoef &c, const IirShape &sh, const float *S, bool save,
-                        hipStream_t s) {
+                        bool joint, hipStream_t s) {
     const dim3 rb(sh.T * sh.Gr);
     const size_t sm = hrow_smem_bytes(sh.T, sh.Gr, sh.L);
-    if (save)
-        BF_LAUNCH("k_hrow", (k_hrow<L, true>), dim3(p.H), rb, sm, s, p, c, S, sh.Hs, sh.P, sh.T, sh.Gr);
+    if (joint)
+        BF_LAUNCH("k_hrow", (k_hrow<L, false, true>), dim3(p.H), rb, sm, s, p, c, S, sh.Hs, sh.P, sh.T, sh.Gr);
+    else if (save)
+        BF_LAUNCH("k_hrow", (k_hrow<L, true, false>), dim3(p.H), rb, sm, s, p, c, S, sh.Hs, sh.P, sh.T, sh.Gr);
     else
-        BF_LAUNCH("k_hrow", (k_hrow<L, false>), dim3(p.H), rb, sm, s, p, c, S, sh.Hs, sh.P, sh.T, sh.Gr);
+        BF_LAUNCH("k_hrow", (k_hrow<L, false, false>), dim3(p.H), rb, sm, s, p, c, S, sh.Hs, sh.P, sh.T, sh.Gr);
+}
+
+template <int B, bool AGG>
+static void vband_launch(const GPParams &p, const IirCoef &c, const IirShape &sh, dim3 grid, float *carry, float *S,
+                         int cgr, int cgp, bool joint, hipStream_t s) {
+    const char *name = AGG ? "k_vband_agg" : "k_vband";
+    if (joint)
+        BF_LAUNCH(name, (k_vband<B, AGG, true>), grid, dim3(64), 0, s, p, c, carry, S, sh.P, sh.G, cgr, cgp);
+    else
+        BF_LAUNCH(name, (k_vband<B, AGG, false>), grid, dim3(64), 0, s, p, c, carry, S, sh.P, sh.G, cgr, cgp);
 }
 
 hipError_t launch_iir(const GPParams &p, const IirCoef &c, const IirShape &shape, float *carry, float *S, bool save,
-                      hipStream_t s) {
+                      bool joint, hipStream_t s) {
     IirShape sh = shape;
-    if (save) sh.Gr = 1;  // the saved terms need the whole Horner sums in one group
+    // the saved terms and the joint recombination need the whole Horner sums
+    // in one group
+    if (save || joint) sh.Gr = 1;
     const int nb = (p.H + sh.B - 1) / sh.B;
     // the end-state pass has nothing to do on the stack's pad columns: its
     // grid covers the image columns only (an even number of waves per SIMD
@@ -143,21 +157,21 @@ hipError_t launch_iir(const GPParams &p, const IirCoef &c, const IirShape &shape
     const int cgr = (p.W + 63) / 64, cgp = (sh.P + 63) / 64 - cgr;
     const dim3 ga(cgr * nb * sh.G), gv((cgr + cgp) * nb * sh.G);
     if (sh.B == 64)
-        BF_LAUNCH("k_vband_agg", (k_vband<64, true>), ga, dim3(64), 0, s, p, c, carry, S, sh.P, sh.G, cgr, cgp);
+        vband_launch<64, true>(p, c, sh, ga, carry, S, cgr, cgp, joint, s);
     else if (sh.B == 32)
-        BF_LAUNCH("k_vband_agg", (k_vband<32, true>), ga, dim3(64), 0, s, p, c, carry, S, sh.P, sh.G, cgr, cgp);
+        vband_launch<32, true>(p, c, sh, ga, carry, S, cgr, cgp, joint, s);
     else
         return hipErrorInvalidValue;
     BF_LAUNCH("k_vresolve", k_vresolve, dim3((p.W + 63) / 64, p.C, 2), dim3(64), 0, s, p, c, nb, carry);
     if (sh.B == 64)
-        BF_LAUNCH("k_vband", (k_vband<64, false>), gv, dim3(64), 0, s, p, c, carry, S, sh.P, sh.G, cgr, cgp);
+        vband_launch<64, false>(p, c, sh, gv, carry, S, cgr, cgp, joint, s);
     else
-        BF_LAUNCH("k_vband", (k_vband<32, false>), gv, dim3(64), 0, s, p, c, carry, S, sh.P, sh.G, cgr, cgp);
+        vband_launch<32, false>(p, c, sh, gv, carry, S, cgr, cgp, joint, s);
     switch (sh.L) {
-        case 4: hrow_launch<4>(p, c, sh, S, save, s); break;
-        case 8: hrow_launch<8>(p, c, sh, S, save, s); break;
-        case 12: hrow_launch<12>(p, c, sh, S, save, s); break;
-        case 16: hrow_launch<16>(p, c, sh, S, save, s); break;
+        case 4: hrow_launch<4>(p, c, sh, S, save, joint, s); break;
+        case 8: hrow_launch<8>(p, c, sh, S, save, joint, s); break;
+        case 12: hrow_launch<12>(p, c, sh, S, save, joint, s); break;
+        case 16: hrow_launch<16>(p, c, sh, S, save, joint, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

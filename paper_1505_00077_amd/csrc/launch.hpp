@@ -42,9 +42,10 @@ struct IirShape {
 // themselves: no channel groups unless the tuning overrides ask for them.
 IirShape iir_shape(int H, int W, int C, bool batch = false);
 // save: also store the terms bf_gp_backward needs (p.saved), with the row pass
-// in one channel group.
+// in one channel group.  joint: the joint filter (p.img the guide, p.data the
+// data, p.C = 2 (N + 1) stack channels), row pass in one channel group.
 hipError_t launch_iir(const GPParams &p, const IirCoef &c, const IirShape &sh, float *carry, float *S, bool save,
-                      hipStream_t s);
+                      bool joint, hipStream_t s);
 hipError_t launch_direct(const DirectArgs &a, hipStream_t s);
 int bwd_tiles(int H, int W);
 hipError_t launch_bwd(const GPParams &p, const BwdParams &b, const FirTaps2 &t, int R, double *corr, double *g_lss,

@@ -91,6 +91,31 @@ def test_backward_modes_and_workspace():
     assert bf.bf_gp_backward_workspace_bytes(0, 512, 20, 12.0, iir) == 0
 
 
+def jfwd(g=FAKE, d=FAKE + 4096, out=FAKE + 8192, H=8, W=8, pitch=8, ss=4.0, sr=30.0, N=20, flags=0,
+         ws=FAKE + 65536, ws_bytes=1 << 30):
+    return bf.bf_gp_joint_forward(g, d, out, H, W, pitch, ss, sr, N, flags, ws, ws_bytes, None)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(g=None), dict(d=None), dict(out=None), dict(ws=None), dict(H=0), dict(pitch=7), dict(ss=0.0),
+    dict(sr=float("nan")), dict(N=65), dict(flags=3), dict(flags=16), dict(out=FAKE), dict(out=FAKE + 4096),
+])
+def test_joint_rejects_invalid_arguments(kw):
+    assert jfwd(**kw) == bf.BF_EINVAL
+
+
+def test_joint_modes_and_workspace():
+    fir, iir = bf.SPATIAL["fir"], bf.SPATIAL["iir"]
+    assert jfwd(flags=fir) == bf.BF_EUNSUPPORTED
+    assert jfwd(H=4, W=9000, pitch=9000) == bf.BF_EUNSUPPORTED
+    # 2 (N + 1) channels: twice the stack of the filter at the same degree
+    j = bf.bf_gp_joint_workspace_bytes(256, 300, 20, 4.0, iir)
+    assert j >= 42 * 256 * 300 * 4 and j > bf.workspace_bytes(256, 300, 20, 4.0, "iir")
+    assert bf.bf_gp_joint_workspace_bytes(256, 300, 20, 4.0, 0) == j
+    assert bf.bf_gp_joint_workspace_bytes(256, 300, 20, 4.0, fir) == 0
+    assert jfwd(H=256, W=300, pitch=300, ws_bytes=j - 1) == bf.BF_ENOMEM
+
+
 def test_workspace_sizes():
     fir = bf.workspace_bytes(1024, 1024, 20, 2.0, "fir")
     iir = bf.workspace_bytes(1024, 1024, 20, 2.0, "iir")
