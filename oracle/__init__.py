@@ -51,6 +51,9 @@ def _load():
     lib.or_gp_alg1.argtypes = [dp, dp, i, i, d, i, dp, i, i]
     lib.or_gp_rescaled.argtypes = [dp, dp, dp, dp, i, i, d, i, dp, i, i]
     lib.or_gp_grad.argtypes = [dp, dp, i, i, d, i, dp, dp, i, i, dp, dp, dp]
+    lib.or_spatial3.argtypes = [dp, dp, i, i, i, dp, i, dp, i]
+    lib.or_volume_direct.argtypes = [dp, dp, i, i, i, dp, i, dp, i, d]
+    lib.or_volume_gp.argtypes = [dp, dp, i, i, i, d, i, dp, i, dp, i, i]
     lib.or_joint_direct.argtypes = [dp, dp, dp, i, i, dp, i, d]
     lib.or_joint_gp.argtypes = [dp, dp, dp, i, i, d, i, dp, i, i]
     lib.or_gauss_poly.argtypes = [d, d, d, i]
@@ -225,6 +228,52 @@ def gp_grad_mode(img, gout, sigma_s, sigma_r, N, mode="fir"):
     kt, R2 = spatial_dtable(mode, sigma_s, *f.shape)
     assert R == R2
     return gp_grad(f, gout, sigma_r, N, k, kt)
+
+
+def _vol(v):
+    a = np.ascontiguousarray(v, dtype=np.float64)
+    if a.ndim != 3:
+        raise ValueError("expected a T x H x W volume")
+    return a
+
+
+def spatial3(vol, kt, ks):
+    """Separable zero-extended filtering of a volume: kt along axis 0, ks along
+    axes 1 and 2."""
+    v = _vol(vol)
+    out = np.empty_like(v)
+    kt = np.ascontiguousarray(kt, np.float64)
+    ks = np.ascontiguousarray(ks, np.float64)
+    _check(_load().or_spatial3(_p(v), _p(out), *v.shape, _p(kt), len(kt) - 1, _p(ks), len(ks) - 1), "spatial3")
+    return out
+
+
+def volume_direct(vol, sigma_r, kt, ks):
+    """Eq. (1) over a volume, computed directly (small volumes)."""
+    v = _vol(vol)
+    out = np.empty_like(v)
+    kt = np.ascontiguousarray(kt, np.float64)
+    ks = np.ascontiguousarray(ks, np.float64)
+    _check(_load().or_volume_direct(_p(v), _p(out), *v.shape, _p(kt), len(kt) - 1, _p(ks), len(ks) - 1,
+                                    float(sigma_r)), "volume_direct")
+    return out
+
+
+def volume_gp(vol, sigma_r, N, kt, ks, center_mode=CENTER_MEAN):
+    """Algorithm 1 over a volume (separable filtering over all three axes)."""
+    v = _vol(vol)
+    out = np.empty_like(v)
+    kt = np.ascontiguousarray(kt, np.float64)
+    ks = np.ascontiguousarray(ks, np.float64)
+    _check(_load().or_volume_gp(_p(v), _p(out), *v.shape, float(sigma_r), int(N), _p(kt), len(kt) - 1, _p(ks),
+                                len(ks) - 1, int(center_mode)), "volume_gp")
+    return out
+
+
+def volume_tables(sigma_t, sigma_s, T, H, W):
+    """Deriche tables over the whole extent of each axis (the recursive mode)."""
+    return (deriche_table(sigma_t, max(1, iir_radius(sigma_t, T, T))),
+            deriche_table(sigma_s, max(1, iir_radius(sigma_s, H, W))))
 
 
 def joint_direct(guide, data, sigma_r, k):

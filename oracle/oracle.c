@@ -360,6 +360,144 @@ int or_joint_gp(const double *g, const double *f, double *out, int H, int W, dou
 }
 
 /* ------------------------------------------------------------------------ */
+/* Volumes and video                                                         */
+/* ------------------------------------------------------------------------ */
+
+/* The extension to higher-dimensional signals the introduction and the
+ * Conclusion name, for a T x H x W volume (frames t, rows y, columns x) with
+ * the separable spatial weight kt[|dt|] * ks[|dy|] * ks[|dx|] (the third axis
+ * may have its own scale, e.g. time in a video).  Offsets outside the volume
+ * are skipped (zero extension). */
+
+/* One 1-D pass along t (axis 0), y (axis 1) or x (axis 2). */
+static void pass_1d_3(const double *in, double *out, int T, int H, int W, const double *k, int R, int axis)
+{
+#pragma omp parallel for schedule(static)
+    for (int t = 0; t < T; ++t) {
+        for (int y = 0; y < H; ++y) {
+            for (int x = 0; x < W; ++x) {
+                double acc = 0.0;
+                for (int d = -R; d <= R; ++d) {
+                    int tt = axis == 0 ? t - d : t, yy = axis == 1 ? y - d : y, xx = axis == 2 ? x - d : x;
+                    if (tt < 0 || tt >= T || yy < 0 || yy >= H || xx < 0 || xx >= W)
+                        continue;
+                    acc += k[d < 0 ? -d : d] * in[((size_t)tt * H + yy) * W + xx];
+                }
+                out[((size_t)t * H + y) * W + x] = acc;
+            }
+        }
+    }
+}
+
+static void spatial_sep3(const double *in, double *out, double *tmp, int T, int H, int W, const double *kt,
+                         int Rt, const double *ks, int Rs)
+{
+    pass_1d_3(in, out, T, H, W, kt, Rt, 0);
+    pass_1d_3(out, tmp, T, H, W, ks, Rs, 1);
+    pass_1d_3(tmp, out, T, H, W, ks, Rs, 2);
+}
+
+int or_spatial3(const double *in, double *out, int T, int H, int W, const double *kt, int Rt, const double *ks,
+                int Rs)
+{
+    if (!in || !out || !kt || !ks || T < 1 || H < 1 || W < 1 || Rt < 0 || Rs < 0)
+        return OR_EINVAL;
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)T * H * W);
+    if (!tmp)
+        return OR_ENOMEM;
+    spatial_sep3(in, out, tmp, T, H, W, kt, Rt, ks, Rs);
+    free(tmp);
+    return OR_OK;
+}
+
+/* Eq. (1) over a volume, computed directly. */
+int or_volume_direct(const double *f, double *out, int T, int H, int W, const double *kt, int Rt,
+                     const double *ks, int Rs, double sigma_r)
+{
+    if (!f || !out || !kt || !ks || T < 1 || H < 1 || W < 1 || Rt < 0 || Rs < 0 || !(sigma_r > 0))
+        return OR_EINVAL;
+    const double inv2r2 = 1.0 / (2.0 * sigma_r * sigma_r);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int t = 0; t < T; ++t) {
+        for (int y = 0; y < H; ++y) {
+            for (int x = 0; x < W; ++x) {
+                const double fi = f[((size_t)t * H + y) * W + x];
+                double num = 0.0, den = 0.0;
+                for (int dt = -Rt; dt <= Rt; ++dt) {
+                    int tt = t - dt;
+                    if (tt < 0 || tt >= T)
+                        continue;
+                    for (int dy = -Rs; dy <= Rs; ++dy) {
+                        int yy = y - dy;
+                        if (yy < 0 || yy >= H)
+                            continue;
+                        for (int dx = -Rs; dx <= Rs; ++dx) {
+                            int xx = x - dx;
+                            if (xx < 0 || xx >= W)
+                                continue;
+                            const double fj = f[((size_t)tt * H + yy) * W + xx];
+                            const double d = fj - fi;
+                            const double w = kt[dt < 0 ? -dt : dt] * ks[dy < 0 ? -dy : dy] * ks[dx < 0 ? -dx : dx] *
+                                             exp(-d * d * inv2r2);
+                            num += w * fj;
+                            den += w;
+                        }
+                    }
+                }
+                out[((size_t)t * H + y) * W + x] = num / den;
+            }
+        }
+    }
+    return OR_OK;
+}
+
+/* Algorithm 1 over a volume: the same steps, with eq. (8) the separable
+ * filtering over all three axes. */
+int or_volume_gp(const double *f, double *out, int T, int H, int W, double sigma_r, int N, const double *kt,
+                 int Rt, const double *ks, int Rs, int center_mode)
+{
+    if (!f || !out || !kt || !ks || T < 1 || H < 1 || W < 1 || Rt < 0 || Rs < 0 || !(sigma_r > 0) || N < 0)
+        return OR_EINVAL;
+    const size_t n = (size_t)T * H * W;
+    double *G = malloc(sizeof(double) * n), *F = malloc(sizeof(double) * n);
+    double *Fb = malloc(sizeof(double) * n), *P = malloc(sizeof(double) * n);
+    double *Q = malloc(sizeof(double) * n), *Hh = malloc(sizeof(double) * n);
+    double *tmp = malloc(sizeof(double) * n);
+    if (!G || !F || !Fb || !P || !Q || !Hh || !tmp) {
+        free(G); free(F); free(Fb); free(P); free(Q); free(Hh); free(tmp);
+        return OR_ENOMEM;
+    }
+    /* the centre over the whole volume (a T H x W image) */
+    const double tc = or_center(f, T * H, W, center_mode);
+    for (size_t i = 0; i < n; ++i) {
+        const double h = f[i] - tc;
+        G[i] = 1.0;
+        F[i] = exp(-h * h / (2.0 * sigma_r * sigma_r));
+        P[i] = 0.0;
+        Q[i] = 0.0;
+        Hh[i] = h / sigma_r;
+    }
+    spatial_sep3(F, Fb, tmp, T, H, W, kt, Rt, ks, Rs);
+    double c = 1.0;
+    for (int m = 0; m <= N; ++m) {
+        for (size_t i = 0; i < n; ++i) {
+            Q[i] += c * G[i] * Fb[i];
+            F[i] = Hh[i] * F[i];
+        }
+        spatial_sep3(F, Fb, tmp, T, H, W, kt, Rt, ks, Rs);
+        for (size_t i = 0; i < n; ++i) {
+            P[i] += c * G[i] * Fb[i];
+            G[i] = Hh[i] * G[i];
+        }
+        c = c / (double)(m + 1);
+    }
+    for (size_t i = 0; i < n; ++i)
+        out[i] = sigma_r * (P[i] / Q[i]) + tc;
+    free(G); free(F); free(Fb); free(P); free(Q); free(Hh); free(tmp);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* The same approximation in rescaled channels                               */
 /* ------------------------------------------------------------------------ */
 

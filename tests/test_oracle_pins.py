@@ -431,3 +431,70 @@ def test_joint_gp_converges_to_joint_direct_and_ignores_guide_offset():
     # constant added to the guide changes nothing
     assert np.max(np.abs(oracle.joint_gp(g + 37.0, f, 30.0, 20, k) - oracle.joint_gp(g, f, 30.0, 20, k))) < 1e-9
 
+
+# ---------------------------------------------------------------------------
+# volumes: separable filtering over three axes
+# ---------------------------------------------------------------------------
+
+def test_spatial3_matches_scipy_and_triple_sum():
+    v = np.random.default_rng(50).uniform(0, 1, size=(5, 7, 9))
+    kt, ks = oracle.gauss_table(0.9, 2), oracle.gauss_table(1.2, 3)
+    wt, ws = np.concatenate([kt[:0:-1], kt]), np.concatenate([ks[:0:-1], ks])
+    ref = ndimage.correlate1d(v, wt, axis=0, mode="constant")
+    ref = ndimage.correlate1d(ref, ws, axis=1, mode="constant")
+    ref = ndimage.correlate1d(ref, ws, axis=2, mode="constant")
+    got = oracle.spatial3(v, kt, ks)
+    assert np.allclose(got, ref, rtol=0, atol=1e-12)
+    # one output by the explicit triple sum
+    t0, y0, x0 = 2, 3, 4
+    acc = 0.0
+    for t in range(5):
+        for y in range(7):
+            for x in range(9):
+                if abs(t - t0) <= 2 and abs(y - y0) <= 3 and abs(x - x0) <= 3:
+                    acc += kt[abs(t - t0)] * ks[abs(y - y0)] * ks[abs(x - x0)] * v[t, y, x]
+    assert got[t0, y0, x0] == pytest.approx(acc, rel=1e-13)
+
+
+def test_volume_direct_matches_quadruple_sum():
+    v = np.random.default_rng(51).uniform(0, 255, size=(3, 5, 6))
+    kt, ks = oracle.gauss_table(0.8, 1), oracle.gauss_table(1.0, 2)
+    got = oracle.volume_direct(v, 30.0, kt, ks)
+    t0, y0, x0 = 1, 2, 3
+    num = den = 0.0
+    for t in range(3):
+        for y in range(5):
+            for x in range(6):
+                if abs(t - t0) <= 1 and abs(y - y0) <= 2 and abs(x - x0) <= 2:
+                    w = kt[abs(t - t0)] * ks[abs(y - y0)] * ks[abs(x - x0)] * \
+                        math.exp(-(v[t, y, x] - v[t0, y0, x0]) ** 2 / 1800.0)
+                    num += w * v[t, y, x]
+                    den += w
+    assert got[t0, y0, x0] == pytest.approx(num / den, rel=1e-13)
+
+
+def test_volume_gp_single_frame_is_alg1():
+    # one frame: the time filter multiplies every channel by kt[0], which the
+    # ratio cancels
+    f = voronoi_image(30, 41, 8, seed=52).astype(np.float64)
+    kt, ks = oracle.deriche_table(2.0, 10), oracle.deriche_table(3.0, 40)
+    got = oracle.volume_gp(f[None], 30.0, 20, kt, ks)[0]
+    assert np.max(np.abs(got - oracle.gp_alg1(f, 30.0, 20, ks))) < 1e-9
+
+
+def test_volume_gp_against_direct_limits_and_invariants():
+    rng = np.random.default_rng(53)
+    vol = np.stack([voronoi_image(18, 24, 6, seed=60 + t) for t in range(6)]).astype(np.float64)
+    kt, ks = oracle.gauss_table(1.0, 3), oracle.gauss_table(1.5, 5)
+    ref = oracle.volume_direct(vol, 30.0, kt, ks)
+    errs = [np.max(np.abs(oracle.volume_gp(vol, 30.0, N, kt, ks) - ref)) for N in (10, 20, 40, 60)]
+    assert errs[0] > errs[1] > errs[2] > errs[3] and errs[3] < 1e-6
+    # constant volume, translation, sigma_r -> inf blur
+    c = np.full((4, 9, 11), 99.5)
+    assert np.max(np.abs(oracle.volume_gp(c, 30.0, 20, kt, ks) - 99.5)) < 1e-11
+    a = oracle.volume_gp(vol + 21.0, 30.0, 20, kt, ks)
+    assert np.max(np.abs(a - (oracle.volume_gp(vol, 30.0, 20, kt, ks) + 21.0))) < 1e-9
+    u = rng.uniform(0, 255, size=(4, 9, 11))
+    blur = oracle.spatial3(u, kt, ks) / oracle.spatial3(np.ones_like(u), kt, ks)
+    assert np.allclose(oracle.volume_gp(u, 1e7, 2, kt, ks), blur, rtol=0, atol=1e-7)
+
