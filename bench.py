@@ -362,6 +362,18 @@ def main():
         modes["joint_1024"] = jres
         log("joint 1024^2: " + ", ".join(f"sigma_s {k} {v['ms']:.3f} ms" for k, v in jres.items()))
 
+    # ---------------- video: 64 frames of 512^2 (16.8 M voxels) ----------------
+    if want("video"):
+        frames = torch.from_numpy(np.stack([synthimg.voronoi_image(512, 512, 200, seed=700 + t)
+                                            for t in range(64)])).to(dev).contiguous()
+        vout = torch.empty_like(frames)
+        vws = bf.volume_workspace(64, 512, 512, DEGREE, 10.0, 3.0)
+        ms_v = timed(lambda: bf.gp_volume_forward(frames, 10.0, 3.0, SIGMA_R, DEGREE, out=vout, ws=vws), K, Wm, torch)
+        modes["video_64x512x512"] = {"ms": ms_v, "mvox_s": frames.numel() / (ms_v * 1e-3) / 1e6, "plan": "iir",
+                                     "sigma_s": 10.0, "sigma_t": 3.0, "sigma_r": SIGMA_R}
+        log(f"video 64x512x512: {ms_v:.3f} ms")
+        del frames, vout, vws
+
     # ---------------- copy calibration for the traffic counters ----------------
     if want("calib"):
         # a plain device-to-device copy of 256 MiB: its FETCH_SIZE / WRITE_SIZE

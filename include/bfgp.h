@@ -115,6 +115,28 @@ int bf_gp_joint_forward(const float *guide, const float *data, float *out, int H
                         double sigma_s, double sigma_r, int N, unsigned flags,
                         void *ws, size_t ws_bytes, void *stream);
 
+/* ---- volumes and video ------------------------------------------------------
+ * The extension to higher-dimensional signals that the introduction and the
+ * Conclusion name: Algorithm 1 on a T x H x W volume (frames t, rows y,
+ * columns x), with eq. (8) the separable spatial filter over all three axes,
+ * scale sigma_s along y and x and sigma_t along t (time in a video; equal to
+ * sigma_s for an isotropic volume), zero extension, the centre taken over the
+ * whole volume.  Recursive spatial mode (BF_SPATIAL_AUTO or BF_SPATIAL_IIR;
+ * BF_SPATIAL_FIR returns BF_EUNSUPPORTED): a time pass on the volume seen as
+ * T rows of H W samples, a column pass in every frame, and the row pass with
+ * the FP64 recombination.  With T = 1 the result is bf_gp_forward's (IIR).
+ *  vol, out     device, contiguous T x H x W float (frame after frame, rows of
+ *               W); may not alias.  W up to 8192, H W below 2^31.
+ *  ws, ws_bytes device workspace of bf_gp_volume_workspace_bytes(...) bytes:
+ *               two channel stacks of the volume (about 8 (N + 2) bytes per
+ *               voxel) and the band carries.
+ * Intensities too far from the centre make the output NaN and set BF_ERANGE
+ * in the workspace status. */
+size_t bf_gp_volume_workspace_bytes(int T, int H, int W, int N, double sigma_s, double sigma_t, unsigned flags);
+
+int bf_gp_volume_forward(const float *vol, float *out, int T, int H, int W, double sigma_s, double sigma_t,
+                         double sigma_r, int N, unsigned flags, void *ws, size_t ws_bytes, void *stream);
+
 /* Blocking: waits for `stream`, then stores the status of the last forward or
  * backward that used `ws` in *status (BF_OK or BF_ERANGE). */
 int bf_gp_status(const void *ws, void *stream, int *status);

@@ -50,6 +50,8 @@ bf_gp_workspace_bytes = _sig("bf_gp_workspace_bytes", _sz, _i, _i, _i, _d, _u)
 bf_gp_forward = _sig("bf_gp_forward", _i, _vp, _vp, _i, _i, _i, _d, _d, _i, _u, _vp, _vp, _sz, _vp)
 bf_gp_joint_workspace_bytes = _sig("bf_gp_joint_workspace_bytes", _sz, _i, _i, _i, _d, _u)
 bf_gp_joint_forward = _sig("bf_gp_joint_forward", _i, _vp, _vp, _vp, _i, _i, _i, _d, _d, _i, _u, _vp, _sz, _vp)
+bf_gp_volume_workspace_bytes = _sig("bf_gp_volume_workspace_bytes", _sz, _i, _i, _i, _i, _d, _d, _u)
+bf_gp_volume_forward = _sig("bf_gp_volume_forward", _i, _vp, _vp, _i, _i, _i, _d, _d, _d, _i, _u, _vp, _sz, _vp)
 bf_gp_status = _sig("bf_gp_status", _i, _vp, _vp, ctypes.POINTER(_i))
 bf_gp_resolve_spatial = _sig("bf_gp_resolve_spatial", _u, _d, _u)
 bf_gp_resolve_spatial_for = _sig("bf_gp_resolve_spatial_for", _u, _i, _i, _d, _u)
@@ -208,6 +210,37 @@ def gp_joint_forward(guide, data, sigma_s, sigma_r, N=20, spatial="auto", center
         st = status(ws, guide.device)
         if st != BF_OK:
             raise BfError(st, "bf_gp_joint_forward (device status)")
+    return out
+
+
+def volume_workspace(T, H, W, N, sigma_s, sigma_t, spatial="auto", center="mean", device="cuda"):
+    n = int(bf_gp_volume_workspace_bytes(int(T), int(H), int(W), int(N), float(sigma_s), float(sigma_t),
+                                         _flags(spatial, center)))
+    return torch.empty(max(n, 256), dtype=torch.uint8, device=device)
+
+
+def gp_volume_forward(vol, sigma_s, sigma_t, sigma_r, N=20, spatial="auto", center="mean", out=None, ws=None,
+                      check=False):
+    """GP bilateral filter of a volume or video: ``vol`` a contiguous float32
+    CUDA tensor (T, H, W); sigma_s along rows and columns, sigma_t along the
+    first axis.  Runs in the recursive spatial mode.  Returns ``out``."""
+    if vol.dtype != torch.float32 or not vol.is_cuda or vol.dim() != 3 or not vol.is_contiguous():
+        raise ValueError("vol must be a contiguous float32 CUDA tensor (T, H, W)")
+    T, H, W = vol.shape
+    if out is None:
+        out = torch.empty_like(vol)
+    elif out.shape != vol.shape or out.dtype != torch.float32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 tensor shaped like vol")
+    flags = _flags(spatial, center)
+    if ws is None:
+        ws = volume_workspace(T, H, W, N, sigma_s, sigma_t, spatial, center, vol.device)
+    _check(bf_gp_volume_forward(vol.data_ptr(), out.data_ptr(), T, H, W, float(sigma_s), float(sigma_t),
+                                float(sigma_r), int(N), flags, ws.data_ptr(), ws.numel(), _stream(vol.device)),
+           "bf_gp_volume_forward")
+    if check:
+        st = status(ws, vol.device)
+        if st != BF_OK:
+            raise BfError(st, "bf_gp_volume_forward (device status)")
     return out
 
 

@@ -558,6 +558,96 @@ int bf_gp_joint_forward(const float *guide, const float *data, float *out, int H
     return BF_OK;
 }
 
+// Workspace of a volume forward (recursive mode): statistics, then the time
+// carries and stack S1, the per-frame column carries and the row-pass stack S2.
+struct VolLayout {
+    size_t parts, status, stats, carry_z, s1, carry_y, s2, total;
+    IirShape shz, shs;
+    int Hs;
+};
+
+VolLayout vol_layout(int T, int H, int W, int N) {
+    VolLayout L;
+    memset(&L, 0, sizeof L);
+    const size_t C = (size_t)N + 2, HW = (size_t)H * W;
+    L.shz = iir_shape(T, (int)HW, (int)C);
+    L.shz.B = 32;
+    L.shs = iir_shape(T * H, W, (int)C);
+    L.shs.B = 32;
+    L.Hs = ((H + 31) / 32) * 32;
+    const size_t nbz = ((size_t)T + 31) / 32, nby = ((size_t)H + 31) / 32;
+    size_t off = 0;
+    L.parts = off;
+    off = align256(off + sizeof(Partial) * kMaxParts);
+    L.status = off;
+    off = align256(off + 16);
+    L.stats = off;
+    off = align256(off + sizeof(Stats));
+    L.carry_z = off;
+    off = align256(off + sizeof(float) * nbz * C * 8 * HW);
+    L.s1 = off;
+    off = align256(off + sizeof(float) * C * nbz * 32 * HW);
+    L.carry_y = off;
+    off = align256(off + sizeof(float) * (size_t)T * nby * C * 8 * (size_t)W);
+    L.s2 = off;
+    off = align256(off + sizeof(float) * (size_t)T * C * (size_t)L.Hs * (size_t)L.shs.P);
+    L.total = off;
+    return L;
+}
+
+bool vol_size_ok(int T, int H, int W) {
+    return T >= 1 && H >= 1 && W >= 1 && W <= kIirMaxW && (long long)H * W < (1LL << 31) &&
+           (long long)T * H < (1LL << 31) && (double)T * H * W < (double)(1LL << 40);
+}
+
+size_t bf_gp_volume_workspace_bytes(int T, int H, int W, int N, double sigma_s, double sigma_t, unsigned flags) {
+    if (!vol_size_ok(T, H, W) || N < 0 || N > BF_MAX_DEGREE || !finite_pos(sigma_s) || !finite_pos(sigma_t)) return 0;
+    if ((flags & BF_SPATIAL_MASK) == BF_SPATIAL_FIR) return 0;
+    return vol_layout(T, H, W, N).total;
+}
+
+int bf_gp_volume_forward(const float *vol, float *out, int T, int H, int W, double sigma_s, double sigma_t,
+                         double sigma_r, int N, unsigned flags, void *ws, size_t ws_bytes, void *stream) {
+    int rc;
+    if (!vol || !out) return fail(BF_EINVAL, "null volume pointer");
+    if (T < 1 || H < 1 || W < 1) return fail(BF_EINVAL, "volume size %dx%dx%d must be at least 1x1x1", T, H, W);
+    if (!vol_size_ok(T, H, W)) return fail(BF_EUNSUPPORTED, "volume %dx%dx%d too large (rows up to %d wide)", T, H, W, kIirMaxW);
+    if ((rc = check_params(sigma_s, sigma_r, N))) return rc;
+    if (!finite_pos(sigma_t)) return fail(BF_EINVAL, "sigma_t must be finite and > 0");
+    if (!ws) return fail(BF_EINVAL, "null workspace");
+    if (flags & ~(BF_SPATIAL_MASK | BF_CENTER_MASK)) return fail(BF_EINVAL, "unknown flag bits 0x%x", flags);
+    if ((flags & BF_SPATIAL_MASK) == 3u || (flags & BF_CENTER_MASK) == 12u) return fail(BF_EINVAL, "invalid flag combination");
+    if ((const void *)vol == (const void *)out) return fail(BF_EINVAL, "vol and out must not alias");
+    if ((flags & BF_SPATIAL_MASK) == BF_SPATIAL_FIR)
+        return fail(BF_EUNSUPPORTED, "volumes run in the recursive (IIR) spatial mode");
+    const VolLayout L = vol_layout(T, H, W, N);
+    if (ws_bytes < L.total) return fail(BF_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    Layout fl;
+    memset(&fl, 0, sizeof fl);
+    fl.parts = L.parts;
+    fl.status = L.status;
+    fl.stats = L.stats;
+    // the volume as a (T H) x W image (statistics, and each frame's passes)
+    GPParams ps = make_params(vol, out, T * H, W, W, sigma_r, N, flags, w, fl, nullptr);
+    // the volume as a T x (H W) image (time direction)
+    GPParams pz = ps;
+    pz.H = T;
+    pz.W = H * W;
+    pz.pitch = H * W;
+    VolumeBuffers vb;
+    vb.carry_z = (float *)(w + L.carry_z);
+    vb.S1 = (float *)(w + L.s1);
+    vb.carry_y = (float *)(w + L.carry_y);
+    vb.S2 = (float *)(w + L.s2);
+    vb.Hs = L.Hs;
+    hipError_t e = launch_volume(pz, ps, make_iir(sigma_t, 32, L.shz.L), make_iir(sigma_s, 32, L.shs.L), L.shz,
+                                 L.shs, T, vb, s);
+    if (e != hipSuccess) return hip_fail(e, "volume launch");
+    return BF_OK;
+}
+
 int bf_gp_status(const void *ws, void *stream, int *status) {
     if (!ws || !status) return fail(BF_EINVAL, "null pointer");
     int v = 0;

@@ -48,10 +48,14 @@ struct IirCoef {
 // JOINT (joint filter, range kernel on the guide p.img, average of p.data):
 // stack channel 2n holds u_n(x) of the guide and 2n+1 holds u_n(x) f of the
 // data, n = 0..N.
-template <int B, bool AGG, bool BIG, bool JOINT = false>
+// STACKIN (a volume's row-direction pass): the channel values are read from a
+// stack that an earlier pass filtered, channel n at src + n * src_cstride with
+// rows of p.pitch, instead of being generated from the image.
+template <int B, bool AGG, bool BIG, bool JOINT = false, bool STACKIN = false>
 __device__ __forceinline__ void vband(const GPParams &p, const IirCoef &c, const Stats &st, int col, int band,
                                       float *__restrict__ carry, float *__restrict__ S, int sp_pitch, float *sacc,
-                                      int cb, int ce) {
+                                      int cb, int ce, const float *__restrict__ src = nullptr,
+                                      size_t src_cstride = 0) {
     const int lane = threadIdx.x & 63;
     const int a = band * B;
     // the stack holds every channel as rows(H) = H rounded up to a whole band
@@ -73,56 +77,83 @@ __device__ __forceinline__ void vband(const GPParams &p, const IirCoef &c, const
     // rows a-1 .. a+B+1: every load is issued unconditionally from a clamped
     // row (so that all of them are in flight together), and samples outside
     // the image are zeroed afterwards
-    float xv[B + 3], u[B + 3], dv[JOINT ? B + 3 : 1];
+    constexpr int NG = STACKIN ? 1 : B + 3;  // samples of the generated channels
+    float xv[NG], u[NG], dv[JOINT ? B + 3 : 1];
+    if constexpr (!STACKIN) {
 #pragma unroll
-    for (int i = 0; i < B + 3; ++i) {
-        const int row = a - 1 + i;
-        const int rc = row < 0 ? 0 : (row >= p.H ? p.H - 1 : row);
-        xv[i] = p.img[(size_t)rc * p.pitch + col];
-        if constexpr (JOINT) dv[i] = p.data[(size_t)rc * p.pitch + col];
-    }
+        for (int i = 0; i < B + 3; ++i) {
+            const int row = a - 1 + i;
+            const int rc = row < 0 ? 0 : (row >= p.H ? p.H - 1 : row);
+            xv[i] = p.img[(size_t)rc * p.pitch + col];
+            if constexpr (JOINT) dv[i] = p.data[(size_t)rc * p.pitch + col];
+        }
 #pragma unroll
-    for (int i = 0; i < B + 3; ++i) {
-        xv[i] = centred(xv[i], st, p.inv_sigma_r);
-        u[i] = gauss_u0(xv[i], BIG ? big_shift(xv[i]) : 0);
-    }
-    // rows outside the image (a uniform test per row: only the first and the
-    // last bands have any)
-    if (a == 0) {
-        xv[0] = 0.f;
-        u[0] = 0.f;
-    }
-    if (a + B + 2 > p.H) {
+        for (int i = 0; i < B + 3; ++i) {
+            xv[i] = centred(xv[i], st, p.inv_sigma_r);
+            u[i] = gauss_u0(xv[i], BIG ? big_shift(xv[i]) : 0);
+        }
+        // rows outside the image (a uniform test per row: only the first and
+        // the last bands have any)
+        if (a == 0) {
+            xv[0] = 0.f;
+            u[0] = 0.f;
+        }
+        if (a + B + 2 > p.H) {
 #pragma unroll
-        for (int i = 1; i < B + 3; ++i)
-            if (a - 1 + i >= p.H) {
-                xv[i] = 0.f;
-                u[i] = 0.f;
-            }
+            for (int i = 1; i < B + 3; ++i)
+                if (a - 1 + i >= p.H) {
+                    xv[i] = 0.f;
+                    u[i] = 0.f;
+                }
+        }
+        // advance u to the first channel's degree (the loop below advances it
+        // on entering every degree n > 0: channel n, or channel 2n of a joint
+        // stack)
+        const int pre = JOINT ? ((cb & 1) ? cb >> 1 : (cb >> 1) - 1) : cb - 1;
+        for (int n = 1; n <= pre; ++n) {
+            const float isq = (float)p.isq[n];
+#pragma unroll
+            for (int i = 0; i < B + 3; ++i) u[i] *= xv[i] * isq;
+        }
     }
     const size_t cstride = (size_t)p.W;
-    // advance u to the first channel's degree (the loop below advances it on
-    // entering every degree n > 0: channel n, or channel 2n of a joint stack)
-    const int pre = JOINT ? ((cb & 1) ? cb >> 1 : (cb >> 1) - 1) : cb - 1;
-    for (int n = 1; n <= pre; ++n) {
-        const float isq = (float)p.isq[n];
-#pragma unroll
-        for (int i = 0; i < B + 3; ++i) u[i] *= xv[i] * isq;
-    }
     for (int n = cb; n < ce; ++n) {
         const int deg = JOINT ? n >> 1 : n;
         const bool dat = JOINT && (n & 1);  // a joint data channel (uniform)
-        const float isq = (float)p.isq[deg];
-        if (deg > 0 && !dat) {
+        float sv[STACKIN ? B + 3 : 1];
+        if constexpr (STACKIN) {
+            // rows a-1 .. a+B+1 of channel n of the source stack (clamped
+            // loads, rows outside the image zeroed)
+            const float *sn = src + (size_t)n * src_cstride + col;
 #pragma unroll
-            for (int i = 0; i < B + 3; ++i) u[i] *= xv[i] * isq;
+            for (int i = 0; i < B + 3; ++i) {
+                const int row = a - 1 + i;
+                const int rc = row < 0 ? 0 : (row >= p.H ? p.H - 1 : row);
+                sv[i] = sn[(size_t)rc * p.pitch];
+            }
+            if (a == 0) sv[0] = 0.f;
+            if (a + B + 2 > p.H) {
+#pragma unroll
+                for (int i = 1; i < B + 3; ++i)
+                    if (a - 1 + i >= p.H) sv[i] = 0.f;
+            }
+        } else {
+            const float isq = (float)p.isq[deg];
+            if (deg > 0 && !dat) {
+#pragma unroll
+                for (int i = 0; i < B + 3; ++i) u[i] *= xv[i] * isq;
+            }
         }
         // channel value of sample i (undoing the range shift of BIG images;
         // times the data for a joint data channel)
         auto V = [&](int i) -> float {
-            const float v = BIG ? ldexpf(u[i], -big_shift(xv[i])) : u[i];
-            if constexpr (JOINT) return dat ? v * dv[i] : v;
-            return v;
+            if constexpr (STACKIN) {
+                return sv[i];
+            } else {
+                const float v = BIG ? ldexpf(u[i], -big_shift(xv[i])) : u[i];
+                if constexpr (JOINT) return dat ? v * dv[i] : v;
+                return v;
+            }
         };
         float *cp = carry + ((size_t)(band * p.C + n) * 8) * cstride + col;
         // incoming states of both directions
@@ -331,10 +362,11 @@ __device__ __forceinline__ void affine2(float *r, const float *v, const float *P
 // and likewise for bM, and the terms the backward pass needs are stored:
 // rho = M/D, drho/dtau = (dM - rho dD) / bD and D' = bD = exp(tau^2/2) D.
 // sm: hrow_smem_bytes(T, groups, L) bytes.
+// foff: element offset of the image and output rows (a volume's frame).
 template <int L, bool SAVE = false, bool JOINT = false>
 __device__ __forceinline__ void hrow(const GPParams &p, const IirCoef &c, const Stats &st, int y,
                                      const float *__restrict__ S, int sp_rows, int sp_pitch, float *sm, int T,
-                                     int groups) {
+                                     int groups, size_t foff = 0) {
     const int g = __builtin_amdgcn_readfirstlane((int)threadIdx.x / T);  // whole waves share a group
     const int t = threadIdx.x - g * T;
     const int lane = threadIdx.x & 63, wave = t >> 6, nw = T >> 6;
@@ -373,7 +405,7 @@ __device__ __forceinline__ void hrow(const GPParams &p, const IirCoef &c, const 
     double dD[SAVE ? L : 1], dM[SAVE ? L : 1];
     {
         // unconditional loads from clamped columns, zeroed past the row end
-        const float *irow = p.img + (size_t)y * p.pitch;
+        const float *irow = p.img + foff + (size_t)y * p.pitch;
 #pragma unroll
         for (int i = 0; i < L; ++i) tau[i] = irow[x0 + i < p.W ? x0 + i : p.W - 1];
 #pragma unroll
@@ -660,10 +692,10 @@ __device__ __forceinline__ void hrow(const GPParams &p, const IirCoef &c, const 
             if (x < p.W) {
                 const double rho = bM[i] / bD[i];
                 if constexpr (JOINT) {
-                    p.out[(size_t)y * p.pitch + x] = st.ok ? (float)rho : __builtin_nanf("");
+                    p.out[foff + (size_t)y * p.pitch + x] = st.ok ? (float)rho : __builtin_nanf("");
                     continue;
                 }
-                p.out[(size_t)y * p.pitch + x] = st.ok ? (float)fma(p.sigma_r, rho, st.tc) : __builtin_nanf("");
+                p.out[foff + (size_t)y * p.pitch + x] = st.ok ? (float)fma(p.sigma_r, rho, st.tc) : __builtin_nanf("");
                 if constexpr (SAVE) {
                     const size_t npx = (size_t)p.H * p.W, idx = (size_t)y * p.W + x;
                     float *sv = (float *)p.saved;

@@ -88,6 +88,59 @@ __global__ __launch_bounds__(512, 1) void k_hrow(GPParams p, IirCoef c, const fl
     hrow<L, SAVE, JOINT>(p, c, st, blockIdx.x, S, srows, sp, sm, T, groups);
 }
 
+// ---- volumes: the row-direction pass per frame and the frame-wise row pass ----
+
+// Column pass of every frame over the time-filtered stack S1 (channel n, frame
+// t at S1 + n * s1_cstride + t * H * W, rows of W): grid x as k_vband, y the
+// frame.  The statistics were published by the time pass.
+template <int B, bool AGG>
+__global__ __launch_bounds__(64, 3) void k_vband3(GPParams p, IirCoef c, float *carry, float *S, int sp, int groups,
+                                                  int cgr, int cgp, const float *S1, size_t s1_cstride,
+                                                  size_t carry_fstride, size_t s_fstride) {
+    __shared__ float sacc[AGG ? 1 : B * 64];
+    const Stats st = load_stats(p);
+    if (!st.ok) return;
+    const int nb = (p.H + B - 1) / B;
+    const int nreal = cgr * nb * groups;
+    int idx = blockIdx.x, cg;
+    if (idx < nreal) {
+        cg = idx % cgr;
+        idx /= cgr;
+    } else {
+        idx -= nreal;
+        cg = cgr + idx % cgp;
+        idx /= cgp;
+    }
+    const int band = idx % nb, grp = idx / nb;
+    const int col = cg * 64 + threadIdx.x;
+    const int cb = (p.C * grp) / groups, ce = (p.C * (grp + 1)) / groups;
+    const size_t t = blockIdx.y;
+    vband<B, AGG, false, false, true>(p, c, st, col, band, carry + t * carry_fstride, S + t * s_fstride, sp, sacc, cb,
+                                      ce, S1 + t * (size_t)p.H * p.W, s1_cstride);
+}
+
+__global__ __launch_bounds__(64) void k_vresolve3(GPParams p, IirCoef c, int nb, float *carry, size_t carry_fstride) {
+    const int col = blockIdx.x * 64 + threadIdx.x;
+    const size_t t = blockIdx.z >> 1;
+    if (col < p.W) vresolve(p, c, nb, col, blockIdx.y, blockIdx.z & 1, carry + t * carry_fstride);
+}
+
+// Row pass of frame blockIdx.x / H, row blockIdx.x % H.
+template <int L>
+__global__ __launch_bounds__(512, 1) void k_hrow3(GPParams p, IirCoef c, const float *S, int srows, int sp, int T,
+                                                  int groups, size_t s_fstride) {
+    extern __shared__ float sm[];
+    const Stats st = load_stats(p);
+    const size_t t = blockIdx.x / p.H;
+    const int y = blockIdx.x % p.H;
+    const size_t foff = t * (size_t)p.H * p.pitch;
+    if (!st.ok) {
+        for (int x = threadIdx.x; x < p.W; x += blockDim.x) p.out[foff + (size_t)y * p.pitch + x] = __builtin_nanf("");
+        return;
+    }
+    hrow<L>(p, c, st, y, S + t * s_fstride, srows, sp, sm, T, groups, foff);
+}
+
 // ---- host launchers ----------------------------------------------------------
 
 hipError_t launch_stats(const GPParams &p, bool final_kernel, hipStream_t s) {
@@ -180,6 +233,51 @@ hipError_t launch_iir(const GPParams &p, const IirCoef &c, const IirShape &shape
 hipError_t launch_direct(const DirectArgs &a, hipStream_t s) {
     dim3 grid((a.W + kDirTX - 1) / kDirTX, (a.H + kDirTY - 1) / kDirTY);
     BF_LAUNCH("k_direct", k_direct, grid, dim3(kBlock), sizeof(float) * direct_smem_floats(), s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_volume(const GPParams &pz, const GPParams &ps, const IirCoef &ct, const IirCoef &cs,
+                         const IirShape &shz, const IirShape &shs, int T, const VolumeBuffers &vb, hipStream_t s) {
+    // 1. statistics of the volume seen as a (T H) x W image (ps)
+    hipError_t e = launch_stats(ps, false, s);
+    if (e != hipSuccess) return e;
+    // 2. time direction: the column passes over the volume seen as a T x (H W)
+    // image (pz); its stack S1 has rows of H W and no pad
+    const int nbz = (pz.H + shz.B - 1) / shz.B;
+    const int cgz = (pz.W + 63) / 64;
+    const dim3 gz(cgz * nbz * shz.G);
+    if (shz.B != 32) return hipErrorInvalidValue;
+    BF_LAUNCH("k_vband_agg", (k_vband<32, true, false>), gz, dim3(64), 0, s, pz, ct, vb.carry_z, vb.S1, pz.W, shz.G,
+              cgz, 0);
+    BF_LAUNCH("k_vresolve", k_vresolve, dim3(cgz, pz.C, 2), dim3(64), 0, s, pz, ct, nbz, vb.carry_z);
+    BF_LAUNCH("k_vband", (k_vband<32, false, false>), gz, dim3(64), 0, s, pz, ct, vb.carry_z, vb.S1, pz.W, shz.G,
+              cgz, 0);
+    // 3. column direction in every frame, from S1 into the row-pass stack S2
+    GPParams py = ps;
+    py.H = ps.H / T;
+    const int nby = (py.H + shs.B - 1) / shs.B;
+    const int cgr = (py.W + 63) / 64, cgp = (shs.P + 63) / 64 - cgr;
+    const size_t s1_cstride = (size_t)((pz.H + shz.B - 1) / shz.B) * shz.B * (size_t)pz.W;
+    const size_t carry_fstride = (size_t)nby * py.C * 8 * py.W;
+    const size_t s_fstride = (size_t)py.C * vb.Hs * shs.P;
+    if (shs.B != 32) return hipErrorInvalidValue;
+    BF_LAUNCH("k_vband_agg", (k_vband3<32, true>), dim3(cgr * nby * shs.G, T), dim3(64), 0, s, py, cs, vb.carry_y,
+              vb.S2, shs.P, shs.G, cgr, cgp, (const float *)vb.S1, s1_cstride, carry_fstride, s_fstride);
+    BF_LAUNCH("k_vresolve", k_vresolve3, dim3(cgr, py.C, 2 * T), dim3(64), 0, s, py, cs, nby, vb.carry_y,
+              carry_fstride);
+    BF_LAUNCH("k_vband", (k_vband3<32, false>), dim3((cgr + cgp) * nby * shs.G, T), dim3(64), 0, s, py, cs,
+              vb.carry_y, vb.S2, shs.P, shs.G, cgr, cgp, (const float *)vb.S1, s1_cstride, carry_fstride, s_fstride);
+    // 4. row direction and the recombination, frame by frame
+    const dim3 rb(shs.T * shs.Gr);
+    const size_t sm = hrow_smem_bytes(shs.T, shs.Gr, shs.L);
+    const dim3 gr((unsigned)(T * py.H));
+    switch (shs.L) {
+#define BF_ROW(l) case l: BF_LAUNCH("k_hrow", (k_hrow3<l>), gr, rb, sm, s, py, cs, (const float *)vb.S2, vb.Hs, \
+                                    shs.P, shs.T, shs.Gr, s_fstride); break;
+        BF_ROW(4) BF_ROW(8) BF_ROW(12) BF_ROW(16)
+#undef BF_ROW
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

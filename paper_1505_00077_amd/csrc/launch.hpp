@@ -47,6 +47,18 @@ IirShape iir_shape(int H, int W, int C, bool batch = false);
 hipError_t launch_iir(const GPParams &p, const IirCoef &c, const IirShape &sh, float *carry, float *S, bool save,
                       bool joint, hipStream_t s);
 hipError_t launch_direct(const DirectArgs &a, hipStream_t s);
+// Buffers of a volume forward: the time-direction carries and stack S1
+// (C x rows_B(T) x (H W)), the per-frame column carries and the row-pass stack
+// S2 (T x C x Hs x P), Hs = H rounded up to the band.
+struct VolumeBuffers {
+    float *carry_z, *S1, *carry_y, *S2;
+    int Hs;
+};
+// pz: the volume as a T x (H W) image (coefficients ct, shape shz); ps: the
+// volume as a (T H) x W image (statistics; coefficients cs and shape shs of
+// each H x W frame).
+hipError_t launch_volume(const GPParams &pz, const GPParams &ps, const IirCoef &ct, const IirCoef &cs,
+                         const IirShape &shz, const IirShape &shs, int T, const VolumeBuffers &vb, hipStream_t s);
 int bwd_tiles(int H, int W);
 hipError_t launch_bwd(const GPParams &p, const BwdParams &b, const FirTaps2 &t, int R, double *corr, double *g_lss,
                       double *g_lsr, hipStream_t s);

@@ -116,6 +116,31 @@ def test_joint_modes_and_workspace():
     assert jfwd(H=256, W=300, pitch=300, ws_bytes=j - 1) == bf.BF_ENOMEM
 
 
+def vfwd(v=FAKE, out=FAKE + 4096, T=4, H=8, W=8, ss=3.0, st=2.0, sr=30.0, N=20, flags=0, ws=FAKE + 65536,
+         ws_bytes=1 << 30):
+    return bf.bf_gp_volume_forward(v, out, T, H, W, ss, st, sr, N, flags, ws, ws_bytes, None)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(v=None), dict(out=None), dict(ws=None), dict(T=0), dict(H=0), dict(W=-1), dict(ss=0.0),
+    dict(st=0.0), dict(st=float("inf")), dict(sr=-1.0), dict(N=65), dict(flags=3), dict(flags=16), dict(out=FAKE),
+])
+def test_volume_rejects_invalid_arguments(kw):
+    assert vfwd(**kw) == bf.BF_EINVAL
+
+
+def test_volume_modes_and_workspace():
+    fir = bf.SPATIAL["fir"]
+    assert vfwd(flags=fir) == bf.BF_EUNSUPPORTED
+    assert vfwd(W=9000) == bf.BF_EUNSUPPORTED
+    need = bf.bf_gp_volume_workspace_bytes(10, 64, 96, 20, 3.0, 2.0, 0)
+    # two channel stacks of the volume
+    assert need >= 2 * 22 * 10 * 64 * 96 * 4
+    assert bf.bf_gp_volume_workspace_bytes(10, 64, 96, 20, 3.0, 2.0, fir) == 0
+    assert bf.bf_gp_volume_workspace_bytes(10, 64, 96, 20, 3.0, 0.0, 0) == 0
+    assert vfwd(T=10, H=64, W=96, ws_bytes=need - 1) == bf.BF_ENOMEM
+
+
 def test_workspace_sizes():
     fir = bf.workspace_bytes(1024, 1024, 20, 2.0, "fir")
     iir = bf.workspace_bytes(1024, 1024, 20, 2.0, "iir")
