@@ -374,6 +374,31 @@ def main():
         log(f"video 64x512x512: {ms_v:.3f} ms")
         del frames, vout, vws
 
+    # ---------------- degree study: error surface against the direct filter ----------------
+    # GP in the FIR mode (window ceil(3 sigma_s), the direct filter's) against
+    # eq. (1) computed directly on the GPU, max abs error over a 512^2 image,
+    # beside the degree rule's choice for a weight tolerance of 1e-3
+    if want("degree"):
+        dimg_np = synthimg.voronoi_image(512, 512, 100, seed=9)
+        dimg = torch.from_numpy(dimg_np).to(dev)
+        study = []
+        for ss_d in (2.0, 5.0):
+            for sr_d in (10.0, 20.0, 30.0, 50.0):
+                ref_d = bf.direct_forward(dimg, ss_d, sr_d)
+                xmax = float(np.max(np.abs(dimg_np.astype(np.float64) - dimg_np.mean()))) / sr_d
+                row = {"sigma_s": ss_d, "sigma_r": sr_d, "xmax": xmax, "max_abs_err": {}}
+                try:
+                    row["rule_N_eps_1e-3"] = bf.degree_for(xmax, 1e-3)
+                except bf.BfError:
+                    row["rule_N_eps_1e-3"] = None
+                for Nd in (4, 8, 12, 16, 20, 24, 32, 40, 64):
+                    got = bf.gp_forward(dimg, ss_d, sr_d, Nd, spatial="fir")
+                    row["max_abs_err"][str(Nd)] = float((got - ref_d).abs().max())
+                study.append(row)
+        modes["degree_study_512"] = study
+        log("degree study: " + "; ".join(f"ss {r['sigma_s']} sr {r['sigma_r']}: N20 {r['max_abs_err']['20']:.3g} "
+                                          f"rule {r['rule_N_eps_1e-3']}" for r in study))
+
     # ---------------- copy calibration for the traffic counters ----------------
     if want("calib"):
         # a plain device-to-device copy of 256 MiB: its FETCH_SIZE / WRITE_SIZE

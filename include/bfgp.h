@@ -141,6 +141,20 @@ int bf_gp_volume_forward(const float *vol, float *out, int T, int H, int W, doub
  * backward that used `ws` in *status (BF_OK or BF_ERANGE). */
 int bf_gp_status(const void *ws, void *stream, int *status);
 
+/* Degree rule (the paper fixes N = 20 and leaves the choice of N open; this
+ * rule is the library's own).  For centred intensities with |x| <= xmax
+ * (x = (f - t_c)/sigma_r), the Gauss-polynomial weight of eqs. (4)-(5) differs
+ * from the exact range weight by at most P(Poisson(xmax^2) > N) for every
+ * pair of intensities once N >= xmax^2 - 1 (pairs of one sign: e^-y (e^y -
+ * T_N(y)), y = t tau <= xmax^2, is that tail; opposite signs: the alternating
+ * remainder times e^-|y| is a Poisson probability the tail dominates there).
+ * Returns the smallest even N >= xmax^2 - 1 with tail <= eps (even N keeps
+ * every weight positive), BF_EINVAL for xmax < 0 or eps outside (0, 1), and
+ * BF_ERANGE when no N up to BF_MAX_DEGREE suffices.  Host only.  The bound is
+ * on each weight; the output error also scales with the intensity spread and
+ * the spatial kernel's mass. */
+int bf_gp_degree_for(double xmax, double eps);
+
 /* The spatial mode BF_SPATIAL_AUTO resolves to for this sigma_s (FIR or IIR)
  * under the process-wide crossover radius. */
 unsigned bf_gp_resolve_spatial(double sigma_s, unsigned flags);

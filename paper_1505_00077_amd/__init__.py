@@ -52,6 +52,7 @@ bf_gp_joint_workspace_bytes = _sig("bf_gp_joint_workspace_bytes", _sz, _i, _i, _
 bf_gp_joint_forward = _sig("bf_gp_joint_forward", _i, _vp, _vp, _vp, _i, _i, _i, _d, _d, _i, _u, _vp, _sz, _vp)
 bf_gp_volume_workspace_bytes = _sig("bf_gp_volume_workspace_bytes", _sz, _i, _i, _i, _i, _d, _d, _u)
 bf_gp_volume_forward = _sig("bf_gp_volume_forward", _i, _vp, _vp, _i, _i, _i, _d, _d, _d, _i, _u, _vp, _sz, _vp)
+bf_gp_degree_for = _sig("bf_gp_degree_for", _i, _d, _d)
 bf_gp_status = _sig("bf_gp_status", _i, _vp, _vp, ctypes.POINTER(_i))
 bf_gp_resolve_spatial = _sig("bf_gp_resolve_spatial", _u, _d, _u)
 bf_gp_resolve_spatial_for = _sig("bf_gp_resolve_spatial_for", _u, _i, _i, _d, _u)
@@ -242,6 +243,15 @@ def gp_volume_forward(vol, sigma_s, sigma_t, sigma_r, N=20, spatial="auto", cent
         if st != BF_OK:
             raise BfError(st, "bf_gp_volume_forward (device status)")
     return out
+
+
+def degree_for(xmax, eps=1e-3):
+    """Smallest even degree whose Gauss-polynomial weights are within eps of the
+    exact range weights for centred intensities |x| <= xmax (see bfgp.h)."""
+    n = bf_gp_degree_for(float(xmax), float(eps))
+    if n < 0:
+        raise BfError(n, "bf_gp_degree_for")
+    return int(n)
 
 
 def status(ws, device=None):

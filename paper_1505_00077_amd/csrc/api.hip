@@ -648,6 +648,32 @@ int bf_gp_volume_forward(const float *vol, float *out, int T, int H, int W, doub
     return BF_OK;
 }
 
+// P(Poisson(lam) > N), summed from the tail side in log space (no
+// cancellation when the tail is small).
+static double poisson_tail(int N, double lam) {
+    if (lam <= 0.0) return 0.0;
+    const double ll = log(lam);
+    double sum = 0.0;
+    for (int k = N + 1; k < N + 4000; ++k) {
+        const double term = exp(-lam + k * ll - lgamma(k + 1.0));
+        sum += term;
+        if (k > lam && term < 1e-18 * sum) break;
+    }
+    return sum;
+}
+
+int bf_gp_degree_for(double xmax, double eps) {
+    if (!isfinite(xmax) || xmax < 0.0) return fail(BF_EINVAL, "xmax must be finite and >= 0");
+    if (!(eps > 0.0 && eps < 1.0)) return fail(BF_EINVAL, "eps must lie in (0, 1)");
+    const double lam = xmax * xmax;
+    int n0 = (int)ceil(lam - 1.0);
+    if (n0 < 0) n0 = 0;
+    if (n0 & 1) ++n0;
+    for (int N = n0; N <= BF_MAX_DEGREE; N += 2)
+        if (poisson_tail(N, lam) <= eps) return N;
+    return fail(BF_ERANGE, "no even degree up to %d bounds the weight error by %g at xmax %g", BF_MAX_DEGREE, eps, xmax);
+}
+
 int bf_gp_status(const void *ws, void *stream, int *status) {
     if (!ws || !status) return fail(BF_EINVAL, "null pointer");
     int v = 0;

@@ -274,3 +274,28 @@ def test_workspace_follows_tuning_overrides():
         assert bf.workspace_bytes(1000, 700, 20, 8.0, "iir") > small
     finally:
         bf.set_iir_tuning(0, 0, 0)
+
+
+def test_degree_rule_against_the_poisson_tail():
+    # the rule is host-only: the smallest even N >= xmax^2 - 1 whose Poisson
+    # tail P(Poisson(xmax^2) > N) is at most eps (SciPy's survival function)
+    from scipy import stats
+    for xmax in (0.0, 0.5, 1.0, 2.0, 3.3, 4.0, 5.5):
+        for eps in (1e-2, 1e-3, 1e-6, 1e-12):
+            lam = xmax * xmax
+            try:
+                n = bf.degree_for(xmax, eps)
+            except bf.BfError as e:
+                assert e.code == bf.BF_ERANGE
+                assert all(stats.poisson.sf(m, lam) > eps for m in range(0, 65, 2))
+                continue
+            assert n % 2 == 0 and n >= lam - 1 and n <= 64
+            assert stats.poisson.sf(n, lam) <= eps * (1 + 1e-9)
+            if n >= 2 and n - 2 >= lam - 1:
+                assert stats.poisson.sf(n - 2, lam) > eps
+    assert bf.bf_gp_degree_for(-1.0, 1e-3) == bf.BF_EINVAL
+    assert bf.bf_gp_degree_for(2.0, 0.0) == bf.BF_EINVAL
+    assert bf.bf_gp_degree_for(2.0, 1.0) == bf.BF_EINVAL
+    assert bf.bf_gp_degree_for(float("nan"), 1e-3) == bf.BF_EINVAL
+    assert bf.bf_gp_degree_for(9.0, 1e-6) == bf.BF_ERANGE
+

@@ -498,3 +498,31 @@ def test_volume_gp_against_direct_limits_and_invariants():
     blur = oracle.spatial3(u, kt, ks) / oracle.spatial3(np.ones_like(u), kt, ks)
     assert np.allclose(oracle.volume_gp(u, 1e7, 2, kt, ks), blur, rtol=0, atol=1e-7)
 
+
+# ---------------------------------------------------------------------------
+# the degree rule: the Gauss-polynomial weight error and the Poisson tail
+# ---------------------------------------------------------------------------
+
+def test_weight_error_is_the_poisson_tail_at_equal_intensities():
+    # eq. (5) at t = tau: 1 - w~ = 1 - e^{-lam} T_N(lam) = P(Poisson(lam) > N)
+    from scipy import stats
+    for tau, N in ((1.0, 4), (2.5, 10), (4.0, 20), (3.0, 6), (0.3, 0)):
+        lam = tau * tau
+        assert 1.0 - oracle.gauss_poly(30.0 * tau, 30.0 * tau, 30.0, N) == pytest.approx(
+            stats.poisson.sf(N, lam), rel=1e-10, abs=1e-15)
+
+
+def test_poisson_tail_bounds_every_weight_error():
+    # for |t|, |tau| <= xmax and N >= xmax^2 - 1, |w - w~| <= P(Poisson(xmax^2) > N)
+    from scipy import stats
+    rng = np.random.default_rng(70)
+    for xmax in (1.0, 2.0, 3.0, 4.0):
+        lam = xmax * xmax
+        for N in range(int(math.ceil(lam - 1)), int(lam) + 8):
+            bound = stats.poisson.sf(N, lam)
+            ts = np.concatenate([rng.uniform(-xmax, xmax, 600), [xmax, -xmax]])
+            taus = np.concatenate([rng.uniform(-xmax, xmax, 600), [xmax, xmax]])
+            for t, tau in zip(ts, taus):
+                err = abs(math.exp(-(t - tau) ** 2 / 2) - oracle.gauss_poly(30.0 * t, 30.0 * tau, 30.0, N))
+                assert err <= bound * (1 + 1e-9) + 1e-15
+
