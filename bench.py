@@ -92,9 +92,9 @@ def launch_ids(stage, bf, H, W, C, fir_radii):
     P = ((T * L + 2 + 31) // 32) * 32
     nb = (H + B - 1) // B
     return {
-        "k_hrow": [(f"k_hrow<{L}, false>", H * T * Gr)],
-        "k_vband": [(f"k_vband<{B}, false>", ((P + 63) // 64) * nb * G * 64)],
-        "k_vband_agg": [(f"k_vband<{B}, true>", ((W + 63) // 64) * nb * G * 64)],
+        "k_hrow": [(f"k_hrow<{L}, false, false>", H * T * Gr)],
+        "k_vband": [(f"k_vband<{B}, false, false>", ((P + 63) // 64) * nb * G * 64)],
+        "k_vband_agg": [(f"k_vband<{B}, true, false>", ((W + 63) // 64) * nb * G * 64)],
         "k_vresolve": [("k_vresolve", ((W + 63) // 64) * 64 * C * 2)],
         "k_stats": [("k_stats", min(H, 256) * 256)],
     }.get(stage, [])

@@ -34,6 +34,17 @@ struct IirCoef {
     float phiW[2][4];     // Phi^(64 L)
 };
 
+// x^e for a small non-negative integer e (binary powering)
+__device__ __forceinline__ double ipow(double x, int e) {
+    double r = 1.0;
+    while (e > 0) {
+        if (e & 1) r *= x;
+        x *= x;
+        e >>= 1;
+    }
+    return r;
+}
+
 // One band of B rows in one column.  AGG: run from rest, write the band's end
 // states (causal end, anticausal start).  !AGG: run from the resolved
 // incoming states and write the column-filtered channel stack S[n][row][col].
@@ -298,17 +309,6 @@ __device__ __forceinline__ void mat_pow_chunks(const IirCoef &c, int s, int m, f
 __host__ __device__ constexpr size_t hrow_smem_bytes(int T, int groups, int L) {
     return sizeof(float) * (size_t)(16 * 64 + groups * 16 * (T / 64)) +
            sizeof(double) * 2 * (size_t)(groups - 1) * (size_t)T * (size_t)L;
-}
-
-// x^e for a small non-negative integer e (binary powering)
-__device__ __forceinline__ double ipow(double x, int e) {
-    double r = 1.0;
-    while (e > 0) {
-        if (e & 1) r *= x;
-        x *= x;
-        e >>= 1;
-    }
-    return r;
 }
 
 // Lane shifts through DPP (no LDS round trip).  Lanes whose source is outside
