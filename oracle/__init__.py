@@ -126,15 +126,27 @@ def iir_radius(sigma_s, H, W):
     return int(min(max(H, W) - 1, math.ceil(40.0 * sigma_s)))
 
 
+def box_table(R):
+    """Box spatial kernel on offsets 0..R: weight 1 everywhere in the window
+    (Section 3 notes, after eq. (11), that any spatial filter with a
+    constant-time implementation, a box for instance, can replace the
+    Gaussian of eq. (8))."""
+    return np.ones(int(R) + 1)
+
+
 def spatial_table(mode, sigma_s, H, W):
-    """(table, R) for spatial mode 'fir' (eq. (8) over W = ceil(3 sigma_s)) or
-    'iir' (Deriche's recursive Gaussian, untruncated)."""
+    """(table, R) for spatial mode 'fir' (eq. (8) over W = ceil(3 sigma_s)),
+    'iir' (Deriche's recursive Gaussian, untruncated) or 'box' (uniform
+    weights over the same window as 'fir')."""
     if mode == "fir":
         R = fir_radius(sigma_s)
         return gauss_table(sigma_s, R), R
     if mode == "iir":
         R = max(1, iir_radius(sigma_s, H, W))
         return deriche_table(sigma_s, R), R
+    if mode == "box":
+        R = fir_radius(sigma_s)
+        return box_table(R), R
     raise ValueError(mode)
 
 
@@ -201,7 +213,7 @@ def gp_rescaled(img, sigma_r, N, k, center_mode=CENTER_MEAN, return_dm=False):
 
 
 def gp(img, sigma_s, sigma_r, N, mode="fir", center_mode=CENTER_MEAN):
-    """Algorithm 1 with the spatial filter of the given mode ('fir'/'iir')."""
+    """Algorithm 1 with the spatial filter of the given mode ('fir'/'iir'/'box')."""
     f = _img(img)
     k, _ = spatial_table(mode, sigma_s, *f.shape)
     return gp_alg1(f, sigma_r, N, k, center_mode)

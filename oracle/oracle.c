@@ -33,8 +33,8 @@
 #define OR_EINVAL -1
 #define OR_ENOMEM -2
 
-/* Centre modes for the centring step (Section 2, the Proposition eq. (6),
- * Algorithm 1 first step).  The paper uses the mean; the others are there so
+/* Centre modes of the centring (Section 2, the Proposition eq. (6),
+ * Algorithm 1).  The paper uses the mean; the others are there so
  * that tests can exercise eq. (6) with other centres. */
 #define OR_CENTER_MEAN 0
 #define OR_CENTER_MIDRANGE 1
@@ -189,7 +189,7 @@ int or_direct(const double *f, double *out, int H, int W, const double *k, int R
 }
 
 /* ------------------------------------------------------------------------ */
-/* Centre of the intensity range (Section 2, eq. (6); Algorithm 1 step 1)    */
+/* Centre of the intensity range (Section 2, eq. (6); Algorithm 1: the mean)*/
 /* ------------------------------------------------------------------------ */
 
 double or_center(const double *f, int H, int W, int mode)
@@ -234,18 +234,19 @@ int or_gp_alg1(const double *f, double *out, int H, int W, double sigma_r, int N
         free(G); free(F); free(Fb); free(P); free(Q); free(Hh); free(tmp);
         return OR_ENOMEM;
     }
-    /* step 1: centre; step 2: h = f - t_c */
+    /* centre t_c and the centred image h = f - t_c; the initial images
+     * G = 1, F = exp(-h^2 / 2 sigma_r^2), P = Q = 0 and H = h / sigma_r */
     const double tc = or_center(f, H, W, center_mode);
     for (size_t i = 0; i < n; ++i) {
         const double h = f[i] - tc;
-        G[i] = 1.0;                                         /* step 3 */
-        F[i] = exp(-h * h / (2.0 * sigma_r * sigma_r));     /* step 4 */
-        P[i] = 0.0;                                         /* step 5 */
-        Q[i] = 0.0;                                         /* step 6 */
-        Hh[i] = h / sigma_r;                                /* step 7 */
+        G[i] = 1.0;
+        F[i] = exp(-h * h / (2.0 * sigma_r * sigma_r));
+        P[i] = 0.0;
+        Q[i] = 0.0;
+        Hh[i] = h / sigma_r;
     }
-    spatial_sep(F, Fb, tmp, H, W, k, k, R);                 /* step 8 */
-    double c = 1.0;                                         /* step 9 */
+    spatial_sep(F, Fb, tmp, H, W, k, k, R);                 /* Fbar: F filtered, eq. (8) */
+    double c = 1.0;                                         /* c = 1/n!, from n = 0 */
     for (int m = 0; m <= N; ++m) {                          /* the loop over n */
         for (size_t i = 0; i < n; ++i) {
             Q[i] += c * G[i] * Fb[i];
@@ -258,7 +259,7 @@ int or_gp_alg1(const double *f, double *out, int H, int W, double sigma_r, int N
         }
         c = c / (double)(m + 1);
     }
-    for (size_t i = 0; i < n; ++i)                          /* output step */
+    for (size_t i = 0; i < n; ++i)                          /* sigma_r P/Q + t_c */
         out[i] = sigma_r * (P[i] / Q[i]) + tc;
     free(G); free(F); free(Fb); free(P); free(Q); free(Hh); free(tmp);
     return OR_OK;
@@ -562,7 +563,7 @@ int or_gp_rescaled(const double *f, double *out, double *Dout, double *Mout, int
 
 /* ------------------------------------------------------------------------ */
 /* Gradients of the rescaled form (the paper has no gradient; this is the    */
-/* plain chain rule through eqs. (7)-(11) and the mean of step 1)           */
+/* plain chain rule through eqs. (7)-(11) and the mean used as centre)    */
 /* ------------------------------------------------------------------------ */
 
 /* Given upstream gout = dL/dout, returns dL/df (grad_f, may be NULL),

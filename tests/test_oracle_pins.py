@@ -526,3 +526,74 @@ def test_poisson_tail_bounds_every_weight_error():
                 err = abs(math.exp(-(t - tau) ** 2 / 2) - oracle.gauss_poly(30.0 * t, 30.0 * tau, 30.0, N))
                 assert err <= bound * (1 + 1e-9) + 1e-15
 
+
+
+# ---------------------------------------------------------------------------
+# the box spatial kernel (Section 3, after eq. (11): any constant-time spatial
+# filter can stand in for the Gaussian of eq. (8))
+# ---------------------------------------------------------------------------
+
+def _box_blur(a, R):
+    # SciPy's uniform filter is the window mean with zeros outside the image
+    return ndimage.uniform_filter(a, size=2 * R + 1, mode="constant", cval=0.0) * (2 * R + 1) ** 2
+
+
+def test_box_window_is_the_fir_window():
+    for s in (0.3, 1.0, 2.0, 3.4, 10.0, 40.0):
+        k, R = oracle.spatial_table("box", s, 64, 64)
+        assert R == oracle.fir_radius(s) and np.array_equal(k, np.ones(R + 1))
+
+
+@pytest.mark.parametrize("R", [1, 3, 7, 30])
+def test_box_spatial_matches_scipy_uniform_filter(R):
+    # R = 30 is wider than the image: every window clips at the borders
+    f = rand_img(23, 17, 200 + R)
+    got = oracle.spatial(f, oracle.box_table(R))
+    assert np.allclose(got, _box_blur(f, R), rtol=1e-12, atol=1e-9)
+    if R <= 3:
+        assert np.allclose(got, oracle.brute_spatial(f, oracle.box_table(R)), rtol=1e-13, atol=1e-10)
+
+
+def test_box_direct_matches_double_sum_and_wide_range_is_box_mean():
+    f = rand_img(7, 9, 210)
+    k = oracle.box_table(2)
+    assert np.allclose(oracle.direct(f, 25.0, k), oracle.brute_direct(f, 25.0, k), rtol=1e-13, atol=1e-10)
+    g = rand_img(21, 30, 211)
+    ref = _box_blur(g, 4) / _box_blur(np.ones_like(g), 4)
+    assert np.allclose(oracle.direct(g, 1e8, oracle.box_table(4)), ref, rtol=1e-9, atol=1e-8)
+
+
+@pytest.mark.parametrize("N", [0, 4, 10, 20])
+def test_box_alg1_matches_explicit_double_sum(N):
+    rng = np.random.default_rng(220 + N)
+    f = rng.uniform(0, 255, size=(6, 8))
+    k = oracle.box_table(2)
+    ref = oracle.brute_gp(f, 45.0, N, k)
+    assert np.allclose(oracle.gp_alg1(f, 45.0, N, k), ref, rtol=0, atol=1e-9)
+    assert np.allclose(oracle.gp_rescaled(f, 45.0, N, k), ref, rtol=0, atol=1e-9)
+
+
+def test_box_alg1_converges_to_box_direct_and_wide_range_is_box_mean():
+    f = voronoi_image(40, 56, 10, seed=230).astype(np.float64)
+    k, R = oracle.spatial_table("box", 2.0, *f.shape)
+    ref = oracle.direct(f, 30.0, k)
+    errs = [np.max(np.abs(oracle.gp_alg1(f, 30.0, N, k) - ref)) for N in (10, 20, 40, 60)]
+    assert errs[0] > errs[1] > errs[2] > errs[3] and errs[3] < 1e-6
+    blur = _box_blur(f, R) / _box_blur(np.ones_like(f), R)
+    assert np.allclose(oracle.gp_alg1(f, 1e7, 2, k), blur, rtol=0, atol=1e-7)
+
+
+def test_box_covering_the_image_is_a_tone_map():
+    # a window wider than the image holds every pixel: the result at i depends
+    # on f(i) only, through the Gauss-polynomial weights of eq. (5) over the
+    # whole image (with t_c the mean)
+    rng = np.random.default_rng(240)
+    f = rng.choice(np.array([12.0, 80.0, 81.5, 140.0, 230.0]), size=(9, 12))
+    sr, N = 40.0, 12
+    out = oracle.gp_alg1(f, sr, N, oracle.box_table(12))
+    tc = f.mean()
+    h = (f - tc).ravel()
+    for v in np.unique(f):
+        w = np.array([oracle.gauss_poly(t, v - tc, sr, N) for t in h])
+        expect = tc + np.sum(w * h) / np.sum(w)
+        assert np.allclose(out[f == v], expect, rtol=0, atol=1e-9)
