@@ -374,6 +374,47 @@ def main():
         log(f"video 64x512x512: {ms_v:.3f} ms")
         del frames, vout, vws
 
+    # ---------------- box spatial kernel: running sums, O(1) in the radius ----------------
+    # the 1024^2 sweep image at the headline's sigma_s, and the 16-MP image; the
+    # two passes move 4 + 4C (column pass) and 4C + 8 (row pass) bytes per
+    # pixel, so the per-kernel rates are against HBM
+    if want("box"):
+        mid = torch.from_numpy(synthimg.mid_1024()).to(dev)
+        xout = torch.empty_like(mid)
+        xres = {}
+        for ss_b in SWEEP:
+            xws = bf.workspace(1024, 1024, DEGREE, ss_b, "box")
+            ms_b = timed(lambda: bf.gp_forward(mid, ss_b, SIGMA_R, DEGREE, spatial="box", out=xout, ws=xws), K, Wm,
+                         torch)
+            xres[str(ss_b)] = {"ms": ms_b, "mpix_s": mid.numel() / (ms_b * 1e-3) / 1e6,
+                               "radius": bf.fir_radius(ss_b)}
+            del xws
+        big = torch.from_numpy(synthimg.large_4096()).to(dev)
+        bout = torch.empty_like(big)
+        xws = bf.workspace(4096, 4096, DEGREE, 10.0, "box")
+        ms_b = timed(lambda: bf.gp_forward(big, 10.0, 20.0, DEGREE, spatial="box", out=bout, ws=xws), K, Wm, torch)
+        bf.profile_enable(True)
+        timed(lambda: bf.gp_forward(big, 10.0, 20.0, DEGREE, spatial="box", out=bout, ws=xws), K, 0, torch)
+        xstage = bf.profile_collect()
+        bf.profile_enable(False)
+        if bf.status(xws) != bf.BF_OK:
+            raise RuntimeError("device status not OK on the 16-MP box run")
+        mp = 4096 * 4096
+        per_px = {"k_boxcol": 4 + 4 * C, "k_boxrow": 4 * C + 8, "k_stats": 4}
+        kern = {}
+        for k, (kc, kt) in sorted(xstage.items()):
+            avg = kt / kc
+            kern[k] = {"ms_per_call": avg,
+                       "algorithmic_gbs": per_px[k] * mp / (avg * 1e-3) / 1e9 if k in per_px else None}
+        modes["box_1024_per_sigma_s"] = xres
+        modes["box_4096"] = {"ms": ms_b, "mpix_s": mp / (ms_b * 1e-3) / 1e6, "sigma_s": 10.0, "sigma_r": 20.0,
+                             "model_bytes_per_px": 12 + 8 * C,
+                             "model_frac_of_hbm_peak": (12 + 8 * C) * mp / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                             "kernels": kern}
+        log("box 1024^2: " + ", ".join(f"sigma_s {k} {v['ms']:.3f} ms" for k, v in xres.items()) +
+            f"; 16MP {ms_b:.3f} ms")
+        del mid, xout, big, bout, xws
+
     # ---------------- degree study: error surface against the direct filter ----------------
     # GP in the FIR mode (window ceil(3 sigma_s), the direct filter's) against
     # eq. (1) computed directly on the GPU, max abs error over a 512^2 image,

@@ -44,6 +44,11 @@ extern "C" {
 #define BF_SPATIAL_IIR 2u    /* Deriche's 4th-order recursive Gaussian (causal +
                                 anticausal, zero initial state), as in the
                                 paper's experiments                                */
+#define BF_SPATIAL_BOX 3u    /* box: uniform weights over the window of eq. (1),
+                                |dy|, |dx| <= ceil(3 sigma_s), by running sums
+                                (O(1) per pixel for any radius; Section 3, the
+                                remark after eq. (11)).  Forward only; AUTO
+                                never picks it                                     */
 #define BF_SPATIAL_MASK 3u
 /* Centre t_c of the intensity range (bits 2-3); Section 2, eq. (6). */
 #define BF_CENTER_MEAN 0u     /* the mean, as in Algorithm 1 (default)           */
@@ -76,11 +81,19 @@ const char *bf_last_error(void);
  *  N            degree of the Gauss-polynomial, 0..BF_MAX_DEGREE.  Even N keeps
  *               every approximate weight positive; with odd N the denominator
  *               can vanish and the output is whatever the division gives.
- *  flags        BF_SPATIAL_* | BF_CENTER_*.
+ *  flags        BF_SPATIAL_* | BF_CENTER_*.  Width limits: FIR none (radius up
+ *               to BF_FIR_MAX_RADIUS), IIR and BOX W <= 8192 (else
+ *               BF_EUNSUPPORTED).  BOX: the window radius is ceil(3 sigma_s)
+ *               (capped at max(H, W), which covers the whole image); its two
+ *               passes keep running and prefix sums in double, and the
+ *               workspace holds the column-filtered stack (4 (N + 2) H P bytes,
+ *               P = W rounded up to a multiple of 256 (W <= 1024), 512
+ *               (W <= 4096) or 1024).
  *  saved        NULL, or a device buffer of 16*H*W bytes that receives what
  *               bf_gp_backward needs (per pixel: M/D and its tau-derivative as
- *               float, the rescaled denominator as double), planar.  Either
- *               spatial mode; the backward must use the same mode.
+ *               float, the rescaled denominator as double), planar.  FIR or
+ *               IIR mode (BOX returns BF_EUNSUPPORTED); the backward must use
+ *               the same mode.
  *  ws, ws_bytes device workspace of at least bf_gp_workspace_bytes(...) bytes.
  * Intensities whose |x| is so large that the channels leave the FP32 range make
  * the output NaN and set BF_ERANGE in the workspace status (bf_gp_status). */
@@ -103,8 +116,9 @@ int bf_gp_forward(const float *img, float *out, int H, int W, int pitch,
  *  guide, data, out  device, H x W with one row pitch `pitch`; out may alias
  *                    neither input.
  *  flags             BF_SPATIAL_AUTO or BF_SPATIAL_IIR (the recursive Gaussian,
- *                    as in the paper's experiments; BF_SPATIAL_FIR returns
- *                    BF_EUNSUPPORTED), | BF_CENTER_*.  W up to 8192.
+ *                    as in the paper's experiments; BF_SPATIAL_FIR and
+ *                    BF_SPATIAL_BOX return BF_EUNSUPPORTED), | BF_CENTER_*.
+ *                    W up to 8192.
  *  ws, ws_bytes      device workspace of bf_gp_joint_workspace_bytes(...) bytes
  *                    (0 for unsupported arguments).
  * A guide too far from its centre for the FP32 channels makes the output NaN
@@ -122,9 +136,9 @@ int bf_gp_joint_forward(const float *guide, const float *data, float *out, int H
  * scale sigma_s along y and x and sigma_t along t (time in a video; equal to
  * sigma_s for an isotropic volume), zero extension, the centre taken over the
  * whole volume.  Recursive spatial mode (BF_SPATIAL_AUTO or BF_SPATIAL_IIR;
- * BF_SPATIAL_FIR returns BF_EUNSUPPORTED): a time pass on the volume seen as
- * T rows of H W samples, a column pass in every frame, and the row pass with
- * the FP64 recombination.  With T = 1 the result is bf_gp_forward's (IIR).
+ * BF_SPATIAL_FIR and BF_SPATIAL_BOX return BF_EUNSUPPORTED): a time pass on
+ * the volume seen as T rows of H W samples, a column pass in every frame, and
+ * the row pass with the FP64 recombination.  With T = 1 the result is bf_gp_forward's (IIR).
  *  vol, out     device, contiguous T x H x W float (frame after frame, rows of
  *               W); may not alias.  W up to 8192, H W below 2^31.
  *  ws, ws_bytes device workspace of bf_gp_volume_workspace_bytes(...) bytes:
@@ -199,7 +213,7 @@ int bf_gp_iir_shape(int H, int W, int N, int *shape /* 5 ints, host */);
 /* ---- GP backward -------------------------------------------------------------
  * Adjoint of bf_gp_forward for a scalar loss L with upstream gradient
  * grad_out = dL/dout.  Derived by the chain rule through eqs. (7)-(11) and the
- * mean of Algorithm 1's first step.  The spatial filter is symmetric with
+ * mean that Algorithm 1 takes as the centre.  The spatial filter is symmetric with
  * zero extension, so its adjoint is itself: the adjoint channels are filtered
  * by the forward's own kernel.  FIR mode: the radius ceil(3 sigma_s) is held
  * fixed when differentiating in sigma_s.  IIR mode: the recursion is
@@ -211,7 +225,8 @@ int bf_gp_iir_shape(int H, int W, int N, int *shape /* 5 ints, host */);
  *  grad_img           NULL or device H x W (pitch) float: dL/dimg.
  *  grad_log_sigma_s   NULL or device double: dL/d(log sigma_s) (overwritten).
  *  grad_log_sigma_r   NULL or device double: dL/d(log sigma_r) (overwritten).
- * Supported for both spatial modes (AUTO resolves as in bf_gp_forward) with
+ * Supported for the FIR and IIR modes (AUTO resolves as in bf_gp_forward;
+ * BF_SPATIAL_BOX returns BF_EUNSUPPORTED and a workspace size of 0) with
  * centre mean or none; the midrange centre returns BF_EUNSUPPORTED. */
 size_t bf_gp_backward_workspace_bytes(int H, int W, int N, double sigma_s, unsigned flags);
 
@@ -235,7 +250,8 @@ int bf_gp_backward(const float *img, const float *grad_out, const void *saved,
  * each image's output is bit-identical to a single call made under
  * bf_gp_set_iir_tuning(0, 1, 1) (with other tuning overrides, under the same
  * overrides), and differs from a default single call only in rounding.
- * Images are limited to 8192 columns (the IIR limit). */
+ * Images are limited to 8192 columns (the IIR limit).  FIR, IIR or AUTO:
+ * BF_SPATIAL_BOX returns BF_EUNSUPPORTED. */
 typedef struct bf_gp_item {
     const float *img; /* device, H x W, row pitch `pitch` elements */
     float *out;       /* device, same shape and pitch */

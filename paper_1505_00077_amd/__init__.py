@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbfgp.so")
 
 BF_OK, BF_EINVAL, BF_ENOMEM, BF_ERANGE, BF_EHIP, BF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-SPATIAL = {"auto": 0, "fir": 1, "iir": 2}
+SPATIAL = {"auto": 0, "fir": 1, "iir": 2, "box": 3}
 CENTER = {"mean": 0, "midrange": 4, "none": 8}
 MAX_DEGREE = 64
 FIR_MAX_RADIUS = 24
@@ -115,12 +115,13 @@ def fir_radius(sigma_s):
 
 def resolve_spatial(sigma_s, spatial="auto", shape=None):
     """"fir" or "iir" for this sigma_s (for an image of `shape` = (H, W) when
-    given, which honours the size-dependent crossover table)."""
+    given, which honours the size-dependent crossover table); "box" stays
+    "box"."""
     if shape is None:
         m = bf_gp_resolve_spatial(float(sigma_s), SPATIAL[spatial])
     else:
         m = bf_gp_resolve_spatial_for(int(shape[0]), int(shape[1]), float(sigma_s), SPATIAL[spatial])
-    return {1: "fir", 2: "iir"}[m]
+    return {1: "fir", 2: "iir", 3: "box"}[m]
 
 
 def set_fir_crossover_table(table):

@@ -14,6 +14,7 @@
 #include "fir.hpp"
 #include "iir.hpp"
 #include "direct.hpp"
+#include "box.hpp"
 #include "bwd.hpp"
 #include "iir_bwd.hpp"
 
@@ -71,7 +72,7 @@ int crossover_for(long long px) {
 // px = H * W of the image, or 0 when unknown (the process-wide radius).
 unsigned resolve_spatial(long long px, double sigma_s, unsigned flags) {
     unsigned m = flags & BF_SPATIAL_MASK;
-    if (m == BF_SPATIAL_FIR || m == BF_SPATIAL_IIR) return m;
+    if (m != BF_SPATIAL_AUTO) return m;
     return fir_radius(sigma_s) <= crossover_for(px) ? BF_SPATIAL_FIR : BF_SPATIAL_IIR;
 }
 
@@ -113,6 +114,47 @@ struct Layout {
     size_t parts, status, stats, carry, stack, total;
 };
 
+// Box mode: samples per row-pass thread, threads per row and stack pitch.
+int box_L(int W) { return W <= 1024 ? 4 : W <= 4096 ? 8 : 16; }
+int box_T(int W) { return ((W + box_L(W) - 1) / box_L(W) + 63) / 64 * 64; }
+int box_pitch(int W) { return box_T(W) * box_L(W); }
+
+// Radius of the box window: that of eq. (1), capped at max(H, W) (a wider
+// window covers the same pixels).
+int box_radius(double sigma_s, int H, int W) {
+    double r = ceil(3.0 * sigma_s * (1.0 - 1e-6));
+    const int m = H > W ? H : W;
+    if (r < 1.0) r = 1.0;
+    return r > (double)m ? m : (int)r;
+}
+
+// Box launch shape: bands of at least two radii (the start-up window costs at
+// most one band), then channel groups until the column pass has a few waves
+// per SIMD (each thread holds at most kBoxKC running sums).
+BoxShape box_shape(int H, int W, int C, int R) {
+    BoxShape sh;
+    sh.R = R;
+    const long twoR = 2L * R;
+    long Bb = ((twoR + 31) / 32) * 32;
+    if (Bb < 32) Bb = 32;
+    if (Bb > H) Bb = H;
+    sh.Bb = (int)Bb;
+    sh.nb = (int)((H + Bb - 1) / Bb);
+    const long waves = (long)((W + 63) / 64) * sh.nb;
+    int G = (int)((kTargetWaves + waves - 1) / waves);
+    if (G > 8) G = 8;
+    const int gmin = (C + kBoxKC - 1) / kBoxKC;
+    if (G < gmin) G = gmin;
+    if (G > C) G = C;
+    sh.G = G;
+    const int per = (C + G - 1) / G;
+    sh.NC = per <= 4 ? 4 : per <= 6 ? 6 : per <= 8 ? 8 : per <= 12 ? 12 : per <= 16 ? 16 : 24;
+    sh.L = box_L(W);
+    sh.T = box_T(W);
+    sh.P = box_pitch(W);
+    return sh;
+}
+
 // C: channels of the stack (N + 2 for the filter, 2 (N + 1) for the joint
 // filter).
 Layout gp_layout_c(int H, int W, int C, unsigned spatial) {
@@ -132,6 +174,9 @@ Layout gp_layout_c(int H, int W, int C, unsigned spatial) {
         off = align256(off + sizeof(float) * nb * (size_t)C * 8 * (size_t)W);
         L.stack = off;
         off = align256(off + sizeof(float) * (size_t)C * (size_t)sh.Hs * (size_t)sh.P);
+    } else if (spatial == BF_SPATIAL_BOX) {
+        L.stack = off;
+        off = align256(off + sizeof(float) * (size_t)C * (size_t)H * (size_t)box_pitch(W));
     }
     L.total = off;
     return L;
@@ -160,6 +205,8 @@ int check_spatial(unsigned spatial, double sigma_s, int W) {
                     BF_FIR_MAX_RADIUS);
     if (spatial == BF_SPATIAL_IIR && W > kIirMaxW)
         return fail(BF_EUNSUPPORTED, "IIR mode supports widths up to %d", kIirMaxW);
+    if (spatial == BF_SPATIAL_BOX && W > kBoxMaxW)
+        return fail(BF_EUNSUPPORTED, "box mode supports widths up to %d", kBoxMaxW);
     return BF_OK;
 }
 
@@ -495,9 +542,11 @@ int bf_gp_forward(const float *img, float *out, int H, int W, int pitch, double 
     if ((rc = check_params(sigma_s, sigma_r, N))) return rc;
     if (!ws) return fail(BF_EINVAL, "null workspace");
     if (flags & ~(BF_SPATIAL_MASK | BF_CENTER_MASK)) return fail(BF_EINVAL, "unknown flag bits 0x%x", flags);
-    if ((flags & BF_SPATIAL_MASK) == 3u || (flags & BF_CENTER_MASK) == 12u) return fail(BF_EINVAL, "invalid flag combination");
+    if ((flags & BF_CENTER_MASK) == 12u) return fail(BF_EINVAL, "invalid flag combination");
     const unsigned spatial = resolve_spatial((long long)H * W, sigma_s, flags);
     if ((rc = check_spatial(spatial, sigma_s, W))) return rc;
+    if (spatial == BF_SPATIAL_BOX && saved)
+        return fail(BF_EUNSUPPORTED, "the box mode has no backward pass (pass saved = NULL)");
     if ((const void *)img == (const void *)out) return fail(BF_EINVAL, "img and out must not alias");
     const Layout L = gp_layout(H, W, N, spatial);
     if (ws_bytes < L.total) return fail(BF_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
@@ -510,6 +559,10 @@ int bf_gp_forward(const float *img, float *out, int H, int W, int pitch, double 
         const int R = fir_radius(sigma_s);
         e = launch_fir(p, make_taps(sigma_s, R), R, saved != nullptr, s);
         if (e != hipSuccess) return hip_fail(e, "FIR launch");
+    } else if (spatial == BF_SPATIAL_BOX) {
+        const BoxShape sh = box_shape(H, W, N + 2, box_radius(sigma_s, H, W));
+        e = launch_box(p, sh, (float *)(w + L.stack), s);
+        if (e != hipSuccess) return hip_fail(e, "box launch");
     } else {
         const IirShape sh = iir_shape(H, W, N + 2);
         e = launch_iir(p, make_iir(sigma_s, sh.B, sh.L), sh, (float *)(w + L.carry), (float *)(w + L.stack),
@@ -521,7 +574,7 @@ int bf_gp_forward(const float *img, float *out, int H, int W, int pitch, double 
 
 size_t bf_gp_joint_workspace_bytes(int H, int W, int N, double sigma_s, unsigned flags) {
     if (H < 1 || W < 1 || N < 0 || N > BF_MAX_DEGREE || !finite_pos(sigma_s)) return 0;
-    if ((flags & BF_SPATIAL_MASK) == BF_SPATIAL_FIR) return 0;
+    if ((flags & BF_SPATIAL_MASK) == BF_SPATIAL_FIR || (flags & BF_SPATIAL_MASK) == BF_SPATIAL_BOX) return 0;
     return gp_layout_c(H, W, 2 * (N + 1), BF_SPATIAL_IIR).total;
 }
 
@@ -533,10 +586,10 @@ int bf_gp_joint_forward(const float *guide, const float *data, float *out, int H
     if ((rc = check_params(sigma_s, sigma_r, N))) return rc;
     if (!ws) return fail(BF_EINVAL, "null workspace");
     if (flags & ~(BF_SPATIAL_MASK | BF_CENTER_MASK)) return fail(BF_EINVAL, "unknown flag bits 0x%x", flags);
-    if ((flags & BF_SPATIAL_MASK) == 3u || (flags & BF_CENTER_MASK) == 12u) return fail(BF_EINVAL, "invalid flag combination");
+    if ((flags & BF_CENTER_MASK) == 12u) return fail(BF_EINVAL, "invalid flag combination");
     if ((const void *)out == (const void *)guide || (const void *)out == (const void *)data)
         return fail(BF_EINVAL, "out must not alias the guide or the data");
-    if ((flags & BF_SPATIAL_MASK) == BF_SPATIAL_FIR)
+    if ((flags & BF_SPATIAL_MASK) == BF_SPATIAL_FIR || (flags & BF_SPATIAL_MASK) == BF_SPATIAL_BOX)
         return fail(BF_EUNSUPPORTED, "the joint filter runs in the recursive (IIR) spatial mode");
     if ((rc = check_spatial(BF_SPATIAL_IIR, sigma_s, W))) return rc;
     const int C = 2 * (N + 1);
@@ -602,7 +655,7 @@ bool vol_size_ok(int T, int H, int W) {
 
 size_t bf_gp_volume_workspace_bytes(int T, int H, int W, int N, double sigma_s, double sigma_t, unsigned flags) {
     if (!vol_size_ok(T, H, W) || N < 0 || N > BF_MAX_DEGREE || !finite_pos(sigma_s) || !finite_pos(sigma_t)) return 0;
-    if ((flags & BF_SPATIAL_MASK) == BF_SPATIAL_FIR) return 0;
+    if ((flags & BF_SPATIAL_MASK) == BF_SPATIAL_FIR || (flags & BF_SPATIAL_MASK) == BF_SPATIAL_BOX) return 0;
     return vol_layout(T, H, W, N).total;
 }
 
@@ -616,9 +669,9 @@ int bf_gp_volume_forward(const float *vol, float *out, int T, int H, int W, doub
     if (!finite_pos(sigma_t)) return fail(BF_EINVAL, "sigma_t must be finite and > 0");
     if (!ws) return fail(BF_EINVAL, "null workspace");
     if (flags & ~(BF_SPATIAL_MASK | BF_CENTER_MASK)) return fail(BF_EINVAL, "unknown flag bits 0x%x", flags);
-    if ((flags & BF_SPATIAL_MASK) == 3u || (flags & BF_CENTER_MASK) == 12u) return fail(BF_EINVAL, "invalid flag combination");
+    if ((flags & BF_CENTER_MASK) == 12u) return fail(BF_EINVAL, "invalid flag combination");
     if ((const void *)vol == (const void *)out) return fail(BF_EINVAL, "vol and out must not alias");
-    if ((flags & BF_SPATIAL_MASK) == BF_SPATIAL_FIR)
+    if ((flags & BF_SPATIAL_MASK) == BF_SPATIAL_FIR || (flags & BF_SPATIAL_MASK) == BF_SPATIAL_BOX)
         return fail(BF_EUNSUPPORTED, "volumes run in the recursive (IIR) spatial mode");
     const VolLayout L = vol_layout(T, H, W, N);
     if (ws_bytes < L.total) return fail(BF_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
@@ -689,7 +742,9 @@ int bf_gp_status(const void *ws, void *stream, int *status) {
 
 size_t bf_gp_backward_workspace_bytes(int H, int W, int N, double sigma_s, unsigned flags) {
     if (H < 1 || W < 1 || N < 0 || N > BF_MAX_DEGREE || !finite_pos(sigma_s)) return 0;
-    return bwd_layout(H, W, N, resolve_spatial((long long)H * W, sigma_s, flags)).total;
+    const unsigned spatial = resolve_spatial((long long)H * W, sigma_s, flags);
+    if (spatial == BF_SPATIAL_BOX) return 0;
+    return bwd_layout(H, W, N, spatial).total;
 }
 
 int bf_gp_backward(const float *img, const float *grad_out, const void *saved, int H, int W, int pitch,
@@ -701,8 +756,9 @@ int bf_gp_backward(const float *img, const float *grad_out, const void *saved, i
     if (!saved) return fail(BF_EINVAL, "null saved buffer");
     if (!ws) return fail(BF_EINVAL, "null workspace");
     if (flags & ~(BF_SPATIAL_MASK | BF_CENTER_MASK)) return fail(BF_EINVAL, "unknown flag bits 0x%x", flags);
-    if ((flags & BF_SPATIAL_MASK) == 3u || (flags & BF_CENTER_MASK) == 12u) return fail(BF_EINVAL, "invalid flag combination");
+    if ((flags & BF_CENTER_MASK) == 12u) return fail(BF_EINVAL, "invalid flag combination");
     const unsigned spatial = resolve_spatial((long long)H * W, sigma_s, flags);
+    if (spatial == BF_SPATIAL_BOX) return fail(BF_EUNSUPPORTED, "the box mode has no backward pass");
     if ((rc = check_spatial(spatial, sigma_s, W))) return rc;
     if ((flags & BF_CENTER_MASK) == BF_CENTER_MIDRANGE)
         return fail(BF_EUNSUPPORTED, "the backward pass supports the mean centre or no centring");

@@ -207,7 +207,9 @@ int bf_gp_plan_batched(const bf_gp_item *items, int count, unsigned flags, void 
     *plan_out = nullptr;
     if (!items || count < 1) return set_error(BF_EINVAL, "empty batch");
     if (flags & ~(BF_SPATIAL_MASK | BF_CENTER_MASK)) return set_error(BF_EINVAL, "unknown flag bits");
-    if ((flags & BF_SPATIAL_MASK) == 3u || (flags & BF_CENTER_MASK) == 12u) return set_error(BF_EINVAL, "invalid flags");
+    if ((flags & BF_CENTER_MASK) == 12u) return set_error(BF_EINVAL, "invalid flags");
+    if ((flags & BF_SPATIAL_MASK) == BF_SPATIAL_BOX)
+        return set_error(BF_EUNSUPPORTED, "the batched path runs the FIR and IIR modes");
     for (int i = 0; i < count; ++i) {
         const bf_gp_item &it = items[i];
         if (!it.img || !it.out || it.img == it.out) return set_error(BF_EINVAL, "bad image pointers in the batch");

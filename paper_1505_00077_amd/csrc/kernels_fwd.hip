@@ -4,6 +4,7 @@
 #include "fir.hpp"
 #include "iir.hpp"
 #include "direct.hpp"
+#include "box.hpp"
 
 namespace bfgp {
 
@@ -139,6 +140,41 @@ __global__ __launch_bounds__(512, 1) void k_hrow3(GPParams p, IirCoef c, const f
         return;
     }
     hrow<L>(p, c, st, y, S + t * s_fstride, srows, sp, sm, T, groups, foff);
+}
+
+// ---- box spatial kernel ----------------------------------------------------------
+
+// Column pass: one 64-column wave per band and channel group (workgroups of
+// the same band and group are adjacent).  The first kernel after the
+// statistics pass: it reduces the partials itself.
+template <int NC>
+__global__ __launch_bounds__(64) void k_boxcol(GPParams p, BoxFact bfct, float *S, int R, int Bb, int nb, int G,
+                                               int cgr, int P) {
+    const Stats st = reduce_stats(p);
+    if (blockIdx.x == 0 && threadIdx.x == 0) publish_stats(p, st);
+    if (!st.ok) return;
+    int idx = blockIdx.x;
+    const int cg = idx % cgr;
+    idx /= cgr;
+    const int band = idx % nb, grp = idx / nb;
+    const int col = cg * 64 + threadIdx.x;
+    if (col >= p.W) return;
+    const int cb = (p.C * grp) / G, ce = (p.C * (grp + 1)) / G;
+    const int y0 = band * Bb, y1 = y0 + Bb < p.H ? y0 + Bb : p.H;
+    boxcol<NC>(p, bfct, st, R, col, y0, y1, cb, ce - cb, S, P);
+}
+
+// Row pass + recombination: one workgroup of T threads per image row, K
+// channels per step.
+template <int L, int K>
+__global__ __launch_bounds__(512) void k_boxrow(GPParams p, const float *S, int R, int P, int T) {
+    extern __shared__ float sm[];
+    const Stats st = load_stats(p);
+    if (!st.ok) {
+        for (int x = threadIdx.x; x < p.W; x += blockDim.x) p.out[(size_t)blockIdx.x * p.pitch + x] = __builtin_nanf("");
+        return;
+    }
+    boxrow<L, K>(p, st, R, blockIdx.x, S, P, T, (double *)sm);
 }
 
 // ---- host launchers ----------------------------------------------------------
@@ -277,6 +313,52 @@ hipError_t launch_volume(const GPParams &pz, const GPParams &ps, const IirCoef &
         BF_ROW(4) BF_ROW(8) BF_ROW(12) BF_ROW(16)
 #undef BF_ROW
         default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_box(const GPParams &p, const BoxShape &sh, float *S, hipStream_t s) {
+    const int cgr = (p.W + 63) / 64;
+    if ((long)cgr * sh.nb * sh.G > 0x7fffffffL || sh.T > 512 || sh.T % 64 || (long)sh.T * sh.L < p.W || sh.P != sh.T * sh.L)
+        return hipErrorInvalidValue;
+    BoxFact bfct;
+    double v = 1.0;
+    for (int n = 0; n < kMaxC; ++n) {
+        if (n > 0) v *= p.isq[n];
+        bfct.ifs[n] = v;
+    }
+    const dim3 cgrid(cgr * sh.nb * sh.G);
+    switch (sh.NC) {
+#define BF_CASE(nc)                                                                                            \
+    case nc:                                                                                                   \
+        BF_LAUNCH("k_boxcol", k_boxcol<nc>, cgrid, dim3(64), 0, s, p, bfct, S, sh.R, sh.Bb, sh.nb, sh.G, cgr, sh.P); \
+        break;
+        BF_CASE(4) BF_CASE(6) BF_CASE(8) BF_CASE(12) BF_CASE(16) BF_CASE(24)
+#undef BF_CASE
+        default: return hipErrorInvalidValue;
+    }
+    // two channels per step, one for the widest rows (registers); rows past
+    // 1024 samples need more than 64 KiB of LDS (the attribute is set once per
+    // instantiation, to its largest row)
+    if (sh.L == 4) {
+        const size_t sm = boxrow_smem_bytes(sh.T, 4, 2);
+        BF_LAUNCH("k_boxrow", (k_boxrow<4, 2>), dim3(p.H), dim3(sh.T), sm, s, p, S, sh.R, sh.P, sh.T);
+    } else if (sh.L == 8) {
+        static hipError_t attr = hipFuncSetAttribute((const void *)k_boxrow<8, 2>,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)boxrow_smem_bytes(512, 8, 2));
+        if (attr != hipSuccess) return attr;
+        const size_t sm = boxrow_smem_bytes(sh.T, 8, 2);
+        BF_LAUNCH("k_boxrow", (k_boxrow<8, 2>), dim3(p.H), dim3(sh.T), sm, s, p, S, sh.R, sh.P, sh.T);
+    } else if (sh.L == 16) {
+        static hipError_t attr = hipFuncSetAttribute((const void *)k_boxrow<16, 1>,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)boxrow_smem_bytes(512, 16, 1));
+        if (attr != hipSuccess) return attr;
+        const size_t sm = boxrow_smem_bytes(sh.T, 16, 1);
+        BF_LAUNCH("k_boxrow", (k_boxrow<16, 1>), dim3(p.H), dim3(sh.T), sm, s, p, S, sh.R, sh.P, sh.T);
+    } else {
+        return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -47,6 +47,10 @@ IirShape iir_shape(int H, int W, int C, bool batch = false);
 hipError_t launch_iir(const GPParams &p, const IirCoef &c, const IirShape &sh, float *carry, float *S, bool save,
                       bool joint, hipStream_t s);
 hipError_t launch_direct(const DirectArgs &a, hipStream_t s);
+struct BoxShape;
+// Box spatial mode: column pass (running sums) into the stack S, then the row
+// pass with the recombination.
+hipError_t launch_box(const GPParams &p, const BoxShape &sh, float *S, hipStream_t s);
 // Buffers of a volume forward: the time-direction carries and stack S1
 // (C x rows_B(T) x (H W)), the per-frame column carries and the row-pass stack
 // S2 (T x C x Hs x P), Hs = H rounded up to the band.

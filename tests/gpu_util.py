@@ -30,19 +30,21 @@ def oracle_gp(img, sigma_s, sigma_r, N, mode, center=oracle.CENTER_MEAN):
 
 def oracle_gp_at(img, y, x, sigma_s, sigma_r, N, mode, reach=None):
     """Oracle output at one pixel of a large image: the FP64 mean of the whole
-    image is the centre; only the pixel's neighbourhood (the FIR window, or 25
-    sigma_s of the recursive kernel, beyond which its weights are below 1e-18)
-    is filtered, with the centred crop and no further centring."""
+    image is the centre; only the pixel's neighbourhood (the FIR or box window,
+    or 25 sigma_s of the recursive kernel, beyond which its weights are below
+    1e-18) is filtered, with the centred crop and no further centring."""
     f = np.asarray(img, np.float64)
     H, W = f.shape
     tc = float(f.mean())
     if reach is None:
-        reach = oracle.fir_radius(sigma_s) if mode == "fir" else int(np.ceil(25 * sigma_s))
+        reach = oracle.fir_radius(sigma_s) if mode in ("fir", "box") else int(np.ceil(25 * sigma_s))
     y0, y1 = max(0, y - reach), min(H, y + reach + 1)
     x0, x1 = max(0, x - reach), min(W, x + reach + 1)
     crop = f[y0:y1, x0:x1] - tc
     if mode == "fir":
         k = oracle.gauss_table(sigma_s, oracle.fir_radius(sigma_s))
+    elif mode == "box":
+        k = oracle.box_table(oracle.fir_radius(sigma_s))
     else:
         k = oracle.deriche_table(sigma_s, max(crop.shape) - 1)
     out = oracle.gp_alg1(crop, sigma_r, N, k, oracle.CENTER_NONE)

@@ -42,7 +42,7 @@ def fwd(img=FAKE, out=FAKE + 4096, H=8, W=8, pitch=8, ss=2.0, sr=30.0, N=20, fla
 @pytest.mark.parametrize("kw", [
     dict(img=None), dict(out=None), dict(ws=None), dict(H=0), dict(W=0), dict(H=-3), dict(pitch=7),
     dict(ss=0.0), dict(ss=-1.0), dict(ss=float("nan")), dict(ss=float("inf")), dict(sr=0.0), dict(sr=float("nan")),
-    dict(N=-1), dict(N=65), dict(flags=3), dict(flags=12), dict(flags=16), dict(out=FAKE),
+    dict(N=-1), dict(N=65), dict(flags=12), dict(flags=16), dict(out=FAKE),
 ])
 def test_forward_rejects_invalid_arguments(kw):
     assert fwd(**kw) == bf.BF_EINVAL
@@ -61,6 +61,33 @@ def test_forward_rejects_unsupported_modes():
     assert fwd(H=4, W=9000, pitch=9000, flags=bf.SPATIAL["iir"]) == bf.BF_EUNSUPPORTED
 
 
+def test_box_mode_contract():
+    box = bf.SPATIAL["box"]
+    assert box == 3 and bf.resolve_spatial(2.0, "box") == "box" and bf.resolve_spatial(50.0, "box") == "box"
+    # width limit, no saved terms (no backward), small workspace
+    assert fwd(H=4, W=9000, pitch=9000, flags=box) == bf.BF_EUNSUPPORTED
+    assert fwd(flags=box, saved=FAKE + 65536) == bf.BF_EUNSUPPORTED
+    # the column-filtered stack: N + 2 channels of H rows of pitch P (W rounded
+    # up to a multiple of 256 up to 1024 columns, of 512 up to 4096, of 1024
+    # beyond), whatever the radius
+    for H, W, P in ((64, 64, 256), (100, 1000, 1024), (9, 1025, 1536), (7, 4097, 5120), (3, 8192, 8192)):
+        need = bf.workspace_bytes(H, W, 20, 2.0, "box")
+        assert 22 * H * P * 4 <= need < 22 * H * P * 4 + 8192
+        assert bf.workspace_bytes(H, W, 20, 400.0, "box") == need
+        assert fwd(H=H, W=W, pitch=W, flags=box, ws_bytes=need - 1) == bf.BF_ENOMEM
+    # the other entry points do not run the box mode
+    assert bwd(flags=box) == bf.BF_EUNSUPPORTED
+    assert bf.bf_gp_backward_workspace_bytes(64, 64, 20, 2.0, box) == 0
+    assert jfwd(flags=box) == bf.BF_EUNSUPPORTED
+    assert bf.bf_gp_joint_workspace_bytes(64, 64, 20, 2.0, box) == 0
+    assert vfwd(flags=box) == bf.BF_EUNSUPPORTED
+    assert bf.bf_gp_volume_workspace_bytes(4, 64, 64, 20, 2.0, 2.0, box) == 0
+    item = bf.BfGpItem(FAKE, FAKE + 4096, 8, 8, 8, 2.0, 30.0, 20)
+    plan = ctypes.c_void_p()
+    assert bf.bf_gp_plan_batched(ctypes.byref(item), 1, box, ctypes.byref(plan)) == bf.BF_EUNSUPPORTED
+    assert not plan.value
+
+
 def bwd(img=FAKE, g=FAKE + 4096, saved=FAKE + 8192, H=8, W=8, pitch=8, ss=2.0, sr=30.0, N=20, flags=0,
         gi=FAKE + 65536, ws=FAKE + 131072, ws_bytes=1 << 30):
     return bf.bf_gp_backward(img, g, saved, H, W, pitch, ss, sr, N, flags, gi, None, None, ws, ws_bytes, None)
@@ -68,7 +95,7 @@ def bwd(img=FAKE, g=FAKE + 4096, saved=FAKE + 8192, H=8, W=8, pitch=8, ss=2.0, s
 
 @pytest.mark.parametrize("kw", [
     dict(img=None), dict(g=None), dict(saved=None), dict(ws=None), dict(H=0), dict(pitch=7), dict(ss=0.0),
-    dict(sr=float("inf")), dict(N=65), dict(flags=3), dict(flags=16), dict(gi=FAKE), dict(gi=FAKE + 4096),
+    dict(sr=float("inf")), dict(N=65), dict(flags=12), dict(flags=16), dict(gi=FAKE), dict(gi=FAKE + 4096),
     dict(flags=2, gi=FAKE), dict(flags=2, N=-1),
 ])
 def test_backward_rejects_invalid_arguments(kw):
@@ -98,7 +125,7 @@ def jfwd(g=FAKE, d=FAKE + 4096, out=FAKE + 8192, H=8, W=8, pitch=8, ss=4.0, sr=3
 
 @pytest.mark.parametrize("kw", [
     dict(g=None), dict(d=None), dict(out=None), dict(ws=None), dict(H=0), dict(pitch=7), dict(ss=0.0),
-    dict(sr=float("nan")), dict(N=65), dict(flags=3), dict(flags=16), dict(out=FAKE), dict(out=FAKE + 4096),
+    dict(sr=float("nan")), dict(N=65), dict(flags=12), dict(flags=16), dict(out=FAKE), dict(out=FAKE + 4096),
 ])
 def test_joint_rejects_invalid_arguments(kw):
     assert jfwd(**kw) == bf.BF_EINVAL
@@ -123,7 +150,7 @@ def vfwd(v=FAKE, out=FAKE + 4096, T=4, H=8, W=8, ss=3.0, st=2.0, sr=30.0, N=20, 
 
 @pytest.mark.parametrize("kw", [
     dict(v=None), dict(out=None), dict(ws=None), dict(T=0), dict(H=0), dict(W=-1), dict(ss=0.0),
-    dict(st=0.0), dict(st=float("inf")), dict(sr=-1.0), dict(N=65), dict(flags=3), dict(flags=16), dict(out=FAKE),
+    dict(st=0.0), dict(st=float("inf")), dict(sr=-1.0), dict(N=65), dict(flags=12), dict(flags=16), dict(out=FAKE),
 ])
 def test_volume_rejects_invalid_arguments(kw):
     assert vfwd(**kw) == bf.BF_EINVAL
