@@ -87,8 +87,7 @@ const char *bf_last_error(void);
  *               (capped at max(H, W), which covers the whole image); its two
  *               passes keep running and prefix sums in double, and the
  *               workspace holds the column-filtered stack (4 (N + 2) H P bytes,
- *               P = W rounded up to a multiple of 256 (W <= 1024), 512
- *               (W <= 4096) or 1024).
+ *               P = W rounded up to a multiple of 256 (W <= 4096) or 1024).
  *  saved        NULL, or a device buffer of 16*H*W bytes that receives what
  *               bf_gp_backward needs (per pixel: M/D and its tau-derivative as
  *               float, the rescaled denominator as double), planar.  FIR or

@@ -115,7 +115,7 @@ struct Layout {
 };
 
 // Box mode: samples per row-pass thread, threads per row and stack pitch.
-int box_L(int W) { return W <= 1024 ? 4 : W <= 4096 ? 8 : 16; }
+int box_L(int W) { return W <= 4096 ? 4 : 16; }
 int box_T(int W) { return ((W + box_L(W) - 1) / box_L(W) + 63) / 64 * 64; }
 int box_pitch(int W) { return box_T(W) * box_L(W); }
 

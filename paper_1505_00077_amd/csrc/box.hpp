@@ -27,7 +27,7 @@
 namespace bfgp {
 
 constexpr int kBoxKC = 24;      // most channels one column-pass thread accumulates
-constexpr int kBoxMaxW = 8192;  // widest row of the row pass (T <= 512, L <= 16)
+constexpr int kBoxMaxW = 8192;  // widest row of the row pass (T L >= W, L 4 or 16)
 
 // Launch shape of the box passes.
 struct BoxShape {
@@ -37,8 +37,9 @@ struct BoxShape {
     int G;   // channel groups of the column pass
     int NC;  // channels one column-pass thread accumulates (4, 6, 8, 12, 16 or 24),
              // at least ceil(C / G)
-    int L;   // samples per thread of the row pass (4, 8 or 16)
-    int T;   // threads per row (a multiple of 64, T L >= W)
+    int L;   // samples per thread of the row pass: 4 (W <= 4096) or 16
+    int T;   // threads per row (a multiple of 64, T L >= W; at most 1024 for
+             // L = 4, 512 for L = 16)
     int P;   // row pitch of the stack: T L
 };
 
@@ -185,12 +186,14 @@ __host__ __device__ constexpr size_t boxrow_pe_stride(int T, int L) { return (si
 __host__ __device__ constexpr size_t boxrow_smem_bytes(int T, int L, int K) {
     return sizeof(double) * (size_t)K * (boxrow_pe_stride(T, L) + (size_t)(T / 64));
 }
+
 // Row pass and recombination of image row y.  Thread t holds the contiguous
 // chunk [t L, t L + L) of the prefix scan and the output pixels t + k T,
 // k < L (consecutive lanes read consecutive prefix values).  K channels are
 // scanned per step (one pair of barriers for all of them, their chains
-// independent); the chunks of the next two steps are in flight meanwhile.  Horner in tau over the channels
-// from the top down, as
+// independent); the next step's chunks are in flight meanwhile (two steps
+// ahead measured no faster).
+// Horner in tau over the channels from the top down, as
 //   bD <- Ubar_n + bD tau / sqrt(n+1)  (n <= N),
 //   bM <- Ubar_n + bM tau sqrt(n+1) / n  (n >= 1),
 // ends with bD = exp(tau^2/2) D and bM = exp(tau^2/2) M, so M/D = bM/bD.
@@ -229,18 +232,14 @@ __device__ __forceinline__ void boxrow(const GPParams &p, const Stats &st, int R
             d[i] = q.x; d[i + 1] = q.y; d[i + 2] = q.z; d[i + 3] = q.w;
         }
     };
-    // chunks of this step (z) and the next (zn) are in registers; the step
-    // after that is loaded at the top of each step
-    float z[K][L], zn[K][L];
+    // the next step's chunks are loaded at the top of each step
+    float z[K][L];
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        load(p.C - 1 - j, z[j]);
-        load(p.C - 1 - K - j, zn[j]);
-    }
+    for (int j = 0; j < K; ++j) load(p.C - 1 - j, z[j]);
     for (int n0 = p.C - 1; n0 >= 0; n0 -= K) {
-        float znn[K][L];
+        float zn[K][L];
 #pragma unroll
-        for (int j = 0; j < K; ++j) load(n0 - 2 * K - j, znn[j]);
+        for (int j = 0; j < K; ++j) load(n0 - K - j, zn[j]);
         double run[K], ex[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
@@ -257,8 +256,15 @@ __device__ __forceinline__ void boxrow(const GPParams &p, const Stats &st, int R
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            double base = ex[j];
-            for (int w = 0; w < wave; ++w) base += wt[j * nw + w];
+            // totals of the waves before this one: lane l < nw (<= 16) reads
+            // wave l's total, a scan inside the first row of 16 lanes sums
+            // them, and lane wave - 1 holds the offset
+            double v = lane < nw ? wt[j * nw + lane] : 0.0;
+            v += box_dpp<kBoxRowShr + 1>(v);
+            v += box_dpp<kBoxRowShr + 2>(v);
+            v += box_dpp<kBoxRowShr + 4>(v);
+            v += box_dpp<kBoxRowShr + 8>(v);
+            const double base = ex[j] + (wave > 0 ? box_lane(v, wave > 0 ? wave - 1 : 0) : 0.0);
             double *pe = Pe + (size_t)j * PS;
             // the chunk's exclusive prefix (the same additions in the same
             // order as its total); slot of m = x0 + i is m + t
@@ -293,10 +299,7 @@ __device__ __forceinline__ void boxrow(const GPParams &p, const Stats &st, int R
 #pragma unroll
         for (int j = 0; j < K; ++j)
 #pragma unroll
-            for (int i = 0; i < L; ++i) {
-                z[j][i] = zn[j][i];
-                zn[j][i] = znn[j][i];
-            }
+            for (int i = 0; i < L; ++i) z[j][i] = zn[j][i];
     }
     float *orow = p.out + (size_t)y * p.pitch;
 #pragma unroll

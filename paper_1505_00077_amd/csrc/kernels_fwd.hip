@@ -167,7 +167,7 @@ __global__ __launch_bounds__(64) void k_boxcol(GPParams p, BoxFact bfct, float *
 // Row pass + recombination: one workgroup of T threads per image row, K
 // channels per step.
 template <int L, int K>
-__global__ __launch_bounds__(512) void k_boxrow(GPParams p, const float *S, int R, int P, int T) {
+__global__ __launch_bounds__(L == 4 ? 1024 : 512) void k_boxrow(GPParams p, const float *S, int R, int P, int T) {
     extern __shared__ float sm[];
     const Stats st = load_stats(p);
     if (!st.ok) {
@@ -319,7 +319,8 @@ hipError_t launch_volume(const GPParams &pz, const GPParams &ps, const IirCoef &
 
 hipError_t launch_box(const GPParams &p, const BoxShape &sh, float *S, hipStream_t s) {
     const int cgr = (p.W + 63) / 64;
-    if ((long)cgr * sh.nb * sh.G > 0x7fffffffL || sh.T > 512 || sh.T % 64 || (long)sh.T * sh.L < p.W || sh.P != sh.T * sh.L)
+    if ((long)cgr * sh.nb * sh.G > 0x7fffffffL || sh.T > (sh.L == 4 ? 1024 : 512) || sh.T % 64 ||
+        (long)sh.T * sh.L < p.W || sh.P != sh.T * sh.L)
         return hipErrorInvalidValue;
     BoxFact bfct;
     double v = 1.0;
@@ -338,18 +339,15 @@ hipError_t launch_box(const GPParams &p, const BoxShape &sh, float *S, hipStream
         default: return hipErrorInvalidValue;
     }
     // two channels per step, one for the widest rows (registers); rows past
-    // 1024 samples need more than 64 KiB of LDS (the attribute is set once per
-    // instantiation, to its largest row)
+    // about 3000 samples need more than 64 KiB of LDS (the attribute is set
+    // once per instantiation, to its largest row)
     if (sh.L == 4) {
+        static hipError_t attr = hipFuncSetAttribute((const void *)k_boxrow<4, 2>,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)boxrow_smem_bytes(1024, 4, 2));
+        if (attr != hipSuccess) return attr;
         const size_t sm = boxrow_smem_bytes(sh.T, 4, 2);
         BF_LAUNCH("k_boxrow", (k_boxrow<4, 2>), dim3(p.H), dim3(sh.T), sm, s, p, S, sh.R, sh.P, sh.T);
-    } else if (sh.L == 8) {
-        static hipError_t attr = hipFuncSetAttribute((const void *)k_boxrow<8, 2>,
-                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                     (int)boxrow_smem_bytes(512, 8, 2));
-        if (attr != hipSuccess) return attr;
-        const size_t sm = boxrow_smem_bytes(sh.T, 8, 2);
-        BF_LAUNCH("k_boxrow", (k_boxrow<8, 2>), dim3(p.H), dim3(sh.T), sm, s, p, S, sh.R, sh.P, sh.T);
     } else if (sh.L == 16) {
         static hipError_t attr = hipFuncSetAttribute((const void *)k_boxrow<16, 1>,
                                                      hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -68,9 +68,10 @@ def test_box_mode_contract():
     assert fwd(H=4, W=9000, pitch=9000, flags=box) == bf.BF_EUNSUPPORTED
     assert fwd(flags=box, saved=FAKE + 65536) == bf.BF_EUNSUPPORTED
     # the column-filtered stack: N + 2 channels of H rows of pitch P (W rounded
-    # up to a multiple of 256 up to 1024 columns, of 512 up to 4096, of 1024
-    # beyond), whatever the radius
-    for H, W, P in ((64, 64, 256), (100, 1000, 1024), (9, 1025, 1536), (7, 4097, 5120), (3, 8192, 8192)):
+    # up to a multiple of 256 up to 4096 columns, of 1024 beyond), whatever
+    # the radius
+    for H, W, P in ((64, 64, 256), (100, 1000, 1024), (9, 1025, 1280), (5, 4096, 4096), (7, 4097, 5120),
+                    (3, 8192, 8192)):
         need = bf.workspace_bytes(H, W, 20, 2.0, "box")
         assert 22 * H * P * 4 <= need < 22 * H * P * 4 + 8192
         assert bf.workspace_bytes(H, W, 20, 400.0, "box") == need

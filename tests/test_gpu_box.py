@@ -156,9 +156,9 @@ def test_deterministic_and_symmetric(bf):
 
 @pytest.mark.parametrize("W", [1024, 1025, 4096, 4097, 6000, 8192])
 def test_wide_rows(bf, W):
-    # 4, 8 or 16 samples per row-pass thread (up to 1024, 4096, 8192 columns);
-    # at 8192 the row's
-    # prefix sums need more than 64 KiB of LDS
+    # 4 samples per row-pass thread up to 4096 columns (1024 threads), 16
+    # beyond; from about 3000 columns the row's prefix sums need more than
+    # 64 KiB of LDS
     img = synthimg.voronoi_image(3, W, 40, seed=W)
     for ss in (2.0, 30.0):
         got = run(bf, img, ss, 30.0, 20)
