@@ -459,14 +459,16 @@ def main():
         f64 = small.astype(np.float64)
         ref_direct = oracle.direct_gauss(f64, 3.0, SIGMA_R)
         acc = {}
-        for mode in ("fir", "iir"):
+        for mode in ("fir", "iir", "box"):
             got = bf.gp_forward(torch.from_numpy(small).to(dev), 3.0, SIGMA_R, DEGREE, spatial=mode, check=True)
             g = got.cpu().numpy().astype(np.float64)
             k, _ = oracle.spatial_table(mode, 3.0, *small.shape)
             ref = oracle.gp_alg1(f64, SIGMA_R, DEGREE, k)
+            # the box mode's own direct filter is eq. (1) with the box kernel
+            rd = oracle.direct(f64, SIGMA_R, k) if mode == "box" else ref_direct
             acc[mode] = {"max_abs_err_vs_oracle": float(np.max(np.abs(g - ref))),
-                         "max_abs_err_vs_direct": float(np.max(np.abs(g - ref_direct))),
-                         "mse_db_vs_direct": oracle.mse_db(g, ref_direct)}
+                         "max_abs_err_vs_direct": float(np.max(np.abs(g - rd))),
+                         "mse_db_vs_direct": oracle.mse_db(g, rd)}
         gd = bf.direct_forward(torch.from_numpy(small).to(dev), 3.0, SIGMA_R).cpu().numpy().astype(np.float64)
         acc["direct"] = {"max_abs_err_vs_oracle": float(np.max(np.abs(gd - ref_direct)))}
         modes["accuracy_256_sigma_s3"] = acc
@@ -483,9 +485,28 @@ def main():
             oracle.gp_alg1(crop, SIGMA_R, DEGREE, k)
         dt = time.perf_counter() - t0
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        model = None
+        try:
+            with open("/proc/cpuinfo") as fh:
+                model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), None)
+        except OSError:
+            pass
         cpu = {"value": len(SWEEP) * crop.size / dt / 1e6, "unit": "Mpix/s", "cores": cores, "kind": "oracle",
                "sample": "one step: the 1024x1024 image at each sigma_s of the sweep, same spatial mode, "
-                         "FP64 Algorithm 1 (C, OpenMP)", "seconds": dt}
+                         "FP64 Algorithm 1 (C, OpenMP)", "seconds": dt, "cpu_model": model}
+
+    # HBM fractions of the 16-MP runs: the two-pass model (12 + 8C B/px) against
+    # the peak and against the measured copy rate, and the on-chip floor
+    # (12 B/px: image reads and output write only) against the peak
+    cal = modes.get("copy_calibration")
+    for key in ("gp_forward_4096", "box_4096"):
+        m = modes.get(key)
+        if m:
+            px = 4096 * 4096
+            m["model_gbs"] = m["model_bytes_per_px"] * px / (m["ms"] * 1e-3) / 1e9
+            m["onchip_floor_frac_of_hbm_peak"] = 12 * px / (m["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS
+            if cal:
+                m["model_frac_of_copy_bw"] = m["model_gbs"] / cal["gbs_read_plus_write"]
 
     line = {
         "metric": METRIC, "value": value, "unit": "Mpix/s", "n_gpus": 1, "steps": K, "warmup": Wm,

@@ -73,7 +73,7 @@ __device__ __forceinline__ double box_lead(float xf, int cb) {
 // row leaving it in one update (two independent power chains), and stores
 // acc[k] / sqrt((cb+k)!).  Channels k >= nch are accumulated but not stored.
 // Rows are loaded eight at a time, the next eight issued before the current
-// ones are used.
+// ones are used (in the start-up window too).
 template <int NC>
 __device__ __forceinline__ void boxcol(const GPParams &p, const BoxFact &bfct, const Stats &st, int R, int col,
                                        int y0, int y1, int cb, int nch, float *__restrict__ S, int P) {
@@ -89,10 +89,13 @@ __device__ __forceinline__ void boxcol(const GPParams &p, const BoxFact &bfct, c
     {
         const int a = y0 - R - 1 > 0 ? y0 - R - 1 : 0;
         const int b = y0 + R < H ? y0 + R : H;  // exclusive
-        for (int y = a; y < b; y += 8) {
-            float f[8];
+        float f[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) f[i] = img[(size_t)clampy(y + i) * pitch];
+        for (int i = 0; i < 8; ++i) f[i] = img[(size_t)clampy(a + i) * pitch];
+        for (int y = a; y < b; y += 8) {
+            float fn[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) fn[i] = img[(size_t)clampy(y + 8 + i) * pitch];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 if (y + i < b) {
@@ -105,6 +108,8 @@ __device__ __forceinline__ void boxcol(const GPParams &p, const BoxFact &bfct, c
                     }
                 }
             }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) f[i] = fn[i];
         }
     }
     float *out = S + ((size_t)cb * H) * P + col;
