@@ -302,8 +302,8 @@ def joint_direct(guide, data, sigma_r, k):
 
 
 def joint_gp(guide, data, sigma_r, N, k, center_mode=CENTER_MEAN):
-    """Gauss-polynomial approximation of the joint filter, Algorithm 1's steps
-    with the guide in every range term (see oracle.c)."""
+    """Gauss-polynomial approximation of the joint filter: Algorithm 1 with
+    the guide in every range term (see oracle.c)."""
     g, f = _img(guide), _img(data)
     if g.shape != f.shape:
         raise ValueError("guide and data shapes differ")

@@ -1,5 +1,5 @@
 // Backward of the GP forward (FIR spatial mode), derived by the chain rule
-// through eqs. (7)-(11) and the mean of Algorithm 1's first step.
+// through eqs. (7)-(11) and the mean that Algorithm 1 takes as the centre.
 //
 // With tau = x(i), rho = M/D, upstream g = dL/dout and the forward's saved
 // rho, drho/dtau and D' = exp(tau^2/2) D (double):

@@ -19,7 +19,7 @@ struct Partial {
     float hi;
 };
 
-// Per-image statistics: the centre t_c of Algorithm 1's first step, plus the
+// Per-image statistics: the centre t_c of Algorithm 1 (the mean), plus the
 // extremes used for the FP32 range check.  Written once per call by the
 // statistics pass, read by every later kernel.
 struct Stats {

@@ -1,7 +1,7 @@
 // Backward of the GP forward in the recursive (IIR) spatial mode.
 //
-// The chain rule is the one of the FIR backward (eqs. (7)-(11) and the mean of
-// Algorithm 1's first step): with a = g sigma_r / D' and p_n = tau^n / sqrt(n!),
+// The chain rule is the one of the FIR backward (eqs. (7)-(11) and the mean
+// that Algorithm 1 takes as the centre): with a = g sigma_r / D' and p_n = tau^n / sqrt(n!),
 //   V_n = a [ sqrt(n) p_{n-1}(tau) - rho p_n(tau) [n <= N] ],  n = 0..N+1,
 //   W_n = K V_n,   Z_n = dK/dlog(sigma_s) V_n,
 //   gH(j) = sum_n W_n(j) u_n'(x_j) + g(j) sigma_r drho/dtau(j),

@@ -20,13 +20,38 @@ from collections import defaultdict
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
 
+def _code_only(text):
+    """C++ source with comments removed and whitespace collapsed (string
+    literals kept), so that edits to comments leave the fingerprint alone."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c == '"' or c == "'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def source_fingerprint():
-    """sha256 over the HIP sources and headers of the library."""
+    """sha256 over the code (comments and whitespace aside) of the library's
+    HIP sources and headers."""
     h = hashlib.sha256()
     for path in sorted(glob.glob(os.path.join(_HERE, "csrc", "*.hip")) + glob.glob(os.path.join(_HERE, "csrc", "*.hpp"))):
         h.update(os.path.basename(path).encode())
-        with open(path, "rb") as f:
-            h.update(f.read())
+        with open(path, encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

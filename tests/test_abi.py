@@ -327,3 +327,14 @@ def test_degree_rule_against_the_poisson_tail():
     assert bf.bf_gp_degree_for(float("nan"), 1e-3) == bf.BF_EINVAL
     assert bf.bf_gp_degree_for(9.0, 1e-6) == bf.BF_ERANGE
 
+
+
+def test_source_fingerprint_ignores_comments_and_layout():
+    # the recorded HBM counters stay valid across comment edits, not code edits
+    from paper_1505_00077_amd import profiling
+    a = 'int f(int x) { // one\n  return x + 1; /* two */ }\nconst char *s = "a // b /* c */";'
+    b = 'int f(int x) {\n\n    return x + 1;\n}\n// three\nconst char *s = "a // b /* c */";'
+    assert profiling._code_only(a) == profiling._code_only(b)
+    assert profiling._code_only(a) != profiling._code_only(a.replace("x + 1", "x + 2"))
+    assert "// b /* c */" in profiling._code_only(a)
+    assert len(profiling.source_fingerprint()) == 16
