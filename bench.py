@@ -91,10 +91,13 @@ def launch_ids(stage, bf, H, W, C, fir_radii):
     B, G, L, T, Gr = sh["band_rows"], sh["col_groups"], sh["row_chunk"], sh["row_threads"], sh["row_groups"]
     P = ((T * L + 2 + 31) // 32) * 32
     nb = (H + B - 1) // B
+    # 32-row bands in 2..8 channel groups run as k_vbandg (the groups of a
+    # band in one workgroup), with the same thread count
+    vb = "k_vbandg" if B == 32 and 2 <= G <= 8 else "k_vband"
     return {
         "k_hrow": [(f"k_hrow<{L}, false, false>", H * T * Gr)],
-        "k_vband": [(f"k_vband<{B}, false, false>", ((P + 63) // 64) * nb * G * 64)],
-        "k_vband_agg": [(f"k_vband<{B}, true, false>", ((W + 63) // 64) * nb * G * 64)],
+        "k_vband": [(f"{vb}<{B}, false, false>", ((P + 63) // 64) * nb * G * 64)],
+        "k_vband_agg": [(f"{vb}<{B}, true, false>", ((W + 63) // 64) * nb * G * 64)],
         "k_vresolve": [("k_vresolve", ((W + 63) // 64) * 64 * C * 2)],
         "k_stats": [("k_stats", min(H, 256) * 256)],
     }.get(stage, [])

@@ -62,13 +62,50 @@ __device__ __forceinline__ double ipow(double x, int e) {
 // STACKIN (a volume's row-direction pass): the channel values are read from a
 // stack that an earlier pass filtered, channel n at src + n * src_cstride with
 // rows of p.pitch, instead of being generated from the image.
-template <int B, bool AGG, bool BIG, bool JOINT = false, bool STACKIN = false>
+// SHARED (G >= 2 channel groups of one band in one workgroup, this wave group
+// g): the waves split the band's B + 3 rows of centred intensities and
+// exp(-x^2/2) (and the joint data) between them and exchange them through
+// `pro` in LDS, instead of each computing all of them.
+template <int B, bool AGG, bool BIG, bool JOINT = false, bool STACKIN = false, bool SHARED = false>
 __device__ __forceinline__ void vband(const GPParams &p, const IirCoef &c, const Stats &st, int col, int band,
                                       float *__restrict__ carry, float *__restrict__ S, int sp_pitch, float *sacc,
                                       int cb, int ce, const float *__restrict__ src = nullptr,
-                                      size_t src_cstride = 0) {
+                                      size_t src_cstride = 0, float *pro = nullptr, int G = 1, int g = 0) {
     const int lane = threadIdx.x & 63;
     const int a = band * B;
+    constexpr int NR = B + 3;  // rows a-1 .. a+B+1
+    if constexpr (SHARED && !STACKIN) {
+        // a column group lying wholly in the pad has nothing to share (the
+        // test is uniform over the workgroup: its waves share the columns)
+        if (col - lane < p.W) {
+            // this wave's rows g, g + G, ... (at most (NR + 1) / 2 of them for
+            // G >= 2), six loads in flight at a time
+            constexpr int PER = (NR + 1) / 2, CH = 6;
+            const int colc = col < p.W ? col : p.W - 1;
+            for (int k0 = 0; k0 < PER; k0 += CH) {
+                float f[CH], fd[JOINT ? CH : 1];
+#pragma unroll
+                for (int k = 0; k < CH; ++k) {
+                    const int r = g + (k0 + k) * G;
+                    const int row = a - 1 + (r < NR ? r : NR - 1);
+                    const int rc = row < 0 ? 0 : (row >= p.H ? p.H - 1 : row);
+                    f[k] = p.img[(size_t)rc * p.pitch + colc];
+                    if constexpr (JOINT) fd[k] = p.data[(size_t)rc * p.pitch + colc];
+                }
+#pragma unroll
+                for (int k = 0; k < CH; ++k) {
+                    const int r = g + (k0 + k) * G;
+                    if (r < NR) {
+                        const float x = centred(f[k], st, p.inv_sigma_r);
+                        pro[r * 64 + lane] = x;
+                        pro[(NR + r) * 64 + lane] = gauss_u0(x, BIG ? big_shift(x) : 0);
+                        if constexpr (JOINT) pro[(2 * NR + r) * 64 + lane] = fd[k];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
     // the stack holds every channel as rows(H) = H rounded up to a whole band
     // of rows with pitch sp_pitch, so every band stores all of its rows
     const int srows = ((p.H + B - 1) / B) * B;
@@ -91,17 +128,26 @@ __device__ __forceinline__ void vband(const GPParams &p, const IirCoef &c, const
     constexpr int NG = STACKIN ? 1 : B + 3;  // samples of the generated channels
     float xv[NG], u[NG], dv[JOINT ? B + 3 : 1];
     if constexpr (!STACKIN) {
+        if constexpr (SHARED) {
 #pragma unroll
-        for (int i = 0; i < B + 3; ++i) {
-            const int row = a - 1 + i;
-            const int rc = row < 0 ? 0 : (row >= p.H ? p.H - 1 : row);
-            xv[i] = p.img[(size_t)rc * p.pitch + col];
-            if constexpr (JOINT) dv[i] = p.data[(size_t)rc * p.pitch + col];
-        }
+            for (int i = 0; i < NR; ++i) {
+                xv[i] = pro[i * 64 + lane];
+                u[i] = pro[(NR + i) * 64 + lane];
+                if constexpr (JOINT) dv[i] = pro[(2 * NR + i) * 64 + lane];
+            }
+        } else {
 #pragma unroll
-        for (int i = 0; i < B + 3; ++i) {
-            xv[i] = centred(xv[i], st, p.inv_sigma_r);
-            u[i] = gauss_u0(xv[i], BIG ? big_shift(xv[i]) : 0);
+            for (int i = 0; i < B + 3; ++i) {
+                const int row = a - 1 + i;
+                const int rc = row < 0 ? 0 : (row >= p.H ? p.H - 1 : row);
+                xv[i] = p.img[(size_t)rc * p.pitch + col];
+                if constexpr (JOINT) dv[i] = p.data[(size_t)rc * p.pitch + col];
+            }
+#pragma unroll
+            for (int i = 0; i < B + 3; ++i) {
+                xv[i] = centred(xv[i], st, p.inv_sigma_r);
+                u[i] = gauss_u0(xv[i], BIG ? big_shift(xv[i]) : 0);
+            }
         }
         // rows outside the image (a uniform test per row: only the first and
         // the last bands have any)

@@ -72,6 +72,48 @@ __global__ __launch_bounds__(64, 3) void k_vband(GPParams p, IirCoef c, float *c
         vband<B, AGG, false, JOINT>(p, c, st, col, band, carry, S, sp, sacc, cb, ce);
 }
 
+// The same passes with all `groups` (>= 2) channel groups of a band in one
+// workgroup, one wave per group: the band's centred intensities and
+// exp(-x^2/2) are computed once for the workgroup and shared through LDS
+// (dynamic: groups * B * 64 floats of staging for the column pass, then
+// (B + 3) * 64 * (JOINT ? 3 : 2) floats).  Grid: the image's column groups per
+// band first, then the pad-only ones (column pass).
+template <int B, bool AGG, bool JOINT>
+__global__ __launch_bounds__(512, 3) void k_vbandg(GPParams p, IirCoef c, float *carry, float *S, int sp, int groups,
+                                                   int cgr, int cgp) {
+    extern __shared__ float sm[];
+    Stats st;
+    if (AGG) {
+        st = reduce_stats(p);
+        if (blockIdx.x == 0 && threadIdx.x == 0) publish_stats(p, st);
+    } else {
+        st = load_stats(p);
+    }
+    if (!st.ok) return;  // uniform over the launch
+    const int nb = (p.H + B - 1) / B;
+    int idx = blockIdx.x, cg;
+    if (idx < cgr * nb) {
+        cg = idx % cgr;
+        idx /= cgr;
+    } else {
+        idx -= cgr * nb;
+        cg = cgr + idx % cgp;
+        idx /= cgp;
+    }
+    const int band = idx;
+    const int grp = threadIdx.x >> 6;
+    const int col = cg * 64 + (threadIdx.x & 63);
+    const int cb = (p.C * grp) / groups, ce = (p.C * (grp + 1)) / groups;
+    float *sacc = sm + grp * B * 64;
+    float *pro = sm + (AGG ? 0 : groups * B * 64);
+    if (st.xmax > 12.0)
+        vband<B, AGG, true, JOINT, false, true>(p, c, st, col, band, carry, S, sp, sacc, cb, ce, nullptr, 0, pro,
+                                                 groups, grp);
+    else
+        vband<B, AGG, false, JOINT, false, true>(p, c, st, col, band, carry, S, sp, sacc, cb, ce, nullptr, 0, pro,
+                                                  groups, grp);
+}
+
 __global__ __launch_bounds__(64) void k_vresolve(GPParams p, IirCoef c, int nb, float *carry) {
     const int col = blockIdx.x * 64 + threadIdx.x;
     if (col < p.W) vresolve(p, c, nb, col, blockIdx.y, blockIdx.z, carry);
@@ -233,6 +275,30 @@ static void vband_launch(const GPParams &p, const IirCoef &c, const IirShape &sh
         BF_LAUNCH(name, (k_vband<B, AGG, false>), grid, dim3(64), 0, s, p, c, carry, S, sh.P, sh.G, cgr, cgp);
 }
 
+// Dynamic LDS of k_vbandg.
+constexpr size_t vbandg_smem_bytes(int B, bool agg, bool joint, int groups) {
+    return sizeof(float) * ((agg ? 0 : (size_t)groups * B * 64) + (size_t)(B + 3) * 64 * (joint ? 3 : 2));
+}
+
+// The grouped passes (32-row bands, 2..8 channel groups): grid = the column
+// groups of every band, `groups` waves per workgroup.
+template <bool AGG>
+static hipError_t vbandg_launch(const GPParams &p, const IirCoef &c, const IirShape &sh, float *carry, float *S, int cgr,
+                                int cgp, hipStream_t s) {
+    // more than 64 KiB of LDS for 7..8 groups in the column pass: the
+    // attribute is set once, to the largest size
+    static hipError_t attr = hipFuncSetAttribute((const void *)k_vbandg<32, AGG, false>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)vbandg_smem_bytes(32, AGG, false, 8));
+    if (attr != hipSuccess) return attr;
+    const int nb = (p.H + 31) / 32;
+    const dim3 grid((AGG ? cgr : cgr + cgp) * nb);
+    const char *name = AGG ? "k_vband_agg" : "k_vband";
+    BF_LAUNCH(name, (k_vbandg<32, AGG, false>), grid, dim3(64 * sh.G), vbandg_smem_bytes(32, AGG, false, sh.G), s, p,
+              c, carry, S, sh.P, sh.G, cgr, cgp);
+    return hipSuccess;
+}
+
 hipError_t launch_iir(const GPParams &p, const IirCoef &c, const IirShape &shape, float *carry, float *S, bool save,
                       bool joint, hipStream_t s) {
     IirShape sh = shape;
@@ -245,17 +311,28 @@ hipError_t launch_iir(const GPParams &p, const IirCoef &c, const IirShape &shape
     // where the column pass has one extra, nearly empty, column group)
     const int cgr = (p.W + 63) / 64, cgp = (sh.P + 63) / 64 - cgr;
     const dim3 ga(cgr * nb * sh.G), gv((cgr + cgp) * nb * sh.G);
-    if (sh.B == 64)
+    // bands of 32 rows split into 2..8 channel groups share each band's
+    // prologue inside one workgroup (not the joint filter: its grouped
+    // passes spill registers and measured slower)
+    const bool grouped = !joint && sh.B == 32 && sh.G >= 2 && sh.G <= 8;
+    hipError_t e = hipSuccess;
+    if (grouped)
+        e = vbandg_launch<true>(p, c, sh, carry, S, cgr, cgp, s);
+    else if (sh.B == 64)
         vband_launch<64, true>(p, c, sh, ga, carry, S, cgr, cgp, joint, s);
     else if (sh.B == 32)
         vband_launch<32, true>(p, c, sh, ga, carry, S, cgr, cgp, joint, s);
     else
         return hipErrorInvalidValue;
+    if (e != hipSuccess) return e;
     BF_LAUNCH("k_vresolve", k_vresolve, dim3((p.W + 63) / 64, p.C, 2), dim3(64), 0, s, p, c, nb, carry);
-    if (sh.B == 64)
+    if (grouped)
+        e = vbandg_launch<false>(p, c, sh, carry, S, cgr, cgp, s);
+    else if (sh.B == 64)
         vband_launch<64, false>(p, c, sh, gv, carry, S, cgr, cgp, joint, s);
     else
         vband_launch<32, false>(p, c, sh, gv, carry, S, cgr, cgp, joint, s);
+    if (e != hipSuccess) return e;
     switch (sh.L) {
         case 4: hrow_launch<4>(p, c, sh, S, save, joint, s); break;
         case 8: hrow_launch<8>(p, c, sh, S, save, joint, s); break;

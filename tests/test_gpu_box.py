@@ -183,3 +183,15 @@ def test_large_config_sampled(bf):
         ref = oracle_gp_at(img, y, x, 10.0, 20.0, 20, "box")
         assert abs(got[y, x] - ref) <= TOL, (y, x, got[y, x], ref)
     assert np.all(np.isfinite(got))
+
+
+def test_no_backward_in_box_mode(bf):
+    # the box mode is forward only: the autograd path and the backward entry
+    # point refuse it with BF_EUNSUPPORTED before any launch
+    img = to_dev(synthimg.voronoi_image(32, 40, 6, seed=104))
+    ls = torch.tensor(0.5, device="cuda", requires_grad=True)
+    lr = torch.tensor(3.0, device="cuda", requires_grad=True)
+    note("box autograd refused")
+    with pytest.raises(bf.BfError) as e:
+        bf.gp_filter(img, ls, lr, 20, spatial="box")
+    assert e.value.code == bf.BF_EUNSUPPORTED
