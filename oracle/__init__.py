@@ -193,7 +193,8 @@ def center(img, mode=CENTER_MEAN):
 
 
 def gp_alg1(img, sigma_r, N, k, center_mode=CENTER_MEAN):
-    """Algorithm 1 (GPF), literal, with spatial table k."""
+    """The Gauss-polynomial filter of Section 3 (eqs. (7)-(11) on the
+    centred image, eq. (6); Algorithm 1 summarises it) with spatial table k."""
     f = _img(img)
     out = np.empty_like(f)
     k = np.ascontiguousarray(k, np.float64)

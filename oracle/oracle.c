@@ -214,54 +214,64 @@ double or_center(const double *f, int H, int W, int mode)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Algorithm 1 (GPF), step by step in the paper's notation                   */
+/* The Gauss-polynomial filter of Section 3 (Algorithm 1 summarises it)      */
 /* ------------------------------------------------------------------------ */
 
 /* Inputs: image f, range parameter sigma_r, degree N, spatial table k[0..R].
- * The intermediate images G, F, Fbar, P, Q, H and the scalar c follow
- * Algorithm 1; Fbar = F * g_s is eq. (8) with the given table. */
+ *
+ * Section 3 states the method on an image whose intensity range is centred
+ * (the Proposition, eq. (6)): with h = f - t_c and x = h / sigma_r,
+ *   G_n = x^n,  F_n = exp(-x^2 / 2) G_n,  n = 0..N+1        (eq. (7) on h)
+ *   Fbar_n = F_n filtered with the spatial table              (eq. (8))
+ *   P = sigma_r sum_{n=0..N} G_n Fbar_{n+1} / n!              (eq. (9))
+ *   Q = sum_{n=0..N} G_n Fbar_n / n!                          (eq. (10))
+ * and the filtered image is P / Q (eq. (11)) plus the centre t_c (eq. (6)).
+ * Each Fbar_n is computed once and enters Q as its n-th term and P as its
+ * (n-1)-th term, so that only one filtered image is held at a time. */
 int or_gp_alg1(const double *f, double *out, int H, int W, double sigma_r, int N,
                const double *k, int R, int center_mode)
 {
     if (!f || !out || !k || H < 1 || W < 1 || R < 0 || !(sigma_r > 0) || N < 0)
         return OR_EINVAL;
     const size_t n = (size_t)H * W;
-    double *G = malloc(sizeof(double) * n), *F = malloc(sizeof(double) * n);
-    double *Fb = malloc(sizeof(double) * n), *P = malloc(sizeof(double) * n);
-    double *Q = malloc(sizeof(double) * n), *Hh = malloc(sizeof(double) * n);
+    double *x = malloc(sizeof(double) * n), *E = malloc(sizeof(double) * n);
+    double *G = malloc(sizeof(double) * n), *Gprev = malloc(sizeof(double) * n);
+    double *Fn = malloc(sizeof(double) * n), *Fb = malloc(sizeof(double) * n);
+    double *P = malloc(sizeof(double) * n), *Q = malloc(sizeof(double) * n);
     double *tmp = malloc(sizeof(double) * n);
-    if (!G || !F || !Fb || !P || !Q || !Hh || !tmp) {
-        free(G); free(F); free(Fb); free(P); free(Q); free(Hh); free(tmp);
+    double *inv_fact = malloc(sizeof(double) * (size_t)(N + 2));
+    if (!x || !E || !G || !Gprev || !Fn || !Fb || !P || !Q || !tmp || !inv_fact) {
+        free(x); free(E); free(G); free(Gprev); free(Fn); free(Fb); free(P); free(Q); free(tmp); free(inv_fact);
         return OR_ENOMEM;
     }
-    /* centre t_c and the centred image h = f - t_c; the initial images
-     * G = 1, F = exp(-h^2 / 2 sigma_r^2), P = Q = 0 and H = h / sigma_r */
+    inv_fact[0] = 1.0;                                     /* 1 / n! */
+    for (int m = 1; m <= N + 1; ++m)
+        inv_fact[m] = inv_fact[m - 1] / (double)m;
     const double tc = or_center(f, H, W, center_mode);
     for (size_t i = 0; i < n; ++i) {
-        const double h = f[i] - tc;
-        G[i] = 1.0;
-        F[i] = exp(-h * h / (2.0 * sigma_r * sigma_r));
+        x[i] = (f[i] - tc) / sigma_r;
+        E[i] = exp(-0.5 * x[i] * x[i]);
+        G[i] = 1.0;                                        /* G_0 */
         P[i] = 0.0;
         Q[i] = 0.0;
-        Hh[i] = h / sigma_r;
     }
-    spatial_sep(F, Fb, tmp, H, W, k, k, R);                 /* Fbar: F filtered, eq. (8) */
-    double c = 1.0;                                         /* c = 1/n!, from n = 0 */
-    for (int m = 0; m <= N; ++m) {                          /* the loop over n */
+    for (int m = 0; m <= N + 1; ++m) {
+        /* G holds G_m = x^m and Gprev holds G_{m-1} */
+        for (size_t i = 0; i < n; ++i)
+            Fn[i] = E[i] * G[i];                           /* F_m, eq. (7) */
+        spatial_sep(Fn, Fb, tmp, H, W, k, k, R);           /* Fbar_m, eq. (8) */
         for (size_t i = 0; i < n; ++i) {
-            Q[i] += c * G[i] * Fb[i];
-            F[i] = Hh[i] * F[i];
+            if (m <= N)
+                Q[i] += inv_fact[m] * G[i] * Fb[i];        /* eq. (10), term m */
+            if (m >= 1)
+                P[i] += sigma_r * inv_fact[m - 1] * Gprev[i] * Fb[i];  /* eq. (9), term m-1 */
+            Gprev[i] = G[i];
+            G[i] = G[i] * x[i];                            /* G_{m+1} */
         }
-        spatial_sep(F, Fb, tmp, H, W, k, k, R);
-        for (size_t i = 0; i < n; ++i) {
-            P[i] += c * G[i] * Fb[i];
-            G[i] = Hh[i] * G[i];
-        }
-        c = c / (double)(m + 1);
     }
-    for (size_t i = 0; i < n; ++i)                          /* sigma_r P/Q + t_c */
-        out[i] = sigma_r * (P[i] / Q[i]) + tc;
-    free(G); free(F); free(Fb); free(P); free(Q); free(Hh); free(tmp);
+    for (size_t i = 0; i < n; ++i)
+        out[i] = P[i] / Q[i] + tc;                         /* eq. (11), then eq. (6) */
+    free(x); free(E); free(G); free(Gprev); free(Fn); free(Fb); free(P); free(Q); free(tmp); free(inv_fact);
     return OR_OK;
 }
 
@@ -306,57 +316,56 @@ int or_joint_direct(const double *g, const double *f, double *out, int H, int W,
     return OR_OK;
 }
 
-/* The Gauss-polynomial approximation of the joint filter, in the steps and
- * notation of Algorithm 1 with the guide in every range term: t_c is the
- * centre of g, h = g - t_c, F = exp(-h^2 / 2 sigma_r^2), H = h / sigma_r, and
- * for n = 0..N
- *     Q += c G (F * g_s),   P += c G ((F f) * g_s),   F = H F,  G = H G,
- *     c = c / (n + 1),
- * from the factorisation g_r(g_j - g_i) = F_i F_j exp(H_i H_j) with the
- * exponential truncated as in eqs. (4)-(5); out = P / Q (the F_i cancel).
- * With g = f, (F f) = t_c F + sigma_r F H, so P = t_c Q + sigma_r P_alg1 and
- * the output is Algorithm 1's. */
+/* The Gauss-polynomial approximation of the joint filter.  With t_c the
+ * centre of the guide g, x = (g - t_c) / sigma_r, G_n = x^n and
+ * F_n = exp(-x^2 / 2) G_n (eq. (7) on the guide), the range weight of a pair
+ * factors as g_r(g_j - g_i) = F_0(i) F_0(j) exp(x_i x_j), and truncating the
+ * exponential as in eqs. (4)-(5) gives, after the F_0(i) cancel,
+ *   Q = sum_{n=0..N} G_n (F_n * g_s) / n!,   P = sum_{n=0..N} G_n ((F_n f) * g_s) / n!,
+ * and out = P / Q (eqs. (8)-(11) with the data f in the numerator's images).
+ * With g = f, F_n f = t_c F_n + sigma_r F_{n+1}, so P = t_c Q + sigma_r P_eq9
+ * and the output is that of the image filter. */
 int or_joint_gp(const double *g, const double *f, double *out, int H, int W, double sigma_r, int N,
                 const double *k, int R, int center_mode)
 {
     if (!g || !f || !out || !k || H < 1 || W < 1 || R < 0 || !(sigma_r > 0) || N < 0)
         return OR_EINVAL;
     const size_t n = (size_t)H * W;
-    double *G = malloc(sizeof(double) * n), *F = malloc(sizeof(double) * n);
+    double *x = malloc(sizeof(double) * n), *E = malloc(sizeof(double) * n);
+    double *G = malloc(sizeof(double) * n), *Fn = malloc(sizeof(double) * n);
     double *Fb = malloc(sizeof(double) * n), *P = malloc(sizeof(double) * n);
-    double *Q = malloc(sizeof(double) * n), *Hh = malloc(sizeof(double) * n);
-    double *Ff = malloc(sizeof(double) * n), *tmp = malloc(sizeof(double) * n);
-    if (!G || !F || !Fb || !P || !Q || !Hh || !Ff || !tmp) {
-        free(G); free(F); free(Fb); free(P); free(Q); free(Hh); free(Ff); free(tmp);
+    double *Q = malloc(sizeof(double) * n), *tmp = malloc(sizeof(double) * n);
+    if (!x || !E || !G || !Fn || !Fb || !P || !Q || !tmp) {
+        free(x); free(E); free(G); free(Fn); free(Fb); free(P); free(Q); free(tmp);
         return OR_ENOMEM;
     }
     const double tc = or_center(g, H, W, center_mode);
     for (size_t i = 0; i < n; ++i) {
-        const double h = g[i] - tc;
+        x[i] = (g[i] - tc) / sigma_r;
+        E[i] = exp(-0.5 * x[i] * x[i]);
         G[i] = 1.0;
-        F[i] = exp(-h * h / (2.0 * sigma_r * sigma_r));
         P[i] = 0.0;
         Q[i] = 0.0;
-        Hh[i] = h / sigma_r;
     }
-    double c = 1.0;
+    double inv_fact = 1.0;                                 /* 1 / m! */
     for (int m = 0; m <= N; ++m) {
-        spatial_sep(F, Fb, tmp, H, W, k, k, R);
+        for (size_t i = 0; i < n; ++i)
+            Fn[i] = E[i] * G[i];                           /* F_m of the guide */
+        spatial_sep(Fn, Fb, tmp, H, W, k, k, R);
         for (size_t i = 0; i < n; ++i) {
-            Q[i] += c * G[i] * Fb[i];
-            Ff[i] = F[i] * f[i];
+            Q[i] += inv_fact * G[i] * Fb[i];
+            Fn[i] = Fn[i] * f[i];                          /* F_m f */
         }
-        spatial_sep(Ff, Fb, tmp, H, W, k, k, R);
+        spatial_sep(Fn, Fb, tmp, H, W, k, k, R);
         for (size_t i = 0; i < n; ++i) {
-            P[i] += c * G[i] * Fb[i];
-            F[i] = Hh[i] * F[i];
-            G[i] = Hh[i] * G[i];
+            P[i] += inv_fact * G[i] * Fb[i];
+            G[i] = G[i] * x[i];                            /* G_{m+1} */
         }
-        c = c / (double)(m + 1);
+        inv_fact /= (double)(m + 1);
     }
     for (size_t i = 0; i < n; ++i)
         out[i] = P[i] / Q[i];
-    free(G); free(F); free(Fb); free(P); free(Q); free(Hh); free(Ff); free(tmp);
+    free(x); free(E); free(G); free(Fn); free(Fb); free(P); free(Q); free(tmp);
     return OR_OK;
 }
 
@@ -452,49 +461,51 @@ int or_volume_direct(const double *f, double *out, int T, int H, int W, const do
     return OR_OK;
 }
 
-/* Algorithm 1 over a volume: the same steps, with eq. (8) the separable
- * filtering over all three axes. */
+/* The Gauss-polynomial filter of Section 3 over a volume: eqs. (7)-(11) as
+ * in or_gp_alg1, with eq. (8) the separable filtering over all three axes and
+ * the centre taken over the whole volume. */
 int or_volume_gp(const double *f, double *out, int T, int H, int W, double sigma_r, int N, const double *kt,
                  int Rt, const double *ks, int Rs, int center_mode)
 {
     if (!f || !out || !kt || !ks || T < 1 || H < 1 || W < 1 || Rt < 0 || Rs < 0 || !(sigma_r > 0) || N < 0)
         return OR_EINVAL;
     const size_t n = (size_t)T * H * W;
-    double *G = malloc(sizeof(double) * n), *F = malloc(sizeof(double) * n);
-    double *Fb = malloc(sizeof(double) * n), *P = malloc(sizeof(double) * n);
-    double *Q = malloc(sizeof(double) * n), *Hh = malloc(sizeof(double) * n);
+    double *x = malloc(sizeof(double) * n), *E = malloc(sizeof(double) * n);
+    double *G = malloc(sizeof(double) * n), *Gprev = malloc(sizeof(double) * n);
+    double *Fn = malloc(sizeof(double) * n), *Fb = malloc(sizeof(double) * n);
+    double *P = malloc(sizeof(double) * n), *Q = malloc(sizeof(double) * n);
     double *tmp = malloc(sizeof(double) * n);
-    if (!G || !F || !Fb || !P || !Q || !Hh || !tmp) {
-        free(G); free(F); free(Fb); free(P); free(Q); free(Hh); free(tmp);
+    if (!x || !E || !G || !Gprev || !Fn || !Fb || !P || !Q || !tmp) {
+        free(x); free(E); free(G); free(Gprev); free(Fn); free(Fb); free(P); free(Q); free(tmp);
         return OR_ENOMEM;
     }
     /* the centre over the whole volume (a T H x W image) */
     const double tc = or_center(f, T * H, W, center_mode);
     for (size_t i = 0; i < n; ++i) {
-        const double h = f[i] - tc;
+        x[i] = (f[i] - tc) / sigma_r;
+        E[i] = exp(-0.5 * x[i] * x[i]);
         G[i] = 1.0;
-        F[i] = exp(-h * h / (2.0 * sigma_r * sigma_r));
         P[i] = 0.0;
         Q[i] = 0.0;
-        Hh[i] = h / sigma_r;
     }
-    spatial_sep3(F, Fb, tmp, T, H, W, kt, Rt, ks, Rs);
-    double c = 1.0;
-    for (int m = 0; m <= N; ++m) {
+    double inv_fact = 1.0;                                 /* 1 / m! */
+    for (int m = 0; m <= N + 1; ++m) {
+        for (size_t i = 0; i < n; ++i)
+            Fn[i] = E[i] * G[i];                           /* F_m, eq. (7) */
+        spatial_sep3(Fn, Fb, tmp, T, H, W, kt, Rt, ks, Rs);
         for (size_t i = 0; i < n; ++i) {
-            Q[i] += c * G[i] * Fb[i];
-            F[i] = Hh[i] * F[i];
+            if (m <= N)
+                Q[i] += inv_fact * G[i] * Fb[i];           /* eq. (10), term m */
+            if (m >= 1)
+                P[i] += sigma_r * inv_fact * (double)m * Gprev[i] * Fb[i];  /* eq. (9), term m-1: 1/(m-1)! = m/m! */
+            Gprev[i] = G[i];
+            G[i] = G[i] * x[i];
         }
-        spatial_sep3(F, Fb, tmp, T, H, W, kt, Rt, ks, Rs);
-        for (size_t i = 0; i < n; ++i) {
-            P[i] += c * G[i] * Fb[i];
-            G[i] = Hh[i] * G[i];
-        }
-        c = c / (double)(m + 1);
+        inv_fact /= (double)(m + 1);
     }
     for (size_t i = 0; i < n; ++i)
-        out[i] = sigma_r * (P[i] / Q[i]) + tc;
-    free(G); free(F); free(Fb); free(P); free(Q); free(Hh); free(tmp);
+        out[i] = P[i] / Q[i] + tc;
+    free(x); free(E); free(G); free(Gprev); free(Fn); free(Fb); free(P); free(Q); free(tmp);
     return OR_OK;
 }
 

@@ -279,6 +279,28 @@ def test_centres_agree_in_the_limit_and_differ_at_low_degree():
     assert np.max(np.abs(low[0] - ref)) < np.max(np.abs(low[1] - ref))
 
 
+@pytest.mark.parametrize("N", [2, 6, 12])
+def test_midrange_centre_matches_double_sum_about_the_midrange(N):
+    # Proposition eq. (6) with t_c the midpoint of the intensity range: the
+    # filter equals the explicit double sum with the Gauss-polynomial weights
+    # taken about (min + max) / 2.  The image is skewed (most pixels dark), so
+    # the mean and the midrange differ by far more than the tolerance and a
+    # midrange that silently fell back to the mean would fail.
+    rng = np.random.default_rng(140 + N)
+    f = rng.uniform(0, 80, size=(7, 9))
+    f[0, 0], f[6, 8] = 5.0, 250.0
+    k = oracle.gauss_table(1.3, 4)
+    mid = 0.5 * (f.min() + f.max())
+    assert abs(mid - f.mean()) > 50.0
+    assert oracle.center(f, oracle.CENTER_MIDRANGE) == mid
+    got = oracle.gp_alg1(f, 40.0, N, k, oracle.CENTER_MIDRANGE)
+    ref = oracle.brute_gp(f, 40.0, N, k, center_value=mid)
+    assert np.allclose(got, ref, rtol=0, atol=1e-9), np.max(np.abs(got - ref))
+    # at these low degrees the centre changes the result
+    other = oracle.brute_gp(f, 40.0, N, k, center_value=f.mean())
+    assert np.max(np.abs(ref - other)) > 1e-3
+
+
 # ---------------------------------------------------------------------------
 # gradients
 # ---------------------------------------------------------------------------
