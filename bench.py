@@ -59,7 +59,12 @@ def timed(fn, steps, warmup, torch):
     return s.elapsed_time(e) / steps  # ms per call
 
 
-FP32_VALU_PEAK_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x FMA (2 flops) x 2.4 GHz, unpacked
+# MI355X's published FP32 vector peak: 256 CU x 4 SIMD x 16 lanes x 2 (packed
+# FP32, two lanes' worth per instruction) x FMA (2 flops) x 2.4 GHz.  This
+# build issues no packed FP32 instructions, so the rate its kernels can reach
+# is half of it, the unpacked figure (one FMA per lane per clock).
+FP32_PEAK_TFLOPS = 157.3
+FP32_UNPACKED_PEAK_TFLOPS = 78.6
 
 
 def step_model(kernel, C, band, fir_radii, n_iir, n_calls, HW):
@@ -196,7 +201,7 @@ def main():
     gbs = bytes_step * per_launch / (avg_ms * 1e-3) / 1e9 if bytes_step else None
     tflops = flops_step * per_launch / (avg_ms * 1e-3) / 1e12 if flops_step else None
     f_hbm = gbs / HBM_PEAK_GBS if gbs else 0.0
-    f_alu = tflops / FP32_VALU_PEAK_TFLOPS if tflops else 0.0
+    f_alu = tflops / FP32_PEAK_TFLOPS if tflops else 0.0
     # measured HBM traffic of the same kernel (rocprofv3 FETCH_SIZE + WRITE_SIZE,
     # calibrated by a device copy), valid only for the sources it was taken with
     from paper_1505_00077_amd import profiling
@@ -207,9 +212,11 @@ def main():
               "algorithmic_bytes_per_launch": bytes_step * per_launch if bytes_step else None,
               "algorithmic_fp32_flops_per_launch": flops_step * per_launch if flops_step else None,
               "avg_launch_ms": avg_ms, "launches": kcount, "share_of_profiled_step": kms / (ms_step_profiled * K),
-              "hbm_frac": f_hbm, "fp32_valu_frac": f_alu}
+              "hbm_frac": f_hbm, "fp32_frac": f_alu,
+              "fp32_unpacked_peak": FP32_UNPACKED_PEAK_TFLOPS,
+              "fp32_unpacked_frac": tflops / FP32_UNPACKED_PEAK_TFLOPS if tflops else 0.0}
     if f_alu > f_hbm:
-        roofline = {"bound": "alu", "achieved": tflops, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+        roofline = {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": f_alu, **common}
     else:
         roofline = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": f_hbm, **common}
@@ -223,6 +230,15 @@ def main():
             ms = timed(lambda: bf.gp_forward(img, ss, SIGMA_R, DEGREE, out=outs[ss], ws=wss[ss]), K, Wm, torch)
             per[str(ss)] = {"plan": plan[ss], "ms": ms, "mpix_s": H * W / (ms * 1e-3) / 1e6}
             log(f"gp sigma_s={ss}: {ms:.3f} ms")
+        # the two spatial modes are different filters: their difference on the
+        # sweep image wherever both exist (the FIR tile reaches radius 24)
+        fvi = {}
+        for ss in SWEEP:
+            if bf.fir_radius(ss) <= bf.FIR_MAX_RADIUS:
+                a = bf.gp_forward(img, ss, SIGMA_R, DEGREE, spatial="fir")
+                b = bf.gp_forward(img, ss, SIGMA_R, DEGREE, spatial="iir")
+                fvi[str(ss)] = float((a - b).abs().max())
+        per["fir_vs_iir_max_abs"] = fvi
         modes["gp_forward_1024_per_sigma_s"] = per
         dper = {}
         dout = torch.empty_like(img)
@@ -267,7 +283,8 @@ def main():
         del big, bws, bout
 
 
-    # ---------------- batched: one persistent launch in a graph ----------------
+    batch_samples, batch = [], []
+    # ---------------- batched: a graph of grouped per-stage launches ----------------
     if want("batched"):
         log("generating the 64-image batch")
         batch = synthimg.batched_64()
@@ -296,6 +313,21 @@ def main():
         bstages = {k: v[1] / K for k, v in sorted(bf.profile_collect().items())}
         bf.profile_enable(False)
         worst = max(float((a - b).abs().max()) for a, b in zip(plan_b.outs, souts))
+        # sampled outputs (image corner and centre) for the oracle leg, and the
+        # degree rule's verdict per image (eqs. (4)-(5) at N 20)
+        batch_samples = []
+        for i, (b, o) in enumerate(zip(batch, plan_b.outs)):
+            Hb, Wb = b[0].shape
+            pts = [(0, 0), (Hb // 2, Wb // 2)]
+            vals = [float(o[y, x]) for y, x in pts]
+            xmax = float(np.max(np.abs(b[0].astype(np.float64) - b[0].astype(np.float64).mean()))) / b[2]
+            try:
+                rule = bf.degree_for(xmax, 1e-3)
+            except bf.BfError:
+                rule = None
+            batch_samples.append({"image": i, "shape": [Hb, Wb], "sigma_s": b[1], "sigma_r": b[2],
+                                  "plan": bf.resolve_spatial(b[1], shape=(Hb, Wb)), "xmax": xmax,
+                                  "rule_N_eps_1e-3": rule, "points": pts, "gpu": vals})
         modes["batched_64"] = {"images": len(bimgs), "megapixels": npx / 1e6, "ms_graph": ms_graph,
                                "mpix_s_graph": npx / (ms_graph * 1e-3) / 1e6, "ms_sequential": ms_seq,
                                "mpix_s_sequential": npx / (ms_seq * 1e-3) / 1e6,
@@ -455,37 +487,21 @@ def main():
                                      "gbs_read_plus_write": 2 * nbytes / (ms * 1e-3) / 1e9}
         del src, dst
 
-    # ---------------- accuracy on the small configuration ----------------
-    if want("accuracy"):
-        import oracle
-        small = synthimg.small_256()
-        f64 = small.astype(np.float64)
-        ref_direct = oracle.direct_gauss(f64, 3.0, SIGMA_R)
-        acc = {}
-        for mode in ("fir", "iir", "box"):
-            got = bf.gp_forward(torch.from_numpy(small).to(dev), 3.0, SIGMA_R, DEGREE, spatial=mode, check=True)
-            g = got.cpu().numpy().astype(np.float64)
-            k, _ = oracle.spatial_table(mode, 3.0, *small.shape)
-            ref = oracle.gp_alg1(f64, SIGMA_R, DEGREE, k)
-            # the box mode's own direct filter is eq. (1) with the box kernel
-            rd = oracle.direct(f64, SIGMA_R, k) if mode == "box" else ref_direct
-            acc[mode] = {"max_abs_err_vs_oracle": float(np.max(np.abs(g - ref))),
-                         "max_abs_err_vs_direct": float(np.max(np.abs(g - rd))),
-                         "mse_db_vs_direct": oracle.mse_db(g, rd)}
-        gd = bf.direct_forward(torch.from_numpy(small).to(dev), 3.0, SIGMA_R).cpu().numpy().astype(np.float64)
-        acc["direct"] = {"max_abs_err_vs_oracle": float(np.max(np.abs(gd - ref_direct)))}
-        modes["accuracy_256_sigma_s3"] = acc
-
-    # ---------------- CPU baseline: the FP64 oracle on a bounded sample ----------------
+    # ---------------- the FP64 oracle: CPU baseline, then accuracy ----------------
+    # The only part of the benchmark that runs the oracle.  It is timed on one
+    # step of the sweep (the CPU baseline); its outputs then give the GPU's
+    # errors on the images the headline times, and it is run on the small
+    # case and on sampled pixels of every image of the batch.
     cpu = None
     if not args.no_cpu:
         import oracle
         crop = synthimg.mid_1024().astype(np.float64)
         log("timing the FP64 oracle on one step of the sweep (the whole 1024x1024 image per sigma_s)")
+        refs = {}
         t0 = time.perf_counter()
         for ss in SWEEP:
             k, _ = oracle.spatial_table(plan[ss], ss, *crop.shape)
-            oracle.gp_alg1(crop, SIGMA_R, DEGREE, k)
+            refs[ss] = oracle.gp_alg1(crop, SIGMA_R, DEGREE, k)
         dt = time.perf_counter() - t0
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         model = None
@@ -497,6 +513,65 @@ def main():
         cpu = {"value": len(SWEEP) * crop.size / dt / 1e6, "unit": "Mpix/s", "cores": cores, "kind": "oracle",
                "sample": "one step: the 1024x1024 image at each sigma_s of the sweep, same spatial mode, "
                          "FP64 Algorithm 1 (C, OpenMP)", "seconds": dt, "cpu_model": model}
+        # the whole headline images against the oracle (the GPU outputs of the
+        # last timed step, in the mode AUTO took under the tuned table)
+        errs = {str(ss): float(np.max(np.abs(outs[ss].cpu().numpy().astype(np.float64) - refs[ss]))) for ss in SWEEP}
+        modes["max_abs_err_vs_oracle_1024"] = errs
+        if "gp_forward_1024_per_sigma_s" in modes:
+            for ss in SWEEP:
+                modes["gp_forward_1024_per_sigma_s"][str(ss)]["max_abs_err_vs_oracle"] = errs[str(ss)]
+        log("max |gpu - oracle| on the 1024^2 sweep: " + ", ".join(f"sigma_s {k} {v:.2e}" for k, v in errs.items()))
+        del refs
+        # ---------------- accuracy on the small configuration ----------------
+        if want("accuracy"):
+            small = synthimg.small_256()
+            f64 = small.astype(np.float64)
+            ref_direct = oracle.direct_gauss(f64, 3.0, SIGMA_R)
+            acc = {}
+            for mode in ("fir", "iir", "box"):
+                got = bf.gp_forward(torch.from_numpy(small).to(dev), 3.0, SIGMA_R, DEGREE, spatial=mode, check=True)
+                g = got.cpu().numpy().astype(np.float64)
+                k, _ = oracle.spatial_table(mode, 3.0, *small.shape)
+                ref = oracle.gp_alg1(f64, SIGMA_R, DEGREE, k)
+                # the box mode's own direct filter is eq. (1) with the box kernel
+                rd = oracle.direct(f64, SIGMA_R, k) if mode == "box" else ref_direct
+                acc[mode] = {"max_abs_err_vs_oracle": float(np.max(np.abs(g - ref))),
+                             "max_abs_err_vs_direct": float(np.max(np.abs(g - rd))),
+                             "mse_db_vs_direct": oracle.mse_db(g, rd)}
+            gd = bf.direct_forward(torch.from_numpy(small).to(dev), 3.0, SIGMA_R).cpu().numpy().astype(np.float64)
+            acc["direct"] = {"max_abs_err_vs_oracle": float(np.max(np.abs(gd - ref_direct)))}
+            modes["accuracy_256_sigma_s3"] = acc
+
+        # sampled pixels of every image of the batch (centre: the whole
+        # image's FP64 mean; neighbourhood: the window, or 15 sigma_s of the
+        # recursive kernel, beyond which its weights are below 1e-9 of the peak)
+        if batch_samples:
+            log("oracle on sampled pixels of the 64-image batch")
+            per_img = []
+            for rec, b in zip(batch_samples, batch):
+                f = b[0].astype(np.float64)
+                s32, r32 = float(np.float32(b[1])), float(np.float32(b[2]))
+                tc = float(f.mean())
+                reach = bf.fir_radius(s32) if rec["plan"] == "fir" else int(np.ceil(15 * s32))
+                errs_i = []
+                for (y, x), g in zip(rec["points"], rec["gpu"]):
+                    y0, y1 = max(0, y - reach), min(f.shape[0], y + reach + 1)
+                    x0, x1 = max(0, x - reach), min(f.shape[1], x + reach + 1)
+                    c = f[y0:y1, x0:x1] - tc
+                    if rec["plan"] == "fir":
+                        kt = oracle.gauss_table(s32, bf.fir_radius(s32))
+                    else:
+                        kt = oracle.deriche_table(s32, max(1, max(c.shape) - 1))
+                    ref = oracle.gp_alg1(c, r32, DEGREE, kt, oracle.CENTER_NONE)[y - y0, x - x0] + tc
+                    errs_i.append(abs(g - ref))
+                per_img.append({"image": rec["image"], "shape": rec["shape"], "plan": rec["plan"],
+                                "sigma_s": rec["sigma_s"], "sigma_r": rec["sigma_r"], "xmax": rec["xmax"],
+                                "rule_N_eps_1e-3": rec["rule_N_eps_1e-3"], "max_abs_err_vs_oracle": max(errs_i)})
+            modes["batched_64"]["per_image_sampled"] = per_img
+            modes["batched_64"]["sampled_max_abs_err_vs_oracle"] = max(p_["max_abs_err_vs_oracle"] for p_ in per_img)
+            modes["batched_64"]["images_within_1e-3"] = sum(1 for p_ in per_img if p_["max_abs_err_vs_oracle"] <= 1e-3)
+            modes["batched_64"]["images_the_rule_accepts_at_N20"] = sum(
+                1 for p_ in per_img if p_["rule_N_eps_1e-3"] is not None and p_["rule_N_eps_1e-3"] <= DEGREE)
 
     # HBM fractions of the 16-MP runs: the two-pass model (12 + 8C B/px) against
     # the peak and against the measured copy rate, and the on-chip floor

@@ -38,7 +38,15 @@ extern "C" {
 
 /* ---- flags ---------------------------------------------------------------- */
 /* Spatial filter used for the Gaussian filterings of eq. (8) (bits 0-1). */
-#define BF_SPATIAL_AUTO 0u   /* FIR below the crossover sigma_s, IIR above        */
+#define BF_SPATIAL_AUTO 0u   /* FIR while ceil(3 sigma_s) is at most the crossover
+                                radius, IIR above.  FIR and IIR are different
+                                filters (truncated sampled Gaussian against
+                                Deriche's untruncated kernel; they differ by
+                                about 0.1 on 8-bit data), so AUTO's result, not
+                                only its speed, depends on the crossover in
+                                force: the process-wide radius (default 9) or
+                                the size-dependent table a tuner installs
+                                (bf_gp_set_fir_crossover_table)            */
 #define BF_SPATIAL_FIR 1u    /* sampled Gaussian over |d| <= ceil(3 sigma_s), the
                                 window of eq. (1)                                 */
 #define BF_SPATIAL_IIR 2u    /* Deriche's 4th-order recursive Gaussian (causal +

@@ -407,10 +407,13 @@ def gp_filter(img, log_ss, log_sr, N=20, spatial="auto", center="mean"):
 # --------------------------------------------------------------------------
 
 class BatchPlan:
-    """One persistent launch over many images of uneven size, each with its
-    own sigma_s and sigma_r.  The plan owns its device workspace; `run()`
-    enqueues the launch on the current stream and `graph()` captures it into a
-    CUDA/HIP graph for replay."""
+    """Many images of uneven size, each with its own sigma_s and sigma_r,
+    filtered by one sequence of grouped per-stage launches (statistics, FIR
+    tiles by radius class, the recursive passes, row passes by workgroup
+    size), each launch covering every image of the batch that takes part in
+    that stage, with one workgroup per work item.  The plan owns its device
+    workspace; `run()` enqueues the launches on the current stream and
+    `graph()` captures them into a HIP graph for replay."""
 
     def __init__(self, imgs, sigmas_s, sigmas_r, N=20, outs=None, spatial="auto", center="mean"):
         n = len(imgs)

@@ -1,11 +1,15 @@
 """FIR / IIR crossover tuner for the AUTO spatial mode.
 
-Both spatial modes compute the same Gaussian filtering step of the method
-(eq. (8)): the FIR mode convolves with the sampled kernel over the window
-radius ceil(3 sigma_s) (its cost grows with the radius), the recursive mode
-costs the same at every sigma_s but pays five launches and two passes through
-a channel stack (a fixed cost that matters on small images).  Which is faster
-for a given radius therefore depends on the image size and the device.
+The two spatial modes are two different spatial filters for the Gaussian
+filtering step of the method (eq. (8)): the FIR mode convolves with the
+sampled Gaussian truncated at the window radius ceil(3 sigma_s) (its cost
+grows with the radius), the recursive mode with Deriche's untruncated
+recursive Gaussian (the same cost at every sigma_s, but five launches and two
+passes through a channel stack: a fixed cost that matters on small images).
+Their outputs differ slightly (about 0.1 gray levels on 8-bit data, from the
+truncation and the fit of the recursive kernel), so the table this tuner
+installs decides which of the two filters AUTO computes, not only how fast.
+Which is faster for a given radius depends on the image size and the device.
 
 `tune()` times both on this device for a ladder of image sizes, finds for
 each size the largest radius at which FIR is still faster (the FIR time rises

@@ -1,4 +1,5 @@
-"""Batched persistent launch against single-image calls and the FP64 oracle."""
+"""Batched path (a graph of grouped per-stage launches over many images)
+against single-image calls and the FP64 oracle."""
 import numpy as np
 import pytest
 import torch
@@ -59,9 +60,16 @@ def test_small_uneven_batch(bf):
     ref = singles(bf, imgs, ss, sr)
     for i in range(len(imgs)):
         assert np.array_equal(outs[i], ref[i]), (i, np.max(np.abs(outs[i] - ref[i])))
-    for i in (0, 1, 3, 4):
+    # every image over its whole extent against the oracle, in the mode the
+    # plan resolved for it (FIR and recursive images alike; the descriptor's
+    # float32 sigmas)
+    for i in range(len(imgs)):
         mode = bf.resolve_spatial(ss[i], shape=host[i].shape)
-        assert np.max(np.abs(outs[i] - oracle_gp(host[i], ss[i], sr[i], 20, mode))) <= 1e-3
+        s32, r32 = float(np.float32(ss[i])), float(np.float32(sr[i]))
+        note(f"oracle image {i} {host[i].shape} {mode}")
+        err = np.max(np.abs(outs[i] - oracle_gp(host[i], s32, r32, 20, mode)))
+        print(f"image {i} {host[i].shape} {mode}: {err:.2e}")
+        assert err <= 1e-3, (i, mode, err)
 
 
 def test_uneven_batch_64(bf):
@@ -89,6 +97,16 @@ def test_uneven_batch_64(bf):
         for (y, x) in [(0, 0), (H // 2, W // 3)]:
             ref1 = oracle_gp_at(host[i], y, x, ss[i], sr[i], 20, mode)
             assert abs(outs[i][y, x] - ref1) <= 1e-3, (i, y, x)
+    # four recursive-mode images over their whole extent (sigma_s 7.2 to 15,
+    # sigma_r 25 to 46, tall, wide and near-square)
+    for i in (58, 34, 15, 47):
+        mode = bf.resolve_spatial(ss[i], shape=host[i].shape)
+        assert mode == "iir"
+        s32, r32 = float(np.float32(ss[i])), float(np.float32(sr[i]))
+        note(f"oracle image {i} {host[i].shape}")
+        err = np.max(np.abs(outs[i] - oracle_gp(host[i], s32, r32, 20, mode)))
+        print(f"image {i} {host[i].shape}: {err:.2e}")
+        assert err <= 1e-3, (i, err)
 
 
 def test_graph_replays_match_eager(bf):

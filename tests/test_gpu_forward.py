@@ -8,7 +8,7 @@ import torch
 
 import oracle
 import synthimg
-from gpu_util import note, oracle_gp, oracle_gp_at, to_dev, to_np
+from gpu_util import note, oracle_gp, oracle_gp_at, oracle_lines, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-3
@@ -56,6 +56,22 @@ def test_fir_radius_range(bf, ss):
     img = synthimg.voronoi_image(90, 150, 30, seed=77)
     got = run(bf, img, ss, 25.0, 20, "fir")
     assert np.max(np.abs(got - oracle_gp(img, ss, 25.0, 20, "fir"))) <= TOL
+
+
+@pytest.mark.parametrize("ss", [4.3, 4.5, 5.0, 5.33, 5.34])
+def test_fir_radii_13_to_17(bf, ss):
+    # radii 13..16 run the register-column tile (the widest of them, 15 and
+    # 16, are what the tuned crossover sends sigma_s 5 to at 1 MP); radius 17
+    # is the first of the region tile, with its 32-row tiles.  Two ragged
+    # shapes: several tiles in each direction with a partial last tile.
+    R = bf.fir_radius(ss)
+    assert R == {4.3: 13, 4.5: 14, 5.0: 15, 5.33: 16, 5.34: 17}[ss]
+    for shape, seed in (((90, 150), 77), ((257, 301), 78)):
+        img = synthimg.voronoi_image(*shape, 40, seed=seed)
+        got = run(bf, img, ss, 25.0, 20, "fir")
+        err = np.max(np.abs(got - oracle_gp(img, ss, 25.0, 20, "fir")))
+        print(f"R {R} {shape}: {err:.2e}")
+        assert err <= TOL
 
 
 @pytest.mark.parametrize("ss", [0.8, 5.0, 12.0, 20.0])
@@ -243,6 +259,39 @@ def test_direct_wide_window_sampled(bf):
         assert abs(got[y, x] - ref) <= TOL
 
 
+@pytest.fixture(scope="module")
+def tuned_table(bf):
+    # the crossover table the benchmark installs (measured on this device,
+    # cached), restored to the previous state afterwards
+    from paper_1505_00077_amd import autotune
+    before = bf.get_fir_crossover_table()
+    note("tuning the FIR/IIR crossover")
+    table = autotune.ensure(20)
+    yield table
+    bf.set_fir_crossover_table(before)
+
+
+@pytest.mark.parametrize("ss", [2.0, 5.0, 10.0, 20.0])
+def test_mid_config_full_image(bf, tuned_table, ss):
+    # the whole 1024^2 sweep image against the oracle, in the mode AUTO takes
+    # under the tuned crossover table (what the benchmark times) and in every
+    # other mode the radius allows (the FIR tile up to radius 24, IIR always)
+    img = synthimg.mid_1024()
+    auto = bf.resolve_spatial(ss, shape=img.shape)
+    modes = {auto, "iir"} | ({"fir"} if bf.fir_radius(ss) <= bf.FIR_MAX_RADIUS else set())
+    outs = {}
+    for mode in sorted(modes):
+        got = run(bf, img, ss, 30.0, 20, mode)
+        outs[mode] = got
+        ref = oracle_gp(img, ss, 30.0, 20, mode)
+        err = np.max(np.abs(got - ref))
+        print(f"sigma_s {ss} {mode}{' (auto)' if mode == auto else ''}: max |gpu - oracle| {err:.2e}")
+        assert err <= TOL, (mode, err)
+    # AUTO returns the output of the mode it resolves to, bit for bit
+    a = run(bf, img, ss, 30.0, 20, "auto")
+    assert np.array_equal(a, outs[auto])
+
+
 def test_mid_config_sweep_sampled(bf):
     img = synthimg.mid_1024()
     rng = np.random.default_rng(5)
@@ -263,3 +312,34 @@ def test_large_config_sampled(bf):
         ref = oracle_gp_at(img, y, x, 10.0, 20.0, 20, mode)
         assert abs(got[y, x] - ref) <= TOL, (y, x, got[y, x], ref)
     assert np.all(np.isfinite(got))
+
+
+def test_large_config_full_rows_and_columns(bf):
+    # the 16-MP image in the recursive mode (AUTO's choice at sigma_s 10 with
+    # any crossover table): whole rows at the image edges, at a 32-row band
+    # boundary (31 | 32) and in the middle, and the first and last columns
+    img = synthimg.large_4096()
+    assert bf.resolve_spatial(10.0, shape=img.shape) == "iir"
+    got = run(bf, img, 10.0, 20.0, 20, "iir")
+    rows, cols = (0, 31, 32, 2047, 4095), (0, 4095)
+    note("oracle on the row and column bands")
+    ref_r, ref_c = oracle_lines(img, 10.0, 20.0, 20, "iir", rows=rows, cols=cols)
+    for y in rows:
+        err = np.max(np.abs(got[y] - ref_r[y]))
+        print(f"row {y}: {err:.2e}")
+        assert err <= TOL, (y, err)
+    for x in cols:
+        err = np.max(np.abs(got[:, x] - ref_c[x]))
+        print(f"column {x}: {err:.2e}")
+        assert err <= TOL, (x, err)
+
+
+@pytest.mark.parametrize("W", [4097, 6000, 8192])
+def test_iir_wide_rows(bf, W):
+    # rows past 4096 samples run the row pass with 512 threads (8 waves), so
+    # the carries cross eight waves of the workgroup
+    img = synthimg.voronoi_image(3, W, 60, seed=W)
+    got = run(bf, img, 7.0, 30.0, 20, "iir")
+    err = np.max(np.abs(got - oracle_gp(img, 7.0, 30.0, 20, "iir")))
+    print(f"W {W}: {err:.2e}")
+    assert err <= TOL
