@@ -259,7 +259,7 @@ def test_direct_wide_window_sampled(bf):
         assert abs(got[y, x] - ref) <= TOL
 
 
-@pytest.fixture(scope="module")
+@pytest.fixture
 def tuned_table(bf):
     # the crossover table the benchmark installs (measured on this device,
     # cached), restored to the previous state afterwards
@@ -297,7 +297,9 @@ def test_mid_config_sweep_sampled(bf):
     rng = np.random.default_rng(5)
     pts = [(0, 0), (1023, 1023), (0, 1023), (512, 3)] + [tuple(rng.integers(0, 1024, 2)) for _ in range(4)]
     for ss in (2.0, 5.0, 10.0, 20.0):
-        mode = bf.resolve_spatial(ss)
+        # the mode AUTO takes for this image size (a size-dependent crossover
+        # table, when installed, takes precedence over the process-wide radius)
+        mode = bf.resolve_spatial(ss, shape=img.shape)
         got = run(bf, img, ss, 30.0, 20, "auto")
         for (y, x) in pts:
             ref = oracle_gp_at(img, int(y), int(x), ss, 30.0, 20, mode)
@@ -307,7 +309,7 @@ def test_mid_config_sweep_sampled(bf):
 def test_large_config_sampled(bf):
     img = synthimg.large_4096()
     got = run(bf, img, 10.0, 20.0, 20, "auto")
-    mode = bf.resolve_spatial(10.0)
+    mode = bf.resolve_spatial(10.0, shape=img.shape)
     for (y, x) in [(0, 0), (4095, 4095), (2047, 3000), (100, 4000)]:
         ref = oracle_gp_at(img, y, x, 10.0, 20.0, 20, mode)
         assert abs(got[y, x] - ref) <= TOL, (y, x, got[y, x], ref)
