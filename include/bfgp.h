@@ -110,6 +110,28 @@ int bf_gp_forward(const float *img, float *out, int H, int W, int pitch,
                   double sigma_s, double sigma_r, int N, unsigned flags,
                   void *saved, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- GP forward without allocation --------------------------------------------
+ * For callers that cannot allocate device memory at call time (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same computation and kernels as bf_gp_forward, with the workspace taken from
+ * a static device array of BF_NOALLOC_SCRATCH_BYTES bytes inside the library
+ * instead of a caller buffer.  Every GPU the library runs this on holds its own
+ * copy of that array until the process ends.  The call allocates nothing (no
+ * hipMalloc, no library routine that allocates); the caller still provides
+ * img, out and, when wanted, saved.  Arguments as for bf_gp_forward.
+ *  - Returns BF_ENOMEM when bf_gp_workspace_bytes(H, W, N, sigma_s, flags)
+ *    exceeds BF_NOALLOC_SCRATCH_BYTES (at N 20: the FIR mode at any image
+ *    size, the IIR mode up to about 1.2 MP).
+ *  - Calls on one GPU share its array: calls that overlap on one GPU (on
+ *    streams with no ordering between them) race and give undefined results.
+ *    Calls ordered on one stream are safe; each rewrites every word it reads.
+ *  - The device status word (BF_ERANGE) lives in that array and is not
+ *    readable: out-of-range intensities show as NaN outputs. */
+#define BF_NOALLOC_SCRATCH_BYTES (128u << 20)
+int bf_gp_forward_noalloc(const float *img, float *out, int H, int W, int pitch,
+                          double sigma_s, double sigma_r, int N, unsigned flags,
+                          void *saved, void *stream);
+
 /* ---- joint (cross) GP forward ------------------------------------------------
  * The variant the Conclusion names as a direct extension: the range kernel is
  * evaluated on a guide image g and the weighted average is taken of a data

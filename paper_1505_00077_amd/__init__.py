@@ -48,6 +48,8 @@ bf_version = _sig("bf_version", _i)
 bf_last_error = _sig("bf_last_error", ctypes.c_char_p)
 bf_gp_workspace_bytes = _sig("bf_gp_workspace_bytes", _sz, _i, _i, _i, _d, _u)
 bf_gp_forward = _sig("bf_gp_forward", _i, _vp, _vp, _i, _i, _i, _d, _d, _i, _u, _vp, _vp, _sz, _vp)
+bf_gp_forward_noalloc = _sig("bf_gp_forward_noalloc", _i, _vp, _vp, _i, _i, _i, _d, _d, _i, _u, _vp, _vp)
+NOALLOC_SCRATCH_BYTES = 128 << 20
 bf_gp_joint_workspace_bytes = _sig("bf_gp_joint_workspace_bytes", _sz, _i, _i, _i, _d, _u)
 bf_gp_joint_forward = _sig("bf_gp_joint_forward", _i, _vp, _vp, _vp, _i, _i, _i, _d, _d, _i, _u, _vp, _sz, _vp)
 bf_gp_volume_workspace_bytes = _sig("bf_gp_volume_workspace_bytes", _sz, _i, _i, _i, _i, _d, _d, _u)
@@ -179,6 +181,27 @@ def gp_forward(img, sigma_s, sigma_r, N=20, spatial="auto", center="mean", out=N
         st = status(ws, img.device)
         if st != BF_OK:
             raise BfError(st, "bf_gp_forward (device status)")
+    return out
+
+
+def gp_forward_noalloc(img, sigma_s, sigma_r, N=20, spatial="auto", center="mean", out=None, saved=None):
+    """GP forward like ``gp_forward``, with the workspace in the library's
+    static device array (bf_gp_forward_noalloc): no workspace is allocated.
+    ``out`` (and ``saved``) must be given by callers that cannot allocate."""
+    H, W, pitch = _image(img)
+    if out is None:
+        out = torch.empty_like(img)
+    else:
+        oh, ow, opitch = _image(out, "out")
+        if (oh, ow, opitch) != (H, W, pitch):
+            raise ValueError("out must have the shape and row stride of img")
+    sp = None
+    if saved is not None:
+        if saved.numel() * saved.element_size() < 16 * H * W:
+            raise ValueError("saved buffer too small")
+        sp = saved.data_ptr()
+    _check(bf_gp_forward_noalloc(img.data_ptr(), out.data_ptr(), H, W, pitch, float(sigma_s), float(sigma_r),
+                                 int(N), _flags(spatial, center), sp, _stream(img.device)), "bf_gp_forward_noalloc")
     return out
 
 

@@ -454,6 +454,21 @@ GPParams gp_params_for(const float *img, float *out, int H, int W, int pitch, do
     p.stats = stats;
     return p;
 }
+int gp_forward_check(const float *img, const float *out, int H, int W, int pitch, double sigma_s, double sigma_r,
+                     int N, unsigned flags, const void *saved, size_t *ws_need) {
+    int rc;
+    if ((rc = check_image(img, out, H, W, pitch))) return rc;
+    if ((rc = check_params(sigma_s, sigma_r, N))) return rc;
+    if (flags & ~(BF_SPATIAL_MASK | BF_CENTER_MASK)) return fail(BF_EINVAL, "unknown flag bits 0x%x", flags);
+    if ((flags & BF_CENTER_MASK) == 12u) return fail(BF_EINVAL, "invalid flag combination");
+    const unsigned spatial = resolve_spatial((long long)H * W, sigma_s, flags);
+    if ((rc = check_spatial(spatial, sigma_s, W))) return rc;
+    if (spatial == BF_SPATIAL_BOX && saved)
+        return fail(BF_EUNSUPPORTED, "the box mode has no backward pass (pass saved = NULL)");
+    if ((const void *)img == (const void *)out) return fail(BF_EINVAL, "img and out must not alias");
+    *ws_need = gp_layout(H, W, N, spatial).total;
+    return BF_OK;
+}
 IirCoef iir_coef_for(double sigma_s, int B, int L) { return make_iir(sigma_s, B, L); }
 FirTaps fir_taps_for(double sigma_s, int R) { return make_taps(sigma_s, R); }
 int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
@@ -538,16 +553,10 @@ size_t bf_gp_workspace_bytes(int H, int W, int N, double sigma_s, unsigned flags
 int bf_gp_forward(const float *img, float *out, int H, int W, int pitch, double sigma_s, double sigma_r, int N,
                   unsigned flags, void *saved, void *ws, size_t ws_bytes, void *stream) {
     int rc;
-    if ((rc = check_image(img, out, H, W, pitch))) return rc;
-    if ((rc = check_params(sigma_s, sigma_r, N))) return rc;
+    size_t need = 0;
+    if ((rc = gp_forward_check(img, out, H, W, pitch, sigma_s, sigma_r, N, flags, saved, &need))) return rc;
     if (!ws) return fail(BF_EINVAL, "null workspace");
-    if (flags & ~(BF_SPATIAL_MASK | BF_CENTER_MASK)) return fail(BF_EINVAL, "unknown flag bits 0x%x", flags);
-    if ((flags & BF_CENTER_MASK) == 12u) return fail(BF_EINVAL, "invalid flag combination");
     const unsigned spatial = resolve_spatial((long long)H * W, sigma_s, flags);
-    if ((rc = check_spatial(spatial, sigma_s, W))) return rc;
-    if (spatial == BF_SPATIAL_BOX && saved)
-        return fail(BF_EUNSUPPORTED, "the box mode has no backward pass (pass saved = NULL)");
-    if ((const void *)img == (const void *)out) return fail(BF_EINVAL, "img and out must not alias");
     const Layout L = gp_layout(H, W, N, spatial);
     if (ws_bytes < L.total) return fail(BF_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
     hipStream_t s = (hipStream_t)stream;

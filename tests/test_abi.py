@@ -338,3 +338,32 @@ def test_source_fingerprint_ignores_comments_and_layout():
     assert profiling._code_only(a) != profiling._code_only(a.replace("x + 1", "x + 2"))
     assert "// b /* c */" in profiling._code_only(a)
     assert len(profiling.source_fingerprint()) == 16
+
+
+def test_noalloc_forward_checks_on_the_host():
+    """bf_gp_forward_noalloc runs bf_gp_forward's argument checks, then refuses
+    a workspace larger than its static scratch, both before any HIP call."""
+    def na(img=FAKE, out=FAKE + 4096, H=8, W=8, pitch=8, ss=2.0, sr=30.0, N=20, flags=0, saved=None):
+        return bf.bf_gp_forward_noalloc(img, out, H, W, pitch, ss, sr, N, flags, saved, None)
+    assert na(img=None) == bf.BF_EINVAL
+    assert na(out=FAKE) == bf.BF_EINVAL  # aliasing
+    assert na(pitch=4) == bf.BF_EINVAL
+    assert na(N=65) == bf.BF_EINVAL
+    assert na(ss=0.0) == bf.BF_EINVAL
+    assert na(flags=1 << 5) == bf.BF_EINVAL
+    assert na(flags=bf.SPATIAL["box"], saved=FAKE + 12288) == bf.BF_EUNSUPPORTED
+    # the IIR mode on an image whose workspace exceeds the static array
+    H = W = 2048
+    need = bf.workspace_bytes(H, W, 20, 10.0, "iir")
+    assert need > bf.NOALLOC_SCRATCH_BYTES
+    assert na(H=H, W=W, pitch=W, ss=10.0, flags=bf.SPATIAL["iir"]) == bf.BF_ENOMEM
+    assert b"static scratch" in bf.bf_last_error()
+    # the headline image fits (IIR at N 20), as does any FIR image
+    assert bf.workspace_bytes(1024, 1024, 20, 10.0, "iir") <= bf.NOALLOC_SCRATCH_BYTES
+    assert bf.workspace_bytes(8192, 8192, 20, 2.0, "fir") <= bf.NOALLOC_SCRATCH_BYTES
+
+
+def test_noalloc_scratch_size_matches_the_header():
+    text = open(HEADER).read()
+    m = re.search(r"#define BF_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == bf.NOALLOC_SCRATCH_BYTES
