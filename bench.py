@@ -100,7 +100,7 @@ def launch_ids(stage, bf, H, W, C, fir_radii):
     # band in one workgroup), with the same thread count
     vb = "k_vbandg" if B == 32 and 2 <= G <= 8 else "k_vband"
     return {
-        "k_hrow": [(f"k_hrow<{L}, false, false>", H * T * Gr)],
+        "k_hrow": [(f"k_hrow2<{L}>", H * T * Gr)],
         "k_vband": [(f"{vb}<{B}, false, false>", ((P + 63) // 64) * nb * G * 64)],
         "k_vband_agg": [(f"{vb}<{B}, true, false>", ((W + 63) // 64) * nb * G * 64)],
         "k_vresolve": [("k_vresolve", ((W + 63) // 64) * 64 * C * 2)],

@@ -13,6 +13,7 @@
 #include "launch.hpp"
 #include "fir.hpp"
 #include "iir.hpp"
+#include "hrow.hpp"
 #include "direct.hpp"
 #include "box.hpp"
 #include "bwd.hpp"
@@ -298,6 +299,35 @@ IirCoef make_iir(double sigma_s, int B, int L) {
     return c;
 }
 
+// Coefficients of the row pass (hrow2) for chunks of L samples: the section
+// coefficients of make_iir and Phi^(L 2^j), j = 0..9.
+RowCoef make_row_coef(double sigma_s, int L) {
+    const IirCoef ic = make_iir(sigma_s, 32, L);
+    RowCoef c;
+    memset(&c, 0, sizeof c);
+    for (int s = 0; s < 2; ++s) {
+        c.n0[s] = ic.n0[s];
+        c.n1[s] = ic.n1[s];
+        c.m1[s] = ic.m1[s];
+        c.m2[s] = ic.m2[s];
+        c.d1[s] = ic.d1[s];
+        c.d2[s] = ic.d2[s];
+        const double Phi[4] = {-(double)ic.d1[s], -(double)ic.d2[s], 1.0, 0.0};
+        for (int j = 0; j < 10; ++j) {
+            double M[4];
+            mat2_pow(Phi, (long)L << j, M);
+            for (int q = 0; q < 4; ++q) c.pw[s][j][q] = (float)M[q];
+        }
+        for (int i = 0; i < kRowMaxL; ++i) {
+            double M[4];
+            mat2_pow(Phi, i + 1, M);
+            c.hom[i][2 * s] = (float)M[0];
+            c.hom[i][2 * s + 1] = (float)M[1];
+        }
+    }
+    return c;
+}
+
 // The same recursion differentiated in log sigma_s (theta = w / s and
 // r = e^{-l / s} give theta' = -theta, r' = r l / s), and the band transfer
 // blocks of the tangent system [[Phi, 0], [Phi', Phi]] over the band lengths of
@@ -413,12 +443,12 @@ IirShape iir_shape(int H, int W, int C, bool batch) {
     if (G > C) G = C;
     sh.G = G;
     // row pass: the fewest waves that hold the row at 16 samples per thread,
-    // then the shortest chunk (4, 8, 12 or 16 samples) that still covers it
+    // then the shortest chunk (a multiple of 4 samples) that still covers it
     // (fewer idle lanes), and channel groups until the rows give enough waves
     // (each group adds an LDS hand-over, so no more than needed)
-    sh.T = (((W + 15) / 16 + 63) / 64) * 64;
-    sh.L = 16;
-    for (int l = 4; l < 16; l += 4)
+    sh.T = (int)(((W + kRowMaxL * 64 - 1) / (kRowMaxL * 64)) * 64);
+    sh.L = kRowMaxL;
+    for (int l = 4; l < kRowMaxL; l += 4)
         if (sh.T * l >= W) {
             sh.L = l;
             break;
@@ -433,11 +463,34 @@ IirShape iir_shape(int H, int W, int C, bool batch) {
     if (Gr > 512 / sh.T) Gr = 512 / sh.T;
     if (Gr > C) Gr = C;
     if (Gr < 1) Gr = 1;
-    while (Gr > 1 && hrow_smem_bytes(sh.T, Gr, sh.L) > 65536) --Gr;
+    while (Gr > 1 && hrow2_smem_bytes(sh.T, Gr, sh.L) > 65536) --Gr;
     sh.Gr = Gr;
-    // stack pitch: past the last chunk's right halo (two samples), rounded up
-    // to a 128-byte line so that every stack row starts on a line
-    sh.P = ((sh.T * sh.L + 2 + 31) / 32) * 32;
+    // the row pass that stores the saved terms, the joint filter's and the
+    // batched path's: at most 16 samples per thread
+    sh.To = (((W + 15) / 16 + 63) / 64) * 64;
+    sh.Lo = 16;
+    for (int l = 4; l < 16; l += 4)
+        if (sh.To * l >= W) {
+            sh.Lo = l;
+            break;
+        }
+    int Gro = g_row_groups.load();
+    if (Gro < 1 && batch) Gro = 1;
+    if (Gro < 1) {
+        const long waves = (long)H * (sh.To / 64);
+        Gro = (int)((kTargetWaves + waves - 1) / waves);
+        if (Gro > 4) Gro = 4;
+    }
+    if (sh.To <= 512 && Gro > 512 / sh.To) Gro = 512 / sh.To;
+    if (Gro > C) Gro = C;
+    if (Gro < 1) Gro = 1;
+    while (Gro > 1 && hrow_smem_bytes(sh.To, Gro, sh.Lo) > 65536) --Gro;
+    sh.Gro = Gro;
+    // stack pitch: past the last chunk's right halo (two samples) of either
+    // row pass, rounded up to a 128-byte line so that every stack row starts
+    // on a line
+    const int span = sh.T * sh.L > sh.To * sh.Lo ? sh.T * sh.L : sh.To * sh.Lo;
+    sh.P = ((span + 2 + 31) / 32) * 32;
     sh.Hs = ((H + B - 1) / B) * B;
     return sh;
 }
@@ -470,6 +523,7 @@ int gp_forward_check(const float *img, const float *out, int H, int W, int pitch
     return BF_OK;
 }
 IirCoef iir_coef_for(double sigma_s, int B, int L) { return make_iir(sigma_s, B, L); }
+RowCoef row_coef_for(double sigma_s, int L) { return make_row_coef(sigma_s, L); }
 FirTaps fir_taps_for(double sigma_s, int R) { return make_taps(sigma_s, R); }
 int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
 }  // namespace bfgp
@@ -574,7 +628,8 @@ int bf_gp_forward(const float *img, float *out, int H, int W, int pitch, double 
         if (e != hipSuccess) return hip_fail(e, "box launch");
     } else {
         const IirShape sh = iir_shape(H, W, N + 2);
-        e = launch_iir(p, make_iir(sigma_s, sh.B, sh.L), sh, (float *)(w + L.carry), (float *)(w + L.stack),
+        e = launch_iir(p, make_iir(sigma_s, sh.B, sh.Lo), make_row_coef(sigma_s, sh.L), sh, (float *)(w + L.carry),
+                       (float *)(w + L.stack),
                        saved != nullptr, false, s);
         if (e != hipSuccess) return hip_fail(e, "IIR launch");
     }
@@ -614,7 +669,8 @@ int bf_gp_joint_forward(const float *guide, const float *data, float *out, int H
     hipError_t e = launch_stats(p, false, s);
     if (e != hipSuccess) return hip_fail(e, "statistics launch");
     const IirShape sh = iir_shape(H, W, C);
-    e = launch_iir(p, make_iir(sigma_s, sh.B, sh.L), sh, (float *)(w + L.carry), (float *)(w + L.stack), false, true,
+    e = launch_iir(p, make_iir(sigma_s, sh.B, sh.Lo), make_row_coef(sigma_s, sh.L), sh, (float *)(w + L.carry),
+                   (float *)(w + L.stack), false, true,
                    s);
     if (e != hipSuccess) return hip_fail(e, "IIR launch");
     return BF_OK;
@@ -704,7 +760,8 @@ int bf_gp_volume_forward(const float *vol, float *out, int T, int H, int W, doub
     vb.carry_y = (float *)(w + L.carry_y);
     vb.S2 = (float *)(w + L.s2);
     vb.Hs = L.Hs;
-    hipError_t e = launch_volume(pz, ps, make_iir(sigma_t, 32, L.shz.L), make_iir(sigma_s, 32, L.shs.L), L.shz,
+    hipError_t e = launch_volume(pz, ps, make_iir(sigma_t, 32, L.shz.Lo), make_iir(sigma_s, 32, L.shs.Lo),
+                                 make_row_coef(sigma_s, L.shs.L), L.shz,
                                  L.shs, T, vb, s);
     if (e != hipSuccess) return hip_fail(e, "volume launch");
     return BF_OK;

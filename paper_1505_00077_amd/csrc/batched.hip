@@ -22,6 +22,7 @@
 #include "launch.hpp"
 #include "fir.hpp"
 #include "iir.hpp"
+#include "hrow.hpp"
 
 namespace bfgp {
 
@@ -40,6 +41,7 @@ constexpr int kBatchMaxW = 8192;
 struct BatchImage {
     GPParams p;
     IirCoef c;
+    RowCoef rc;
     FirTaps taps;
     int iir;       // 0 FIR, 1 IIR
     int R;         // FIR radius
@@ -148,14 +150,12 @@ __global__ __launch_bounds__(512) void k_brow(const BatchImage *imgs, const Batc
         for (int x = threadIdx.x; x < B.p.W; x += blockDim.x) B.p.out[(size_t)w.idx * B.p.pitch + x] = __builtin_nanf("");
         return;
     }
-    if (B.L == 4)
-        hrow<4>(B.p, B.c, st, w.idx, B.S, B.Sr, B.Sp, sm, B.T, B.Gr);
-    else if (B.L == 8)
-        hrow<8>(B.p, B.c, st, w.idx, B.S, B.Sr, B.Sp, sm, B.T, B.Gr);
-    else if (B.L == 12)
-        hrow<12>(B.p, B.c, st, w.idx, B.S, B.Sr, B.Sp, sm, B.T, B.Gr);
-    else
-        hrow<16>(B.p, B.c, st, w.idx, B.S, B.Sr, B.Sp, sm, B.T, B.Gr);
+    switch (B.L) {
+        case 4: hrow2<4>(B.p, B.rc, st, w.idx, B.S, B.Sr, B.Sp, sm, B.T, B.Gr); break;
+        case 8: hrow2<8>(B.p, B.rc, st, w.idx, B.S, B.Sr, B.Sp, sm, B.T, B.Gr); break;
+        case 12: hrow2<12>(B.p, B.rc, st, w.idx, B.S, B.Sr, B.Sp, sm, B.T, B.Gr); break;
+        default: hrow2<16>(B.p, B.rc, st, w.idx, B.S, B.Sr, B.Sp, sm, B.T, B.Gr); break;
+    }
 }
 
 // ---- host side -------------------------------------------------------------
@@ -196,6 +196,7 @@ namespace bfgp {
 GPParams gp_params_for(const float *img, float *out, int H, int W, int pitch, double sigma_r, int N, unsigned flags,
                        const Partial *parts, int nparts, int *status, Stats *stats);
 IirCoef iir_coef_for(double sigma_s, int B, int L);
+RowCoef row_coef_for(double sigma_s, int L);
 FirTaps fir_taps_for(double sigma_s, int R);
 int set_error(int code, const char *msg);
 }  // namespace bfgp
@@ -276,7 +277,7 @@ int bf_gp_plan_batched(const bf_gp_item *items, int count, unsigned flags, void 
             const int ncg = (sh.P + 63) / 64;
             const int G = sh.G;
             const int cls = sh.T * sh.Gr / 64 - 1;  // T * Gr is a multiple of 64, at most 512
-            row_smem[cls] = std::max(row_smem[cls], hrow_smem_bytes(sh.T, sh.Gr, sh.L));
+            row_smem[cls] = std::max(row_smem[cls], hrow2_smem_bytes(sh.T, sh.Gr, sh.L));
             for (int t = 0; t < nb * ncg * G; ++t) per[kStAgg].push_back({i, t});
             const int ng = (it.W + kBlock - 1) / kBlock;
             for (int t = 0; t < (int)C * ng * 2; ++t) per[kStResolve].push_back({i, t});
@@ -330,7 +331,8 @@ int bf_gp_plan_upload(void *plan, void *ws, size_t ws_bytes, void *stream) {
         B.Sp = sh.P;
         B.Sr = sh.Hs;
         if (B.iir) {
-            B.c = iir_coef_for(it.sigma_s, sh.B, sh.L);
+            B.c = iir_coef_for(it.sigma_s, sh.B, sh.Lo);
+            B.rc = row_coef_for(it.sigma_s, sh.L);
             B.carry = (float *)(w + P->off_carry[i]);
             B.S = (float *)(w + P->off_S[i]);
         } else {

@@ -1,0 +1,422 @@
+// Row pass of the recursive (IIR) spatial filter fused with the FP64
+// recombination (eqs. (8)-(11)): one workgroup owns one image row and filters
+// every channel of the column-filtered stack along it.
+//
+// Thread t of a channel group owns the chunk of L samples [t L, t L + L).  Per
+// channel:
+//   1. the chunk runs causally and anticausally from rest (with its true halo
+//      inputs), giving local outputs and the chunk's end states;
+//   2. the chunk states are combined in order in three levels: a Kogge-Stone
+//      scan inside each row of 16 lanes (DPP shifts, distances 1, 2, 4, 8
+//      chunks), a scan over the wave's four row totals (gathered into four
+//      lanes by cross-lane permutes), and, when a row spans several waves, a
+//      scan over the wave totals that the waves leave in LDS (one barrier per
+//      channel);
+//   3. each chunk adds the homogeneous response of its true incoming states.
+// The states are those of Deriche's second-order sections (two per
+// direction), y_n = n0 x_n + n1 x_{n-1} - d1 y_{n-1} - d2 y_{n-2} and its
+// anticausal mirror; a state (y_{n-1}, y_{n-2}) moves over m samples without
+// input by Phi^m, Phi = [[-d1, -d2], [1, 0]].
+//
+// Recombination.  With a_k = Ubar_k / sqrt(k!) (the filtered channel k, in
+// double) and P(tau) = sum_{k=0}^{N+1} a_k tau^k, the two sums of eq. (11)
+// times exp(tau^2/2) are
+//     D = sum_{k<=N} a_k tau^k,   M = sum_{k=1}^{N+1} k a_k tau^{k-1} = P'(tau),
+// (M is the derivative of the channel polynomial: sqrt(n+1) u_n(tau) /
+// exp(-tau^2/2) = (n+1) tau^n / sqrt((n+1)!)).  Channels are visited from the
+// top down and both are evaluated by Horner in tau with the same multiplier:
+//     b <- b tau + a_k            (D, channels k <= N),
+//     c <- c tau + b_{previous}   (D', the derivative scheme),
+// with c seeded by (N+1) a_{N+1} at the top channel, which after the N
+// remaining multiplications by tau is the N+1 term of M.  A channel group
+// that starts at channel cb > 0 evaluates its part relative to tau^cb; the
+// groups' parts are added by group 0 in order:
+//     D = sum_g tau^cb_g b_g,  M = sum_g (cb_g tau^(cb_g - 1) b_g + tau^cb_g c_g),
+// except for a group that holds channel N+1 alone (cb = N+1), whose c is the
+// unmultiplied seed: it adds tau^N c to M and nothing to D.
+#pragma once
+#include "iir.hpp"
+
+namespace bfgp {
+
+// Coefficients of the row pass for one sigma_s and chunk length L.
+constexpr int kRowMaxL = 16;  // samples per thread
+struct RowCoef {
+    float n0[2], n1[2], m1[2], m2[2], d1[2], d2[2];
+    float pw[2][10][4];        // Phi^(L 2^j), j = 0..9, row-major (chunk distances 1 .. 512)
+    float hom[kRowMaxL][4];    // first rows of Phi_0^(i+1) and Phi_1^(i+1): the homogeneous
+                               // response i samples after a state, (alpha_0, beta_0, alpha_1, beta_1)
+};
+
+// LDS of hrow2 in floats: the power matrices Phi^(L 2^j) (2 x 10 x 4), the
+// homogeneous-response table (16 x 4), the per-lane power table (16 x 8), the
+// per-row power table (4 x 8), the wave totals of every group
+// (double-buffered, 2 x 8 x 8 each); then as doubles the centred intensities
+// of the row (T L) and the hand-over of groups 1.. to group 0 (2 per pixel).
+constexpr int kRowSmemHead = 80 + 4 * kRowMaxL + 128 + 32;
+__host__ __device__ constexpr size_t hrow2_smem_bytes(int T, int groups, int L) {
+    return sizeof(float) * ((size_t)kRowSmemHead + (size_t)groups * 128) +
+           sizeof(double) * ((size_t)T * L + 2 * (size_t)(groups - 1) * (size_t)T * (size_t)L);
+}
+
+// s[0..1] += P * (v0, v1), P a 2x2 matrix (row-major) in LDS
+__device__ __forceinline__ void acc2v(float *s, const float *P, float v0, float v1) {
+    const float4 m = *(const float4 *)P;
+    s[0] = fmaf(m.x, v0, fmaf(m.y, v1, s[0]));
+    s[1] = fmaf(m.z, v0, fmaf(m.w, v1, s[1]));
+}
+
+__device__ __forceinline__ float bperm_f(float v, int src_lane) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src_lane << 2, __float_as_int(v)));
+}
+
+// One image row (see the file comment).  The workgroup holds `groups` channel
+// groups of T threads (T a multiple of 64, T L >= W, groups * T <= 512,
+// T <= 512, L <= kRowMaxL);
+// group g filters channels [C g / groups, C (g + 1) / groups).
+// S: the column-filtered stack, channel n row r at S + (n * sp_rows + r) *
+// sp_pitch; columns W .. sp_pitch - 1 hold zeros and sp_pitch >= T L + 2.
+// sm: hrow2_smem_bytes(T, groups, L) bytes.  foff: element offset of the image
+// and output rows (a volume's frame).
+template <int L>
+__device__ __forceinline__ void hrow2(const GPParams &p, const RowCoef &c, const Stats &st, int y,
+                                      const float *__restrict__ S, int sp_rows, int sp_pitch, float *sm, int T,
+                                      int groups, size_t foff = 0) {
+    const int g = __builtin_amdgcn_readfirstlane((int)threadIdx.x / T);  // whole waves share a group
+    const int t = threadIdx.x - g * T;
+    const int lane = threadIdx.x & 63, jj = lane & 15;
+    const int nw = T >> 6;  // waves in a group
+    const int wv = t >> 6;  // this chunk's wave in the group
+    const int r16 = lane >> 4;  // this chunk's row of 16 lanes in the wave
+    const int x0 = t * L;
+    const int cb = (p.C * g) / groups, ce = (p.C * (g + 1)) / groups;
+    const int steps = (p.C + groups - 1) / groups;  // channels of the largest group
+    float *pws = sm;                      // pws[(10 s + j) * 4 + q] = Phi_s^(L 2^j)
+    float *homs = sm + 80;                // homs[i * 4 + q] = c.hom[i][q]
+    float *Gt = homs + 4 * kRowMaxL;      // Gt[jj * 8 + 4 s + q] = Phi_s^(L jj)
+    float *Gw = Gt + 128;                 // Gw[r * 8 + 4 s + q] = Phi_s^(16 L r), r = 0..3
+    float *wtot = sm + kRowSmemHead + (size_t)g * 128;  // [2][8 waves][8]
+    double *taus = (double *)(sm + kRowSmemHead + (size_t)groups * 128);  // taus[i * T + t]
+    double *comb = taus + (size_t)T * L;
+
+    // the coefficient tables go through LDS (as kernel arguments held in
+    // scalar registers they would spill)
+    for (int k = threadIdx.x; k < 80 + 4 * kRowMaxL; k += blockDim.x)
+        sm[k] = k < 80 ? (&c.pw[0][0][0])[k] : (&c.hom[0][0])[k - 80];
+    if (threadIdx.x < 16) {
+        const int k = threadIdx.x;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            float G[4] = {1.f, 0.f, 0.f, 1.f};
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (k & (1 << j)) mat_mul(G, c.pw[s][j], G);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Gt[k * 8 + 4 * s + q] = G[q];
+            if (k < 4) {
+                float H[4] = {1.f, 0.f, 0.f, 1.f};
+                if (k & 1) mat_mul(H, c.pw[s][4], H);
+                if (k & 2) mat_mul(H, c.pw[s][5], H);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) Gw[k * 8 + 4 * s + q] = H[q];
+            }
+        }
+    }
+    if (g == 0) {
+        // centred intensities of the row (unconditional loads from clamped
+        // columns, zero past the row end)
+        const float *irow = p.img + foff + (size_t)y * p.pitch;
+        float f[L];
+#pragma unroll
+        for (int i = 0; i < L; ++i) f[i] = irow[x0 + i < p.W ? x0 + i : p.W - 1];
+#pragma unroll
+        for (int i = 0; i < L; ++i)
+            taus[i * T + t] = x0 + i < p.W ? (double)centred(f[i], st, p.inv_sigma_r) : 0.0;
+    }
+    __syncthreads();
+    float gc[8], ga[8];  // Phi^(L jj) and Phi^(L (15 - jj)), both sections
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        gc[q] = Gt[jj * 8 + q];
+        ga[q] = Gt[(15 - jj) * 8 + q];
+    }
+
+    double bP[L], bC[L];  // Horner accumulators of D and of D' (+ the N+1 term)
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        bP[i] = 0.0;
+        bC[i] = 0.0;
+    }
+    const int top = (ce - 1 < p.N ? ce - 1 : p.N);  // the group's highest channel <= N
+    // 1 / sqrt(n!) of the group's first (highest) channel, then divided by
+    // sqrt(n) at every step down
+    double kap = 1.0;
+    for (int n = 2; n < ce; ++n) kap *= p.isq[n];
+
+    // samples x0-1 .. x0+L+1 of channel n's stack row (columns W .. pitch-1
+    // are zero pad; only the sample left of the row start is masked).  The
+    // next channel's samples are loaded while the current one is filtered.
+    auto load = [&](float *z, int n) {
+        const float *srow = S + ((size_t)n * sp_rows + y) * sp_pitch;
+        z[0] = srow[x0 > 0 ? x0 - 1 : 0];
+#pragma unroll
+        for (int i = 0; i < L; i += 4) {
+            const float4 q = *(const float4 *)(srow + x0 + i);
+            z[1 + i] = q.x; z[2 + i] = q.y; z[3 + i] = q.z; z[4 + i] = q.w;
+        }
+        z[L + 1] = srow[x0 + L];
+        z[L + 2] = srow[x0 + L + 1];
+    };
+    float zn[L + 3];
+    if (ce - 1 >= cb) load(zn, ce - 1);
+    for (int it = 0; it < steps; ++it) {
+        const int n = ce - 1 - it;
+        const bool act = n >= cb;  // uniform over the group
+        float o[L];
+        float sc[4], sa[4];
+        if (act) {
+            float z[L + 3];
+#pragma unroll
+            for (int i = 0; i < L + 3; ++i) z[i] = zn[i];
+            if (n - 1 >= cb) load(zn, n - 1);
+            z[0] = x0 > 0 ? z[0] : 0.f;
+            // 1. the chunk from rest
+            {
+                float y1[2] = {0.f, 0.f}, y2[2] = {0.f, 0.f};
+#pragma unroll
+                for (int i = 0; i < L; ++i) {
+                    float v[2];
+#pragma unroll
+                    for (int s = 0; s < 2; ++s) {
+                        const float b = fmaf(c.n0[s], z[i + 1], fmaf(c.n1[s], z[i], -c.d2[s] * y2[s]));
+                        v[s] = fmaf(-c.d1[s], y1[s], b);
+                        y2[s] = y1[s];
+                        y1[s] = v[s];
+                    }
+                    o[i] = v[0] + v[1];
+                }
+                sc[0] = y1[0]; sc[1] = y2[0]; sc[2] = y1[1]; sc[3] = y2[1];
+            }
+            {
+                float z1[2] = {0.f, 0.f}, z2[2] = {0.f, 0.f};
+#pragma unroll
+                for (int i = L - 1; i >= 0; --i) {
+                    float v[2];
+#pragma unroll
+                    for (int s = 0; s < 2; ++s) {
+                        const float b = fmaf(c.m1[s], z[i + 2], fmaf(c.m2[s], z[i + 3], -c.d2[s] * z2[s]));
+                        v[s] = fmaf(-c.d1[s], z1[s], b);
+                        z2[s] = z1[s];
+                        z1[s] = v[s];
+                    }
+                    o[i] += v[0] + v[1];
+                }
+                sa[0] = z1[0]; sa[1] = z2[0]; sa[2] = z1[1]; sa[3] = z2[1];
+            }
+            // 2a. inclusive scans inside each row of 16 lanes: causal from the
+            // left (row_shr), anticausal from the right (row_shl)
+#define BF_ROWSTEP2(J, D)                                                                  \
+            {                                                                              \
+                float pc[4], pa[4];                                                        \
+                _Pragma("unroll") for (int q = 0; q < 4; ++q) {                            \
+                    pc[q] = dpp_f<kDppRowShr + D>(sc[q]);                                  \
+                    pa[q] = dpp_f<kDppRowShl + D>(sa[q]);                                  \
+                }                                                                          \
+                _Pragma("unroll") for (int s = 0; s < 2; ++s) {                            \
+                    acc2v(&sc[2 * s], pws + (10 * s + J) * 4, pc[2 * s], pc[2 * s + 1]);   \
+                    acc2v(&sa[2 * s], pws + (10 * s + J) * 4, pa[2 * s], pa[2 * s + 1]);   \
+                }                                                                          \
+            }
+            BF_ROWSTEP2(0, 1)
+            BF_ROWSTEP2(1, 2)
+            BF_ROWSTEP2(2, 4)
+            BF_ROWSTEP2(3, 8)
+#undef BF_ROWSTEP2
+        }
+        // 2b. the four rows of the wave: lane r (r < 4) takes row r's totals
+        // (the causal one ends at its lane 15, the anticausal one at its lane
+        // 0) and the lanes scan them (DPP, distances 1 and 2 rows)
+        float rc[4], ra[4];
+        if (act) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                rc[q] = bperm_f(sc[q], (lane & 3) * 16 + 15);
+                ra[q] = bperm_f(sa[q], (lane & 3) * 16);
+                rc[q] = lane < 4 ? rc[q] : 0.f;
+                ra[q] = lane < 4 ? ra[q] : 0.f;
+            }
+#define BF_L2STEP(J, D)                                                                      \
+            {                                                                                \
+                float pc[4], pa[4];                                                          \
+                _Pragma("unroll") for (int q = 0; q < 4; ++q) {                              \
+                    pc[q] = dpp_f<kDppRowShr + D>(rc[q]);                                    \
+                    pa[q] = dpp_f<kDppRowShl + D>(ra[q]);                                    \
+                }                                                                            \
+                _Pragma("unroll") for (int s = 0; s < 2; ++s) {                              \
+                    acc2v(&rc[2 * s], pws + (10 * s + J) * 4, pc[2 * s], pc[2 * s + 1]);     \
+                    acc2v(&ra[2 * s], pws + (10 * s + J) * 4, pa[2 * s], pa[2 * s + 1]);     \
+                }                                                                            \
+            }
+            BF_L2STEP(4, 1)
+            BF_L2STEP(5, 2)
+        }
+        // 2c. across the waves of the group: wave totals through LDS (lane 3
+        // holds the causal total of the wave, lane 0 the anticausal one), a
+        // DPP scan over the waves (distances 1, 2, 4), and the wave's
+        // incoming states (uniform).  Every wave meets the barrier.
+        float wc[4] = {0.f, 0.f, 0.f, 0.f}, wa[4] = {0.f, 0.f, 0.f, 0.f};
+        if (nw > 1) {
+            float *tb = wtot + (it & 1) * 64;
+            if (act && lane == 3) *(float4 *)(tb + wv * 8) = make_float4(rc[0], rc[1], rc[2], rc[3]);
+            if (act && lane == 0) *(float4 *)(tb + wv * 8 + 4) = make_float4(ra[0], ra[1], ra[2], ra[3]);
+            __syncthreads();
+            if (act) {
+                const int l = lane < nw ? lane : 0;
+                const float4 c4 = *(const float4 *)(tb + l * 8), a4 = *(const float4 *)(tb + l * 8 + 4);
+                const bool in = lane < nw;
+                float xc[4] = {in ? c4.x : 0.f, in ? c4.y : 0.f, in ? c4.z : 0.f, in ? c4.w : 0.f};
+                float xa[4] = {in ? a4.x : 0.f, in ? a4.y : 0.f, in ? a4.z : 0.f, in ? a4.w : 0.f};
+#define BF_WSTEP(J, D)                                                                       \
+                if (D < nw) {                                                                \
+                    float pc[4], pa[4];                                                      \
+                    _Pragma("unroll") for (int q = 0; q < 4; ++q) {                          \
+                        pc[q] = dpp_f<kDppRowShr + D>(xc[q]);                                \
+                        pa[q] = dpp_f<kDppRowShl + D>(xa[q]);                                \
+                    }                                                                        \
+                    _Pragma("unroll") for (int s = 0; s < 2; ++s) {                          \
+                        acc2v(&xc[2 * s], pws + (10 * s + J) * 4, pc[2 * s], pc[2 * s + 1]); \
+                        acc2v(&xa[2 * s], pws + (10 * s + J) * 4, pa[2 * s], pa[2 * s + 1]); \
+                    }                                                                        \
+                }
+                BF_WSTEP(6, 1)
+                BF_WSTEP(7, 2)
+                BF_WSTEP(8, 4)
+#undef BF_WSTEP
+                // exclusive: the waves before (causal) and after (anticausal)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    xc[q] = dpp_f<kDppRowShr + 1>(xc[q]);
+                    xa[q] = dpp_f<kDppRowShl + 1>(xa[q]);
+                    wc[q] = lane_f(xc[q], wv);
+                    wa[q] = lane_f(xa[q], wv);
+                }
+            }
+        }
+        if (!act) continue;
+        // row-exclusive incoming states of the wave's rows (lanes 0..3): the
+        // rows before (after) inside the wave plus the wave's incoming state
+        // moved over the rows between; then each chunk fetches its row's
+        float qc[4], qa[4];
+        {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                qc[q] = dpp_f<kDppRowShr + 1>(rc[q]);
+                qa[q] = dpp_f<kDppRowShl + 1>(ra[q]);
+            }
+            const int rr = lane & 3;
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                acc2v(&qc[2 * s], Gw + rr * 8 + 4 * s, wc[2 * s], wc[2 * s + 1]);
+                acc2v(&qa[2 * s], Gw + (3 - rr) * 8 + 4 * s, wa[2 * s], wa[2 * s + 1]);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                qc[q] = bperm_f(qc[q], r16);
+                qa[q] = bperm_f(qa[q], r16);
+            }
+        }
+        // incoming states of this chunk: the row-exclusive prefix inside the
+        // row (a shift by one lane) plus the row's incoming state moved over
+        // the chunks between
+        float ic[4], ia[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            ic[q] = dpp_f<kDppRowShr + 1>(sc[q]);
+            ia[q] = dpp_f<kDppRowShl + 1>(sa[q]);
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            acc2(&ic[2 * s], &gc[4 * s], qc[2 * s], qc[2 * s + 1]);
+            acc2(&ia[2 * s], &ga[4 * s], qa[2 * s], qa[2 * s + 1]);
+        }
+        // 3. homogeneous responses of the incoming states (by recursion)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const float d1 = c.d1[s], d2 = c.d2[s];
+            float a1 = ic[2 * s], a2 = ic[2 * s + 1];
+#pragma unroll
+            for (int i = 0; i < L; ++i) {
+                const float h = fmaf(-d1, a1, -d2 * a2);
+                o[i] += h;
+                a2 = a1;
+                a1 = h;
+            }
+            float b1 = ia[2 * s], b2 = ia[2 * s + 1];
+#pragma unroll
+            for (int i = L - 1; i >= 0; --i) {
+                const float h = fmaf(-d1, b1, -d2 * b2);
+                o[i] += h;
+                b2 = b1;
+                b1 = h;
+            }
+        }
+        // recombination (uniform branches on the channel index)
+        if (n == p.N + 1) {
+            // the top channel enters M only: seed of the derivative chain
+            const double k = (double)(p.N + 1) * kap;
+#pragma unroll
+            for (int i = 0; i < L; ++i) bC[i] = k * (double)o[i];
+        } else if (n == top) {
+            // the group's highest channel <= N starts the D chain
+#pragma unroll
+            for (int i = 0; i < L; ++i) bP[i] = kap * (double)o[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < L; ++i) {
+                const double tv = taus[i * T + t];
+                bC[i] = fma(bC[i], tv, bP[i]);
+                bP[i] = fma(bP[i], tv, kap * (double)o[i]);
+            }
+        }
+        kap *= p.sq[n];  // 1 / sqrt((n-1)!)
+    }
+    if (groups > 1) {
+        // parts of groups 1.. in the full sums, through LDS
+        if (g > 0) {
+            // a group that holds channel N+1 alone (cb = N+1) has no D part;
+            // its seed was never multiplied by tau and stands for (N+1) a_{N+1}
+            // tau^N
+            const bool only_top = cb > p.N;
+#pragma unroll
+            for (int i = 0; i < L; ++i) {
+                const double tv = taus[i * T + t];
+                const double tp = ipow(tv, only_top ? p.N : cb - 1);  // tau^(cb - 1), or tau^N
+                comb[((size_t)(g - 1) * 2 * L + 2 * i) * T + t] = only_top ? 0.0 : bP[i] * (tp * tv);
+                comb[((size_t)(g - 1) * 2 * L + 2 * i + 1) * T + t] =
+                    only_top ? tp * bC[i] : (double)cb * tp * bP[i] + tp * tv * bC[i];
+            }
+        }
+        __syncthreads();
+        if (g == 0) {
+            for (int gg = 1; gg < groups; ++gg) {
+#pragma unroll
+                for (int i = 0; i < L; ++i) {
+                    bP[i] += comb[((size_t)(gg - 1) * 2 * L + 2 * i) * T + t];
+                    bC[i] += comb[((size_t)(gg - 1) * 2 * L + 2 * i + 1) * T + t];
+                }
+            }
+        }
+    }
+    if (g == 0 && y < p.H) {
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            const int x = x0 + i;
+            if (x < p.W) {
+                const double rho = bC[i] / bP[i];
+                p.out[foff + (size_t)y * p.pitch + x] = st.ok ? (float)fma(p.sigma_r, rho, st.tc) : __builtin_nanf("");
+            }
+        }
+    }
+}
+
+}  // namespace bfgp

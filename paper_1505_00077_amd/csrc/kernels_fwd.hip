@@ -3,6 +3,7 @@
 #include "launch.hpp"
 #include "fir.hpp"
 #include "iir.hpp"
+#include "hrow.hpp"
 #include "direct.hpp"
 #include "box.hpp"
 
@@ -131,6 +132,20 @@ __global__ __launch_bounds__(512, 1) void k_hrow(GPParams p, IirCoef c, const fl
     hrow<L, SAVE, JOINT>(p, c, st, blockIdx.x, S, srows, sp, sm, T, groups);
 }
 
+// Row pass + recombination of one image row (hrow2): T threads per channel
+// group, `groups` groups, T * groups <= 512.
+template <int L>
+__global__ __launch_bounds__(512) void k_hrow2(GPParams p, RowCoef c, const float *S, int srows, int sp, int T,
+                                               int groups) {
+    extern __shared__ float sm[];
+    const Stats st = load_stats(p);
+    if (!st.ok) {
+        for (int x = threadIdx.x; x < p.W; x += blockDim.x) p.out[(size_t)blockIdx.x * p.pitch + x] = __builtin_nanf("");
+        return;
+    }
+    hrow2<L>(p, c, st, blockIdx.x, S, srows, sp, sm, T, groups);
+}
+
 // ---- volumes: the row-direction pass per frame and the frame-wise row pass ----
 
 // Column pass of every frame over the time-filtered stack S1 (channel n, frame
@@ -170,8 +185,8 @@ __global__ __launch_bounds__(64) void k_vresolve3(GPParams p, IirCoef c, int nb,
 
 // Row pass of frame blockIdx.x / H, row blockIdx.x % H.
 template <int L>
-__global__ __launch_bounds__(512, 1) void k_hrow3(GPParams p, IirCoef c, const float *S, int srows, int sp, int T,
-                                                  int groups, size_t s_fstride) {
+__global__ __launch_bounds__(512) void k_hrow3(GPParams p, RowCoef c, const float *S, int srows, int sp, int T,
+                                               int groups, size_t s_fstride) {
     extern __shared__ float sm[];
     const Stats st = load_stats(p);
     const size_t t = blockIdx.x / p.H;
@@ -181,7 +196,7 @@ __global__ __launch_bounds__(512, 1) void k_hrow3(GPParams p, IirCoef c, const f
         for (int x = threadIdx.x; x < p.W; x += blockDim.x) p.out[foff + (size_t)y * p.pitch + x] = __builtin_nanf("");
         return;
     }
-    hrow<L>(p, c, st, y, S + t * s_fstride, srows, sp, sm, T, groups, foff);
+    hrow2<L>(p, c, st, y, S + t * s_fstride, srows, sp, sm, T, groups, foff);
 }
 
 // ---- box spatial kernel ----------------------------------------------------------
@@ -252,18 +267,40 @@ hipError_t launch_fir(const GPParams &p, const FirTaps &t, int R, bool save, hip
 }
 
 
+// The row pass that stores the saved terms or recombines the joint filter
+// (chunks of sh.Lo samples, one channel group).
 template <int L>
 static void hrow_launch(const GPParams &p, const IirCoef &c, const IirShape &sh, const float *S, bool save,
                         bool joint, hipStream_t s) {
-    const dim3 rb(sh.T * sh.Gr);
-    const size_t sm = hrow_smem_bytes(sh.T, sh.Gr, sh.L);
+    const dim3 rb(sh.To);
+    const size_t sm = hrow_smem_bytes(sh.To, 1, sh.Lo);
     if (joint)
-        BF_LAUNCH("k_hrow", (k_hrow<L, false, true>), dim3(p.H), rb, sm, s, p, c, S, sh.Hs, sh.P, sh.T, sh.Gr);
-    else if (save)
-        BF_LAUNCH("k_hrow", (k_hrow<L, true, false>), dim3(p.H), rb, sm, s, p, c, S, sh.Hs, sh.P, sh.T, sh.Gr);
+        BF_LAUNCH("k_hrow", (k_hrow<L, false, true>), dim3(p.H), rb, sm, s, p, c, S, sh.Hs, sh.P, sh.To, 1);
     else
-        BF_LAUNCH("k_hrow", (k_hrow<L, false, false>), dim3(p.H), rb, sm, s, p, c, S, sh.Hs, sh.P, sh.T, sh.Gr);
+        BF_LAUNCH("k_hrow", (k_hrow<L, true, false>), dim3(p.H), rb, sm, s, p, c, S, sh.Hs, sh.P, sh.To, 1);
 }
+
+// The row pass of the plain forward (chunks of sh.L samples).
+template <int L>
+static hipError_t hrow2_launch(const GPParams &p, const RowCoef &c, const IirShape &sh, const float *S, hipStream_t s) {
+    const size_t sm = hrow2_smem_bytes(sh.T, sh.Gr, sh.L);
+    if (sm > 65536) {
+        static hipError_t attr = hipFuncSetAttribute((const void *)k_hrow2<L>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     160 * 1024);
+        if (attr != hipSuccess) return attr;
+    }
+    BF_LAUNCH("k_hrow", (k_hrow2<L>), dim3(p.H), dim3(sh.T * sh.Gr), sm, s, p, c, S, sh.Hs, sh.P, sh.T, sh.Gr);
+    return hipSuccess;
+}
+
+#define BF_ROW2_SWITCH(Lv, CALL)                                                         \
+    switch (Lv) {                                                                        \
+        case 4: CALL(4); break;                                                          \
+        case 8: CALL(8); break;                                                          \
+        case 12: CALL(12); break;                                                        \
+        case 16: CALL(16); break;                                                        \
+        default: return hipErrorInvalidValue;                                            \
+    }
 
 template <int B, bool AGG>
 static void vband_launch(const GPParams &p, const IirCoef &c, const IirShape &sh, dim3 grid, float *carry, float *S,
@@ -299,12 +336,9 @@ static hipError_t vbandg_launch(const GPParams &p, const IirCoef &c, const IirSh
     return hipSuccess;
 }
 
-hipError_t launch_iir(const GPParams &p, const IirCoef &c, const IirShape &shape, float *carry, float *S, bool save,
-                      bool joint, hipStream_t s) {
+hipError_t launch_iir(const GPParams &p, const IirCoef &c, const RowCoef &rc, const IirShape &shape, float *carry,
+                      float *S, bool save, bool joint, hipStream_t s) {
     IirShape sh = shape;
-    // the saved terms and the joint recombination need the whole Horner sums
-    // in one group
-    if (save || joint) sh.Gr = 1;
     const int nb = (p.H + sh.B - 1) / sh.B;
     // the end-state pass has nothing to do on the stack's pad columns: its
     // grid covers the image columns only (an even number of waves per SIMD
@@ -333,12 +367,21 @@ hipError_t launch_iir(const GPParams &p, const IirCoef &c, const IirShape &shape
     else
         vband_launch<32, false>(p, c, sh, gv, carry, S, cgr, cgp, joint, s);
     if (e != hipSuccess) return e;
-    switch (sh.L) {
-        case 4: hrow_launch<4>(p, c, sh, S, save, joint, s); break;
-        case 8: hrow_launch<8>(p, c, sh, S, save, joint, s); break;
-        case 12: hrow_launch<12>(p, c, sh, S, save, joint, s); break;
-        case 16: hrow_launch<16>(p, c, sh, S, save, joint, s); break;
-        default: return hipErrorInvalidValue;
+    if (save || joint) {
+        // the saved terms and the joint recombination: the row pass with the
+        // whole Horner sums in one group
+        switch (sh.Lo) {
+            case 4: hrow_launch<4>(p, c, sh, S, save, joint, s); break;
+            case 8: hrow_launch<8>(p, c, sh, S, save, joint, s); break;
+            case 12: hrow_launch<12>(p, c, sh, S, save, joint, s); break;
+            case 16: hrow_launch<16>(p, c, sh, S, save, joint, s); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+#define BF_CALL(l) e = hrow2_launch<l>(p, rc, sh, S, s)
+        BF_ROW2_SWITCH(sh.L, BF_CALL)
+#undef BF_CALL
+        if (e != hipSuccess) return e;
     }
     return hipGetLastError();
 }
@@ -350,7 +393,8 @@ hipError_t launch_direct(const DirectArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_volume(const GPParams &pz, const GPParams &ps, const IirCoef &ct, const IirCoef &cs,
-                         const IirShape &shz, const IirShape &shs, int T, const VolumeBuffers &vb, hipStream_t s) {
+                         const RowCoef &rcs, const IirShape &shz, const IirShape &shs, int T, const VolumeBuffers &vb,
+                         hipStream_t s) {
     // 1. statistics of the volume seen as a (T H) x W image (ps)
     hipError_t e = launch_stats(ps, false, s);
     if (e != hipSuccess) return e;
@@ -382,15 +426,13 @@ hipError_t launch_volume(const GPParams &pz, const GPParams &ps, const IirCoef &
               vb.carry_y, vb.S2, shs.P, shs.G, cgr, cgp, (const float *)vb.S1, s1_cstride, carry_fstride, s_fstride);
     // 4. row direction and the recombination, frame by frame
     const dim3 rb(shs.T * shs.Gr);
-    const size_t sm = hrow_smem_bytes(shs.T, shs.Gr, shs.L);
+    const size_t sm = hrow2_smem_bytes(shs.T, shs.Gr, shs.L);
+    if (sm > 65536) return hipErrorInvalidValue;
     const dim3 gr((unsigned)(T * py.H));
-    switch (shs.L) {
-#define BF_ROW(l) case l: BF_LAUNCH("k_hrow", (k_hrow3<l>), gr, rb, sm, s, py, cs, (const float *)vb.S2, vb.Hs, \
-                                    shs.P, shs.T, shs.Gr, s_fstride); break;
-        BF_ROW(4) BF_ROW(8) BF_ROW(12) BF_ROW(16)
-#undef BF_ROW
-        default: return hipErrorInvalidValue;
-    }
+#define BF_CALL(l) BF_LAUNCH("k_hrow", (k_hrow3<l>), gr, rb, sm, s, py, rcs, (const float *)vb.S2, vb.Hs, shs.P, \
+                             shs.T, shs.Gr, s_fstride)
+    BF_ROW2_SWITCH(shs.L, BF_CALL)
+#undef BF_CALL
     return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 namespace bfgp {
 
 struct IirCoef;
+struct RowCoef;
 struct DirectArgs;
 struct BwdParams;
 struct FirTaps2;
@@ -32,10 +33,13 @@ struct IirShape {
     int B;   // band height of the column passes (32 or 64 rows)
     int G;   // channel groups of the column passes
     int L;   // samples per thread in the row pass (4, 8, 12 or 16)
-    int T;   // threads per channel group of the row pass (T L >= W)
+    int T;   // threads per channel group of the row pass (T L >= W, T Gr <= 512)
     int Gr;  // channel groups of the row pass
-    int P;   // row pitch of the channel stack, >= T L + 2, a multiple of 32
-             // (columns W .. P-1 are zero)
+    int Lo;  // the same for the row pass with the saved terms and the joint
+    int To;  // filter (and the batched path): L 4, 8, 12 or 16, T <= 512
+    int Gro;
+    int P;   // row pitch of the channel stack, >= max(T L, To Lo) + 2, a
+             // multiple of 32 (columns W .. P-1 are zero)
     int Hs;  // rows per channel of the stack: H rounded up to a multiple of B
 };
 // batch: the image is one of many filtered together, which fill the device by
@@ -44,8 +48,10 @@ IirShape iir_shape(int H, int W, int C, bool batch = false);
 // save: also store the terms bf_gp_backward needs (p.saved), with the row pass
 // in one channel group.  joint: the joint filter (p.img the guide, p.data the
 // data, p.C = 2 (N + 1) stack channels), row pass in one channel group.
-hipError_t launch_iir(const GPParams &p, const IirCoef &c, const IirShape &sh, float *carry, float *S, bool save,
-                      bool joint, hipStream_t s);
+// c: the column passes' coefficients (and the row pass of the saved terms and
+// the joint filter, chunks of sh.Lo); rc: the row pass's (chunks of sh.L).
+hipError_t launch_iir(const GPParams &p, const IirCoef &c, const RowCoef &rc, const IirShape &sh, float *carry,
+                      float *S, bool save, bool joint, hipStream_t s);
 hipError_t launch_direct(const DirectArgs &a, hipStream_t s);
 struct BoxShape;
 // Box spatial mode: column pass (running sums) into the stack S, then the row
@@ -62,7 +68,8 @@ struct VolumeBuffers {
 // volume as a (T H) x W image (statistics; coefficients cs and shape shs of
 // each H x W frame).
 hipError_t launch_volume(const GPParams &pz, const GPParams &ps, const IirCoef &ct, const IirCoef &cs,
-                         const IirShape &shz, const IirShape &shs, int T, const VolumeBuffers &vb, hipStream_t s);
+                         const RowCoef &rcs, const IirShape &shz, const IirShape &shs, int T, const VolumeBuffers &vb,
+                         hipStream_t s);
 int bwd_tiles(int H, int W);
 hipError_t launch_bwd(const GPParams &p, const BwdParams &b, const FirTaps2 &t, int R, double *corr, double *g_lss,
                       double *g_lsr, hipStream_t s);
