@@ -30,7 +30,10 @@ namespace bfgp {
 // kStFir: FIR images with radius up to kBatchFirSplit; kStFirWide: the rest
 // (separate launches, so that wide radii do not set the register budget of
 // narrow ones)
-enum { kStStats = 0, kStFir, kStFirWide, kStAgg, kStResolve, kStBand, kStRow, kNumStages = kStRow + 8 };
+// kStAggM: end states by weighted sums (stacks of at most kAggMaxC channels),
+// four items of one image per workgroup; kStAgg: by the recursion (wider
+// stacks), one item per workgroup.
+enum { kStStats = 0, kStFir, kStFirWide, kStAggM, kStAgg, kStResolve, kStBand, kStRow, kNumStages = kStRow + 8 };
 constexpr int kBatchFirSplit = 12;
 // same partial count as the single-image path, so that both reduce the image
 // sum in the same order and produce bit-identical centres and outputs
@@ -128,6 +131,42 @@ __global__ __launch_bounds__(64, 3) void k_bband(const BatchImage *imgs, const B
         vband<BH, AGG, true>(B.p, B.c, st, col, band, B.carry, B.S, B.Sp, sa, cb, ce);
     else
         vband<BH, AGG, false>(B.p, B.c, st, col, band, B.carry, B.S, B.Sp, sa, cb, ce);
+}
+
+// End states by weighted sums (as the single-image k_vagg, with the same
+// channel groups, so that both give the same bits): item idx of an image
+// covers its bands 4 idx / G .. 4 (idx + 1) / G - 1, G waves per band.
+__global__ __launch_bounds__(256) void k_bagg(const BatchImage *imgs, const BatchItem *items) {
+    __shared__ float sm[vagg_smem_floats(32, 2)];
+    float *wts = sm;
+    const BatchItem w = items[blockIdx.x];
+    const BatchImage &B = imgs[w.img];
+    const Stats st = reduce_stats(B.p);
+    if (w.idx == 0 && threadIdx.x == 0) publish_stats(B.p, st);
+    if (!st.ok) return;
+    agg_weights<32>(B.c, wts);
+    const int G = agg_groups(B.p.H, B.p.W, B.p.C);
+    const int cgr = (B.p.W + 63) / 64;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int pr = wave / G, gw = wave % G;
+    const int pair = w.idx * (4 / G) + pr;
+    const bool live = pair < cgr * B.nb;
+    const int cg = pair % cgr, band = pair / cgr;
+    const int col = cg * 64 + (threadIdx.x & 63);
+    float *pro = sm + 35 * 8 + pr * 2 * 35 * 64;
+    const bool big = st.xmax > 12.0;
+    if (live) {
+        if (big)
+            vagg_prologue<32, true>(B.p, st, col, band, gw, G, pro);
+        else
+            vagg_prologue<32, false>(B.p, st, col, band, gw, G, pro);
+    }
+    __syncthreads();
+    if (!live) return;
+    if (big)
+        vagg_moments<32, kAggG, true>(B.p, col, band, B.carry, gw, G, wts, pro);
+    else
+        vagg_moments<32, kAggG, false>(B.p, col, band, B.carry, gw, G, wts, pro);
 }
 
 __global__ __launch_bounds__(kBlock) void k_bresolve(const BatchImage *imgs, const BatchItem *items) {
@@ -278,7 +317,13 @@ int bf_gp_plan_batched(const bf_gp_item *items, int count, unsigned flags, void 
             const int G = sh.G;
             const int cls = sh.T * sh.Gr / 64 - 1;  // T * Gr is a multiple of 64, at most 512
             row_smem[cls] = std::max(row_smem[cls], hrow2_smem_bytes(sh.T, sh.Gr, sh.L));
-            for (int t = 0; t < nb * ncg * G; ++t) per[kStAgg].push_back({i, t});
+            if (sh.B == 32 && (int)C <= kAggMaxC) {
+                const int G = agg_groups(it.H, it.W, (int)C);
+                const int nbands = (it.W + 63) / 64 * nb;
+                for (int t = 0; t < (nbands * G + 3) / 4; ++t) per[kStAggM].push_back({i, t});
+            } else {
+                for (int t = 0; t < nb * ncg * G; ++t) per[kStAgg].push_back({i, t});
+            }
             const int ng = (it.W + kBlock - 1) / kBlock;
             for (int t = 0; t < (int)C * ng * 2; ++t) per[kStResolve].push_back({i, t});
             for (int t = 0; t < nb * ncg * G; ++t) per[kStBand].push_back({i, t});
@@ -368,11 +413,14 @@ int bf_gp_forward_batched(void *plan, void *ws, size_t ws_bytes, void *stream) {
         BF_LAUNCH("k_bfir", k_bfir<false>, dim3(n(kStFir)), dim3(kBlock), P->fir_smem[0], s, imgs, at(kStFir));
     if (n(kStFirWide))
         BF_LAUNCH("k_bfir", k_bfir<true>, dim3(n(kStFirWide)), dim3(kBlock), P->fir_smem[1], s, imgs, at(kStFirWide));
-    if (n(kStAgg)) {
-        if (P->band_rows == 32)
-            BF_LAUNCH("k_bband_agg", (k_bband<32, true>), dim3(n(kStAgg)), dim3(64), 0, s, imgs, at(kStAgg));
-        else
-            BF_LAUNCH("k_bband_agg", (k_bband<64, true>), dim3(n(kStAgg)), dim3(64), 0, s, imgs, at(kStAgg));
+    if (n(kStAggM) || n(kStAgg)) {
+        if (n(kStAggM)) BF_LAUNCH("k_bband_agg", k_bagg, dim3(n(kStAggM)), dim3(256), 0, s, imgs, at(kStAggM));
+        if (n(kStAgg)) {
+            if (P->band_rows == 32)
+                BF_LAUNCH("k_bband_agg", (k_bband<32, true>), dim3(n(kStAgg)), dim3(64), 0, s, imgs, at(kStAgg));
+            else
+                BF_LAUNCH("k_bband_agg", (k_bband<64, true>), dim3(n(kStAgg)), dim3(64), 0, s, imgs, at(kStAgg));
+        }
         BF_LAUNCH("k_bresolve", k_bresolve, dim3(n(kStResolve)), dim3(kBlock), 0, s, imgs, at(kStResolve));
         if (P->band_rows == 32)
             BF_LAUNCH("k_bband", (k_bband<32, false>), dim3(n(kStBand)), dim3(64), 0, s, imgs, at(kStBand));

@@ -26,6 +26,10 @@
 namespace bfgp {
 
 constexpr int kIirMaxL = 16;
+// End states by weighted sums: channel groups of at most kAggG channels, for
+// stacks of at most kAggMaxC channels (unnormalised powers stay in FP32 up
+// to degree 47; 4 groups of at most 12 channels).
+constexpr int kAggG = 12, kAggMaxC = 48;
 
 struct IirCoef {
     float n0[2], n1[2], m1[2], m2[2], d1[2], d2[2];
@@ -289,6 +293,175 @@ __device__ __forceinline__ void vband(const GPParams &p, const IirCoef &c, const
         }
     }
 }
+
+// Band end states as weighted sums ("moments").  The end states that vband
+// <B, AGG> leaves for a band (causal y_{a+B-1}, y_{a+B-2} and anticausal z_a,
+// z_{a+1} of both sections, from rest, with the true halo inputs) are linear
+// in the band's B + 3 input samples (rows a-1 .. a+B+1):
+//     e_k = sum_i w_k(i) u_n(x_i),   k = 0..7.
+// The weights are the recursion's responses to unit inputs; agg_weights
+// computes them (by running the same recursions on e_i, one thread per i)
+// into LDS.  Per sample and channel this costs one multiply (the next power)
+// and eight FMAs instead of both recursions.  The channels are taken
+// unnormalised, p_n = exp(-x^2/2) x^n, and the end states are scaled by
+// 1/sqrt(n!) at the store; the powers stay in the FP32 range up to degree 47
+// (N <= 46), which the caller checks.
+// wts: (B + 3) * 8 floats, wts[i * 8 + k]; the workgroup's threads share
+// the 4 (B + 3) responses (position i, section s, direction).
+template <int B>
+__device__ __forceinline__ void agg_weights(const IirCoef &c, float *wts) {
+    for (int task = threadIdx.x; task < 4 * (B + 3); task += blockDim.x) {
+        const int i = task % (B + 3), s = (task / (B + 3)) & 1, anti = task / (2 * (B + 3));
+        if (!anti) {
+            // causal: inputs rows a-1 (i = 0) .. a+B-1 (i = B)
+            float y1 = 0.f, y2 = 0.f, xp = i == 0 ? 1.f : 0.f;
+            for (int j = 0; j < B; ++j) {
+                const float v = (j + 1 == i) ? 1.f : 0.f;
+                const float b = fmaf(c.n0[s], v, fmaf(c.n1[s], xp, -c.d2[s] * y2));
+                const float y = fmaf(-c.d1[s], y1, b);
+                y2 = y1;
+                y1 = y;
+                xp = v;
+            }
+            wts[i * 8 + 2 * s] = y1;
+            wts[i * 8 + 2 * s + 1] = y2;
+        } else {
+            // anticausal: inputs rows a+1 (i = 2) .. a+B+1 (i = B+2)
+            float z1 = 0.f, z2 = 0.f;
+            float xn1 = (B + 1 == i) ? 1.f : 0.f, xn2 = (B + 2 == i) ? 1.f : 0.f;
+            for (int j = B - 1; j >= 0; --j) {
+                const float b = fmaf(c.m1[s], xn1, fmaf(c.m2[s], xn2, -c.d2[s] * z2));
+                const float z = fmaf(-c.d1[s], z1, b);
+                z2 = z1;
+                z1 = z;
+                xn2 = xn1;
+                xn1 = (j + 1 == i) ? 1.f : 0.f;
+            }
+            wts[i * 8 + 4 + 2 * s] = z1;
+            wts[i * 8 + 5 + 2 * s] = z2;
+        }
+    }
+}
+
+// Prologue of vagg_moments for the band's rows a-1 .. a+B+1 of one column
+// group: the centred intensity x and exp(-x^2/2) (times the power-of-two
+// shift of big_shift(x) when BIG) of rows r = g0, g0 + G, ... into pro
+// (pro[r * 64 + lane] and pro[(B + 3 + r) * 64 + lane]), zeros for rows
+// outside the image.  The G waves of a band each store their share.
+template <int B, bool BIG>
+__device__ __forceinline__ void vagg_prologue(const GPParams &p, const Stats &st, int col, int band, int g0, int G,
+                                              float *pro) {
+    const int lane = threadIdx.x & 63;
+    const int a = band * B;
+    const int colc = col < p.W ? col : p.W - 1;
+    constexpr int NR = B + 3, CH = 6;
+    for (int r0 = g0; r0 < NR; r0 += CH * G) {
+        float f[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int r = r0 + k * G;
+            const int row = a - 1 + (r < NR ? r : NR - 1);
+            const int rc = row < 0 ? 0 : (row >= p.H ? p.H - 1 : row);
+            f[k] = p.img[(size_t)rc * p.pitch + colc];
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int r = r0 + k * G;
+            if (r < NR) {
+                const int row = a - 1 + r;
+                const bool in = row >= 0 && row < p.H;
+                const float x = in ? centred(f[k], st, p.inv_sigma_r) : 0.f;
+                pro[r * 64 + lane] = x;
+                pro[(NR + r) * 64 + lane] = in ? gauss_u0(x, BIG ? big_shift(x) : 0) : 0.f;
+            }
+        }
+    }
+}
+
+// End states of one band of B rows in one column for the channels g, g + G,
+// g + 2 G, ... < C (at most MAXG of them), by weighted sums, into carry (the
+// layout of vband), from the band's prologue in pro (vagg_prologue).  The
+// powers advance by x^G per channel.
+// BIG: exp(-x^2/2) leaves the FP32 range (|x| > 12): it is carried with the
+// per-sample power-of-two shift of vband, and every term is unscaled before
+// it is accumulated (the channel values themselves are in range where they
+// matter, as in the recursion).
+template <int B, int MAXG, bool BIG>
+__device__ __forceinline__ void vagg_moments(const GPParams &p, int col, int band, float *__restrict__ carry, int g,
+                                             int G, const float *wts, const float *pro) {
+    const int lane = threadIdx.x & 63;
+    const int ng = (p.C - g + G - 1) / G;
+    float acc[MAXG][8];
+#pragma unroll
+    for (int n = 0; n < MAXG; ++n)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[n][k] = 0.f;
+    constexpr int NR = B + 3;
+    // the next sample's prologue and weights are read one step ahead
+    float xn = pro[lane], gn = pro[NR * 64 + lane];
+    float4 w0n = *(const float4 *)wts, w1n = *(const float4 *)(wts + 4);
+#pragma unroll 1
+    for (int i = 0; i < NR; ++i) {
+        const float x = xn, g0 = gn;
+        const float4 w0 = w0n, w1 = w1n;
+        const int in = i + 1 < NR ? i + 1 : i;
+        xn = pro[in * 64 + lane];
+        gn = pro[(NR + in) * 64 + lane];
+        w0n = *(const float4 *)(wts + in * 8);
+        w1n = *(const float4 *)(wts + in * 8 + 4);
+        const int sh = BIG ? big_shift(x) : 0;
+        // exp(-x^2/2) x^g and the step x^G (g < G <= 4, uniform)
+        float pw = g0, xg = x;
+        for (int e = 0; e < g; ++e) pw *= x;
+        for (int e = 1; e < G; ++e) xg *= x;
+#pragma unroll
+        for (int n = 0; n < MAXG; ++n) {
+            if (n < ng) {
+                const float v = BIG ? ldexpf(pw, -sh) : pw;
+                acc[n][0] = fmaf(w0.x, v, acc[n][0]);
+                acc[n][1] = fmaf(w0.y, v, acc[n][1]);
+                acc[n][2] = fmaf(w0.z, v, acc[n][2]);
+                acc[n][3] = fmaf(w0.w, v, acc[n][3]);
+                acc[n][4] = fmaf(w1.x, v, acc[n][4]);
+                acc[n][5] = fmaf(w1.y, v, acc[n][5]);
+                acc[n][6] = fmaf(w1.z, v, acc[n][6]);
+                acc[n][7] = fmaf(w1.w, v, acc[n][7]);
+                pw *= xg;
+            }
+        }
+    }
+    if (col >= p.W) return;
+    // 1/sqrt(n!) for n = g, then over G factors per channel
+    double kap = 1.0;
+    for (int j = 2; j <= g; ++j) kap *= p.isq[j];
+    const size_t cstride = (size_t)p.W;
+#pragma unroll
+    for (int m = 0; m < MAXG; ++m) {
+        if (m < ng) {
+            const int n = g + m * G;
+            const float kf = (float)kap;
+            float *cp = carry + ((size_t)(band * p.C + n) * 8) * cstride + col;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) cp[k * cstride] = acc[m][k] * kf;
+            for (int j = 1; j <= G; ++j) kap *= p.isq[n + j];
+        }
+    }
+}
+
+// Channel groups of the weighted-sum end states for an image: 2 (the two
+// waves of a band take the even and the odd channels) when the image gives
+// at least kTargetAggWaves waves that way and C <= 2 kAggG, else 4.  Depends on
+// the image size and channel count only, so that single and batched calls
+// group alike (the grouping decides the rounding of the powers).
+constexpr long kTargetAggWaves = 2048;
+__host__ __device__ inline int agg_groups(int H, int W, int C) {
+    const long bands = (long)((W + 63) / 64) * ((H + 31) / 32);
+    return (2 * bands >= kTargetAggWaves && C <= 2 * kAggG) ? 2 : 4;
+}
+
+// LDS floats of one workgroup (four waves) of the weighted-sum end states:
+// the weights and one prologue per band it holds.
+__host__ __device__ constexpr int vagg_smem_floats(int B, int G) { return (B + 3) * 8 + (4 / G) * 2 * (B + 3) * 64; }
 
 // Resolves, for one (column, channel) and one direction (dir 0 causal, top to
 // bottom; dir 1 anticausal, bottom to top), the true incoming states of every

@@ -115,6 +115,44 @@ __global__ __launch_bounds__(512, 3) void k_vbandg(GPParams p, IirCoef c, float 
                                                   groups, grp);
 }
 
+// Band end states by weighted sums (vagg_moments): four waves per
+// workgroup, 4 / G bands (64-column group and band of 32 rows), the G waves of
+// a band taking the channels g, g + G, ... (g = 0..G-1) and sharing its prologue
+// through LDS; the
+// workgroup computes the weight table in LDS.  Images whose range needs the
+// per-sample shift (xmax > 12) take the BIG branch, uniform over the launch.
+// The first kernel after the statistics pass: it reduces the partials itself.
+template <int B, int G>
+__global__ __launch_bounds__(256) void k_vagg(GPParams p, IirCoef c, float *carry, int cgr) {
+    __shared__ float sm[vagg_smem_floats(B, G)];
+    float *wts = sm;
+    const Stats st = reduce_stats(p);
+    if (blockIdx.x == 0 && threadIdx.x == 0) publish_stats(p, st);
+    if (!st.ok) return;  // uniform over the launch
+    agg_weights<B>(c, wts);
+    const int nb = (p.H + B - 1) / B;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int pr = wave / G, gw = wave % G;
+    const int pair = blockIdx.x * (4 / G) + pr;
+    const bool live = pair < cgr * nb;
+    const int cg = pair % cgr, band = pair / cgr;
+    const int col = cg * 64 + (threadIdx.x & 63);
+    float *pro = sm + (B + 3) * 8 + pr * 2 * (B + 3) * 64;
+    const bool big = st.xmax > 12.0;
+    if (live) {
+        if (big)
+            vagg_prologue<B, true>(p, st, col, band, gw, G, pro);
+        else
+            vagg_prologue<B, false>(p, st, col, band, gw, G, pro);
+    }
+    __syncthreads();
+    if (!live) return;
+    if (big)
+        vagg_moments<B, kAggG, true>(p, col, band, carry, gw, G, wts, pro);
+    else
+        vagg_moments<B, kAggG, false>(p, col, band, carry, gw, G, wts, pro);
+}
+
 __global__ __launch_bounds__(64) void k_vresolve(GPParams p, IirCoef c, int nb, float *carry) {
     const int col = blockIdx.x * 64 + threadIdx.x;
     if (col < p.W) vresolve(p, c, nb, col, blockIdx.y, blockIdx.z, carry);
@@ -350,7 +388,16 @@ hipError_t launch_iir(const GPParams &p, const IirCoef &c, const RowCoef &rc, co
     // passes spill registers and measured slower)
     const bool grouped = !joint && sh.B == 32 && sh.G >= 2 && sh.G <= 8;
     hipError_t e = hipSuccess;
-    if (grouped)
+    if (!joint && sh.B == 32 && p.C <= kAggMaxC) {
+        // end states by weighted sums, 2 or 4 channel groups per band
+        const int G = agg_groups(p.H, p.W, p.C);
+        const long bands = (long)cgr * nb;
+        if (G == 2)
+            BF_LAUNCH("k_vband_agg", (k_vagg<32, 2>), dim3((unsigned)((bands + 1) / 2)), dim3(256), 0, s, p, c, carry,
+                      cgr);
+        else
+            BF_LAUNCH("k_vband_agg", (k_vagg<32, 4>), dim3((unsigned)bands), dim3(256), 0, s, p, c, carry, cgr);
+    } else if (grouped)
         e = vbandg_launch<true>(p, c, sh, carry, S, cgr, cgp, s);
     else if (sh.B == 64)
         vband_launch<64, true>(p, c, sh, ga, carry, S, cgr, cgp, joint, s);
