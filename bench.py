@@ -359,8 +359,29 @@ def main():
             fws = bf.workspace(H_, W_, DEGREE, ss_g, mode)
             bws = bf.backward_workspace(H_, W_, DEGREE, ss_g, mode)
             flags = bf._flags(mode)
+            # the stacked calls: every stage one launch over the 16 images
+            sfws = torch.empty(bf.bf_gp_forward_stacked_workspace_bytes(B_, H_, W_, DEGREE, ss_g, flags),
+                               dtype=torch.uint8, device=dev)
+            sbws = torch.empty(bf.bf_gp_backward_stacked_workspace_bytes(B_, H_, W_, DEGREE, ss_g, flags),
+                               dtype=torch.uint8, device=dev)
 
             def fwd_bwd():
+                bf._check(bf.bf_gp_forward_stacked(gimgs.data_ptr(), fout.data_ptr(), B_, H_, W_, W_, H_ * W_, ss_g,
+                                                   sr_g, DEGREE, flags, saved.data_ptr(), sfws.data_ptr(),
+                                                   sfws.numel(), stream), "stacked forward")
+                torch.sub(fout, tgt, out=gout)
+                bf._check(bf.bf_gp_backward_stacked(gimgs.data_ptr(), gout.data_ptr(), saved.data_ptr(), B_, H_, W_,
+                                                    W_, H_ * W_, ss_g, sr_g, DEGREE, flags, gimg.data_ptr(),
+                                                    gls.data_ptr(), glr.data_ptr(), sbws.data_ptr(), sbws.numel(),
+                                                    stream), "stacked backward")
+
+            def fwd_only():
+                bf._check(bf.bf_gp_forward_stacked(gimgs.data_ptr(), fout.data_ptr(), B_, H_, W_, W_, H_ * W_, ss_g,
+                                                   sr_g, DEGREE, flags, None, sfws.data_ptr(), sfws.numel(), stream),
+                          "stacked forward")
+
+            # the same work as 16 single-image calls of each pass
+            def fwd_bwd_single():
                 for i in range(B_):
                     bf.gp_forward(gimgs[i], ss_g, sr_g, DEGREE, spatial=mode, out=fout[i], ws=fws, saved=saved[i])
                     torch.sub(fout[i], tgt, out=gout[i])
@@ -369,17 +390,16 @@ def main():
                                                 gls[i:].data_ptr(), glr[i:].data_ptr(), bws.data_ptr(), bws.numel(),
                                                 stream), "backward")
 
-            def fwd_only():
-                for i in range(B_):
-                    bf.gp_forward(gimgs[i], ss_g, sr_g, DEGREE, spatial=mode, out=fout[i], ws=fws)
-
+            ms_single = timed(fwd_bwd_single, K, Wm, torch)
             ms_fb = timed(fwd_bwd, K, Wm, torch)
             ms_f = timed(fwd_only, K, Wm, torch)
             modes[key] = {"ms": ms_fb, "mpix_s": npx / (ms_fb * 1e-3) / 1e6, "fwd_only_ms": ms_f,
-                          "fwd_only_mpix_s": npx / (ms_f * 1e-3) / 1e6, "plan": mode, "sigma_s": ss_g,
+                          "fwd_only_mpix_s": npx / (ms_f * 1e-3) / 1e6, "ms_single_image_calls": ms_single,
+                          "plan": mode, "sigma_s": ss_g, "launches": "stacked (one per stage over the 16 images)",
                           "grad_log_sigma_s_sum": float(gls.sum()), "grad_log_sigma_r_sum": float(glr.sum())}
-            log(f"fwd+bwd {mode} sigma_s {ss_g}: {ms_fb:.3f} ms (fwd only {ms_f:.3f} ms)")
-            del fws, bws
+            log(f"fwd+bwd {mode} sigma_s {ss_g}: {ms_fb:.3f} ms stacked (fwd only {ms_f:.3f} ms), "
+                f"{ms_single:.3f} ms as single-image calls")
+            del fws, bws, sfws, sbws
 
     # ---------------- joint (cross) filter: 1024^2, guide and data images ----------------
     if want("joint"):

@@ -264,6 +264,33 @@ int bf_gp_backward(const float *img, const float *grad_out, const void *saved,
                    unsigned flags, float *grad_img, double *grad_log_sigma_s,
                    double *grad_log_sigma_r, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- stacked batch: forward with saved terms and backward --------------------
+ * B images of one size H x W filtered with one (sigma_s, sigma_r, N) and one
+ * spatial mode (a training batch): Algorithm 1 per image, its backward as
+ * bf_gp_backward, every stage one launch over all B images.  Image b is at
+ * img + b * img_stride (elements); out, grad_out and grad_img use the same
+ * stride and pitch; saved holds B blocks of 16 H W bytes (image b's block at
+ * saved + b * 16 H W).  Every image's outputs and gradients equal those of a
+ * single bf_gp_forward / bf_gp_backward call on it bit for bit.
+ *  img_stride   >= H * pitch; the image, output and gradient batches must not
+ *               overlap (BF_EINVAL).
+ *  ws           device workspace of at least the *_stacked_workspace_bytes.
+ *  grad_log_sigma_s, grad_log_sigma_r
+ *               device arrays of B doubles (nullable): the scalar gradients of
+ *               each image, as bf_gp_backward gives them (sum them for a
+ *               shared parameter).
+ * FIR and IIR modes (BOX returns BF_EUNSUPPORTED); the same width limits and
+ * error behaviour as the single-image calls. */
+size_t bf_gp_forward_stacked_workspace_bytes(int B, int H, int W, int N, double sigma_s, unsigned flags);
+int bf_gp_forward_stacked(const float *img, float *out, int B, int H, int W, int pitch, size_t img_stride,
+                          double sigma_s, double sigma_r, int N, unsigned flags, void *saved,
+                          void *ws, size_t ws_bytes, void *stream);
+size_t bf_gp_backward_stacked_workspace_bytes(int B, int H, int W, int N, double sigma_s, unsigned flags);
+int bf_gp_backward_stacked(const float *img, const float *grad_out, const void *saved, int B, int H, int W,
+                           int pitch, size_t img_stride, double sigma_s, double sigma_r, int N,
+                           unsigned flags, float *grad_img, double *grad_log_sigma_s,
+                           double *grad_log_sigma_r, void *ws, size_t ws_bytes, void *stream);
+
 /* ---- batched GP forward ---------------------------------------------------
  * Many images of uneven size, each with its own sigma_s and sigma_r (Algorithm 1
  * applied per image), filtered by one short sequence of grouped launches: one

@@ -68,6 +68,12 @@ bf_gp_set_iir_tuning = _sig("bf_gp_set_iir_tuning", _i, _i, _i, _i)
 bf_gp_iir_shape = _sig("bf_gp_iir_shape", _i, _i, _i, _i, ctypes.POINTER(_i))
 bf_gp_backward_workspace_bytes = _sig("bf_gp_backward_workspace_bytes", _sz, _i, _i, _i, _d, _u)
 bf_gp_backward = _sig("bf_gp_backward", _i, _vp, _vp, _vp, _i, _i, _i, _d, _d, _i, _u, _vp, _vp, _vp, _vp, _sz, _vp)
+bf_gp_forward_stacked_workspace_bytes = _sig("bf_gp_forward_stacked_workspace_bytes", _sz, _i, _i, _i, _i, _d, _u)
+bf_gp_forward_stacked = _sig("bf_gp_forward_stacked", _i, _vp, _vp, _i, _i, _i, _i, _sz, _d, _d, _i, _u, _vp, _vp,
+                             _sz, _vp)
+bf_gp_backward_stacked_workspace_bytes = _sig("bf_gp_backward_stacked_workspace_bytes", _sz, _i, _i, _i, _i, _d, _u)
+bf_gp_backward_stacked = _sig("bf_gp_backward_stacked", _i, _vp, _vp, _vp, _i, _i, _i, _i, _sz, _d, _d, _i, _u, _vp,
+                              _vp, _vp, _vp, _sz, _vp)
 bf_gp_plan_batched = _sig("bf_gp_plan_batched", _i, ctypes.POINTER(BfGpItem), _i, _u, ctypes.POINTER(_vp))
 bf_gp_plan_workspace_bytes = _sig("bf_gp_plan_workspace_bytes", _sz, _vp)
 bf_gp_plan_upload = _sig("bf_gp_plan_upload", _i, _vp, _vp, _sz, _vp)
@@ -107,6 +113,13 @@ def _image(t, name="img"):
     if t.stride(1) != 1:
         raise ValueError(f"{name} must have unit column stride")
     return t.shape[0], t.shape[1], t.stride(0)
+
+
+def _like(t):
+    """An uninitialised tensor with t's shape and strides (the kernels write
+    outputs with the input's pitch; torch.empty_like makes a padded view
+    contiguous)."""
+    return torch.empty_strided(t.shape, t.stride(), dtype=t.dtype, device=t.device)
 
 
 def fir_radius(sigma_s):
@@ -161,7 +174,7 @@ def gp_forward(img, sigma_s, sigma_r, N=20, spatial="auto", center="mean", out=N
     ``check=True`` the call synchronises and raises on BF_ERANGE."""
     H, W, pitch = _image(img)
     if out is None:
-        out = torch.empty_like(img)
+        out = _like(img)
     else:
         oh, ow, opitch = _image(out, "out")
         if (oh, ow, opitch) != (H, W, pitch):
@@ -190,7 +203,7 @@ def gp_forward_noalloc(img, sigma_s, sigma_r, N=20, spatial="auto", center="mean
     ``out`` (and ``saved``) must be given by callers that cannot allocate."""
     H, W, pitch = _image(img)
     if out is None:
-        out = torch.empty_like(img)
+        out = _like(img)
     else:
         oh, ow, opitch = _image(out, "out")
         if (oh, ow, opitch) != (H, W, pitch):
@@ -220,7 +233,7 @@ def gp_joint_forward(guide, data, sigma_s, sigma_r, N=20, spatial="auto", center
     if (dh, dw, dp) != (H, W, pitch):
         raise ValueError("data must have the shape and row stride of the guide")
     if out is None:
-        out = torch.empty_like(guide)
+        out = _like(guide)
     else:
         oh, ow, opitch = _image(out, "out")
         if (oh, ow, opitch) != (H, W, pitch):
@@ -253,7 +266,7 @@ def gp_volume_forward(vol, sigma_s, sigma_t, sigma_r, N=20, spatial="auto", cent
         raise ValueError("vol must be a contiguous float32 CUDA tensor (T, H, W)")
     T, H, W = vol.shape
     if out is None:
-        out = torch.empty_like(vol)
+        out = _like(vol)
     elif out.shape != vol.shape or out.dtype != torch.float32 or not out.is_contiguous():
         raise ValueError("out must be a contiguous float32 tensor shaped like vol")
     flags = _flags(spatial, center)
@@ -289,7 +302,7 @@ def direct_forward(img, sigma_s, sigma_r, window=-1, out=None):
     """Eq. (1) evaluated directly on the GPU (the O(sigma_s^2) comparator)."""
     H, W, pitch = _image(img)
     if out is None:
-        out = torch.empty_like(img)
+        out = _like(img)
     _check(bf_direct_forward(img.data_ptr(), out.data_ptr(), H, W, pitch, float(sigma_s), float(sigma_r), int(window),
                              _stream(img.device)), "bf_direct_forward")
     return out
@@ -358,7 +371,7 @@ def gp_backward(img, grad_out, saved, sigma_s, sigma_r, N=20, spatial="auto", ce
     gh, gw, gp = _image(grad_out, "grad_out")
     if (gh, gw, gp) != (H, W, pitch):
         raise ValueError("grad_out must have the shape and row stride of img")
-    gi = torch.empty_like(img) if grad_img else None
+    gi = _like(img) if grad_img else None
     gs = torch.zeros(1, dtype=torch.float64, device=img.device)
     gr = torch.zeros(1, dtype=torch.float64, device=img.device)
     if ws is None:
@@ -370,29 +383,87 @@ def gp_backward(img, grad_out, saved, sigma_s, sigma_r, N=20, spatial="auto", ce
     return gi, gs, gr
 
 
+def _stack(t, name="img"):
+    """(B, H, W) float32 CUDA tensor with unit column stride: (B, H, W, pitch, image stride)."""
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float32 CUDA tensor")
+    if t.dim() != 3:
+        raise ValueError(f"{name} must be 3-D (B, H, W)")
+    if t.stride(2) != 1:
+        raise ValueError(f"{name} must have unit column stride")
+    B, H, W = t.shape
+    return B, H, W, t.stride(1), t.stride(0) if B > 1 else H * t.stride(1)
+
+
+def gp_forward_stacked(imgs, sigma_s, sigma_r, N=20, spatial="auto", center="mean", out=None, saved=None, ws=None):
+    """GP filter of B images of one size (B, H, W) with one (sigma_s, sigma_r, N), one launch per stage over all
+    images (bf_gp_forward_stacked); each image's output equals a single gp_forward call's.  ``saved`` (uint8 CUDA
+    tensor of B * 16 * H * W bytes) receives what ``gp_backward_stacked`` needs."""
+    B, H, W, pitch, stride = _stack(imgs)
+    if out is None:
+        out = _like(imgs)
+    elif _stack(out, "out") != (B, H, W, pitch, stride):
+        raise ValueError("out must have the shape and strides of imgs")
+    flags = _flags(spatial, center)
+    if ws is None:
+        n = int(bf_gp_forward_stacked_workspace_bytes(B, H, W, int(N), float(sigma_s), flags))
+        ws = torch.empty(max(n, 256), dtype=torch.uint8, device=imgs.device)
+    sp = None
+    if saved is not None:
+        if saved.numel() * saved.element_size() < 16 * B * H * W:
+            raise ValueError("saved buffer too small")
+        sp = saved.data_ptr()
+    _check(bf_gp_forward_stacked(imgs.data_ptr(), out.data_ptr(), B, H, W, pitch, stride, float(sigma_s),
+                                 float(sigma_r), int(N), flags, sp, ws.data_ptr(), ws.numel(), _stream(imgs.device)),
+           "bf_gp_forward_stacked")
+    return out
+
+
+def gp_backward_stacked(imgs, grad_out, saved, sigma_s, sigma_r, N=20, spatial="auto", center="mean",
+                        grad_img=True, ws=None):
+    """Adjoint of gp_forward_stacked (bf_gp_backward_stacked).  Returns (dL/dimgs or None, dL/dlog sigma_s,
+    dL/dlog sigma_r) with the scalar gradients per image as float64 CUDA tensors of shape (B,)."""
+    B, H, W, pitch, stride = _stack(imgs)
+    if _stack(grad_out, "grad_out") != (B, H, W, pitch, stride):
+        raise ValueError("grad_out must have the shape and strides of imgs")
+    gi = _like(imgs) if grad_img else None
+    gs = torch.zeros(B, dtype=torch.float64, device=imgs.device)
+    gr = torch.zeros(B, dtype=torch.float64, device=imgs.device)
+    flags = _flags(spatial, center)
+    if ws is None:
+        n = int(bf_gp_backward_stacked_workspace_bytes(B, H, W, int(N), float(sigma_s), flags))
+        ws = torch.empty(max(n, 256), dtype=torch.uint8, device=imgs.device)
+    _check(bf_gp_backward_stacked(imgs.data_ptr(), grad_out.data_ptr(), saved.data_ptr(), B, H, W, pitch, stride,
+                                  float(sigma_s), float(sigma_r), int(N), flags,
+                                  gi.data_ptr() if gi is not None else None, gs.data_ptr(), gr.data_ptr(),
+                                  ws.data_ptr(), ws.numel(), _stream(imgs.device)), "bf_gp_backward_stacked")
+    return gi, gs, gr
+
+
 class GPFilterFn(torch.autograd.Function):
     """GP bilateral filter with learnable log sigma_s and log sigma_r.
 
     forward(img (H, W) or (B, H, W) float32 CUDA, log_ss, log_sr, N, spatial, center).
-    Both passes run in the library's kernels.  The spatial mode is resolved
+    Both passes run in the library's kernels, a batch as one launch per stage
+    over all its images (the stacked calls).  The spatial mode is resolved
     once per call (AUTO: by image size and sigma_s) and used by both passes;
     in the FIR mode the radius ceil(3 sigma_s) is held fixed when
     differentiating in sigma_s, in the IIR mode the recursive kernel is
     differentiated exactly.  The sigmas are read on the host (one
-    device-to-host copy when they are tensors)."""
+    device-to-host copy when they are tensors); their gradients are the sums
+    of the per-image ones."""
 
     @staticmethod
     def forward(ctx, img, log_ss, log_sr, N=20, spatial="auto", center="mean"):
         ss = math.exp(float(log_ss))
         sr = math.exp(float(log_sr))
         batch = img if img.dim() == 3 else img.unsqueeze(0)
+        if batch.stride(2) != 1:
+            batch = batch.contiguous()
         B, H, W = batch.shape
         spatial = resolve_spatial(ss, spatial, shape=(H, W))
-        out = torch.empty_like(batch)
         saved = torch.empty(B, 16 * H * W, dtype=torch.uint8, device=img.device)
-        ws = workspace(H, W, N, ss, spatial, img.device)
-        for i in range(B):
-            gp_forward(batch[i], ss, sr, N, spatial=spatial, center=center, out=out[i], ws=ws, saved=saved[i])
+        out = gp_forward_stacked(batch, ss, sr, N, spatial=spatial, center=center, saved=saved)
         ctx.save_for_backward(batch, saved)
         shp = lambda v: (v.shape, v.dtype) if isinstance(v, torch.Tensor) else None
         ctx.params = (ss, sr, int(N), spatial, center, img.dim(), shp(log_ss), shp(log_sr))
@@ -402,21 +473,13 @@ class GPFilterFn(torch.autograd.Function):
     def backward(ctx, grad_out):
         batch, saved = ctx.saved_tensors
         ss, sr, N, spatial, center, dim, t_ss, t_sr = ctx.params
-        g = grad_out.contiguous()
-        g = g if g.dim() == 3 else g.unsqueeze(0)
-        B, H, W = batch.shape
-        gimg = torch.empty_like(batch)
-        gls = torch.zeros((), dtype=torch.float64, device=batch.device)
-        glr = torch.zeros((), dtype=torch.float64, device=batch.device)
-        ws = backward_workspace(H, W, N, ss, spatial, batch.device)
-        for i in range(B):
-            gi, gs, gr = gp_backward(batch[i], g[i], saved[i], ss, sr, N, spatial, center, ws=ws)
-            gimg[i] = gi
-            gls = gls + gs[0]
-            glr = glr + gr[0]
+        g = grad_out if grad_out.dim() == 3 else grad_out.unsqueeze(0)
+        if g.stride() != batch.stride():
+            g = _like(batch).copy_(g)
+        gimg, gs, gr = gp_backward_stacked(batch, g, saved, ss, sr, N, spatial, center)
         gimg = gimg if dim == 3 else gimg[0]
-        gss = gls.to(t_ss[1]).reshape(t_ss[0]) if t_ss else None
-        gsr = glr.to(t_sr[1]).reshape(t_sr[0]) if t_sr else None
+        gss = gs.sum().to(t_ss[1]).reshape(t_ss[0]) if t_ss else None
+        gsr = gr.sum().to(t_sr[1]).reshape(t_sr[0]) if t_sr else None
         return gimg, gss, gsr, None, None, None
 
 
@@ -443,7 +506,7 @@ class BatchPlan:
         if not (len(sigmas_s) == len(sigmas_r) == n) or n == 0:
             raise ValueError("one sigma_s and one sigma_r per image")
         self.imgs = list(imgs)
-        self.outs = list(outs) if outs is not None else [torch.empty_like(x) for x in self.imgs]
+        self.outs = list(outs) if outs is not None else [_like(x) for x in self.imgs]
         items = (BfGpItem * n)()
         for i, (x, o) in enumerate(zip(self.imgs, self.outs)):
             H, W, pitch = _image(x)

@@ -813,9 +813,9 @@ size_t bf_gp_backward_workspace_bytes(int H, int W, int N, double sigma_s, unsig
     return bwd_layout(H, W, N, spatial).total;
 }
 
-int bf_gp_backward(const float *img, const float *grad_out, const void *saved, int H, int W, int pitch,
-                   double sigma_s, double sigma_r, int N, unsigned flags, float *grad_img, double *grad_log_sigma_s,
-                   double *grad_log_sigma_r, void *ws, size_t ws_bytes, void *stream) {
+static int bwd_check(const float *img, const float *grad_out, const void *saved, int H, int W, int pitch,
+                     double sigma_s, double sigma_r, int N, unsigned flags, const float *grad_img, const void *ws,
+                     unsigned *spatial_out) {
     int rc;
     if ((rc = check_image(img, grad_out, H, W, pitch))) return rc;
     if ((rc = check_params(sigma_s, sigma_r, N))) return rc;
@@ -830,6 +830,56 @@ int bf_gp_backward(const float *img, const float *grad_out, const void *saved, i
         return fail(BF_EUNSUPPORTED, "the backward pass supports the mean centre or no centring");
     if (grad_img && ((const void *)grad_img == (const void *)img || (const void *)grad_img == (const void *)grad_out))
         return fail(BF_EINVAL, "grad_img must not alias img or grad_out");
+    *spatial_out = spatial;
+    return BF_OK;
+}
+
+// The IIR backward's buffers and channel groups for image buffers at the given
+// pointers and the workspace layout L at w.
+static BwdIir bwd_iir_args(const float *grad_out, const void *saved, float *grad_img, char *w, const BwdLayout &L,
+                           int H, int W, int N) {
+    const size_t npx = (size_t)H * W;
+    BwdIir b;
+    memset(&b, 0, sizeof b);
+    b.grad_out = grad_out;
+    b.rho = (const float *)saved;
+    b.drho = (const float *)saved + npx;
+    b.Dp = (const double *)((const float *)saved + 2 * npx);
+    b.grad_img = grad_img;
+    b.cv = (float *)(w + L.cv);
+    b.PT = (float *)(w + L.pt);
+    b.QT = (float *)(w + L.qt);
+    b.chz = (float *)(w + L.chz);
+    b.bparts = (BwdPartial *)(w + L.bparts);
+    b.Hp = L.Hp;
+    bwd_iir_groups(H, W, N + 2, &b.Gv, &b.Gh);
+    // the tuning overrides of the column and row channel groups apply here too
+    if (g_col_groups.load() > 0) b.Gv = g_col_groups.load() < N + 2 ? g_col_groups.load() : N + 2;
+    if (g_row_groups.load() > 0) {
+        const int gr = g_row_groups.load() < 4 ? g_row_groups.load() : 4;
+        b.Gh = gr < N + 2 ? gr : N + 2;
+    }
+    return b;
+}
+
+static FirTaps2 bwd_taps(double sigma_s, int R) {
+    FirTaps2 t;
+    memset(&t, 0, sizeof t);
+    for (int d = 0; d <= R; ++d) {
+        const double q = (double)d * d / (sigma_s * sigma_s);
+        t.k[d] = (float)exp(-0.5 * q);
+        t.kt[d] = (float)(q * exp(-0.5 * q));
+    }
+    return t;
+}
+
+int bf_gp_backward(const float *img, const float *grad_out, const void *saved, int H, int W, int pitch,
+                   double sigma_s, double sigma_r, int N, unsigned flags, float *grad_img, double *grad_log_sigma_s,
+                   double *grad_log_sigma_r, void *ws, size_t ws_bytes, void *stream) {
+    int rc;
+    unsigned spatial = 0;
+    if ((rc = bwd_check(img, grad_out, saved, H, W, pitch, sigma_s, sigma_r, N, flags, grad_img, ws, &spatial)))
+        return rc;
     const BwdLayout L = bwd_layout(H, W, N, spatial);
     if (ws_bytes < L.total) return fail(BF_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
     hipStream_t s = (hipStream_t)stream;
@@ -842,45 +892,137 @@ int bf_gp_backward(const float *img, const float *grad_out, const void *saved, i
     hipError_t e = launch_stats(p, true, s);
     if (e != hipSuccess) return hip_fail(e, "statistics launch");
     if (spatial == BF_SPATIAL_IIR) {
-        const size_t npx = (size_t)H * W;
-        BwdIir b;
-        memset(&b, 0, sizeof b);
-        b.grad_out = grad_out;
-        b.rho = (const float *)saved;
-        b.drho = (const float *)saved + npx;
-        b.Dp = (const double *)((const float *)saved + 2 * npx);
-        b.grad_img = grad_img;
-        b.cv = (float *)(w + L.cv);
-        b.PT = (float *)(w + L.pt);
-        b.QT = (float *)(w + L.qt);
-        b.chz = (float *)(w + L.chz);
-        b.bparts = (BwdPartial *)(w + L.bparts);
-        b.Hp = L.Hp;
-        bwd_iir_groups(H, W, N + 2, &b.Gv, &b.Gh);
-        // the tuning overrides of the column and row channel groups apply here too
-        if (g_col_groups.load() > 0) b.Gv = g_col_groups.load() < N + 2 ? g_col_groups.load() : N + 2;
-        if (g_row_groups.load() > 0) {
-            const int gr = g_row_groups.load() < 4 ? g_row_groups.load() : 4;
-            b.Gh = gr < N + 2 ? gr : N + 2;
-        }
+        const BwdIir b = bwd_iir_args(grad_out, saved, grad_img, w, L, H, W, N);
         e = launch_bwd_iir(p, b, make_iir_tan(sigma_s), (double *)(w + L.corr), grad_log_sigma_s, grad_log_sigma_r, s);
         if (e != hipSuccess) return hip_fail(e, "backward launch");
         return BF_OK;
     }
     const int R = fir_radius(sigma_s);
-    FirTaps2 t;
-    memset(&t, 0, sizeof t);
-    for (int d = 0; d <= R; ++d) {
-        const double q = (double)d * d / (sigma_s * sigma_s);
-        t.k[d] = (float)exp(-0.5 * q);
-        t.kt[d] = (float)(q * exp(-0.5 * q));
-    }
+    const FirTaps2 t = bwd_taps(sigma_s, R);
     BwdParams b;
     b.grad_out = grad_out;
     b.saved = (const float *)saved;
     b.grad_img = grad_img;
     b.bparts = (BwdPartial *)(w + L.bparts);
     e = launch_bwd(p, b, t, R, (double *)(w + L.corr), grad_log_sigma_s, grad_log_sigma_r, s);
+    if (e != hipSuccess) return hip_fail(e, "backward launch");
+    return BF_OK;
+}
+
+// ---- stacked batch --------------------------------------------------------------
+
+// Per-image workspace slice and descriptor block of a stacked call.
+static size_t stk_desc_bytes(int B) { return align256(sizeof(GPParams) * (size_t)B); }
+
+static int stk_check(int B, int H, int pitch, size_t img_stride, const void *a, const void *b) {
+    if (B < 1) return fail(BF_EINVAL, "batch of %d images", B);
+    if (img_stride < (size_t)H * (size_t)pitch) return fail(BF_EINVAL, "image stride smaller than an image");
+    if ((double)img_stride * B >= (double)((size_t)1 << 40)) return fail(BF_EINVAL, "batch too large");
+    // the two batches' element ranges must not overlap
+    if (a && b) {
+        const char *a0 = (const char *)a, *b0 = (const char *)b;
+        const size_t span = sizeof(float) * (img_stride * (size_t)(B - 1) + (size_t)H * pitch);
+        if (a0 < b0 + span && b0 < a0 + span) return fail(BF_EINVAL, "batches overlap");
+    }
+    return BF_OK;
+}
+
+size_t bf_gp_forward_stacked_workspace_bytes(int B, int H, int W, int N, double sigma_s, unsigned flags) {
+    if (B < 1 || H < 1 || W < 1 || N < 0 || N > BF_MAX_DEGREE || !finite_pos(sigma_s)) return 0;
+    const unsigned spatial = resolve_spatial((long long)H * W, sigma_s, flags);
+    if (spatial == BF_SPATIAL_BOX) return 0;
+    return stk_desc_bytes(B) + (size_t)B * align256(gp_layout(H, W, N, spatial).total);
+}
+
+int bf_gp_forward_stacked(const float *img, float *out, int B, int H, int W, int pitch, size_t img_stride,
+                          double sigma_s, double sigma_r, int N, unsigned flags, void *saved, void *ws,
+                          size_t ws_bytes, void *stream) {
+    int rc;
+    size_t need = 0;
+    if ((rc = gp_forward_check(img, out, H, W, pitch, sigma_s, sigma_r, N, flags, saved, &need))) return rc;
+    if ((rc = stk_check(B, H, pitch, img_stride, img, out))) return rc;
+    if (!ws) return fail(BF_EINVAL, "null workspace");
+    const unsigned spatial = resolve_spatial((long long)H * W, sigma_s, flags);
+    if (spatial == BF_SPATIAL_BOX) return fail(BF_EUNSUPPORTED, "the stacked path runs the FIR and IIR modes");
+    const Layout L = gp_layout(H, W, N, spatial);
+    const size_t slice = align256(L.total), total = stk_desc_bytes(B) + (size_t)B * slice;
+    if (ws_bytes < total) return fail(BF_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, total);
+    hipStream_t s = (hipStream_t)stream;
+    char *w0 = (char *)ws + stk_desc_bytes(B);
+    GPParams *pd = (GPParams *)ws;
+    const GPParams p0 = make_params(img, out, H, W, pitch, sigma_r, N, flags, w0, L, saved);
+    StkOfs o;
+    o.img = img_stride;
+    o.ws = slice;
+    o.saved = (size_t)16 * H * W;
+    o.B = B;
+    hipError_t e = launch_stk_setup(p0, o, pd, s);
+    if (e == hipSuccess) e = launch_stk_stats(p0, pd, o, false, s);
+    if (e != hipSuccess) return hip_fail(e, "statistics launch");
+    if (spatial == BF_SPATIAL_FIR) {
+        const int R = fir_radius(sigma_s);
+        e = launch_stk_fir(p0, pd, o, make_taps(sigma_s, R), R, saved != nullptr, s);
+        if (e != hipSuccess) return hip_fail(e, "FIR launch");
+    } else {
+        const IirShape sh = iir_shape(H, W, N + 2);
+        e = launch_stk_iir(p0, pd, o, make_iir(sigma_s, sh.B, sh.Lo), make_row_coef(sigma_s, sh.L), sh,
+                           (float *)(w0 + L.carry), (float *)(w0 + L.stack), saved != nullptr, s);
+        if (e != hipSuccess) return hip_fail(e, "IIR launch");
+    }
+    return BF_OK;
+}
+
+size_t bf_gp_backward_stacked_workspace_bytes(int B, int H, int W, int N, double sigma_s, unsigned flags) {
+    if (B < 1 || H < 1 || W < 1 || N < 0 || N > BF_MAX_DEGREE || !finite_pos(sigma_s)) return 0;
+    const unsigned spatial = resolve_spatial((long long)H * W, sigma_s, flags);
+    if (spatial == BF_SPATIAL_BOX) return 0;
+    return stk_desc_bytes(B) + align256(sizeof(double) * (size_t)B) +
+           (size_t)B * align256(bwd_layout(H, W, N, spatial).total);
+}
+
+int bf_gp_backward_stacked(const float *img, const float *grad_out, const void *saved, int B, int H, int W, int pitch,
+                           size_t img_stride, double sigma_s, double sigma_r, int N, unsigned flags, float *grad_img,
+                           double *grad_log_sigma_s, double *grad_log_sigma_r, void *ws, size_t ws_bytes,
+                           void *stream) {
+    int rc;
+    unsigned spatial = 0;
+    if ((rc = bwd_check(img, grad_out, saved, H, W, pitch, sigma_s, sigma_r, N, flags, grad_img, ws, &spatial)))
+        return rc;
+    if ((rc = stk_check(B, H, pitch, img_stride, img, grad_img))) return rc;
+    if ((rc = stk_check(B, H, pitch, img_stride, grad_out, grad_img))) return rc;
+    const BwdLayout L = bwd_layout(H, W, N, spatial);
+    const size_t slice = align256(L.total);
+    const size_t total = stk_desc_bytes(B) + align256(sizeof(double) * (size_t)B) + (size_t)B * slice;
+    if (ws_bytes < total) return fail(BF_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, total);
+    hipStream_t s = (hipStream_t)stream;
+    GPParams *pd = (GPParams *)ws;
+    double *corr = (double *)((char *)ws + stk_desc_bytes(B));
+    char *w0 = (char *)ws + stk_desc_bytes(B) + align256(sizeof(double) * (size_t)B);
+    Layout fl;
+    fl.parts = L.parts;
+    fl.status = L.status;
+    fl.stats = L.stats;
+    const GPParams p0 = make_params(img, nullptr, H, W, pitch, sigma_r, N, flags, w0, fl, const_cast<void *>(saved));
+    StkOfs o;
+    o.img = img_stride;
+    o.ws = slice;
+    o.saved = (size_t)16 * H * W;
+    o.B = B;
+    hipError_t e = launch_stk_setup(p0, o, pd, s);
+    if (e == hipSuccess) e = launch_stk_stats(p0, pd, o, true, s);
+    if (e != hipSuccess) return hip_fail(e, "statistics launch");
+    if (spatial == BF_SPATIAL_IIR) {
+        const BwdIir b = bwd_iir_args(grad_out, saved, grad_img, w0, L, H, W, N);
+        e = launch_stk_bwd_iir(p0, pd, b, o, make_iir_tan(sigma_s), corr, grad_log_sigma_s, grad_log_sigma_r, s);
+    } else {
+        const int R = fir_radius(sigma_s);
+        BwdParams b;
+        b.grad_out = grad_out;
+        b.saved = (const float *)saved;
+        b.grad_img = grad_img;
+        b.bparts = (BwdPartial *)(w0 + L.bparts);
+        e = launch_stk_bwd(p0, pd, b, o, bwd_taps(sigma_s, R), R, corr, grad_log_sigma_s, grad_log_sigma_r, s);
+    }
     if (e != hipSuccess) return hip_fail(e, "backward launch");
     return BF_OK;
 }

@@ -70,6 +70,28 @@ struct VolumeBuffers {
 hipError_t launch_volume(const GPParams &pz, const GPParams &ps, const IirCoef &ct, const IirCoef &cs,
                          const RowCoef &rcs, const IirShape &shz, const IirShape &shs, int T, const VolumeBuffers &vb,
                          hipStream_t s);
+// Stacked batch (B images of one size): image b at img + b * img elements
+// (image, output, gradients), workspace slice ws0 + b * ws bytes, saved terms
+// saved0 + b * saved bytes.
+struct StkOfs {
+    size_t img, ws, saved;
+    int B;
+};
+struct RowCoef;
+struct FirTaps2;
+struct BwdParams;
+struct BwdIir;
+struct IirTan;
+hipError_t launch_stk_setup(const GPParams &p0, const StkOfs &o, GPParams *pd, hipStream_t s);
+hipError_t launch_stk_stats(const GPParams &p0, const GPParams *pd, const StkOfs &o, bool final_kernel, hipStream_t s);
+hipError_t launch_stk_fir(const GPParams &p0, const GPParams *pd, const StkOfs &o, const FirTaps &t, int R, bool save,
+                          hipStream_t s);
+hipError_t launch_stk_iir(const GPParams &p0, const GPParams *pd, const StkOfs &o, const IirCoef &c,
+                          const RowCoef &rc, const IirShape &sh, float *carry, float *S, bool save, hipStream_t s);
+hipError_t launch_stk_bwd(const GPParams &p0, const GPParams *pd, const BwdParams &b, const StkOfs &o,
+                          const FirTaps2 &t, int R, double *corr, double *g_lss, double *g_lsr, hipStream_t s);
+hipError_t launch_stk_bwd_iir(const GPParams &p0, const GPParams *pd, const BwdIir &b, const StkOfs &o,
+                              const IirTan &c, double *corr, double *g_lss, double *g_lsr, hipStream_t s);
 int bwd_tiles(int H, int W);
 hipError_t launch_bwd(const GPParams &p, const BwdParams &b, const FirTaps2 &t, int R, double *corr, double *g_lss,
                       double *g_lsr, hipStream_t s);

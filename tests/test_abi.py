@@ -367,3 +367,43 @@ def test_noalloc_scratch_size_matches_the_header():
     text = open(HEADER).read()
     m = re.search(r"#define BF_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
     assert m and int(m.group(1)) << int(m.group(2)) == bf.NOALLOC_SCRATCH_BYTES
+
+
+def test_stacked_entry_points_check_on_the_host():
+    """The stacked forward and backward run the single-image checks on image 0,
+    then the batch's own: at least one image, a stride covering an image, no
+    overlap between the image, output and gradient batches, enough workspace."""
+    B, H, W = 4, 8, 8
+    stride = H * W
+    span = 4 * stride * B
+    img, out = FAKE, FAKE + span
+    ws = FAKE + 8 * span
+
+    def fwd(img=img, out=out, B=B, pitch=W, stride=stride, flags=0, saved=None, ws=ws, ws_bytes=1 << 30):
+        return bf.bf_gp_forward_stacked(img, out, B, H, W, pitch, stride, 2.0, 30.0, 20, flags, saved, ws, ws_bytes,
+                                        None)
+
+    assert fwd(B=0) == bf.BF_EINVAL
+    assert fwd(stride=H * W - 1) == bf.BF_EINVAL
+    assert fwd(out=img + 4 * stride) == bf.BF_EINVAL  # overlaps image 1
+    assert fwd(img=None) == bf.BF_EINVAL
+    assert fwd(ws=None) == bf.BF_EINVAL
+    assert fwd(flags=bf.SPATIAL["box"]) == bf.BF_EUNSUPPORTED
+    need = bf.bf_gp_forward_stacked_workspace_bytes(B, H, W, 20, 2.0, 0)
+    assert need >= B * bf.workspace_bytes(H, W, 20, 2.0)
+    assert fwd(ws_bytes=need - 1) == bf.BF_ENOMEM
+    assert bf.bf_gp_forward_stacked_workspace_bytes(0, H, W, 20, 2.0, 0) == 0
+
+    def bwd(img=img, gout=out, saved=FAKE + 4 * span, gimg=FAKE + 2 * span, B=B, stride=stride, flags=0, ws=ws,
+            ws_bytes=1 << 30):
+        return bf.bf_gp_backward_stacked(img, gout, saved, B, H, W, W, stride, 2.0, 30.0, 20, flags, gimg, None,
+                                         None, ws, ws_bytes, None)
+
+    assert bwd(B=0) == bf.BF_EINVAL
+    assert bwd(gimg=img + 4) == bf.BF_EINVAL
+    assert bwd(gimg=out + 4 * stride) == bf.BF_EINVAL
+    assert bwd(saved=None) == bf.BF_EINVAL
+    assert bwd(flags=bf.CENTER["midrange"]) == bf.BF_EUNSUPPORTED
+    bneed = bf.bf_gp_backward_stacked_workspace_bytes(B, H, W, 20, 2.0, 0)
+    assert bneed >= B * bf.bf_gp_backward_workspace_bytes(H, W, 20, 2.0, 0)
+    assert bwd(ws_bytes=bneed - 1) == bf.BF_ENOMEM
