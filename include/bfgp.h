@@ -90,8 +90,11 @@ const char *bf_last_error(void);
  *               every approximate weight positive; with odd N the denominator
  *               can vanish and the output is whatever the division gives.
  *  flags        BF_SPATIAL_* | BF_CENTER_*.  Width limits: FIR none (radius up
- *               to BF_FIR_MAX_RADIUS), IIR and BOX W <= 8192 (else
- *               BF_EUNSUPPORTED).  BOX: the window radius is ceil(3 sigma_s)
+ *               to BF_FIR_MAX_RADIUS), IIR and BOX W <= 16384, IIR with saved
+ *               terms W <= 8192 (else BF_EUNSUPPORTED).  IIR rows past 8192
+ *               samples are filtered as segments of 8192 whose end states
+ *               are handed on through the workspace (8 floats per row,
+ *               segment and channel).  BOX: the window radius is ceil(3 sigma_s)
  *               (capped at max(H, W), which covers the whole image); its two
  *               passes keep running and prefix sums in double, and the
  *               workspace holds the column-filtered stack (4 (N + 2) H P bytes,
@@ -236,7 +239,8 @@ int bf_gp_set_iir_tuning(int band_rows, int col_groups, int row_groups);
 /* The IIR launch shape an H x W image of degree N gets under the current
  * settings: shape[0] band rows, [1] column channel groups, [2] samples per row
  * thread, [3] row threads per channel group, [4] row channel groups.
- * W up to 8192. */
+ * W up to 16384; past 8192 the row pass runs ceil(W / 8192) segments of 512
+ * threads x 16 samples per row. */
 int bf_gp_iir_shape(int H, int W, int N, int *shape /* 5 ints, host */);
 
 /* ---- GP backward -------------------------------------------------------------

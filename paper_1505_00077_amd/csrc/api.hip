@@ -109,14 +109,15 @@ double range_limit(int N) {
 std::atomic<int> g_band_rows{0}, g_col_groups{0}, g_row_groups{0};
 // Waves the column passes aim for: a few per SIMD of the 1024 on the device.
 constexpr long kTargetWaves = 2048;
-constexpr int kIirMaxW = 8192;
+constexpr int kIirMaxW = 8192;       // IIR widths of the saved terms, joint, volume, batched and stacked calls
+constexpr int kIirMaxWide = 2 * kRowSeg;  // IIR widths of the plain forward (row segments)
 
 struct Layout {
-    size_t parts, status, stats, carry, stack, total;
+    size_t parts, status, stats, carry, stack, segst, total;
 };
 
 // Box mode: samples per row-pass thread, threads per row and stack pitch.
-int box_L(int W) { return W <= 4096 ? 4 : 16; }
+int box_L(int W) { return W <= 4096 ? 4 : W <= 8192 ? 16 : 32; }
 int box_T(int W) { return ((W + box_L(W) - 1) / box_L(W) + 63) / 64 * 64; }
 int box_pitch(int W) { return box_T(W) * box_L(W); }
 
@@ -167,7 +168,7 @@ Layout gp_layout_c(int H, int W, int C, unsigned spatial) {
     off = align256(off + 16);
     L.stats = off;
     off = align256(off + sizeof(Stats));
-    L.carry = L.stack = off;
+    L.carry = L.stack = L.segst = off;
     if (spatial == BF_SPATIAL_IIR) {
         const IirShape sh = iir_shape(H, W, C);
         const size_t nb = ((size_t)H + sh.B - 1) / sh.B;
@@ -175,6 +176,8 @@ Layout gp_layout_c(int H, int W, int C, unsigned spatial) {
         off = align256(off + sizeof(float) * nb * (size_t)C * 8 * (size_t)W);
         L.stack = off;
         off = align256(off + sizeof(float) * (size_t)C * (size_t)sh.Hs * (size_t)sh.P);
+        L.segst = off;
+        if (sh.nseg > 1) off = align256(off + sizeof(float) * (size_t)H * sh.nseg * C * 8);
     } else if (spatial == BF_SPATIAL_BOX) {
         L.stack = off;
         off = align256(off + sizeof(float) * (size_t)C * (size_t)H * (size_t)box_pitch(W));
@@ -204,8 +207,8 @@ int check_spatial(unsigned spatial, double sigma_s, int W) {
     if (spatial == BF_SPATIAL_FIR && fir_radius(sigma_s) > BF_FIR_MAX_RADIUS)
         return fail(BF_EUNSUPPORTED, "FIR radius %d exceeds %d (use the IIR mode)", fir_radius(sigma_s),
                     BF_FIR_MAX_RADIUS);
-    if (spatial == BF_SPATIAL_IIR && W > kIirMaxW)
-        return fail(BF_EUNSUPPORTED, "IIR mode supports widths up to %d", kIirMaxW);
+    if (spatial == BF_SPATIAL_IIR && W > kIirMaxWide)
+        return fail(BF_EUNSUPPORTED, "IIR mode supports widths up to %d", kIirMaxWide);
     if (spatial == BF_SPATIAL_BOX && W > kBoxMaxW)
         return fail(BF_EUNSUPPORTED, "box mode supports widths up to %d", kBoxMaxW);
     return BF_OK;
@@ -446,6 +449,7 @@ IirShape iir_shape(int H, int W, int C, bool batch) {
     // then the shortest chunk (a multiple of 4 samples) that still covers it
     // (fewer idle lanes), and channel groups until the rows give enough waves
     // (each group adds an LDS hand-over, so no more than needed)
+    sh.nseg = 1;
     sh.T = (int)(((W + kRowMaxL * 64 - 1) / (kRowMaxL * 64)) * 64);
     sh.L = kRowMaxL;
     for (int l = 4; l < kRowMaxL; l += 4)
@@ -453,6 +457,12 @@ IirShape iir_shape(int H, int W, int C, bool batch) {
             sh.L = l;
             break;
         }
+    if (sh.T > 512) {
+        // rows wider than 8192: segments of 512 threads x 16 samples
+        sh.T = 512;
+        sh.L = kRowMaxL;
+        sh.nseg = (W + kRowSeg - 1) / kRowSeg;
+    }
     int Gr = g_row_groups.load();
     if (Gr < 1 && batch) Gr = 1;
     if (Gr < 1) {
@@ -462,7 +472,7 @@ IirShape iir_shape(int H, int W, int C, bool batch) {
     }
     if (Gr > 512 / sh.T) Gr = 512 / sh.T;
     if (Gr > C) Gr = C;
-    if (Gr < 1) Gr = 1;
+    if (Gr < 1 || sh.nseg > 1) Gr = 1;
     while (Gr > 1 && hrow2_smem_bytes(sh.T, Gr, sh.L) > 65536) --Gr;
     sh.Gr = Gr;
     // the row pass that stores the saved terms, the joint filter's and the
@@ -489,7 +499,7 @@ IirShape iir_shape(int H, int W, int C, bool batch) {
     // stack pitch: past the last chunk's right halo (two samples) of either
     // row pass, rounded up to a 128-byte line so that every stack row starts
     // on a line
-    const int span = sh.T * sh.L > sh.To * sh.Lo ? sh.T * sh.L : sh.To * sh.Lo;
+    const int span = sh.nseg * sh.T * sh.L > sh.To * sh.Lo ? sh.nseg * sh.T * sh.L : sh.To * sh.Lo;
     sh.P = ((span + 2 + 31) / 32) * 32;
     sh.Hs = ((H + B - 1) / B) * B;
     return sh;
@@ -518,6 +528,8 @@ int gp_forward_check(const float *img, const float *out, int H, int W, int pitch
     if ((rc = check_spatial(spatial, sigma_s, W))) return rc;
     if (spatial == BF_SPATIAL_BOX && saved)
         return fail(BF_EUNSUPPORTED, "the box mode has no backward pass (pass saved = NULL)");
+    if (spatial == BF_SPATIAL_IIR && saved && W > kIirMaxW)
+        return fail(BF_EUNSUPPORTED, "the saved terms of the IIR mode need widths up to %d", kIirMaxW);
     if ((const void *)img == (const void *)out) return fail(BF_EINVAL, "img and out must not alias");
     *ws_need = gp_layout(H, W, N, spatial).total;
     return BF_OK;
@@ -589,7 +601,7 @@ int bf_gp_set_iir_tuning(int band_rows, int col_groups, int row_groups) {
 
 int bf_gp_iir_shape(int H, int W, int N, int *shape) {
     if (!shape) return fail(BF_EINVAL, "null shape");
-    if (H < 1 || W < 1 || W > kIirMaxW || N < 0 || N > BF_MAX_DEGREE) return fail(BF_EINVAL, "bad image size or degree");
+    if (H < 1 || W < 1 || W > kIirMaxWide || N < 0 || N > BF_MAX_DEGREE) return fail(BF_EINVAL, "bad image size or degree");
     const IirShape sh = iir_shape(H, W, N + 2);
     shape[0] = sh.B;
     shape[1] = sh.G;
@@ -629,8 +641,7 @@ int bf_gp_forward(const float *img, float *out, int H, int W, int pitch, double 
     } else {
         const IirShape sh = iir_shape(H, W, N + 2);
         e = launch_iir(p, make_iir(sigma_s, sh.B, sh.Lo), make_row_coef(sigma_s, sh.L), sh, (float *)(w + L.carry),
-                       (float *)(w + L.stack),
-                       saved != nullptr, false, s);
+                       (float *)(w + L.stack), saved != nullptr, false, s, (float *)(w + L.segst));
         if (e != hipSuccess) return hip_fail(e, "IIR launch");
     }
     return BF_OK;
@@ -656,6 +667,7 @@ int bf_gp_joint_forward(const float *guide, const float *data, float *out, int H
     if ((flags & BF_SPATIAL_MASK) == BF_SPATIAL_FIR || (flags & BF_SPATIAL_MASK) == BF_SPATIAL_BOX)
         return fail(BF_EUNSUPPORTED, "the joint filter runs in the recursive (IIR) spatial mode");
     if ((rc = check_spatial(BF_SPATIAL_IIR, sigma_s, W))) return rc;
+    if (W > kIirMaxW) return fail(BF_EUNSUPPORTED, "the joint filter supports widths up to %d", kIirMaxW);
     const int C = 2 * (N + 1);
     const Layout L = gp_layout_c(H, W, C, BF_SPATIAL_IIR);
     if (ws_bytes < L.total) return fail(BF_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
@@ -826,6 +838,8 @@ static int bwd_check(const float *img, const float *grad_out, const void *saved,
     const unsigned spatial = resolve_spatial((long long)H * W, sigma_s, flags);
     if (spatial == BF_SPATIAL_BOX) return fail(BF_EUNSUPPORTED, "the box mode has no backward pass");
     if ((rc = check_spatial(spatial, sigma_s, W))) return rc;
+    if (spatial == BF_SPATIAL_IIR && W > kIirMaxW)
+        return fail(BF_EUNSUPPORTED, "the IIR backward supports widths up to %d", kIirMaxW);
     if ((flags & BF_CENTER_MASK) == BF_CENTER_MIDRANGE)
         return fail(BF_EUNSUPPORTED, "the backward pass supports the mean centre or no centring");
     if (grad_img && ((const void *)grad_img == (const void *)img || (const void *)grad_img == (const void *)grad_out))
@@ -944,6 +958,8 @@ int bf_gp_forward_stacked(const float *img, float *out, int B, int H, int W, int
     if (!ws) return fail(BF_EINVAL, "null workspace");
     const unsigned spatial = resolve_spatial((long long)H * W, sigma_s, flags);
     if (spatial == BF_SPATIAL_BOX) return fail(BF_EUNSUPPORTED, "the stacked path runs the FIR and IIR modes");
+    if (spatial == BF_SPATIAL_IIR && W > kIirMaxW)
+        return fail(BF_EUNSUPPORTED, "the stacked IIR path supports widths up to %d", kIirMaxW);
     const Layout L = gp_layout(H, W, N, spatial);
     const size_t slice = align256(L.total), total = stk_desc_bytes(B) + (size_t)B * slice;
     if (ws_bytes < total) return fail(BF_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, total);

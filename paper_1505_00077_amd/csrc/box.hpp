@@ -27,7 +27,7 @@
 namespace bfgp {
 
 constexpr int kBoxKC = 24;      // most channels one column-pass thread accumulates
-constexpr int kBoxMaxW = 8192;  // widest row of the row pass (T L >= W, L 4 or 16)
+constexpr int kBoxMaxW = 16384;  // widest row of the row pass (T L >= W, L 4, 16 or 32)
 
 // Launch shape of the box passes.
 struct BoxShape {
@@ -204,9 +204,12 @@ __host__ __device__ constexpr size_t boxrow_smem_bytes(int T, int L, int K) {
 // ends with bD = exp(tau^2/2) D and bM = exp(tau^2/2) M, so M/D = bM/bD.
 // sm: boxrow_smem_bytes(T, L, K) bytes.  Every thread of the workgroup takes
 // part in every barrier.
-template <int L, int K>
+// LO < L: the workgroup scans the whole row but evaluates only the outputs
+// t + k T for k in [ob, ob + LO) (rows too wide for L accumulators a thread:
+// two workgroups per row share the outputs).
+template <int L, int K, int LO = L>
 __device__ __forceinline__ void boxrow(const GPParams &p, const Stats &st, int R, int y, const float *__restrict__ S,
-                                       int P, int T, double *sm) {
+                                       int P, int T, double *sm, int ob = 0) {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, nw = T >> 6;
     const int TL = T * L, x0 = t * L;
     // channel j of a step: prefix values at Pe + j PS (the sum of the row's
@@ -217,13 +220,13 @@ __device__ __forceinline__ void boxrow(const GPParams &p, const Stats &st, int R
     const size_t PS = boxrow_pe_stride(T, L);
     double *Pe = sm;
     double *wt = sm + (size_t)K * PS;
-    float tau[L];
-    double bD[L], bM[L];
+    float tau[LO];
+    double bD[LO], bM[LO];
     {
         const float *irow = p.img + (size_t)y * p.pitch;
 #pragma unroll
-        for (int k = 0; k < L; ++k) {
-            const int x = t + k * T;
+        for (int k = 0; k < LO; ++k) {
+            const int x = t + (ob + k) * T;
             tau[k] = x < p.W ? centred(irow[x], st, p.inv_sigma_r) : 0.f;
             bD[k] = 0.0;
             bM[k] = 0.0;
@@ -291,8 +294,8 @@ __device__ __forceinline__ void boxrow(const GPParams &p, const Stats &st, int R
             const double rM = p.rm[n];
             const bool inD = n <= p.N, inM = n >= 1;
 #pragma unroll
-            for (int k = 0; k < L; ++k) {
-                const int x = t + k * T;
+            for (int k = 0; k < LO; ++k) {
+                const int x = t + (ob + k) * T;
                 const int hi = x + R + 1 < p.W ? x + R + 1 : p.W;
                 const int lo = x - R > 0 ? x - R : 0;
                 const double ub = x < p.W ? pe[hi + hi / L] - pe[lo + lo / L] : 0.0;
@@ -308,8 +311,8 @@ __device__ __forceinline__ void boxrow(const GPParams &p, const Stats &st, int R
     }
     float *orow = p.out + (size_t)y * p.pitch;
 #pragma unroll
-    for (int k = 0; k < L; ++k) {
-        const int x = t + k * T;
+    for (int k = 0; k < LO; ++k) {
+        const int x = t + (ob + k) * T;
         if (x < p.W) orow[x] = (float)fma(p.sigma_r, bM[k] / bD[k], st.tc);
     }
 }

@@ -41,6 +41,7 @@ namespace bfgp {
 
 // Coefficients of the row pass for one sigma_s and chunk length L.
 constexpr int kRowMaxL = 16;  // samples per thread
+constexpr int kRowSeg = 512 * kRowMaxL;  // columns of a row segment (rows wider than one workgroup)
 struct RowCoef {
     float n0[2], n1[2], m1[2], m2[2], d1[2], d2[2];
     float pw[2][10][4];        // Phi^(L 2^j), j = 0..9, row-major (chunk distances 1 .. 512)
@@ -78,17 +79,26 @@ __device__ __forceinline__ float bperm_f(float v, int src_lane) {
 // sp_pitch; columns W .. sp_pitch - 1 hold zeros and sp_pitch >= T L + 2.
 // sm: hrow2_smem_bytes(T, groups, L) bytes.  foff: element offset of the image
 // and output rows (a volume's frame).
-template <int L>
+//
+// Rows wider than one workgroup's T L samples are cut into segments of T L
+// (T = 512, L = 16): MODE 1 runs a segment from rest and stores its end states
+// (the causal state at its end and the anticausal one at its start, per
+// channel) in segst; MODE 2 then filters each segment with the incoming
+// states of the segments before and after it (the end states moved over the
+// segments between by Phi^(T L)), added to the states its waves hand over.
+// segst: [row][segment][channel][8].  MODE 0: one segment per row.
+template <int L, int MODE = 0>
 __device__ __forceinline__ void hrow2(const GPParams &p, const RowCoef &c, const Stats &st, int y,
                                       const float *__restrict__ S, int sp_rows, int sp_pitch, float *sm, int T,
-                                      int groups, size_t foff = 0) {
+                                      int groups, size_t foff = 0, int seg = 0, int nseg = 1,
+                                      float *segst = nullptr) {
     const int g = __builtin_amdgcn_readfirstlane((int)threadIdx.x / T);  // whole waves share a group
     const int t = threadIdx.x - g * T;
     const int lane = threadIdx.x & 63, jj = lane & 15;
     const int nw = T >> 6;  // waves in a group
     const int wv = t >> 6;  // this chunk's wave in the group
     const int r16 = lane >> 4;  // this chunk's row of 16 lanes in the wave
-    const int x0 = t * L;
+    const int x0 = (seg * T + t) * L;
     const int cb = (p.C * g) / groups, ce = (p.C * (g + 1)) / groups;
     const int steps = (p.C + groups - 1) / groups;  // channels of the largest group
     float *pws = sm;                      // pws[(10 s + j) * 4 + q] = Phi_s^(L 2^j)
@@ -292,6 +302,13 @@ __device__ __forceinline__ void hrow2(const GPParams &p, const RowCoef &c, const
                 BF_WSTEP(7, 2)
                 BF_WSTEP(8, 4)
 #undef BF_WSTEP
+                if constexpr (MODE == 1) {
+                    // the segment's end states: the causal one after its
+                    // last wave, the anticausal one before its first
+                    float *sg = segst + (((size_t)y * nseg + seg) * p.C + n) * 8;
+                    if (wv == 0 && lane == nw - 1) *(float4 *)sg = make_float4(xc[0], xc[1], xc[2], xc[3]);
+                    if (wv == 0 && lane == 0) *(float4 *)(sg + 4) = make_float4(xa[0], xa[1], xa[2], xa[3]);
+                }
                 // exclusive: the waves before (causal) and after (anticausal)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -300,8 +317,46 @@ __device__ __forceinline__ void hrow2(const GPParams &p, const RowCoef &c, const
                     wc[q] = lane_f(xc[q], wv);
                     wa[q] = lane_f(xa[q], wv);
                 }
+                if constexpr (MODE == 2) {
+                    // the segment's incoming states from the segments before
+                    // and after it, moved over this wave's place in it
+                    float ci[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
+                    const float *sr = segst + ((size_t)y * nseg * p.C + n) * 8;
+                    const size_t sstep = (size_t)p.C * 8;
+                    for (int j = 0; j < seg; ++j) {
+#pragma unroll
+                        for (int s2 = 0; s2 < 2; ++s2) {
+                            float r2[2];
+                            affine2(r2, sr + j * sstep + 2 * s2, pws + (10 * s2 + 9) * 4, &ci[2 * s2]);
+                            ci[2 * s2] = r2[0];
+                            ci[2 * s2 + 1] = r2[1];
+                        }
+                    }
+                    for (int j = nseg - 1; j > seg; --j) {
+#pragma unroll
+                        for (int s2 = 0; s2 < 2; ++s2) {
+                            float r2[2];
+                            affine2(r2, sr + j * sstep + 4 + 2 * s2, pws + (10 * s2 + 9) * 4, &ai[2 * s2]);
+                            ai[2 * s2] = r2[0];
+                            ai[2 * s2 + 1] = r2[1];
+                        }
+                    }
+#pragma unroll
+                    for (int s2 = 0; s2 < 2; ++s2) {
+                        float Mc[4] = {1.f, 0.f, 0.f, 1.f}, Ma[4] = {1.f, 0.f, 0.f, 1.f};
+                        const int wa_ = nw - 1 - wv;
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) {
+                            if (wv & (1 << b)) mat_mul(Mc, pws + (10 * s2 + 6 + b) * 4, Mc);
+                            if (wa_ & (1 << b)) mat_mul(Ma, pws + (10 * s2 + 6 + b) * 4, Ma);
+                        }
+                        acc2(&wc[2 * s2], Mc, ci[2 * s2], ci[2 * s2 + 1]);
+                        acc2(&wa[2 * s2], Ma, ai[2 * s2], ai[2 * s2 + 1]);
+                    }
+                }
             }
         }
+        if constexpr (MODE == 1) continue;
         if (!act) continue;
         // row-exclusive incoming states of the wave's rows (lanes 0..3): the
         // rows before (after) inside the wave plus the wave's incoming state
@@ -380,6 +435,7 @@ __device__ __forceinline__ void hrow2(const GPParams &p, const RowCoef &c, const
         }
         kap *= p.sq[n];  // 1 / sqrt((n-1)!)
     }
+    if constexpr (MODE == 1) return;
     if (groups > 1) {
         // parts of groups 1.. in the full sums, through LDS
         if (g > 0) {

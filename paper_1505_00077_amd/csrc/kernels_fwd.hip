@@ -184,6 +184,23 @@ __global__ __launch_bounds__(512) void k_hrow2(GPParams p, RowCoef c, const floa
     hrow2<L>(p, c, st, blockIdx.x, S, srows, sp, sm, T, groups);
 }
 
+// Row pass of rows wider than one workgroup: segment blockIdx.y of row
+// blockIdx.x (512 threads, 16 samples each); MODE 1 stores the segments' end
+// states, MODE 2 filters the segments with them.
+template <int MODE>
+__global__ __launch_bounds__(512) void k_hrow2seg(GPParams p, RowCoef c, const float *S, int srows, int sp,
+                                                  float *segst) {
+    extern __shared__ float sm[];
+    const Stats st = load_stats(p);
+    if (!st.ok) {
+        if (MODE == 2)
+            for (int x = blockIdx.y * kRowSeg + threadIdx.x; x < p.W && x < (blockIdx.y + 1) * kRowSeg; x += blockDim.x)
+                p.out[(size_t)blockIdx.x * p.pitch + x] = __builtin_nanf("");
+        return;
+    }
+    hrow2<kRowMaxL, MODE>(p, c, st, blockIdx.x, S, srows, sp, sm, 512, 1, 0, blockIdx.y, gridDim.y, segst);
+}
+
 // ---- volumes: the row-direction pass per frame and the frame-wise row pass ----
 
 // Column pass of every frame over the time-filtered stack S1 (channel n, frame
@@ -260,16 +277,18 @@ __global__ __launch_bounds__(64) void k_boxcol(GPParams p, BoxFact bfct, float *
 }
 
 // Row pass + recombination: one workgroup of T threads per image row, K
-// channels per step.
-template <int L, int K>
+// channels per step; LO < L: blockIdx.y selects the row's LO-th part of the
+// outputs.
+template <int L, int K, int LO = L>
 __global__ __launch_bounds__(L == 4 ? 1024 : 512) void k_boxrow(GPParams p, const float *S, int R, int P, int T) {
     extern __shared__ float sm[];
     const Stats st = load_stats(p);
     if (!st.ok) {
-        for (int x = threadIdx.x; x < p.W; x += blockDim.x) p.out[(size_t)blockIdx.x * p.pitch + x] = __builtin_nanf("");
+        if (blockIdx.y == 0)
+            for (int x = threadIdx.x; x < p.W; x += blockDim.x) p.out[(size_t)blockIdx.x * p.pitch + x] = __builtin_nanf("");
         return;
     }
-    boxrow<L, K>(p, st, R, blockIdx.x, S, P, T, (double *)sm);
+    boxrow<L, K, LO>(p, st, R, blockIdx.x, S, P, T, (double *)sm, blockIdx.y * LO);
 }
 
 // ---- host launchers ----------------------------------------------------------
@@ -375,7 +394,7 @@ static hipError_t vbandg_launch(const GPParams &p, const IirCoef &c, const IirSh
 }
 
 hipError_t launch_iir(const GPParams &p, const IirCoef &c, const RowCoef &rc, const IirShape &shape, float *carry,
-                      float *S, bool save, bool joint, hipStream_t s) {
+                      float *S, bool save, bool joint, hipStream_t s, float *segst) {
     IirShape sh = shape;
     const int nb = (p.H + sh.B - 1) / sh.B;
     // the end-state pass has nothing to do on the stack's pad columns: its
@@ -424,6 +443,21 @@ hipError_t launch_iir(const GPParams &p, const IirCoef &c, const RowCoef &rc, co
             case 16: hrow_launch<16>(p, c, sh, S, save, joint, s); break;
             default: return hipErrorInvalidValue;
         }
+    } else if (sh.nseg > 1) {
+        if (sh.T != 512 || sh.L != kRowMaxL || !segst) return hipErrorInvalidValue;
+        const size_t sm = hrow2_smem_bytes(512, 1, kRowMaxL);
+        static hipError_t attr = [] {
+            hipError_t a = hipFuncSetAttribute((const void *)k_hrow2seg<1>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            if (a == hipSuccess)
+                a = hipFuncSetAttribute((const void *)k_hrow2seg<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        160 * 1024);
+            return a;
+        }();
+        if (attr != hipSuccess) return attr;
+        const dim3 grid(p.H, sh.nseg);
+        BF_LAUNCH("k_hrow_seg", k_hrow2seg<1>, grid, dim3(512), sm, s, p, rc, S, sh.Hs, sh.P, segst);
+        BF_LAUNCH("k_hrow", k_hrow2seg<2>, grid, dim3(512), sm, s, p, rc, S, sh.Hs, sh.P, segst);
     } else {
 #define BF_CALL(l) e = hrow2_launch<l>(p, rc, sh, S, s)
         BF_ROW2_SWITCH(sh.L, BF_CALL)
@@ -521,6 +555,15 @@ hipError_t launch_box(const GPParams &p, const BoxShape &sh, float *S, hipStream
         if (attr != hipSuccess) return attr;
         const size_t sm = boxrow_smem_bytes(sh.T, 16, 1);
         BF_LAUNCH("k_boxrow", (k_boxrow<16, 1>), dim3(p.H), dim3(sh.T), sm, s, p, S, sh.R, sh.P, sh.T);
+    } else if (sh.L == 32) {
+        // rows past 8192 samples: the row's prefix fills 135 KiB of LDS, and
+        // two workgroups per row each evaluate half of the outputs
+        static hipError_t attr = hipFuncSetAttribute((const void *)k_boxrow<32, 1, 16>,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)boxrow_smem_bytes(512, 32, 1));
+        if (attr != hipSuccess) return attr;
+        const size_t sm = boxrow_smem_bytes(sh.T, 32, 1);
+        BF_LAUNCH("k_boxrow", (k_boxrow<32, 1, 16>), dim3(p.H, 2), dim3(sh.T), sm, s, p, S, sh.R, sh.P, sh.T);
     } else {
         return hipErrorInvalidValue;
     }

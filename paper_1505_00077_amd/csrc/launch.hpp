@@ -38,9 +38,11 @@ struct IirShape {
     int Lo;  // the same for the row pass with the saved terms and the joint
     int To;  // filter (and the batched path): L 4, 8, 12 or 16, T <= 512
     int Gro;
-    int P;   // row pitch of the channel stack, >= max(T L, To Lo) + 2, a
+    int P;   // row pitch of the channel stack, >= max(nseg T L, To Lo) + 2, a
              // multiple of 32 (columns W .. P-1 are zero)
     int Hs;  // rows per channel of the stack: H rounded up to a multiple of B
+    int nseg;  // segments of T L = 8192 columns per row in the row pass (rows
+               // wider than 8192, the plain forward only); 1 otherwise
 };
 // batch: the image is one of many filtered together, which fill the device by
 // themselves: no channel groups unless the tuning overrides ask for them.
@@ -50,8 +52,9 @@ IirShape iir_shape(int H, int W, int C, bool batch = false);
 // data, p.C = 2 (N + 1) stack channels), row pass in one channel group.
 // c: the column passes' coefficients (and the row pass of the saved terms and
 // the joint filter, chunks of sh.Lo); rc: the row pass's (chunks of sh.L).
+// segst: the segments' end states of rows wider than 8192 (sh.nseg > 1).
 hipError_t launch_iir(const GPParams &p, const IirCoef &c, const RowCoef &rc, const IirShape &sh, float *carry,
-                      float *S, bool save, bool joint, hipStream_t s);
+                      float *S, bool save, bool joint, hipStream_t s, float *segst = nullptr);
 hipError_t launch_direct(const DirectArgs &a, hipStream_t s);
 struct BoxShape;
 // Box spatial mode: column pass (running sums) into the stack S, then the row

@@ -57,21 +57,26 @@ def test_forward_rejects_small_workspace():
 def test_forward_rejects_unsupported_modes():
     # FIR radius ceil(3 * 9) = 27 > 24
     assert fwd(ss=9.0, flags=bf.SPATIAL["fir"]) == bf.BF_EUNSUPPORTED
-    # IIR width limit
-    assert fwd(H=4, W=9000, pitch=9000, flags=bf.SPATIAL["iir"]) == bf.BF_EUNSUPPORTED
+    # IIR width limits: rows up to 16384 in the plain forward (row segments
+    # of 8192), 8192 where the saved terms are stored
+    iir = bf.SPATIAL["iir"]
+    assert fwd(H=4, W=16385, pitch=16385, flags=iir) == bf.BF_EUNSUPPORTED
+    assert fwd(H=4, W=9000, pitch=9000, flags=iir, saved=FAKE + (1 << 20)) == bf.BF_EUNSUPPORTED
+    need = bf.workspace_bytes(4, 12000, 20, 5.0, "iir")
+    assert fwd(H=4, W=12000, pitch=12000, flags=iir, ws_bytes=need - 1) == bf.BF_ENOMEM
 
 
 def test_box_mode_contract():
     box = bf.SPATIAL["box"]
     assert box == 3 and bf.resolve_spatial(2.0, "box") == "box" and bf.resolve_spatial(50.0, "box") == "box"
     # width limit, no saved terms (no backward), small workspace
-    assert fwd(H=4, W=9000, pitch=9000, flags=box) == bf.BF_EUNSUPPORTED
+    assert fwd(H=4, W=16385, pitch=16385, flags=box) == bf.BF_EUNSUPPORTED
     assert fwd(flags=box, saved=FAKE + 65536) == bf.BF_EUNSUPPORTED
     # the column-filtered stack: N + 2 channels of H rows of pitch P (W rounded
-    # up to a multiple of 256 up to 4096 columns, of 1024 beyond), whatever
-    # the radius
+    # up to a multiple of 256 up to 4096 columns, of 1024 up to 8192, of 2048
+    # beyond), whatever the radius
     for H, W, P in ((64, 64, 256), (100, 1000, 1024), (9, 1025, 1280), (5, 4096, 4096), (7, 4097, 5120),
-                    (3, 8192, 8192)):
+                    (3, 8192, 8192), (3, 8193, 10240), (2, 12000, 12288), (2, 16384, 16384)):
         need = bf.workspace_bytes(H, W, 20, 2.0, "box")
         assert 22 * H * P * 4 <= need < 22 * H * P * 4 + 8192
         assert bf.workspace_bytes(H, W, 20, 400.0, "box") == need
@@ -241,6 +246,12 @@ def test_iir_shape_rule_and_overrides():
         s = bf.iir_shape(8, W, 20)
         assert s["row_threads"] % 64 == 0 and s["row_threads"] * s["row_chunk"] >= W
         assert s["row_chunk"] == 4 or s["row_threads"] * (s["row_chunk"] - 4) < W
+    # wider rows: segments of 512 threads x 16 samples, one channel group
+    for W in (8193, 12000, 16384):
+        s = bf.iir_shape(8, W, 20)
+        assert (s["row_threads"], s["row_chunk"], s["row_groups"]) == (512, 16, 1)
+    with pytest.raises(bf.BfError):
+        bf.iir_shape(8, 16385, 20)
     # never more channel groups than channels (N = 0: two channels)
     s = bf.iir_shape(64, 64, 0)
     assert s["col_groups"] <= 2 and s["row_groups"] <= 2
@@ -264,7 +275,7 @@ def test_iir_shape_rule_and_overrides():
         bf.set_iir_tuning(0, 0, 0)
     assert bf.workspace_bytes(1024, 1024, 20, 8.0, "iir") == ws_auto
     with pytest.raises(bf.BfError):
-        bf.iir_shape(10, 9000, 20)
+        bf.iir_shape(10, 16385, 20)
 
 
 def test_crossover_table():

@@ -154,11 +154,11 @@ def test_deterministic_and_symmetric(bf):
     assert np.max(np.abs(run(bf, img[:, ::-1].copy(), 3.0, 30.0, 20) - a[:, ::-1])) <= TOL
 
 
-@pytest.mark.parametrize("W", [1024, 1025, 4096, 4097, 6000, 8192])
+@pytest.mark.parametrize("W", [1024, 1025, 4096, 4097, 6000, 8192, 8193, 12000, 16384])
 def test_wide_rows(bf, W):
     # 4 samples per row-pass thread up to 4096 columns (1024 threads), 16
-    # beyond; from about 3000 columns the row's prefix sums need more than
-    # 64 KiB of LDS
+    # up to 8192, 32 beyond (two workgroups per row share the outputs); from
+    # about 3000 columns the row's prefix sums need more than 64 KiB of LDS
     img = synthimg.voronoi_image(3, W, 40, seed=W)
     for ss in (2.0, 30.0):
         got = run(bf, img, ss, 30.0, 20)

@@ -336,12 +336,28 @@ def test_large_config_full_rows_and_columns(bf):
         assert err <= TOL, (x, err)
 
 
-@pytest.mark.parametrize("W", [4097, 6000, 8192])
+@pytest.mark.parametrize("W", [4097, 6000, 8192, 8193, 12000, 16384])
 def test_iir_wide_rows(bf, W):
     # rows past 4096 samples run the row pass with 512 threads (8 waves), so
-    # the carries cross eight waves of the workgroup
+    # the carries cross eight waves of the workgroup; past 8192 the row is cut
+    # into segments of 8192 whose end states cross between workgroups (8193:
+    # a one-sample last segment)
     img = synthimg.voronoi_image(3, W, 60, seed=W)
     got = run(bf, img, 7.0, 30.0, 20, "iir")
     err = np.max(np.abs(got - oracle_gp(img, 7.0, 30.0, 20, "iir")))
     print(f"W {W}: {err:.2e}")
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("shape,ss", [((5, 12000), 25.0), ((37, 12000), 3.0), ((2, 16384), 40.0)])
+def test_iir_row_segments(bf, shape, ss):
+    # wide support (sigma_s 25 and 40: the response reaches over a whole
+    # segment), and bands of rows with segments (37 rows: two bands, a ragged
+    # one); an edge step placed on the segment boundary
+    H, W = shape
+    img = synthimg.voronoi_image(H, W, 80, seed=H * W)
+    img[:, 8190:8195] = 255.0 - img[:, 8190:8195]
+    got = run(bf, img, ss, 30.0, 20, "iir")
+    err = np.max(np.abs(got - oracle_gp(img, ss, 30.0, 20, "iir")))
+    print(f"{shape} sigma_s {ss}: {err:.2e}")
     assert err <= TOL
