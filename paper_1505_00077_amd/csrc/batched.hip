@@ -426,6 +426,13 @@ int bf_gp_forward_batched(void *plan, void *ws, size_t ws_bytes, void *stream) {
             BF_LAUNCH("k_bband", (k_bband<32, false>), dim3(n(kStBand)), dim3(64), 0, s, imgs, at(kStBand));
         else
             BF_LAUNCH("k_bband", (k_bband<64, false>), dim3(n(kStBand)), dim3(64), 0, s, imgs, at(kStBand));
+        for (int k = 0; k < 8; ++k) {
+            if (n(kStRow + k) && P->row_smem[k] > 65536) {
+                static hipError_t attr = hipFuncSetAttribute((const void *)k_brow,
+                                                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                if (attr != hipSuccess) return set_error(BF_EHIP, hipGetErrorString(attr));
+            }
+        }
         for (int k = 0; k < 8; ++k)
             if (n(kStRow + k))
                 BF_LAUNCH("k_brow", k_brow, dim3(n(kStRow + k)), dim3(64 * (k + 1)), P->row_smem[k], s, imgs,

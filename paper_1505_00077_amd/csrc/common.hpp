@@ -12,6 +12,16 @@ constexpr int kFirMaxR = 24;         // largest FIR radius compiled
 constexpr int kMaxParts = 256;       // partial sums of the statistics pass
 constexpr int kDirectMaxW = 64;      // largest direct-filter window
 
+// Workgroups are handed to the eight XCDs in turn (linear workgroup i runs on
+// XCD i mod 8), and each XCD has its own L2.  xcd_block maps the linear index
+// i of a grid of n workgroups to a tile index such that every XCD receives a
+// contiguous run of tiles (XCD k the k-th eighth, in tile order): tiles that
+// share halo samples then meet in one L2.  A bijection of [0, n).
+__device__ __forceinline__ int xcd_block(int i, int n) {
+    const int q = n >> 3, r = n & 7, x = i & 7, j = i >> 3;
+    return x < r ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
+}
+
 // One workgroup's share of the image statistics.
 struct Partial {
     double sum;

@@ -30,57 +30,69 @@ constexpr int kFirRegMaxN = 46;
 __host__ __device__ constexpr bool fir_reg(int R, bool save) { return !save && R <= kFirRegMaxR; }
 
 // Output tile of a FIR launch: fir_tx(R, save) columns by fir_ty(R, save)
-// rows.  Kernels that can take the register variant use 16 x 128 tiles (the
-// region's 128 + 2R columns fill at least two waves); the region variant then
-// covers such a tile as two 16 x 64 halves.  Other kernels use the region
-// variant's own tile, 64 columns wide: 16-row tiles give twice the workgroups
-// and fewer registers per thread; they were measured faster except for radii
-// 10..17 without the saved terms, where the halo rows of a 16-row tile cost
-// more than the extra parallelism gains.  With the saved terms (more
+// rows.  Kernels that can take the register variant use 8 x 224 tiles: the
+// region's 224 + 2R columns (R <= 16) give every one of the four waves a
+// column-pass share (fewer than 193 columns would leave a wave idle through
+// the heaviest phase); the region variant then covers such a tile as four
+// 8 x 64 pieces, the last one cut at the tile's edge.  Other kernels use the
+// region variant's own tile, 64 columns wide: 16-row tiles give twice the
+// workgroups and fewer registers per thread; they were measured faster except
+// for radii 10..17 without the saved terms, where the halo rows of a 16-row
+// tile cost more than the extra parallelism gains.  With the saved terms (more
 // accumulators) 16 rows keep two waves per SIMD.
+constexpr int kFirRegTY = 8, kFirRegTX = 224;
 __host__ __device__ constexpr int fir_region_ty(int R, bool save = false) {
     return (!fir_reg(R, save) && !save && R >= 10 && R <= 17) ? 32 : 16;
 }
-__host__ __device__ constexpr int fir_tx(int R, bool save = false) { return fir_reg(R, save) ? 128 : 64; }
-__host__ __device__ constexpr int fir_ty(int R, bool save = false) { return fir_region_ty(R, save); }
+__host__ __device__ constexpr int fir_tx(int R, bool save = false) { return fir_reg(R, save) ? kFirRegTX : 64; }
+__host__ __device__ constexpr int fir_ty(int R, bool save = false) {
+    return fir_reg(R, save) ? kFirRegTY : fir_region_ty(R, save);
+}
 
+// LDS floats of one channel stage of the region variant with TY-row tiles:
+// the region, then the column-pass output (odd pitch).
+__host__ __device__ constexpr int fir_stage_floats(int R, int TY) {
+    return (TY + 2 * R) * (64 + 2 * R) + TY * (64 + 2 * R + 1);
+}
 // Channels processed between two barrier pairs by the region variant: two
 // (twice the independent work per barrier) where the LDS stages of two
 // channels fit in 64 KB.
-__host__ __device__ constexpr int fir_ch(int R, bool save = false) {
-    return (!save && 2 * ((fir_region_ty(R) + 2 * R) * (64 + 2 * R) + fir_region_ty(R) * (64 + 2 * R + 1)) <= 16384)
-               ? 2 : 1;
+__host__ __device__ constexpr int fir_ch_ty(int R, int TY, bool save) {
+    return (!save && 2 * fir_stage_floats(R, TY) <= 16384) ? 2 : 1;
 }
+__host__ __device__ constexpr int fir_ch(int R, bool save = false) { return fir_ch_ty(R, fir_region_ty(R, save), save); }
 
-// Shape of the region variant's tile (64 columns).
-template <int R, bool SAVE = false>
+// Shape of the region variant's tile (64 columns, TYO rows).
+template <int R, bool SAVE = false, int TYO = fir_region_ty(R, SAVE)>
 struct FirShape {
-    static constexpr int TY = fir_region_ty(R, SAVE), TX = 64;  // output tile
+    static constexpr int TY = TYO, TX = 64;       // output tile
     static constexpr int RY = TY + 2 * R, RX = TX + 2 * R;
     static constexpr int REG = RY * RX;           // region elements
     static constexpr int PER = (REG + kBlock - 1) / kBlock;
     static constexpr int SV = 4;                  // column-pass outputs per item
     static constexpr int BP = RX + 1;             // odd pitch of the row-pass input
     static constexpr int PX = TY * TX / kBlock;   // output pixels per thread (one row segment)
-    static constexpr int CH = fir_ch(R, SAVE);    // channels per barrier pair
+    static constexpr int CH = fir_ch_ty(R, TY, SAVE);  // channels per barrier pair
     static constexpr int STAGE = REG + TY * BP;   // LDS floats per channel
     static constexpr int SMEM_FLOATS = CH * STAGE;
 };
 
 // Number of LDS floats needed by fir_tile_auto<R, save> (either variant).
 __host__ __device__ constexpr int fir_smem_floats(int R, bool save = false) {
-    return fir_ch(R, save) * ((fir_region_ty(R, save) + 2 * R) * (64 + 2 * R) +
-                              fir_region_ty(R, save) * (64 + 2 * R + 1)) >
-                   (fir_reg(R, save) ? 2 * 16 * (128 + 2 * R + 1) : 0)
-               ? fir_ch(R, save) * ((fir_region_ty(R, save) + 2 * R) * (64 + 2 * R) +
-                                    fir_region_ty(R, save) * (64 + 2 * R + 1))
-               : 2 * 16 * (128 + 2 * R + 1);
+    return fir_reg(R, save)
+               ? (fir_ch_ty(R, kFirRegTY, save) * fir_stage_floats(R, kFirRegTY) >
+                          2 * kFirRegTY * (kFirRegTX + 2 * R + 1)
+                      ? fir_ch_ty(R, kFirRegTY, save) * fir_stage_floats(R, kFirRegTY)
+                      : 2 * kFirRegTY * (kFirRegTX + 2 * R + 1))
+               : fir_ch(R, save) * fir_stage_floats(R, fir_region_ty(R, save));
 }
 
-template <int R, bool SAVE>
+// Region variant; outputs at columns >= xlim are left to the tile that owns
+// them.
+template <int R, bool SAVE, int TYO = fir_region_ty(R, SAVE)>
 __device__ __forceinline__ void fir_tile(const GPParams &p, const FirTaps &taps, const Stats &st,
-                                         int ty0, int tx0, float *smem) {
-    using S = FirShape<R, SAVE>;
+                                         int ty0, int tx0, float *smem, int xlim = 0x7fffffff) {
+    using S = FirShape<R, SAVE, TYO>;
     // stage c (one per channel in flight): region A_c (RY x RX), then the
     // column-pass output B_c (TY x BP)
     auto A = [&](int c) { return smem + c * S::STAGE; };
@@ -258,7 +270,7 @@ __device__ __forceinline__ void fir_tile(const GPParams &p, const FirTaps &taps,
 #pragma unroll
         for (int i = 0; i < S::PX; ++i) {
             const int gx = tx0 + ox0 + i;
-            if (gx < p.W) {
+            if (gx < p.W && gx < xlim) {
                 const double rho = Mp[i] / Dp[i];
                 const float o = st.ok ? (float)fma(p.sigma_r, rho, st.tc) : __builtin_nanf("");
                 p.out[(size_t)gy * p.pitch + gx] = o;
@@ -274,23 +286,25 @@ __device__ __forceinline__ void fir_tile(const GPParams &p, const FirTaps &taps,
     }
 }
 
-// Register-column variant (16 x 128 tile, radius R <= kFirRegMaxR).  The
+// Register-column variant (8 x 224 tile, radius R <= kFirRegMaxR).  The
 // channels are carried unnormalised, w_n = exp(-x^2/2) x^n = sqrt(n!) u_n
 // (one multiply per sample and channel); the 1/sqrt(n!) goes into the
 // recombination weights: with q_n = tau^n / n!,
 //   D' = sum_{n<=N} q_n (k * w_n),   M' = sum_{n=1}^{N+1} q_{n-1} (k * w_n),
 // the same D' = exp(tau^2/2) D and M' = exp(tau^2/2) M as the region variant.
 // w_n stays in the FP32 range for |x| <= 12 and n <= kFirRegMaxN + 1.
-// Per channel: threads 0 .. 127+2R update their region column and run its
+// Per channel: threads 0 .. 223+2R update their region column and run its
 // column pass from registers into LDS (two buffers, one barrier per channel),
-// then every thread runs the row pass at its 8 pixels and accumulates D', M'
-// in double.
+// then every thread runs the row pass at its 7 pixels (one row segment; the
+// 32 threads of a row read LDS at a stride of 7 words, on distinct banks)
+// and accumulates D', M' in double.
 template <int R>
 __device__ __forceinline__ void fir_tile_reg(const GPParams &p, const FirTaps &taps, const Stats &st, int ty0,
                                              int tx0, float *smem) {
-    constexpr int TY = 16, TX = 128, RX = TX + 2 * R, RY = TY + 2 * R, BP = RX + 1;
-    constexpr int PX = TY * TX / kBlock;
+    constexpr int TY = kFirRegTY, TX = kFirRegTX, RX = TX + 2 * R, RY = TY + 2 * R, BP = RX + 1;
+    constexpr int PX = TY * TX / kBlock, RT = TX / PX;  // pixels per thread, threads per output row
     static_assert(RX <= kBlock, "one region column per thread");
+    static_assert(PX * RT == TX && RT * TY == kBlock, "row segments cover the tile");
     const int tid = threadIdx.x;
     const bool colt = tid < RX;
 
@@ -318,8 +332,8 @@ __device__ __forceinline__ void fir_tile_reg(const GPParams &p, const FirTaps &t
     }
 
     // ---- output ownership: row oy, PX consecutive columns from ox0 ----
-    const int oy = tid % TY;
-    const int ox0 = (tid / TY) * PX;
+    const int oy = tid / RT;
+    const int ox0 = (tid % RT) * PX;
     double tau[PX], Dp[PX], Mp[PX], q[PX];
     {
         const int gy = ty0 + oy;
@@ -420,8 +434,10 @@ __device__ __forceinline__ void fir_tile_auto(const GPParams &p, const FirTaps &
         if (st.xmax <= 12.0 && p.N <= kFirRegMaxN) {
             fir_tile_reg<R>(p, taps, st, ty0, tx0, smem);
         } else {
-            fir_tile<R, SAVE>(p, taps, st, ty0, tx0, smem);
-            fir_tile<R, SAVE>(p, taps, st, ty0, tx0 + 64, smem);
+            for (int k = 0; k < kFirRegTX; k += 64) {
+                fir_tile<R, SAVE, kFirRegTY>(p, taps, st, ty0, tx0 + k, smem, tx0 + kFirRegTX);
+                __syncthreads();  // the next piece reuses the LDS stages
+            }
         }
     } else {
         fir_tile<R, SAVE>(p, taps, st, ty0, tx0, smem);

@@ -21,19 +21,21 @@
 // Recombination.  With a_k = Ubar_k / sqrt(k!) (the filtered channel k, in
 // double) and P(tau) = sum_{k=0}^{N+1} a_k tau^k, the two sums of eq. (11)
 // times exp(tau^2/2) are
-//     D = sum_{k<=N} a_k tau^k,   M = sum_{k=1}^{N+1} k a_k tau^{k-1} = P'(tau),
+//     D = sum_{k<=N} a_k tau^k = P(tau) - a_{N+1} tau^(N+1),
+//     M = sum_{k=1}^{N+1} k a_k tau^{k-1} = P'(tau)
 // (M is the derivative of the channel polynomial: sqrt(n+1) u_n(tau) /
 // exp(-tau^2/2) = (n+1) tau^n / sqrt((n+1)!)).  Channels are visited from the
-// top down and both are evaluated by Horner in tau with the same multiplier:
-//     b <- b tau + a_k            (D, channels k <= N),
-//     c <- c tau + b_{previous}   (D', the derivative scheme),
-// with c seeded by (N+1) a_{N+1} at the top channel, which after the N
-// remaining multiplications by tau is the N+1 term of M.  A channel group
-// that starts at channel cb > 0 evaluates its part relative to tau^cb; the
-// groups' parts are added by group 0 in order:
-//     D = sum_g tau^cb_g b_g,  M = sum_g (cb_g tau^(cb_g - 1) b_g + tau^cb_g c_g),
-// except for a group that holds channel N+1 alone (cb = N+1), whose c is the
-// unmultiplied seed: it adds tau^N c to M and nothing to D.
+// top down and P and P' are evaluated together by Horner in tau, the same
+// step for every channel:
+//     c <- c tau + b,   b <- b tau + a_k,
+// and the top term is taken out of D at the end (from the top channel's
+// filtered row, kept in LDS).  Where |x| is large that term dominates P, and
+// the difference loses about log10(P / D) of the sixteen digits of the
+// double sums: one or two.  A channel group that starts at channel cb > 0
+// evaluates its part relative to tau^cb; the groups' parts are added by
+// group 0 in order:
+//     D = sum_g tau^cb_g d_g,  M = sum_g (cb_g tau^(cb_g - 1) b_g + tau^cb_g c_g),
+// with d_g = b_g except in the group holding channel N+1.
 #pragma once
 #include "iir.hpp"
 
@@ -53,11 +55,13 @@ struct RowCoef {
 // homogeneous-response table (16 x 4), the per-lane power table (16 x 8), the
 // per-row power table (4 x 8), the wave totals of every group
 // (double-buffered, 2 x 8 x 8 each); then as doubles the centred intensities
-// of the row (T L) and the hand-over of groups 1.. to group 0 (2 per pixel).
+// of the row (T rows of L + 1, one pad) and the hand-over of groups 1.. to
+// group 0 (2 per pixel); then the top channel's filtered row (T rows of L + 1
+// floats).
 constexpr int kRowSmemHead = 80 + 4 * kRowMaxL + 128 + 32;
 __host__ __device__ constexpr size_t hrow2_smem_bytes(int T, int groups, int L) {
-    return sizeof(float) * ((size_t)kRowSmemHead + (size_t)groups * 128) +
-           sizeof(double) * ((size_t)T * L + 2 * (size_t)(groups - 1) * (size_t)T * (size_t)L);
+    return sizeof(float) * ((size_t)kRowSmemHead + (size_t)groups * 128 + (size_t)T * (L + 1)) +
+           sizeof(double) * ((size_t)T * (L + 1) + 2 * (size_t)(groups - 1) * (size_t)T * (size_t)L);
 }
 
 // s[0..1] += P * (v0, v1), P a 2x2 matrix (row-major) in LDS
@@ -106,8 +110,11 @@ __device__ __forceinline__ void hrow2(const GPParams &p, const RowCoef &c, const
     float *Gt = homs + 4 * kRowMaxL;      // Gt[jj * 8 + 4 s + q] = Phi_s^(L jj)
     float *Gw = Gt + 128;                 // Gw[r * 8 + 4 s + q] = Phi_s^(16 L r), r = 0..3
     float *wtot = sm + kRowSmemHead + (size_t)g * 128;  // [2][8 waves][8]
-    double *taus = (double *)(sm + kRowSmemHead + (size_t)groups * 128);  // taus[i * T + t]
-    double *comb = taus + (size_t)T * L;
+    // per-thread rows of L + 1 (the odd stride puts the lanes of a wave on
+    // distinct banks; a thread's L values sit at immediate offsets)
+    double *taus = (double *)(sm + kRowSmemHead + (size_t)groups * 128) + (size_t)t * (L + 1);  // taus[i]
+    double *comb = (double *)(sm + kRowSmemHead + (size_t)groups * 128) + (size_t)T * (L + 1);
+    float *otop = (float *)(comb + 2 * (size_t)(groups - 1) * (size_t)T * L) + (size_t)t * (L + 1);  // otop[i]
 
     // the coefficient tables go through LDS (as kernel arguments held in
     // scalar registers they would spill)
@@ -141,27 +148,21 @@ __device__ __forceinline__ void hrow2(const GPParams &p, const RowCoef &c, const
         for (int i = 0; i < L; ++i) f[i] = irow[x0 + i < p.W ? x0 + i : p.W - 1];
 #pragma unroll
         for (int i = 0; i < L; ++i)
-            taus[i * T + t] = x0 + i < p.W ? (double)centred(f[i], st, p.inv_sigma_r) : 0.0;
+            taus[i] = x0 + i < p.W ? (double)centred(f[i], st, p.inv_sigma_r) : 0.0;
     }
     __syncthreads();
-    float gc[8], ga[8];  // Phi^(L jj) and Phi^(L (15 - jj)), both sections
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        gc[q] = Gt[jj * 8 + q];
-        ga[q] = Gt[(15 - jj) * 8 + q];
-    }
 
-    double bP[L], bC[L];  // Horner accumulators of D and of D' (+ the N+1 term)
+    double bP[L], bC[L];  // Horner accumulators of P and P' (relative to tau^cb)
 #pragma unroll
     for (int i = 0; i < L; ++i) {
         bP[i] = 0.0;
         bC[i] = 0.0;
     }
-    const int top = (ce - 1 < p.N ? ce - 1 : p.N);  // the group's highest channel <= N
     // 1 / sqrt(n!) of the group's first (highest) channel, then divided by
     // sqrt(n) at every step down
     double kap = 1.0;
     for (int n = 2; n < ce; ++n) kap *= p.isq[n];
+    const double ktop = kap;  // 1 / sqrt((N+1)!) in the group holding channel N+1
 
     // samples x0-1 .. x0+L+1 of channel n's stack row (columns W .. pitch-1
     // are zero pad; only the sample left of the row start is masked).  The
@@ -177,17 +178,13 @@ __device__ __forceinline__ void hrow2(const GPParams &p, const RowCoef &c, const
         z[L + 1] = srow[x0 + L];
         z[L + 2] = srow[x0 + L + 1];
     };
-    float zn[L + 3];
-    if (ce - 1 >= cb) load(zn, ce - 1);
-    for (int it = 0; it < steps; ++it) {
+    // one channel step: z holds channel n = ce - 1 - it, zn receives n - 1
+    auto step = [&](float *z, float *zn, int it) {
         const int n = ce - 1 - it;
         const bool act = n >= cb;  // uniform over the group
         float o[L];
         float sc[4], sa[4];
         if (act) {
-            float z[L + 3];
-#pragma unroll
-            for (int i = 0; i < L + 3; ++i) z[i] = zn[i];
             if (n - 1 >= cb) load(zn, n - 1);
             z[0] = x0 > 0 ? z[0] : 0.f;
             // 1. the chunk from rest
@@ -356,8 +353,8 @@ __device__ __forceinline__ void hrow2(const GPParams &p, const RowCoef &c, const
                 }
             }
         }
-        if constexpr (MODE == 1) continue;
-        if (!act) continue;
+        if constexpr (MODE == 1) return;
+        if (!act) return;
         // row-exclusive incoming states of the wave's rows (lanes 0..3): the
         // rows before (after) inside the wave plus the wave's incoming state
         // moved over the rows between; then each chunk fetches its row's
@@ -384,6 +381,12 @@ __device__ __forceinline__ void hrow2(const GPParams &p, const RowCoef &c, const
         // row (a shift by one lane) plus the row's incoming state moved over
         // the chunks between
         float ic[4], ia[4];
+        // (the power tables are read from LDS at their use: an opaque zero
+        // keeps the reads from being hoisted out of the channel loop, where
+        // they would hold 16 registers)
+        int jz0 = 0;
+        asm volatile("" : "+s"(jz0));
+        const int jz = jj + jz0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             ic[q] = dpp_f<kDppRowShr + 1>(sc[q]);
@@ -391,65 +394,73 @@ __device__ __forceinline__ void hrow2(const GPParams &p, const RowCoef &c, const
         }
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
-            acc2(&ic[2 * s], &gc[4 * s], qc[2 * s], qc[2 * s + 1]);
-            acc2(&ia[2 * s], &ga[4 * s], qa[2 * s], qa[2 * s + 1]);
+            acc2v(&ic[2 * s], Gt + jz * 8 + 4 * s, qc[2 * s], qc[2 * s + 1]);
+            acc2v(&ia[2 * s], Gt + (15 - jj + jz0) * 8 + 4 * s, qa[2 * s], qa[2 * s + 1]);
         }
-        // 3. homogeneous responses of the incoming states (by recursion)
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const float d1 = c.d1[s], d2 = c.d2[s];
-            float a1 = ic[2 * s], a2 = ic[2 * s + 1];
+        // 3. homogeneous responses of the incoming states: the response i
+        // samples after a state (a1, a2) of section s is alpha a1 + beta a2,
+        // (alpha, beta) the first row of Phi_s^(i+1) (four table entries per
+        // i; the anticausal states act from the chunk's right end).  The
+        // opaque zero keeps the table reads at their use (hoisted out of the
+        // loop they would hold 64 registers).
+        {
+            int z0 = 0;
+            asm volatile("" : "+s"(z0));
+            const float *hp = homs + z0;
 #pragma unroll
             for (int i = 0; i < L; ++i) {
-                const float h = fmaf(-d1, a1, -d2 * a2);
-                o[i] += h;
-                a2 = a1;
-                a1 = h;
-            }
-            float b1 = ia[2 * s], b2 = ia[2 * s + 1];
-#pragma unroll
-            for (int i = L - 1; i >= 0; --i) {
-                const float h = fmaf(-d1, b1, -d2 * b2);
-                o[i] += h;
-                b2 = b1;
-                b1 = h;
+                const float4 h = *(const float4 *)(hp + 4 * i);
+                o[i] = fmaf(h.x, ic[0], fmaf(h.y, ic[1], o[i]));
+                o[i] = fmaf(h.z, ic[2], fmaf(h.w, ic[3], o[i]));
+                o[L - 1 - i] = fmaf(h.x, ia[0], fmaf(h.y, ia[1], o[L - 1 - i]));
+                o[L - 1 - i] = fmaf(h.z, ia[2], fmaf(h.w, ia[3], o[L - 1 - i]));
             }
         }
-        // recombination (uniform branches on the channel index)
+        // the top channel's row is kept for taking its term out of D
         if (n == p.N + 1) {
-            // the top channel enters M only: seed of the derivative chain
-            const double k = (double)(p.N + 1) * kap;
 #pragma unroll
-            for (int i = 0; i < L; ++i) bC[i] = k * (double)o[i];
-        } else if (n == top) {
-            // the group's highest channel <= N starts the D chain
+            for (int i = 0; i < L; ++i) otop[i] = o[i];
+        }
+        // Horner step of P and P' (the same for every channel)
 #pragma unroll
-            for (int i = 0; i < L; ++i) bP[i] = kap * (double)o[i];
-        } else {
-#pragma unroll
-            for (int i = 0; i < L; ++i) {
-                const double tv = taus[i * T + t];
-                bC[i] = fma(bC[i], tv, bP[i]);
-                bP[i] = fma(bP[i], tv, kap * (double)o[i]);
-            }
+        for (int i = 0; i < L; ++i) {
+            const double tv = taus[i];
+            bC[i] = fma(bC[i], tv, bP[i]);
+            bP[i] = fma(bP[i], tv, kap * (double)o[i]);
         }
         kap *= p.sq[n];  // 1 / sqrt((n-1)!)
+    };
+    float zn[L + 3];
+    if (ce - 1 >= cb) load(zn, ce - 1);
+    for (int it = 0; it < steps; ++it) {
+        float z[L + 3];
+#pragma unroll
+        for (int i = 0; i < L + 3; ++i) z[i] = zn[i];
+        step(z, zn, it);
     }
     if constexpr (MODE == 1) return;
+    // D of this group: P without the top channel's term (the group holding
+    // channel N+1 subtracts a_{N+1} tau^(N+1-cb); uniform branch)
+    double bD[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) bD[i] = bP[i];
+    if (ce == p.C) {
+        const int e = p.N + 1 - cb;
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            const double tv = taus[i];
+            bD[i] = fma(-(ktop * (double)otop[i]), ipow(tv, e), bP[i]);
+        }
+    }
     if (groups > 1) {
         // parts of groups 1.. in the full sums, through LDS
         if (g > 0) {
-            // a group that holds channel N+1 alone (cb = N+1) has no D part;
-            // its seed was never multiplied by tau and stands for (N+1) a_{N+1}
-            // tau^N
-            const bool only_top = cb > p.N;
 #pragma unroll
             for (int i = 0; i < L; ++i) {
-                const double tv = taus[i * T + t];
-                const double tp = ipow(tv, only_top ? p.N : cb - 1);  // tau^(cb - 1), or tau^N
-                comb[((size_t)(g - 1) * 2 * L + 2 * i) * T + t] = only_top ? 0.0 : bP[i] * (tp * tv);
-                comb[((size_t)(g - 1) * 2 * L + 2 * i + 1) * T + t] =
-                    only_top ? tp * bC[i] : (double)cb * tp * bP[i] + tp * tv * bC[i];
+                const double tv = taus[i];
+                const double tp = ipow(tv, cb - 1);  // tau^(cb - 1)
+                comb[((size_t)(g - 1) * 2 * L + 2 * i) * T + t] = bD[i] * (tp * tv);
+                comb[((size_t)(g - 1) * 2 * L + 2 * i + 1) * T + t] = (double)cb * tp * bP[i] + tp * tv * bC[i];
             }
         }
         __syncthreads();
@@ -457,7 +468,7 @@ __device__ __forceinline__ void hrow2(const GPParams &p, const RowCoef &c, const
             for (int gg = 1; gg < groups; ++gg) {
 #pragma unroll
                 for (int i = 0; i < L; ++i) {
-                    bP[i] += comb[((size_t)(gg - 1) * 2 * L + 2 * i) * T + t];
+                    bD[i] += comb[((size_t)(gg - 1) * 2 * L + 2 * i) * T + t];
                     bC[i] += comb[((size_t)(gg - 1) * 2 * L + 2 * i + 1) * T + t];
                 }
             }
@@ -468,7 +479,7 @@ __device__ __forceinline__ void hrow2(const GPParams &p, const RowCoef &c, const
         for (int i = 0; i < L; ++i) {
             const int x = x0 + i;
             if (x < p.W) {
-                const double rho = bC[i] / bP[i];
+                const double rho = bC[i] / bD[i];
                 p.out[foff + (size_t)y * p.pitch + x] = st.ok ? (float)fma(p.sigma_r, rho, st.tc) : __builtin_nanf("");
             }
         }

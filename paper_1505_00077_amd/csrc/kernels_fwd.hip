@@ -20,7 +20,9 @@ __global__ __launch_bounds__(kBlock) void k_fir(GPParams p, FirTaps taps) {
     extern __shared__ float smem[];
     const Stats st = reduce_stats(p);
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) publish_stats(p, st);
-    fir_tile_auto<R, SAVE>(p, taps, st, blockIdx.y * fir_ty(R, SAVE), blockIdx.x * fir_tx(R, SAVE), smem);
+    const int t = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    const int tx = t % gridDim.x, ty = t / gridDim.x;
+    fir_tile_auto<R, SAVE>(p, taps, st, ty * fir_ty(R, SAVE), tx * fir_tx(R, SAVE), smem);
 }
 
 __global__ __launch_bounds__(kBlock) void k_direct(DirectArgs a) {
@@ -508,10 +510,17 @@ hipError_t launch_volume(const GPParams &pz, const GPParams &ps, const IirCoef &
     // 4. row direction and the recombination, frame by frame
     const dim3 rb(shs.T * shs.Gr);
     const size_t sm = hrow2_smem_bytes(shs.T, shs.Gr, shs.L);
-    if (sm > 65536) return hipErrorInvalidValue;
     const dim3 gr((unsigned)(T * py.H));
-#define BF_CALL(l) BF_LAUNCH("k_hrow", (k_hrow3<l>), gr, rb, sm, s, py, rcs, (const float *)vb.S2, vb.Hs, shs.P, \
-                             shs.T, shs.Gr, s_fstride)
+#define BF_CALL(l)                                                                                               \
+    {                                                                                                            \
+        if (sm > 65536) {                                                                                        \
+            static hipError_t attr = hipFuncSetAttribute((const void *)k_hrow3<l>,                               \
+                                                         hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024); \
+            if (attr != hipSuccess) return attr;                                                                 \
+        }                                                                                                        \
+        BF_LAUNCH("k_hrow", (k_hrow3<l>), gr, rb, sm, s, py, rcs, (const float *)vb.S2, vb.Hs, shs.P, shs.T,      \
+                  shs.Gr, s_fstride);                                                                            \
+    }
     BF_ROW2_SWITCH(shs.L, BF_CALL)
 #undef BF_CALL
     return hipGetLastError();

@@ -407,10 +407,14 @@ hipError_t launch_stk_iir(const GPParams &p0, const GPParams *pd, const StkOfs &
         }
     } else {
         const size_t sm = hrow2_smem_bytes(sh.T, sh.Gr, sh.L);
-        if (sm > 65536) return hipErrorInvalidValue;
         switch (sh.L) {
 #define BF_CASE(l)                                                                                              \
     case l:                                                                                                     \
+        if (sm > 65536) {                                                                                       \
+            static hipError_t attr = hipFuncSetAttribute((const void *)ks_hrow2<l>,                             \
+                                                         hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024); \
+            if (attr != hipSuccess) return attr;                                                                \
+        }                                                                                                       \
         BF_LAUNCH("k_hrow", (ks_hrow2<l>), dim3(p0.H, 1, B), dim3(sh.T * sh.Gr), sm, s, pd, rc, (const float *)S, \
                   o, sh.Hs, sh.P, sh.T, sh.Gr);                                                                 \
         break;

@@ -48,6 +48,24 @@ def test_forced_fir_wide_radii(bf):
         assert np.max(np.abs(outs[i] - oracle_gp(host[i], ss[i], sr[i], 20, "fir"))) <= 1e-3
 
 
+def test_wide_rows_batch(bf):
+    # rows of 5000 and 8192 samples: the row pass of such images needs more
+    # than 64 KiB of LDS per workgroup
+    shapes = [(3, 5000), (2, 8192), (40, 300)]
+    ss, sr = [6.0, 9.0, 7.0], [30.0, 25.0, 35.0]
+    host = [synthimg.voronoi_image(H, W, 40, seed=1200 + i) for i, (H, W) in enumerate(shapes)]
+    imgs = [to_dev(h) for h in host]
+    note("batched wide rows 5000 / 8192")
+    plan = bf.BatchPlan(imgs, ss, sr, 20, spatial="iir")
+    outs = [to_np(o) for o in plan.run()]
+    ref = singles(bf, imgs, ss, sr, spatial="iir")
+    f32 = lambda v: float(np.float32(v))
+    for i in range(len(imgs)):
+        assert np.array_equal(outs[i], ref[i]), i
+        err = np.max(np.abs(outs[i] - oracle_gp(host[i], f32(ss[i]), f32(sr[i]), 20, "iir")))
+        assert err <= 1e-3, (i, err)
+
+
 def test_small_uneven_batch(bf):
     shapes = [(37, 70), (128, 200), (300, 129), (1, 64), (64, 1), (513, 777), (90, 2048), (40, 3000), (20, 300)]
     ss = [1.0, 2.5, 6.0, 3.0, 1.5, 11.0, 4.5, 7.0, 5.0]

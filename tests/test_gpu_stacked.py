@@ -5,7 +5,7 @@ import pytest
 import torch
 
 import synthimg
-from gpu_util import note
+from gpu_util import note, oracle_gp
 
 pytestmark = pytest.mark.gpu
 
@@ -60,6 +60,21 @@ def test_stacked_pitched_batch_and_forward_without_saved(bf):
         torch.cuda.synchronize()
         for b in range(B):
             assert torch.equal(out[b], bf.gp_forward(x[b], ss, 25.0, 20, spatial=spatial)), b
+
+
+def test_stacked_wide_rows(bf):
+    # rows of 6000 samples: the fused row pass then needs more than 64 KiB of
+    # LDS per workgroup
+    B, H, W = 2, 3, 6000
+    x = _batch(B, H, W, 1300)
+    note("stacked iir wide rows 6000")
+    out = bf.gp_forward_stacked(x, 8.0, 25.0, 20, spatial="iir")
+    torch.cuda.synchronize()
+    for b in range(B):
+        o1 = bf.gp_forward(x[b], 8.0, 25.0, 20, spatial="iir")
+        assert torch.equal(out[b], o1), b
+        ref = oracle_gp(x[b].cpu().numpy(), 8.0, 25.0, 20, "iir")
+        assert np.max(np.abs(out[b].cpu().numpy().astype(np.float64) - ref)) <= 1e-3
 
 
 def test_gp_filter_batch_uses_stacked_path(bf):

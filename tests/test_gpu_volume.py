@@ -60,6 +60,15 @@ def test_volume_matches_oracle(bf, shape, ss, st, N):
     assert np.max(np.abs(got - ref(vol, ss, st, 30.0, N))) <= TOL
 
 
+@pytest.mark.parametrize("W", [5000, 8192])
+def test_volume_wide_frames(bf, W):
+    # frame rows past about 4000 samples need more than 64 KiB of LDS in the
+    # row pass (one row of 512 threads x 16 samples at 8192)
+    vol = video(3, 2, W, seed=W)
+    got = run(bf, vol, 3.0, 2.0, 30.0, 20)
+    assert np.max(np.abs(got - ref(vol, 3.0, 2.0, 30.0, 20))) <= TOL
+
+
 def test_single_frame_is_the_image_filter(bf):
     img = synthimg.voronoi_image(70, 90, 15, seed=51)
     got = run(bf, img[None], 5.0, 3.0, 30.0, 20)[0]
