@@ -138,16 +138,42 @@ def kernel_trace_table(trace_csv, top=16):
     return "\n".join(out)
 
 
+def sq_table(counter_csv, kernels=None):
+    """Markdown table of SQ counters per dispatch (mean over the dispatches of
+    each kernel and grid size) from a rocprofv3 `--pmc SQ_...` run: wave64
+    VALU, LDS and SALU instructions, waves, and the shader engines' busy
+    cycles (summed over the engines)."""
+    per = defaultdict(lambda: defaultdict(list))
+    for r in csv.DictReader(open(counter_csv)):
+        per[(_short(r["Kernel_Name"]), int(r["Grid_Size"]))][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    out = ["| kernel | grid | dispatches | VALU instr | LDS instr | SALU instr | waves | busy cycles |",
+           "|---|---:|---:|---:|---:|---:|---:|---:|"]
+    rows = []
+    for (name, grid), c in per.items():
+        if kernels and not any(name.startswith(k) for k in kernels):
+            continue
+        m = {k: sum(v) / len(v) for k, v in c.items()}
+        n = max(len(v) for v in c.values())
+        rows.append((-m.get("SQ_INSTS_VALU", 0), f"| `{name}` | {grid} | {n} | {m.get('SQ_INSTS_VALU', 0):.4g} | "
+                     f"{m.get('SQ_INSTS_LDS', 0):.4g} | {m.get('SQ_INSTS_SALU', 0):.4g} | "
+                     f"{m.get('SQ_WAVES', 0):.4g} | {m.get('SQ_BUSY_CYCLES', 0):.4g} |"))
+    out += [r for _, r in sorted(rows)]
+    return "\n".join(out)
+
+
 def main(argv):
     """python -m paper_1505_00077_amd.profiling counters FETCH.csv WRITE.csv COPY_BYTES
        python -m paper_1505_00077_amd.profiling stats KERNEL_STATS.csv
-       python -m paper_1505_00077_amd.profiling trace KERNEL_TRACE.csv"""
+       python -m paper_1505_00077_amd.profiling trace KERNEL_TRACE.csv
+       python -m paper_1505_00077_amd.profiling sq SQ_COUNTERS.csv [kernel prefix ...]"""
     if len(argv) >= 4 and argv[0] == "counters":
         print(json.dumps(counter_summary(argv[1], argv[2], int(argv[3])), indent=1))
     elif len(argv) >= 2 and argv[0] == "stats":
         print(kernel_stats_table(argv[1]))
     elif len(argv) >= 2 and argv[0] == "trace":
         print(kernel_trace_table(argv[1]))
+    elif len(argv) >= 2 and argv[0] == "sq":
+        print(sq_table(argv[1], argv[2:] or None))
     else:
         print(main.__doc__)
         return 2
