@@ -81,9 +81,9 @@ struct FirShape {
 __host__ __device__ constexpr int fir_smem_floats(int R, bool save = false) {
     return fir_reg(R, save)
                ? (fir_ch_ty(R, kFirRegTY, save) * fir_stage_floats(R, kFirRegTY) >
-                          2 * kFirRegTY * (kFirRegTX + 2 * R + 1)
+                          4 * kFirRegTY * (kFirRegTX + 2 * R + 1)
                       ? fir_ch_ty(R, kFirRegTY, save) * fir_stage_floats(R, kFirRegTY)
-                      : 2 * kFirRegTY * (kFirRegTX + 2 * R + 1))
+                      : 4 * kFirRegTY * (kFirRegTX + 2 * R + 1))
                : fir_ch(R, save) * fir_stage_floats(R, fir_region_ty(R, save));
 }
 
@@ -293,11 +293,11 @@ __device__ __forceinline__ void fir_tile(const GPParams &p, const FirTaps &taps,
 //   D' = sum_{n<=N} q_n (k * w_n),   M' = sum_{n=1}^{N+1} q_{n-1} (k * w_n),
 // the same D' = exp(tau^2/2) D and M' = exp(tau^2/2) M as the region variant.
 // w_n stays in the FP32 range for |x| <= 12 and n <= kFirRegMaxN + 1.
-// Per channel: threads 0 .. 223+2R update their region column and run its
-// column pass from registers into LDS (two buffers, one barrier per channel),
-// then every thread runs the row pass at its 7 pixels (one row segment; the
-// 32 threads of a row read LDS at a stride of 7 words, on distinct banks)
-// and accumulates D', M' in double.
+// Per pair of channels: threads 0 .. 223+2R update their region column and
+// run its column pass from registers into LDS (two pairs of buffers, one
+// barrier per pair), then every thread runs the row pass at its 7 pixels (one
+// row segment; the 32 threads of a row read LDS at a stride of 7 words, on
+// distinct banks) and accumulates D', M' in double.
 template <int R>
 __device__ __forceinline__ void fir_tile_reg(const GPParams &p, const FirTaps &taps, const Stats &st, int ty0,
                                              int tx0, float *smem) {
@@ -354,35 +354,35 @@ __device__ __forceinline__ void fir_tile_reg(const GPParams &p, const FirTaps &t
         }
     }
 
-    for (int n = 0; n < p.C; ++n) {
-        float *Bn = smem + (n & 1) * (TY * BP);
-        // column pass of channel n from registers
-        if (colt) {
-            if (n > 0) {
+    // column pass of the next channel from registers into B
+    auto column = [&](int n, float *B) {
+        if (n > 0) {
 #pragma unroll
-                for (int j = 0; j < RY; ++j) w[j] *= xc[j];
-            }
-            float acc[TY];
-#pragma unroll
-            for (int i = 0; i < TY; ++i) {
-                float a = 0.f;
-#pragma unroll
-                for (int d = -R; d <= R; ++d) a = fmaf(taps.k[d < 0 ? -d : d], w[i + R + d], a);
-                acc[i] = a;
-            }
-#pragma unroll
-            for (int i = 0; i < TY; ++i) Bn[i * BP + tid] = acc[i];
+            for (int j = 0; j < RY; ++j) w[j] *= xc[j];
         }
-        __syncthreads();
-        // row pass at the owned pixels
+        float acc[TY];
+#pragma unroll
+        for (int i = 0; i < TY; ++i) {
+            float a = 0.f;
+#pragma unroll
+            for (int d = -R; d <= R; ++d) a = fmaf(taps.k[d < 0 ? -d : d], w[i + R + d], a);
+            acc[i] = a;
+        }
+#pragma unroll
+        for (int i = 0; i < TY; ++i) B[i * BP + tid] = acc[i];
+    };
+    // row pass of channel n at the owned pixels, then the recombination
+    // (double): M' takes q_{n-1}, D' takes q_n; channel 0 only starts D',
+    // channel N+1 only ends M' (uniform branches)
+    auto row = [&](int n, const float *B) {
         float h[PX];
 #pragma unroll
         for (int i = 0; i < PX; ++i) h[i] = 0.f;
         {
-            const float *row = Bn + oy * BP + ox0;
+            const float *r = B + oy * BP + ox0;
 #pragma unroll
             for (int j = 0; j < PX + 2 * R; ++j) {
-                const float v = row[j];
+                const float v = r[j];
 #pragma unroll
                 for (int i = 0; i < PX; ++i) {
                     const int d = j - i;
@@ -390,8 +390,6 @@ __device__ __forceinline__ void fir_tile_reg(const GPParams &p, const FirTaps &t
                 }
             }
         }
-        // recombination (double): M' takes q_{n-1}, D' takes q_n; channel 0
-        // only starts D', channel N+1 only ends M' (uniform branches)
         if (n == 0) {
 #pragma unroll
             for (int i = 0; i < PX; ++i) Dp[i] = (double)h[i];
@@ -410,6 +408,21 @@ __device__ __forceinline__ void fir_tile_reg(const GPParams &p, const FirTaps &t
                 for (int i = 0; i < PX; ++i) Mp[i] = fma(q[i], (double)h[i], Mp[i]);
             }
         }
+    };
+    // two channels per step between barriers (pairs of buffers, alternating
+    // between steps): half the barriers, and each phase has two channels'
+    // independent work in flight
+    for (int n = 0; n < p.C; n += 2) {
+        const bool two = n + 1 < p.C;  // uniform
+        float *B0 = smem + ((n >> 1) & 1) * (2 * TY * BP);
+        float *B1 = B0 + TY * BP;
+        if (colt) {
+            column(n, B0);
+            if (two) column(n + 1, B1);
+        }
+        __syncthreads();
+        row(n, B0);
+        if (two) row(n + 1, B1);
     }
 
     const int gy = ty0 + oy;
