@@ -535,6 +535,7 @@ class BatchPlan:
 
     def __del__(self):
         plan = getattr(self, "_plan", None)
-        if plan is not None and plan.value:
-            bf_gp_plan_free(plan)
+        free = bf_gp_plan_free  # None once the interpreter tears the module down
+        if plan is not None and plan.value and free is not None:
+            free(plan)
             self._plan = None

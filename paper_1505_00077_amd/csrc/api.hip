@@ -496,11 +496,14 @@ IirShape iir_shape(int H, int W, int C, bool batch) {
     if (Gro < 1) Gro = 1;
     while (Gro > 1 && hrow_smem_bytes(sh.To, Gro, sh.Lo) > 65536) --Gro;
     sh.Gro = Gro;
-    // stack pitch: past the last chunk's right halo (two samples) of either
-    // row pass, rounded up to a 128-byte line so that every stack row starts
-    // on a line
-    const int span = sh.nseg * sh.T * sh.L > sh.To * sh.Lo ? sh.nseg * sh.T * sh.L : sh.To * sh.Lo;
-    sh.P = ((span + 2 + 31) / 32) * 32;
+    // stack pitch: the image columns rounded up to 4, then the zero pad that
+    // the loads of either row pass reach (a chunk that straddles the row end
+    // reads L + 2 columns past it; chunks wholly past the row end read the pad
+    // at the rounded width), rounded up to a 128-byte line so that every stack
+    // row starts on a line
+    const int W4 = (W + 3) & ~3;
+    const int Lm = sh.L > sh.Lo ? sh.L : sh.Lo;
+    sh.P = ((W4 + Lm + 2 + 31) / 32) * 32;
     sh.Hs = ((H + B - 1) / B) * B;
     return sh;
 }

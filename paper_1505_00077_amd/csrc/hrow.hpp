@@ -103,6 +103,10 @@ __device__ __forceinline__ void hrow2(const GPParams &p, const RowCoef &c, const
     const int wv = t >> 6;  // this chunk's wave in the group
     const int r16 = lane >> 4;  // this chunk's row of 16 lanes in the wave
     const int x0 = (seg * T + t) * L;
+    // where the chunk's stack samples are read: chunks wholly past the row end
+    // read the zero pad at the row width rounded up to 4 (the stack is no
+    // wider than the row plus that pad)
+    const int xl = x0 < p.W ? x0 : ((p.W + 3) & ~3);
     const int cb = (p.C * g) / groups, ce = (p.C * (g + 1)) / groups;
     const int steps = (p.C + groups - 1) / groups;  // channels of the largest group
     float *pws = sm;                      // pws[(10 s + j) * 4 + q] = Phi_s^(L 2^j)
@@ -169,14 +173,14 @@ __device__ __forceinline__ void hrow2(const GPParams &p, const RowCoef &c, const
     // next channel's samples are loaded while the current one is filtered.
     auto load = [&](float *z, int n) {
         const float *srow = S + ((size_t)n * sp_rows + y) * sp_pitch;
-        z[0] = srow[x0 > 0 ? x0 - 1 : 0];
+        z[0] = srow[xl > 0 ? xl - 1 : 0];
 #pragma unroll
         for (int i = 0; i < L; i += 4) {
-            const float4 q = *(const float4 *)(srow + x0 + i);
+            const float4 q = *(const float4 *)(srow + xl + i);
             z[1 + i] = q.x; z[2 + i] = q.y; z[3 + i] = q.z; z[4 + i] = q.w;
         }
-        z[L + 1] = srow[x0 + L];
-        z[L + 2] = srow[x0 + L + 1];
+        z[L + 1] = srow[xl + L];
+        z[L + 2] = srow[xl + L + 1];
     };
     // one channel step: z holds channel n = ce - 1 - it, zn receives n - 1
     auto step = [&](float *z, float *zn, int it) {

@@ -591,6 +591,7 @@ __device__ __forceinline__ void hrow(const GPParams &p, const IirCoef &c, const 
     const int lane = threadIdx.x & 63, wave = t >> 6, nw = T >> 6;
     const int r16 = lane >> 4, j16 = lane & 15;
     const int x0 = t * L;
+    const int xl = x0 < p.W ? x0 : ((p.W + 3) & ~3);  // chunks past the row end read the zero pad
     const bool member = g < groups;
     const int cb = member ? (p.C * g) / groups : p.C;
     const int ce = member ? (p.C * (g + 1)) / groups : p.C;
@@ -649,14 +650,14 @@ __device__ __forceinline__ void hrow(const GPParams &p, const IirCoef &c, const 
             // mask (the pitch is a multiple of 4 and the rows 16-byte aligned)
             const float *row = S + ((size_t)n * sp_rows + y) * sp_pitch;
             float z[L + 3];
-            z[0] = row[x0 > 0 ? x0 - 1 : 0];
+            z[0] = row[xl > 0 ? xl - 1 : 0];
 #pragma unroll
             for (int i = 0; i < L; i += 4) {
-                const float4 q = *(const float4 *)(row + x0 + i);
+                const float4 q = *(const float4 *)(row + xl + i);
                 z[1 + i] = q.x; z[2 + i] = q.y; z[3 + i] = q.z; z[4 + i] = q.w;
             }
-            z[L + 1] = row[x0 + L];
-            z[L + 2] = row[x0 + L + 1];
+            z[L + 1] = row[xl + L];
+            z[L + 2] = row[xl + L + 1];
             z[0] = x0 > 0 ? z[0] : 0.f;
 
             // 1. chunk from rest

@@ -38,8 +38,9 @@ struct IirShape {
     int Lo;  // the same for the row pass with the saved terms and the joint
     int To;  // filter (and the batched path): L 4, 8, 12 or 16, T <= 512
     int Gro;
-    int P;   // row pitch of the channel stack, >= max(nseg T L, To Lo) + 2, a
-             // multiple of 32 (columns W .. P-1 are zero)
+    int P;   // row pitch of the channel stack, >= W rounded up to 4 plus
+             // max(L, Lo) + 2, a multiple of 32 (columns W .. P-1 are zero;
+             // row-pass chunks past the row end read them)
     int Hs;  // rows per channel of the stack: H rounded up to a multiple of B
     int nseg;  // segments of T L = 8192 columns per row in the row pass (rows
                // wider than 8192, the plain forward only); 1 otherwise
