@@ -349,6 +349,24 @@ def test_iir_wide_rows(bf, W):
     assert err <= TOL
 
 
+@pytest.mark.parametrize("N", [0, 8, 64])
+def test_iir_row_segments_degrees_and_pitch(bf, N):
+    # two channels (N 0), a small degree and the largest degree across row
+    # segments, with a row pitch larger than the width
+    H, W = 3, 9001
+    img = synthimg.voronoi_image(H, W, 50, seed=N + 11)
+    base = torch.zeros(H, W + 37, device="cuda")
+    x = base[:, :W]
+    x.copy_(to_dev(img))
+    note(f"gp_forward pitched {H}x{W} N={N} iir")
+    out = torch.full((H, W + 37), -1.0, device="cuda")[:, :W]
+    bf.gp_forward(x, 6.0, 40.0, N, spatial="iir", out=out, check=True)
+    got = to_np(out)
+    err = np.max(np.abs(got - oracle_gp(img, 6.0, 40.0, N, "iir")))
+    print(f"N {N}: {err:.2e}")
+    assert err <= TOL
+
+
 @pytest.mark.parametrize("shape,ss", [((5, 12000), 25.0), ((37, 12000), 3.0), ((2, 16384), 40.0)])
 def test_iir_row_segments(bf, shape, ss):
     # wide support (sigma_s 25 and 40: the response reaches over a whole

@@ -54,6 +54,17 @@ def test_noalloc_saved_terms_and_headline_image():
         assert torch.equal(s_ref, s_got)
 
 
+def test_noalloc_wide_rows():
+    # rows past 8192 samples: the row segments' states live in the array too;
+    # a wide call, then a narrower one
+    dev = torch.device("cuda:0")
+    for (H, W), ss, spatial in (((3, 12000), 9.0, "iir"), ((5, 9000), 4.0, "box"), ((4, 3000), 9.0, "iir")):
+        img = torch.from_numpy(voronoi_image(H, W, 40, seed=W)).to(dev)
+        print(f"noalloc {spatial} {H}x{W} sigma_s {ss}", flush=True)
+        ref, got = _pair(img, ss, 30.0, 20, spatial)
+        assert torch.equal(ref, got), float((ref - got).abs().max())
+
+
 def test_noalloc_rejects_oversize_without_running():
     dev = torch.device("cuda:0")
     img = torch.zeros(2048, 2048, device=dev)
