@@ -91,7 +91,14 @@ __device__ __forceinline__ float bperm_f(float v, int src_lane) {
 // states of the segments before and after it (the end states moved over the
 // segments between by Phi^(T L)), added to the states its waves hand over.
 // segst: [row][segment][channel][8].  MODE 0: one segment per row.
-template <int L, int MODE = 0>
+//
+// SAVE (one channel group, MODE 0): the Horner scheme carries a third chain,
+// e <- e tau + c, which ends at P''/2, and the terms the backward pass needs
+// are stored: rho = M/D, drho/dtau = (M' - rho D') / D with M' = P'' and
+// D' = P' - (N+1) a_{N+1} tau^N (the derivatives in tau with the filtered
+// channels held fixed), and D itself (= exp(tau^2/2) times eq. (11)'s
+// denominator).
+template <int L, int MODE = 0, bool SAVE = false>
 __device__ __forceinline__ void hrow2(const GPParams &p, const RowCoef &c, const Stats &st, int y,
                                       const float *__restrict__ S, int sp_rows, int sp_pitch, float *sm, int T,
                                       int groups, size_t foff = 0, int seg = 0, int nseg = 1,
@@ -157,10 +164,12 @@ __device__ __forceinline__ void hrow2(const GPParams &p, const RowCoef &c, const
     __syncthreads();
 
     double bP[L], bC[L];  // Horner accumulators of P and P' (relative to tau^cb)
+    double bS[SAVE ? L : 1];  // SAVE: P''/2
 #pragma unroll
     for (int i = 0; i < L; ++i) {
         bP[i] = 0.0;
         bC[i] = 0.0;
+        if constexpr (SAVE) bS[i] = 0.0;
     }
     // 1 / sqrt(n!) of the group's first (highest) channel, then divided by
     // sqrt(n) at every step down
@@ -429,6 +438,7 @@ __device__ __forceinline__ void hrow2(const GPParams &p, const RowCoef &c, const
 #pragma unroll
         for (int i = 0; i < L; ++i) {
             const double tv = taus[i];
+            if constexpr (SAVE) bS[i] = fma(bS[i], tv, bC[i]);
             bC[i] = fma(bC[i], tv, bP[i]);
             bP[i] = fma(bP[i], tv, kap * (double)o[i]);
         }
@@ -485,6 +495,17 @@ __device__ __forceinline__ void hrow2(const GPParams &p, const RowCoef &c, const
             if (x < p.W) {
                 const double rho = bC[i] / bD[i];
                 p.out[foff + (size_t)y * p.pitch + x] = st.ok ? (float)fma(p.sigma_r, rho, st.tc) : __builtin_nanf("");
+                if constexpr (SAVE) {
+                    // one group (cb = 0): D' = P' - (N+1) a_{N+1} tau^N
+                    const double tv = taus[i];
+                    const double a = ktop * (double)otop[i];
+                    const double dD = fma(-(double)(p.N + 1) * a, ipow(tv, p.N), bC[i]);
+                    const size_t npx = (size_t)p.H * p.W, idx = (size_t)y * p.W + x;
+                    float *sv = (float *)p.saved;
+                    sv[idx] = (float)rho;
+                    sv[npx + idx] = (float)((2.0 * bS[i] - rho * dD) / bD[i]);
+                    ((double *)(sv + 2 * npx))[idx] = bD[i];
+                }
             }
         }
     }

@@ -576,13 +576,11 @@ __device__ __forceinline__ void affine2(float *r, const float *v, const float *P
 //   tau^cb / sqrt(cb!)                                  (bD),
 //   prod_{j=1}^{cb-1} tau sqrt(j+1) / j = tau^(cb-1) sqrt(cb!) / (cb-1)!  (bM),
 // and group 0 adds the shares of groups 1, 2, ... in that order.
-// SAVE (one channel group only): the Horner recursions are differentiated in
-// tau alongside (Ubar held fixed), dD <- rD (bD + tau dD) before each bD step
-// and likewise for bM, and the terms the backward pass needs are stored:
-// rho = M/D, drho/dtau = (dM - rho dD) / bD and D' = bD = exp(tau^2/2) D.
+// (The plain forward, its saved terms and the batches take the row pass of
+// hrow.hpp; this one serves the joint filter.)
 // sm: hrow_smem_bytes(T, groups, L) bytes.
 // foff: element offset of the image and output rows (a volume's frame).
-template <int L, bool SAVE = false, bool JOINT = false>
+template <int L, bool JOINT = false>
 __device__ __forceinline__ void hrow(const GPParams &p, const IirCoef &c, const Stats &st, int y,
                                      const float *__restrict__ S, int sp_rows, int sp_pitch, float *sm, int T,
                                      int groups, size_t foff = 0) {
@@ -622,7 +620,6 @@ __device__ __forceinline__ void hrow(const GPParams &p, const IirCoef &c, const 
 
     float tau[L];
     double bD[L], bM[L];
-    double dD[SAVE ? L : 1], dM[SAVE ? L : 1];
     {
         // unconditional loads from clamped columns, zeroed past the row end
         const float *irow = p.img + foff + (size_t)y * p.pitch;
@@ -633,10 +630,6 @@ __device__ __forceinline__ void hrow(const GPParams &p, const IirCoef &c, const 
             tau[i] = x0 + i < p.W ? centred(tau[i], st, p.inv_sigma_r) : 0.f;
             bD[i] = 0.0;
             bM[i] = 0.0;
-            if constexpr (SAVE) {
-                dD[i] = 0.0;
-                dM[i] = 0.0;
-            }
         }
     }
     for (int it = 0; it < steps; ++it) {
@@ -859,23 +852,17 @@ __device__ __forceinline__ void hrow(const GPParams &p, const IirCoef &c, const 
             for (int i = 0; i < L; ++i) {
                 const double ub = (double)o[i];
                 const double tv = (double)tau[i];
-                if constexpr (SAVE) {
-                    dD[i] = rD * fma(tv, dD[i], bD[i]);
-                    dM[i] = rM * fma(tv, dM[i], bM[i]);
-                }
                 bD[i] = fma(bD[i], tv * rD, ub);
                 bM[i] = fma(bM[i], tv * rM, ub);
             }
         } else if (n >= 1) {
 #pragma unroll
             for (int i = 0; i < L; ++i) {
-                if constexpr (SAVE) dM[i] = rM * fma((double)tau[i], dM[i], bM[i]);
                 bM[i] = fma(bM[i], (double)tau[i] * rM, (double)o[i]);
             }
         } else {
 #pragma unroll
             for (int i = 0; i < L; ++i) {
-                if constexpr (SAVE) dD[i] = rD * fma((double)tau[i], dD[i], bD[i]);
                 bD[i] = fma(bD[i], (double)tau[i] * rD, (double)o[i]);
             }
         }
@@ -916,13 +903,6 @@ __device__ __forceinline__ void hrow(const GPParams &p, const IirCoef &c, const 
                     continue;
                 }
                 p.out[foff + (size_t)y * p.pitch + x] = st.ok ? (float)fma(p.sigma_r, rho, st.tc) : __builtin_nanf("");
-                if constexpr (SAVE) {
-                    const size_t npx = (size_t)p.H * p.W, idx = (size_t)y * p.W + x;
-                    float *sv = (float *)p.saved;
-                    sv[idx] = (float)rho;
-                    sv[npx + idx] = (float)((dM[i] - rho * dD[i]) / bD[i]);
-                    ((double *)(sv + 2 * npx))[idx] = bD[i];
-                }
             }
         }
     }

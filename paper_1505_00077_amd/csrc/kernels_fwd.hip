@@ -160,7 +160,7 @@ __global__ __launch_bounds__(64) void k_vresolve(GPParams p, IirCoef c, int nb, 
     if (col < p.W) vresolve(p, c, nb, col, blockIdx.y, blockIdx.z, carry);
 }
 
-template <int L, bool SAVE, bool JOINT>
+template <int L, bool JOINT>
 __global__ __launch_bounds__(512, 1) void k_hrow(GPParams p, IirCoef c, const float *S, int srows, int sp, int T,
                                                  int groups) {
     extern __shared__ float sm[];
@@ -169,12 +169,13 @@ __global__ __launch_bounds__(512, 1) void k_hrow(GPParams p, IirCoef c, const fl
         for (int x = threadIdx.x; x < p.W; x += blockDim.x) p.out[(size_t)blockIdx.x * p.pitch + x] = __builtin_nanf("");
         return;
     }
-    hrow<L, SAVE, JOINT>(p, c, st, blockIdx.x, S, srows, sp, sm, T, groups);
+    hrow<L, JOINT>(p, c, st, blockIdx.x, S, srows, sp, sm, T, groups);
 }
 
 // Row pass + recombination of one image row (hrow2): T threads per channel
-// group, `groups` groups, T * groups <= 512.
-template <int L>
+// group, `groups` groups, T * groups <= 512 (SAVE: one group, the saved
+// terms stored too).
+template <int L, bool SAVE = false>
 __global__ __launch_bounds__(512) void k_hrow2(GPParams p, RowCoef c, const float *S, int srows, int sp, int T,
                                                int groups) {
     extern __shared__ float sm[];
@@ -183,7 +184,7 @@ __global__ __launch_bounds__(512) void k_hrow2(GPParams p, RowCoef c, const floa
         for (int x = threadIdx.x; x < p.W; x += blockDim.x) p.out[(size_t)blockIdx.x * p.pitch + x] = __builtin_nanf("");
         return;
     }
-    hrow2<L>(p, c, st, blockIdx.x, S, srows, sp, sm, T, groups);
+    hrow2<L, 0, SAVE>(p, c, st, blockIdx.x, S, srows, sp, sm, T, SAVE ? 1 : groups);
 }
 
 // Row pass of rows wider than one workgroup: segment blockIdx.y of row
@@ -326,30 +327,34 @@ hipError_t launch_fir(const GPParams &p, const FirTaps &t, int R, bool save, hip
 }
 
 
-// The row pass that stores the saved terms or recombines the joint filter
-// (chunks of sh.Lo samples, one channel group).
+// The row pass that recombines the joint filter (chunks of sh.Lo samples, one
+// channel group).
 template <int L>
-static void hrow_launch(const GPParams &p, const IirCoef &c, const IirShape &sh, const float *S, bool save,
-                        bool joint, hipStream_t s) {
+static void hrow_launch_joint(const GPParams &p, const IirCoef &c, const IirShape &sh, const float *S, hipStream_t s) {
     const dim3 rb(sh.To);
     const size_t sm = hrow_smem_bytes(sh.To, 1, sh.Lo);
-    if (joint)
-        BF_LAUNCH("k_hrow", (k_hrow<L, false, true>), dim3(p.H), rb, sm, s, p, c, S, sh.Hs, sh.P, sh.To, 1);
-    else
-        BF_LAUNCH("k_hrow", (k_hrow<L, true, false>), dim3(p.H), rb, sm, s, p, c, S, sh.Hs, sh.P, sh.To, 1);
+    BF_LAUNCH("k_hrow", (k_hrow<L, true>), dim3(p.H), rb, sm, s, p, c, S, sh.Hs, sh.P, sh.To, 1);
 }
 
-// The row pass of the plain forward (chunks of sh.L samples).
-template <int L>
-static hipError_t hrow2_launch(const GPParams &p, const RowCoef &c, const IirShape &sh, const float *S, hipStream_t s) {
-    const size_t sm = hrow2_smem_bytes(sh.T, sh.Gr, sh.L);
+// The row pass of the plain forward (chunks of sh.L samples); with the saved
+// terms in one channel group.
+template <int L, bool SAVE>
+static hipError_t hrow2_launch_s(const GPParams &p, const RowCoef &c, const IirShape &sh, const float *S,
+                                 hipStream_t s) {
+    const int gr = SAVE ? 1 : sh.Gr;
+    const size_t sm = hrow2_smem_bytes(sh.T, gr, sh.L);
     if (sm > 65536) {
-        static hipError_t attr = hipFuncSetAttribute((const void *)k_hrow2<L>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                     160 * 1024);
+        static hipError_t attr = hipFuncSetAttribute((const void *)k_hrow2<L, SAVE>,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (attr != hipSuccess) return attr;
     }
-    BF_LAUNCH("k_hrow", (k_hrow2<L>), dim3(p.H), dim3(sh.T * sh.Gr), sm, s, p, c, S, sh.Hs, sh.P, sh.T, sh.Gr);
+    BF_LAUNCH("k_hrow", (k_hrow2<L, SAVE>), dim3(p.H), dim3(sh.T * gr), sm, s, p, c, S, sh.Hs, sh.P, sh.T, gr);
     return hipSuccess;
+}
+template <int L>
+static hipError_t hrow2_launch(const GPParams &p, const RowCoef &c, const IirShape &sh, const float *S, bool save,
+                               hipStream_t s) {
+    return save ? hrow2_launch_s<L, true>(p, c, sh, S, s) : hrow2_launch_s<L, false>(p, c, sh, S, s);
 }
 
 #define BF_ROW2_SWITCH(Lv, CALL)                                                         \
@@ -435,17 +440,18 @@ hipError_t launch_iir(const GPParams &p, const IirCoef &c, const RowCoef &rc, co
     else
         vband_launch<32, false>(p, c, sh, gv, carry, S, cgr, cgp, joint, s);
     if (e != hipSuccess) return e;
-    if (save || joint) {
-        // the saved terms and the joint recombination: the row pass with the
-        // whole Horner sums in one group
+    if (joint) {
+        // the joint recombination: the row pass with the whole Horner sums of
+        // the channel pairs in one group
         switch (sh.Lo) {
-            case 4: hrow_launch<4>(p, c, sh, S, save, joint, s); break;
-            case 8: hrow_launch<8>(p, c, sh, S, save, joint, s); break;
-            case 12: hrow_launch<12>(p, c, sh, S, save, joint, s); break;
-            case 16: hrow_launch<16>(p, c, sh, S, save, joint, s); break;
+            case 4: hrow_launch_joint<4>(p, c, sh, S, s); break;
+            case 8: hrow_launch_joint<8>(p, c, sh, S, s); break;
+            case 12: hrow_launch_joint<12>(p, c, sh, S, s); break;
+            case 16: hrow_launch_joint<16>(p, c, sh, S, s); break;
             default: return hipErrorInvalidValue;
         }
     } else if (sh.nseg > 1) {
+        if (save) return hipErrorInvalidValue;  // the saved terms stop at 8192 columns
         if (sh.T != 512 || sh.L != kRowMaxL || !segst) return hipErrorInvalidValue;
         const size_t sm = hrow2_smem_bytes(512, 1, kRowMaxL);
         static hipError_t attr = [] {
@@ -461,7 +467,7 @@ hipError_t launch_iir(const GPParams &p, const IirCoef &c, const RowCoef &rc, co
         BF_LAUNCH("k_hrow_seg", k_hrow2seg<1>, grid, dim3(512), sm, s, p, rc, S, sh.Hs, sh.P, segst);
         BF_LAUNCH("k_hrow", k_hrow2seg<2>, grid, dim3(512), sm, s, p, rc, S, sh.Hs, sh.P, segst);
     } else {
-#define BF_CALL(l) e = hrow2_launch<l>(p, rc, sh, S, s)
+#define BF_CALL(l) e = hrow2_launch<l>(p, rc, sh, S, save, s)
         BF_ROW2_SWITCH(sh.L, BF_CALL)
 #undef BF_CALL
         if (e != hipSuccess) return e;

@@ -202,20 +202,6 @@ __global__ __launch_bounds__(64) void ks_vresolve(const GPParams *pd, IirCoef c,
 }
 
 template <int L, bool SAVE>
-__global__ __launch_bounds__(512, 1) void ks_hrow(const GPParams *pd, IirCoef c, const float *S0, StkOfs o, int srows,
-                                                  int sp, int T) {
-    extern __shared__ float sm[];
-    const GPParams &p = pd[blockIdx.z];
-    const float *S = shifted(S0, o.ws * blockIdx.z);
-    const Stats st = load_stats(p);
-    if (!st.ok) {
-        for (int x = threadIdx.x; x < p.W; x += blockDim.x) p.out[(size_t)blockIdx.x * p.pitch + x] = __builtin_nanf("");
-        return;
-    }
-    hrow<L, SAVE, false>(p, c, st, blockIdx.x, S, srows, sp, sm, T, 1);
-}
-
-template <int L>
 __global__ __launch_bounds__(512) void ks_hrow2(const GPParams *pd, RowCoef c, const float *S0, StkOfs o, int srows,
                                                 int sp, int T, int groups) {
     extern __shared__ float sm[];
@@ -226,7 +212,7 @@ __global__ __launch_bounds__(512) void ks_hrow2(const GPParams *pd, RowCoef c, c
         for (int x = threadIdx.x; x < p.W; x += blockDim.x) p.out[(size_t)blockIdx.x * p.pitch + x] = __builtin_nanf("");
         return;
     }
-    hrow2<L>(p, c, st, blockIdx.x, S, srows, sp, sm, T, groups);
+    hrow2<L, 0, SAVE>(p, c, st, blockIdx.x, S, srows, sp, sm, T, SAVE ? 1 : groups);
 }
 
 // ---- backward -------------------------------------------------------------------
@@ -393,33 +379,30 @@ hipError_t launch_stk_iir(const GPParams &p0, const GPParams *pd, const StkOfs &
         BF_LAUNCH("k_vband", (ks_vband<32, false>), dim3((cgr + cgp) * nb * sh.G, 1, B), dim3(64), 0, s, pd, c, carry, S,
                   o, sh.P, sh.G, cgr, cgp);
     }
-    if (save) {
-        const size_t sm = hrow_smem_bytes(sh.To, 1, sh.Lo);
-        switch (sh.Lo) {
-#define BF_CASE(l)                                                                                            \
-    case l:                                                                                                   \
-        BF_LAUNCH("k_hrow", (ks_hrow<l, true>), dim3(p0.H, 1, B), dim3(sh.To), sm, s, pd, c, (const float *)S, o, \
-                  sh.Hs, sh.P, sh.To);                                                                        \
-        break;
-            BF_CASE(4) BF_CASE(8) BF_CASE(12) BF_CASE(16)
-#undef BF_CASE
-            default: return hipErrorInvalidValue;
-        }
-    } else {
-        const size_t sm = hrow2_smem_bytes(sh.T, sh.Gr, sh.L);
+    {
+        // the row pass and the recombination (the saved terms in one channel
+        // group)
+        const int gr = save ? 1 : sh.Gr;
+        const size_t sm = hrow2_smem_bytes(sh.T, gr, sh.L);
         switch (sh.L) {
-#define BF_CASE(l)                                                                                              \
-    case l:                                                                                                     \
-        if (sm > 65536) {                                                                                       \
-            static hipError_t attr = hipFuncSetAttribute((const void *)ks_hrow2<l>,                             \
+#define BF_CASE2(l, sv)                                                                                           \
+    {                                                                                                             \
+        if (sm > 65536) {                                                                                         \
+            static hipError_t attr = hipFuncSetAttribute((const void *)ks_hrow2<l, sv>,                           \
                                                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024); \
-            if (attr != hipSuccess) return attr;                                                                \
-        }                                                                                                       \
-        BF_LAUNCH("k_hrow", (ks_hrow2<l>), dim3(p0.H, 1, B), dim3(sh.T * sh.Gr), sm, s, pd, rc, (const float *)S, \
-                  o, sh.Hs, sh.P, sh.T, sh.Gr);                                                                 \
+            if (attr != hipSuccess) return attr;                                                                  \
+        }                                                                                                         \
+        BF_LAUNCH("k_hrow", (ks_hrow2<l, sv>), dim3(p0.H, 1, B), dim3(sh.T * gr), sm, s, pd, rc, (const float *)S, \
+                  o, sh.Hs, sh.P, sh.T, gr);                                                                      \
+    }
+#define BF_CASE(l)                        \
+    case l:                               \
+        if (save) BF_CASE2(l, true)       \
+        else BF_CASE2(l, false)           \
         break;
             BF_CASE(4) BF_CASE(8) BF_CASE(12) BF_CASE(16)
 #undef BF_CASE
+#undef BF_CASE2
             default: return hipErrorInvalidValue;
         }
     }
