@@ -19,15 +19,17 @@
 namespace bfgp {
 
 // Two variants share each kernel.  The register-column variant (radii up to
-// kFirRegMaxR, forward without the saved terms) gives every thread one column
+// kFirRegMaxR, kFirRegMaxRSave with the saved terms) gives every thread one column
 // of the input region: its channel values stay in registers and its column
 // pass runs from them, so LDS only carries the column-filtered rows to the row
 // pass.  The region variant (below) stages the region in LDS; it serves wider
 // radii, the saved terms, and images the register variant cannot represent
 // (|x| > 12, degree above kFirRegMaxN), with the same tile shape.
 constexpr int kFirRegMaxR = 16;
+constexpr int kFirRegMaxRSave = 12;  // with the saved terms (two more FP64 sums per pixel)
+constexpr int kFirXcStride = 36;     // floats per thread of the x rows kept in LDS with the saved terms
 constexpr int kFirRegMaxN = 46;
-__host__ __device__ constexpr bool fir_reg(int R, bool save) { return !save && R <= kFirRegMaxR; }
+__host__ __device__ constexpr bool fir_reg(int R, bool save) { return R <= (save ? kFirRegMaxRSave : kFirRegMaxR); }
 
 // Output tile of a FIR launch: fir_tx(R, save) columns by fir_ty(R, save)
 // rows.  Kernels that can take the register variant use 8 x 224 tiles: the
@@ -81,9 +83,9 @@ struct FirShape {
 __host__ __device__ constexpr int fir_smem_floats(int R, bool save = false) {
     return fir_reg(R, save)
                ? (fir_ch_ty(R, kFirRegTY, save) * fir_stage_floats(R, kFirRegTY) >
-                          4 * kFirRegTY * (kFirRegTX + 2 * R + 1)
+                          4 * kFirRegTY * (kFirRegTX + 2 * R + 1) + (save ? kBlock * kFirXcStride : 0)
                       ? fir_ch_ty(R, kFirRegTY, save) * fir_stage_floats(R, kFirRegTY)
-                      : 4 * kFirRegTY * (kFirRegTX + 2 * R + 1))
+                      : 4 * kFirRegTY * (kFirRegTX + 2 * R + 1) + (save ? kBlock * kFirXcStride : 0))
                : fir_ch(R, save) * fir_stage_floats(R, fir_region_ty(R, save));
 }
 
@@ -298,7 +300,11 @@ __device__ __forceinline__ void fir_tile(const GPParams &p, const FirTaps &taps,
 // barrier per pair), then every thread runs the row pass at its 7 pixels (one
 // row segment; the 32 threads of a row read LDS at a stride of 7 words, on
 // distinct banks) and accumulates D', M' in double.
-template <int R>
+// SAVE: the terms the backward pass needs are stored as well: rho = M'/D',
+// drho/dtau = (dM'/dtau - rho dD'/dtau) / D' and D', with (filtered channels
+// held fixed) dD'/dtau = sum_{1<=n<=N} q_{n-1} (k * w_n) (M' without its
+// N+1 term) and dM'/dtau = sum_{n>=2} q_{n-2} (k * w_n).
+template <int R, bool SAVE = false>
 __device__ __forceinline__ void fir_tile_reg(const GPParams &p, const FirTaps &taps, const Stats &st, int ty0,
                                              int tx0, float *smem) {
     constexpr int TY = kFirRegTY, TX = kFirRegTX, RX = TX + 2 * R, RY = TY + 2 * R, BP = RX + 1;
@@ -309,7 +315,13 @@ __device__ __forceinline__ void fir_tile_reg(const GPParams &p, const FirTaps &t
     const bool colt = tid < RX;
 
     // ---- region column tid: centred x and w_0 = exp(-x^2/2) ----
-    float w[RY], xc[RY];
+    // SAVE: the column's x values wait in LDS (a row of kFirXcStride floats per
+    // thread after the four row-pass buffers; the stride is 4 more than a
+    // multiple of 32, so eight lanes' 16-byte reads fall on distinct banks),
+    // which leaves the registers to the two more FP64 sums per pixel
+    static_assert(!SAVE || RY <= kFirXcStride, "x row fits");
+    float w[RY], xc[SAVE ? 1 : RY];
+    float *xcs = smem + 4 * TY * BP + tid * kFirXcStride;
     {
         const int gx = tx0 - R + tid;
         const int xcl = gx < 0 ? 0 : (gx >= p.W ? p.W - 1 : gx);
@@ -326,7 +338,11 @@ __device__ __forceinline__ void fir_tile_reg(const GPParams &p, const FirTaps &t
             const int gy = ty0 - R + j;
             const bool in = inx && gy >= 0 && gy < p.H;
             const float x = in ? centred(f[j], st, p.inv_sigma_r) : 0.f;
-            xc[j] = x;
+            if constexpr (SAVE) {
+                if (colt) xcs[j] = x;
+            } else {
+                xc[j] = x;
+            }
             w[j] = in ? gauss_u0(x, 0) : 0.f;
         }
     }
@@ -335,6 +351,7 @@ __device__ __forceinline__ void fir_tile_reg(const GPParams &p, const FirTaps &t
     const int oy = tid / RT;
     const int ox0 = (tid % RT) * PX;
     double tau[PX], Dp[PX], Mp[PX], q[PX];
+    double Mt[SAVE ? PX : 1], qq[SAVE ? PX : 1], Dt[SAVE ? PX : 1];  // dM'/dtau, q_{n-2}, dD'/dtau
     {
         const int gy = ty0 + oy;
         const int yc = gy < p.H ? gy : p.H - 1;
@@ -351,14 +368,29 @@ __device__ __forceinline__ void fir_tile_reg(const GPParams &p, const FirTaps &t
             Dp[i] = 0.0;
             Mp[i] = 0.0;
             q[i] = 1.0;
+            if constexpr (SAVE) {
+                Mt[i] = 0.0;
+                qq[i] = 0.0;
+                Dt[i] = 0.0;
+            }
         }
     }
 
     // column pass of the next channel from registers into B
     auto column = [&](int n, float *B) {
         if (n > 0) {
+            if constexpr (SAVE) {
 #pragma unroll
-            for (int j = 0; j < RY; ++j) w[j] *= xc[j];
+                for (int j = 0; j + 3 < RY; j += 4) {
+                    const float4 v = *(const float4 *)(xcs + j);
+                    w[j] *= v.x; w[j + 1] *= v.y; w[j + 2] *= v.z; w[j + 3] *= v.w;
+                }
+#pragma unroll
+                for (int j = RY & ~3; j < RY; ++j) w[j] *= xcs[j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < RY; ++j) w[j] *= xc[j];
+            }
         }
         float acc[TY];
 #pragma unroll
@@ -399,13 +431,24 @@ __device__ __forceinline__ void fir_tile_reg(const GPParams &p, const FirTaps &t
 #pragma unroll
                 for (int i = 0; i < PX; ++i) {
                     const double hd = (double)h[i];
+                    if constexpr (SAVE) {
+                        Mt[i] = fma(qq[i], hd, Mt[i]);  // q_{n-2} (0 at n = 1)
+                        qq[i] = q[i];
+                    }
                     Mp[i] = fma(q[i], hd, Mp[i]);
                     q[i] *= tau[i] * rn;
                     Dp[i] = fma(q[i], hd, Dp[i]);
                 }
             } else {
 #pragma unroll
-                for (int i = 0; i < PX; ++i) Mp[i] = fma(q[i], (double)h[i], Mp[i]);
+                for (int i = 0; i < PX; ++i) {
+                    const double hd = (double)h[i];
+                    if constexpr (SAVE) {
+                        Mt[i] = fma(qq[i], hd, Mt[i]);
+                        Dt[i] = Mp[i];  // M' without the N+1 term
+                    }
+                    Mp[i] = fma(q[i], hd, Mp[i]);
+                }
             }
         }
     };
@@ -427,12 +470,20 @@ __device__ __forceinline__ void fir_tile_reg(const GPParams &p, const FirTaps &t
 
     const int gy = ty0 + oy;
     if (gy < p.H) {
+        const size_t npx = (size_t)p.H * p.W;
 #pragma unroll
         for (int i = 0; i < PX; ++i) {
             const int gx = tx0 + ox0 + i;
             if (gx < p.W) {
                 const double rho = Mp[i] / Dp[i];
                 p.out[(size_t)gy * p.pitch + gx] = st.ok ? (float)fma(p.sigma_r, rho, st.tc) : __builtin_nanf("");
+                if constexpr (SAVE) {
+                    const size_t idx = (size_t)gy * p.W + gx;
+                    float *sv = (float *)p.saved;
+                    sv[idx] = (float)rho;
+                    sv[npx + idx] = (float)(Mt[i] / Dp[i] - rho * Dt[i] / Dp[i]);
+                    ((double *)(sv + 2 * npx))[idx] = Dp[i];
+                }
             }
         }
     }
@@ -445,7 +496,7 @@ __device__ __forceinline__ void fir_tile_auto(const GPParams &p, const FirTaps &
                                               int tx0, float *smem) {
     if constexpr (fir_reg(R, SAVE)) {
         if (st.xmax <= 12.0 && p.N <= kFirRegMaxN) {
-            fir_tile_reg<R>(p, taps, st, ty0, tx0, smem);
+            fir_tile_reg<R, SAVE>(p, taps, st, ty0, tx0, smem);
         } else {
             for (int k = 0; k < kFirRegTX; k += 64) {
                 fir_tile<R, SAVE, kFirRegTY>(p, taps, st, ty0, tx0 + k, smem, tx0 + kFirRegTX);
