@@ -88,34 +88,42 @@ def step_model(kernel, C, band, fir_radii, n_iir, n_calls, HW):
 
 def launch_ids(stage, bf, H, W, C, fir_radii):
     """(kernel instantiation, grid threads) of every launch of `stage` in one
-    step, as the counter files name them."""
+    step, as the counter files name them (the launch shapes the library
+    chooses, restated here)."""
     if stage == "k_fir":
         return [(f"k_fir<{r}, false>", ((W + fir_tx(r) - 1) // fir_tx(r)) * ((H + fir_ty(r) - 1) // fir_ty(r)) * 256)
                 for r in fir_radii]
     sh = bf.iir_shape(H, W, C - 2)
     B, G, L, T, Gr = sh["band_rows"], sh["col_groups"], sh["row_chunk"], sh["row_threads"], sh["row_groups"]
-    P = ((T * L + 2 + 31) // 32) * 32
+    # stack pitch: the width rounded up to 4 plus the row passes' reach
+    # (16 + 2 columns at most), rounded up to 32
+    P = (((W + 3) // 4 * 4 + 16 + 2 + 31) // 32) * 32
     nb = (H + B - 1) // B
+    cg = (W + 63) // 64
     # 32-row bands in 2..8 channel groups run as k_vbandg (the groups of a
-    # band in one workgroup), with the same thread count
+    # band in one workgroup), with the same thread count; the end states of
+    # 32-row bands come from k_vagg (2 or 4 interleaved groups, 256 threads
+    # for one band (4 groups) or two (2 groups))
     vb = "k_vbandg" if B == 32 and 2 <= G <= 8 else "k_vband"
+    ga = 2 if 2 * cg * nb >= 2048 and C <= 24 else 4
+    agg = (f"k_vagg<32, {ga}>", (cg * nb if ga == 4 else (cg * nb + 1) // 2) * 256)
     return {
-        "k_hrow": [(f"k_hrow2<{L}>", H * T * Gr)],
+        "k_hrow": [(f"k_hrow2<{L}, false>", H * T * Gr)],
         "k_vband": [(f"{vb}<{B}, false, false>", ((P + 63) // 64) * nb * G * 64)],
-        "k_vband_agg": [(f"{vb}<{B}, true, false>", ((W + 63) // 64) * nb * G * 64)],
-        "k_vresolve": [("k_vresolve", ((W + 63) // 64) * 64 * C * 2)],
+        "k_vband_agg": [agg],
+        "k_vresolve": [("k_vresolve", cg * 64 * C * 2)],
         "k_stats": [("k_stats", min(H, 256) * 256)],
     }.get(stage, [])
 
 
 def fir_tx(r):
     """Columns of the FIR output tile for radius r (forward without saved terms)."""
-    return 128 if r <= 16 else 64
+    return 224 if r <= 16 else 64
 
 
 def fir_ty(r):
     """Rows of the FIR output tile for radius r (forward without saved terms)."""
-    return 32 if r == 17 else 16
+    return 8 if r <= 16 else (32 if r == 17 else 16)
 
 
 def main():
