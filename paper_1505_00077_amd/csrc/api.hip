@@ -852,9 +852,9 @@ static int bwd_check(const float *img, const float *grad_out, const void *saved,
 }
 
 // The IIR backward's buffers and channel groups for image buffers at the given
-// pointers and the workspace layout L at w.
+// pointers and the workspace layout L at w; nimg: the images of a stacked call.
 static BwdIir bwd_iir_args(const float *grad_out, const void *saved, float *grad_img, char *w, const BwdLayout &L,
-                           int H, int W, int N) {
+                           int H, int W, int N, int nimg = 1) {
     const size_t npx = (size_t)H * W;
     BwdIir b;
     memset(&b, 0, sizeof b);
@@ -869,7 +869,7 @@ static BwdIir bwd_iir_args(const float *grad_out, const void *saved, float *grad
     b.chz = (float *)(w + L.chz);
     b.bparts = (BwdPartial *)(w + L.bparts);
     b.Hp = L.Hp;
-    bwd_iir_groups(H, W, N + 2, &b.Gv, &b.Gh);
+    bwd_iir_groups(H, W, N + 2, nimg, &b.Gv, &b.Gh);
     // the tuning overrides of the column and row channel groups apply here too
     if (g_col_groups.load() > 0) b.Gv = g_col_groups.load() < N + 2 ? g_col_groups.load() : N + 2;
     if (g_row_groups.load() > 0) {
@@ -1031,7 +1031,7 @@ int bf_gp_backward_stacked(const float *img, const float *grad_out, const void *
     if (e == hipSuccess) e = launch_stk_stats(p0, pd, o, true, s);
     if (e != hipSuccess) return hip_fail(e, "statistics launch");
     if (spatial == BF_SPATIAL_IIR) {
-        const BwdIir b = bwd_iir_args(grad_out, saved, grad_img, w0, L, H, W, N);
+        const BwdIir b = bwd_iir_args(grad_out, saved, grad_img, w0, L, H, W, N, B);
         e = launch_stk_bwd_iir(p0, pd, b, o, make_iir_tan(sigma_s), corr, grad_log_sigma_s, grad_log_sigma_r, s);
     } else {
         const int R = fir_radius(sigma_s);

@@ -147,10 +147,12 @@ __device__ __forceinline__ void bvband(const GPParams &p, const BwdIir &b, const
         rr[i] = in ? r : 0.f;
         s[i] = in ? (double)g * p.sigma_r / dp : 0.0;
     }
-    if (cb > 1) {
-        const double cf = inv_sqrt_fact(p, cb - 1);
+    // a p_{cb-1} by the products the channels 1 .. cb-1 would apply in turn,
+    // so that every column grouping rounds the adjoint channels alike
+    for (int j = 1; j < cb; ++j) {
+        const double isqj = p.isq[j];
 #pragma unroll
-        for (int i = 0; i < B + 3; ++i) s[i] *= ipow((double)xr[i], cb - 1) * cf;  // a p_{cb-1}
+        for (int i = 0; i < B + 3; ++i) s[i] *= (double)xr[i] * isqj;
     }
     float *tp = tile, *tq = tile + B * 65;
     for (int n = cb; n < ce; ++n) {

@@ -113,9 +113,13 @@ int bwd_iir_parts(int H, int W) { return (iir_hp(H) / 64) * ((W + kBwdBH - 1) / 
 
 // Channel groups of the backward passes: enough waves for the device (about
 // two per SIMD), at most 8 (column pass) and 4 (row pass, one workgroup).
-void bwd_iir_groups(int H, int W, int C, int *Gv, int *Gh) {
+// The column groups count the waves of all nimg images of a stacked call (the
+// grouping does not change the column pass's rounding); the row groups, whose
+// partial sums are added per group, count one image's, so that a stacked call
+// and single calls give the same bits.
+void bwd_iir_groups(int H, int W, int C, int nimg, int *Gv, int *Gh) {
     const long target = 2048;
-    const long wv = (long)((W + 63) / 64) * ((H + kBwdBV - 1) / kBwdBV);
+    const long wv = (long)((W + 63) / 64) * ((H + kBwdBV - 1) / kBwdBV) * (nimg > 1 ? nimg : 1);
     const long wh = (long)(iir_hp(H) / 64) * ((W + kBwdBH - 1) / kBwdBH);
     long gv = (target + wv - 1) / wv, gh = (target + wh - 1) / wh;
     gv = gv < 1 ? 1 : (gv > 8 ? 8 : gv);

@@ -102,7 +102,7 @@ hipError_t launch_bwd(const GPParams &p, const BwdParams &b, const FirTaps2 &t, 
 struct BwdIir;
 struct IirTan;
 int bwd_iir_parts(int H, int W);
-void bwd_iir_groups(int H, int W, int C, int *Gv, int *Gh);
+void bwd_iir_groups(int H, int W, int C, int nimg, int *Gv, int *Gh);
 hipError_t launch_bwd_iir(const GPParams &p, const BwdIir &b, const IirTan &c, double *corr, double *g_lss,
                           double *g_lsr, hipStream_t s);
 
