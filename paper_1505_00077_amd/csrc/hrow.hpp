@@ -440,7 +440,9 @@ __device__ __forceinline__ void hrow2(const GPParams &p, const RowCoef &c, const
             const double tv = taus[i];
             if constexpr (SAVE) bS[i] = fma(bS[i], tv, bC[i]);
             bC[i] = fma(bC[i], tv, bP[i]);
-            bP[i] = fma(bP[i], tv, kap * (double)o[i]);
+            // bP tau + kap o with the product bP tau rounded: both updates
+            // then stay in their own registers
+            bP[i] = fma(kap, (double)o[i], bP[i] * tv);
         }
         kap *= p.sq[n];  // 1 / sqrt((n-1)!)
     };

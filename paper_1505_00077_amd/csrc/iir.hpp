@@ -397,14 +397,16 @@ __device__ __forceinline__ void vagg_moments(const GPParams &p, int col, int ban
 #pragma unroll
         for (int k = 0; k < 8; ++k) acc[n][k] = 0.f;
     constexpr int NR = B + 3;
-    // the next sample's prologue and weights are read one step ahead
+    // the next sample's prologue and weights are read one step ahead; the
+    // reads past the band's last sample land in the next array of the LDS
+    // (or its pad row) and are not used
     float xn = pro[lane], gn = pro[NR * 64 + lane];
     float4 w0n = *(const float4 *)wts, w1n = *(const float4 *)(wts + 4);
 #pragma unroll 1
     for (int i = 0; i < NR; ++i) {
         const float x = xn, g0 = gn;
         const float4 w0 = w0n, w1 = w1n;
-        const int in = i + 1 < NR ? i + 1 : i;
+        const int in = i + 1;
         xn = pro[in * 64 + lane];
         gn = pro[(NR + in) * 64 + lane];
         w0n = *(const float4 *)(wts + in * 8);
@@ -460,8 +462,10 @@ __host__ __device__ inline int agg_groups(int H, int W, int C) {
 }
 
 // LDS floats of one workgroup (four waves) of the weighted-sum end states:
-// the weights and one prologue per band it holds.
-__host__ __device__ constexpr int vagg_smem_floats(int B, int G) { return (B + 3) * 8 + (4 / G) * 2 * (B + 3) * 64; }
+// the weights, one prologue per band it holds and a pad row.
+__host__ __device__ constexpr int vagg_smem_floats(int B, int G) {
+    return (B + 3) * 8 + (4 / G) * 2 * (B + 3) * 64 + 64;  // + the pad row of the read-ahead
+}
 
 // Resolves, for one (column, channel) and one direction (dir 0 causal, top to
 // bottom; dir 1 anticausal, bottom to top), the true incoming states of every
