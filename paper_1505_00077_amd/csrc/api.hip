@@ -108,7 +108,7 @@ double range_limit(int N) {
 // Launch-shape overrides of the IIR passes (0 = automatic), for tuning.
 std::atomic<int> g_band_rows{0}, g_col_groups{0}, g_row_groups{0};
 // Waves the column passes aim for: a few per SIMD of the 1024 on the device.
-constexpr long kTargetWaves = 2048;
+constexpr long kTargetWaves = 2048, kBand64Waves = 1024;
 constexpr int kIirMaxW = 8192;       // IIR widths of the saved terms, joint, volume, batched and stacked calls
 constexpr int kIirMaxWide = 2 * kRowSeg;  // IIR widths of the plain forward (row segments)
 
@@ -427,10 +427,14 @@ namespace bfgp {
 IirShape iir_shape(int H, int W, int C, bool batch) {
     IirShape sh;
     const long cols = (W + 63) / 64;  // one wave per 64 columns of one band
-    // band height: 32 rows (measured faster than 64 at every size: more waves
-    // for the same work, and fewer registers per wave)
+    // band height: 64 rows once the image gives at least kBand64Waves column
+    // waves at that height (half the band carries of 32 rows: 11 instead of 22
+    // bytes per pixel written by the end-state pass and read by the column
+    // pass, and half the resolve's traffic; measured on MI355X: 4096^2 1.30 ->
+    // 1.21 ms, 2048^2 0.35 -> 0.34 ms), else 32 (more waves: 1024^2 is 0.11
+    // ms at 32 rows and 0.12 at 64).  A batch plan keeps 32 for all images.
     int B = g_band_rows.load();
-    if (B != 32 && B != 64) B = 32;
+    if (B != 32 && B != 64) B = (!batch && cols * ((H + 63) / 64) >= kBand64Waves) ? 64 : 32;
     sh.B = B;
     // channel groups of the column passes: each repeats the band's channel
     // generation up to its first channel, so only images with too few waves

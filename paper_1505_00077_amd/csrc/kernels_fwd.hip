@@ -43,7 +43,7 @@ __global__ __launch_bounds__(kBlock) void k_direct(DirectArgs a) {
 // column groups (cgp, column pass only: they store zeros) last, so that the
 // light pad workgroups fill in behind the full ones.
 template <int B, bool AGG, bool JOINT>
-__global__ __launch_bounds__(64, 3) void k_vband(GPParams p, IirCoef c, float *carry, float *S, int sp, int groups,
+__global__ __launch_bounds__(64, (B == 32 ? 3 : 2)) void k_vband(GPParams p, IirCoef c, float *carry, float *S, int sp, int groups,
                                                  int cgr, int cgp) {
     __shared__ float sacc[AGG ? 1 : B * 64];
     Stats st;
@@ -414,7 +414,12 @@ hipError_t launch_iir(const GPParams &p, const IirCoef &c, const RowCoef &rc, co
     // passes spill registers and measured slower)
     const bool grouped = !joint && sh.B == 32 && sh.G >= 2 && sh.G <= 8;
     hipError_t e = hipSuccess;
-    if (!joint && sh.B == 32 && p.C <= kAggMaxC) {
+    if (!joint && sh.B == 64 && p.C <= kAggMaxC) {
+        // 64-row bands (large images): four channel groups per band, one
+        // band per workgroup (the prologues of two bands would not fit the LDS)
+        const long bands = (long)cgr * nb;
+        BF_LAUNCH("k_vband_agg", (k_vagg<64, 4>), dim3((unsigned)bands), dim3(256), 0, s, p, c, carry, cgr);
+    } else if (!joint && sh.B == 32 && p.C <= kAggMaxC) {
         // end states by weighted sums, 2 or 4 channel groups per band
         const int G = agg_groups(p.H, p.W, p.C);
         const long bands = (long)cgr * nb;

@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void ks_vagg(const GPParams *pd, IirCoef c, fl
 }
 
 template <int B, bool AGG>
-__global__ __launch_bounds__(64, 3) void ks_vband(const GPParams *pd, IirCoef c, float *carry0, float *S0, StkOfs o,
+__global__ __launch_bounds__(64, (B == 32 ? 3 : 2)) void ks_vband(const GPParams *pd, IirCoef c, float *carry0, float *S0, StkOfs o,
                                                   int sp, int groups, int cgr, int cgp) {
     __shared__ float sacc[AGG ? 1 : B * 64];
     const GPParams &p = pd[blockIdx.z];
@@ -337,16 +337,23 @@ hipError_t launch_stk_fir(const GPParams &p0, const GPParams *pd, const StkOfs &
 }
 
 // The stages of launch_iir (same choices: end states by weighted sums for
-// 32-row bands of at most kAggMaxC channels, the grouped column passes for 2..8
-// channel groups, the row pass of the saved terms or hrow2), image blockIdx.z.
+// bands of at most kAggMaxC channels, the grouped column passes for 32-row
+// bands in 2..8 channel groups, the row pass of the saved terms or hrow2),
+// image blockIdx.z.
 hipError_t launch_stk_iir(const GPParams &p0, const GPParams *pd, const StkOfs &o, const IirCoef &c,
                           const RowCoef &rc, const IirShape &sh, float *carry, float *S, bool save, hipStream_t s) {
     const int nb = (p0.H + sh.B - 1) / sh.B;
     const int cgr = (p0.W + 63) / 64, cgp = (sh.P + 63) / 64 - cgr;
     const bool grouped = sh.B == 32 && sh.G >= 2 && sh.G <= 8;
     const unsigned B = (unsigned)o.B;
-    if (sh.B != 32) return hipErrorInvalidValue;
-    if (p0.C <= kAggMaxC) {
+    if (sh.B != 32 && sh.B != 64) return hipErrorInvalidValue;
+    if (sh.B == 64 && p0.C <= kAggMaxC) {
+        BF_LAUNCH("k_vband_agg", (ks_vagg<64, 4>), dim3((unsigned)(cgr * nb), 1, B), dim3(256), 0, s, pd, c, carry, o,
+                  cgr);
+    } else if (sh.B == 64) {
+        BF_LAUNCH("k_vband_agg", (ks_vband<64, true>), dim3(cgr * nb * sh.G, 1, B), dim3(64), 0, s, pd, c, carry, S, o,
+                  sh.P, sh.G, cgr, cgp);
+    } else if (p0.C <= kAggMaxC) {
         const int G = agg_groups(p0.H, p0.W, p0.C);
         const long bands = (long)cgr * nb;
         if (G == 2)
@@ -375,6 +382,9 @@ hipError_t launch_stk_iir(const GPParams &p0, const GPParams *pd, const StkOfs &
         if (attr != hipSuccess) return attr;
         BF_LAUNCH("k_vband", (ks_vbandg<32, false>), dim3((cgr + cgp) * nb, 1, B), dim3(64 * sh.G), smb, s, pd, c,
                   carry, S, o, sh.P, sh.G, cgr, cgp);
+    } else if (sh.B == 64) {
+        BF_LAUNCH("k_vband", (ks_vband<64, false>), dim3((cgr + cgp) * nb * sh.G, 1, B), dim3(64), 0, s, pd, c, carry, S,
+                  o, sh.P, sh.G, cgr, cgp);
     } else {
         BF_LAUNCH("k_vband", (ks_vband<32, false>), dim3((cgr + cgp) * nb * sh.G, 1, B), dim3(64), 0, s, pd, c, carry, S,
                   o, sh.P, sh.G, cgr, cgp);

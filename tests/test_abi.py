@@ -231,7 +231,7 @@ def test_iir_shape_rule_and_overrides():
     # automatic shapes: small images split the channels over more waves
     assert bf.iir_shape(1024, 1024, 20) == dict(band_rows=32, col_groups=4, row_chunk=16, row_threads=64,
                                                 row_groups=2)
-    assert bf.iir_shape(4096, 4096, 20) == dict(band_rows=32, col_groups=1, row_chunk=16, row_threads=256,
+    assert bf.iir_shape(4096, 4096, 20) == dict(band_rows=64, col_groups=1, row_chunk=16, row_threads=256,
                                                 row_groups=1)
     assert bf.iir_shape(512, 512, 20)["col_groups"] == 8
     assert bf.iir_shape(512, 512, 20)["row_groups"] == 4
@@ -252,6 +252,11 @@ def test_iir_shape_rule_and_overrides():
         assert (s["row_threads"], s["row_chunk"], s["row_groups"]) == (512, 16, 1)
     with pytest.raises(bf.BfError):
         bf.iir_shape(8, 16385, 20)
+    # 64-row bands where the image still gives 1024 column waves at that height
+    assert bf.iir_shape(1024, 1024, 20)["band_rows"] == 32
+    assert bf.iir_shape(2048, 2048, 20)["band_rows"] == 64
+    assert bf.iir_shape(4096, 4096, 20)["band_rows"] == 64
+    assert bf.iir_shape(64, 16384, 20)["band_rows"] == 32
     # never more channel groups than channels (N = 0: two channels)
     s = bf.iir_shape(64, 64, 0)
     assert s["col_groups"] <= 2 and s["row_groups"] <= 2

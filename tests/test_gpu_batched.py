@@ -21,11 +21,11 @@ def bf():
 
 def singles(bf, imgs, ss, sr, N=20, spatial="auto"):
     # the batch descriptor holds the sigmas as float32: use the same values;
-    # the batch runs its IIR images without channel groups, which single calls
-    # get under the tuning override (0, 1, 1)
+    # the batch runs its IIR images in 32-row bands without channel groups,
+    # which single calls get under the tuning override (32, 1, 1)
     f32 = lambda v: float(np.float32(v))
     try:
-        bf.set_iir_tuning(0, 1, 1)
+        bf.set_iir_tuning(32, 1, 1)
         return [to_np(bf.gp_forward(x, f32(s), f32(r), N, spatial=spatial, check=True))
                 for x, s, r in zip(imgs, ss, sr)]
     finally:

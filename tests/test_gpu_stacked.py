@@ -46,6 +46,35 @@ def test_stacked_forward_backward_equal_single_calls(bf, spatial, ss, shape, B):
         assert float(gs[b]) == float(gs1[0]) and float(gr[b]) == float(gr1[0]), b
 
 
+@pytest.mark.parametrize("tune", [(64, 0, 0), (64, 2, 1)])
+def test_stacked_band_rows_64(bf, tune):
+    # 64-row bands (the default of large images) in the stacked launches:
+    # still equal to single calls under the same shape, and to the oracle
+    B, H, W = 2, 150, 200
+    x = _batch(B, H, W, 1100)
+    g = _batch(B, H, W, 1150) - 128.0
+    try:
+        bf.set_iir_tuning(*tune)
+        note(f"stacked iir tuning {tune} shape {bf.iir_shape(H, W, 20)}")
+        saved = torch.empty(B, 16 * H * W, dtype=torch.uint8, device="cuda")
+        out = bf.gp_forward_stacked(x, 7.0, 30.0, 20, spatial="iir", saved=saved)
+        gi, gs, gr = bf.gp_backward_stacked(x, g, saved, 7.0, 30.0, 20, "iir")
+        torch.cuda.synchronize()
+        for b in range(B):
+            sv = bf.saved_buffer(H, W)
+            o1 = bf.gp_forward(x[b], 7.0, 30.0, 20, spatial="iir", saved=sv)
+            gi1, gs1, gr1 = bf.gp_backward(x[b], g[b], sv, 7.0, 30.0, 20, "iir")
+            torch.cuda.synchronize()
+            assert torch.equal(out[b], o1), b
+            assert torch.equal(saved[b], sv), b
+            assert torch.equal(gi[b], gi1), b
+            assert float(gs[b]) == float(gs1[0]) and float(gr[b]) == float(gr1[0]), b
+    finally:
+        bf.set_iir_tuning(0, 0, 0)
+    ref = oracle_gp(x[1].cpu().numpy(), 7.0, 30.0, 20, "iir")
+    assert np.max(np.abs(out[1].cpu().numpy().astype(np.float64) - ref)) <= 1e-3
+
+
 def test_stacked_pitched_batch_and_forward_without_saved(bf):
     # a batch with padded rows and a gap between images; the plain forward
     # (no saved terms) takes the fused row pass in the recursive mode
