@@ -137,7 +137,7 @@ __global__ __launch_bounds__(64, 3) void k_bband(const BatchImage *imgs, const B
 // channel groups, so that both give the same bits): item idx of an image
 // covers its bands 4 idx / G .. 4 (idx + 1) / G - 1, G waves per band.
 __global__ __launch_bounds__(256) void k_bagg(const BatchImage *imgs, const BatchItem *items) {
-    __shared__ float sm[vagg_smem_floats(32, 2)];
+    __shared__ float sm[vagg_smem_floats(32, 2)];  // at most two bands (G >= 2)
     float *wts = sm;
     const BatchItem w = items[blockIdx.x];
     const BatchImage &B = imgs[w.img];

@@ -461,10 +461,10 @@ __host__ __device__ inline int agg_groups(int H, int W, int C) {
     return (2 * bands >= kTargetAggWaves && C <= 2 * kAggG) ? 2 : 4;
 }
 
-// LDS floats of one workgroup (four waves) of the weighted-sum end states:
-// the weights, one prologue per band it holds and a pad row.
-__host__ __device__ constexpr int vagg_smem_floats(int B, int G) {
-    return (B + 3) * 8 + (4 / G) * 2 * (B + 3) * 64 + 64;  // + the pad row of the read-ahead
+// LDS floats of one workgroup of the weighted-sum end states holding NBW
+// bands: the weights, one prologue per band and a pad row.
+__host__ __device__ constexpr int vagg_smem_floats(int B, int NBW) {
+    return (B + 3) * 8 + NBW * 2 * (B + 3) * 64 + 64;  // + the pad row of the read-ahead
 }
 
 // Resolves, for one (column, channel) and one direction (dir 0 causal, top to

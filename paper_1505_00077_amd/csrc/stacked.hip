@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kBlock) void ks_fir(const GPParams *pd, FirTaps tap
 
 template <int B, int G>
 __global__ __launch_bounds__(256) void ks_vagg(const GPParams *pd, IirCoef c, float *carry0, StkOfs o, int cgr) {
-    __shared__ float sm[vagg_smem_floats(B, G)];
+    __shared__ float sm[vagg_smem_floats(B, 4 / G)];
     float *wts = sm;
     const GPParams &p = pd[blockIdx.z];
     float *carry = shifted(carry0, o.ws * blockIdx.z);
