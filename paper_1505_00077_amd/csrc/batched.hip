@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_bfir(const BatchImage *imgs, const B
 // after the statistics pass for IIR images.  The band height is the same for
 // every image of a plan (it depends on no image property).
 template <int BH, bool AGG>
-__global__ __launch_bounds__(64, 3) void k_bband(const BatchImage *imgs, const BatchItem *items) {
+__global__ __launch_bounds__(64, (BH == 32 ? 3 : 2)) void k_bband(const BatchImage *imgs, const BatchItem *items) {
     __shared__ float sacc[AGG ? 1 : BH * 64];
     const BatchItem w = items[blockIdx.x];
     const BatchImage &B = imgs[w.img];
@@ -135,17 +135,20 @@ __global__ __launch_bounds__(64, 3) void k_bband(const BatchImage *imgs, const B
 
 // End states by weighted sums (as the single-image k_vagg, with the same
 // channel groups, so that both give the same bits): item idx of an image
-// covers its bands 4 idx / G .. 4 (idx + 1) / G - 1, G waves per band.
+// covers its bands 4 idx / G .. 4 (idx + 1) / G - 1, G waves per band
+// (bands of 64 rows: four groups, one band per item).
+template <int BH>
 __global__ __launch_bounds__(256) void k_bagg(const BatchImage *imgs, const BatchItem *items) {
-    __shared__ float sm[vagg_smem_floats(32, 2)];  // at most two bands (G >= 2)
+    constexpr int NR = BH + 3;
+    __shared__ float sm[vagg_smem_floats(BH, BH == 32 ? 2 : 1)];  // at most two bands (G >= 2) of 32 rows
     float *wts = sm;
     const BatchItem w = items[blockIdx.x];
     const BatchImage &B = imgs[w.img];
     const Stats st = reduce_stats(B.p);
     if (w.idx == 0 && threadIdx.x == 0) publish_stats(B.p, st);
     if (!st.ok) return;
-    agg_weights<32>(B.c, wts);
-    const int G = agg_groups(B.p.H, B.p.W, B.p.C);
+    agg_weights<BH>(B.c, wts);
+    const int G = BH == 32 ? agg_groups(B.p.H, B.p.W, B.p.C) : 4;
     const int cgr = (B.p.W + 63) / 64;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int pr = wave / G, gw = wave % G;
@@ -153,20 +156,20 @@ __global__ __launch_bounds__(256) void k_bagg(const BatchImage *imgs, const Batc
     const bool live = pair < cgr * B.nb;
     const int cg = pair % cgr, band = pair / cgr;
     const int col = cg * 64 + (threadIdx.x & 63);
-    float *pro = sm + 35 * 8 + pr * 2 * 35 * 64;
+    float *pro = sm + NR * 8 + pr * 2 * NR * 64;
     const bool big = st.xmax > 12.0;
     if (live) {
         if (big)
-            vagg_prologue<32, true>(B.p, st, col, band, gw, G, pro);
+            vagg_prologue<BH, true>(B.p, st, col, band, gw, G, pro);
         else
-            vagg_prologue<32, false>(B.p, st, col, band, gw, G, pro);
+            vagg_prologue<BH, false>(B.p, st, col, band, gw, G, pro);
     }
     __syncthreads();
     if (!live) return;
     if (big)
-        vagg_moments<32, kAggG, true>(B.p, col, band, B.carry, gw, G, wts, pro);
+        vagg_moments<BH, kAggG, true>(B.p, col, band, B.carry, gw, G, wts, pro);
     else
-        vagg_moments<32, kAggG, false>(B.p, col, band, B.carry, gw, G, wts, pro);
+        vagg_moments<BH, kAggG, false>(B.p, col, band, B.carry, gw, G, wts, pro);
 }
 
 __global__ __launch_bounds__(kBlock) void k_bresolve(const BatchImage *imgs, const BatchItem *items) {
@@ -317,8 +320,8 @@ int bf_gp_plan_batched(const bf_gp_item *items, int count, unsigned flags, void 
             const int G = sh.G;
             const int cls = sh.T * sh.Gr / 64 - 1;  // T * Gr is a multiple of 64, at most 512
             row_smem[cls] = std::max(row_smem[cls], hrow2_smem_bytes(sh.T, sh.Gr, sh.L));
-            if (sh.B == 32 && (int)C <= kAggMaxC) {
-                const int G = agg_groups(it.H, it.W, (int)C);
+            if ((int)C <= kAggMaxC) {
+                const int G = sh.B == 32 ? agg_groups(it.H, it.W, (int)C) : 4;
                 const int nbands = (it.W + 63) / 64 * nb;
                 for (int t = 0; t < (nbands * G + 3) / 4; ++t) per[kStAggM].push_back({i, t});
             } else {
@@ -414,7 +417,12 @@ int bf_gp_forward_batched(void *plan, void *ws, size_t ws_bytes, void *stream) {
     if (n(kStFirWide))
         BF_LAUNCH("k_bfir", k_bfir<true>, dim3(n(kStFirWide)), dim3(kBlock), P->fir_smem[1], s, imgs, at(kStFirWide));
     if (n(kStAggM) || n(kStAgg)) {
-        if (n(kStAggM)) BF_LAUNCH("k_bband_agg", k_bagg, dim3(n(kStAggM)), dim3(256), 0, s, imgs, at(kStAggM));
+        if (n(kStAggM)) {
+            if (P->band_rows == 32)
+                BF_LAUNCH("k_bband_agg", k_bagg<32>, dim3(n(kStAggM)), dim3(256), 0, s, imgs, at(kStAggM));
+            else
+                BF_LAUNCH("k_bband_agg", k_bagg<64>, dim3(n(kStAggM)), dim3(256), 0, s, imgs, at(kStAggM));
+        }
         if (n(kStAgg)) {
             if (P->band_rows == 32)
                 BF_LAUNCH("k_bband_agg", (k_bband<32, true>), dim3(n(kStAgg)), dim3(64), 0, s, imgs, at(kStAgg));
