@@ -155,7 +155,22 @@ __device__ __forceinline__ void bvband(const GPParams &p, const BwdIir &b, const
         for (int i = 0; i < B + 3; ++i) s[i] *= (double)xr[i] * isqj;
     }
     float *tp = tile, *tq = tile + B * 65;
+    // the incoming states of the next channel are read while the current one
+    // is filtered (the rerun only)
+    float cinn[AGG ? 1 : 16];
+    auto load_in = [&](int n) {
+        const float *cq = b.cv + ((size_t)(band * p.C + n) * 16) * p.W + cl;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) cinn[k] = cq[(size_t)k * p.W];
+    };
+    if (!AGG && ce > cb) load_in(cb);
     for (int n = cb; n < ce; ++n) {
+        float cin[AGG ? 1 : 16];
+        if constexpr (!AGG) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) cin[k] = cinn[k];
+            if (n + 1 < ce) load_in(n + 1);
+        }
         float v[B + 3];
         if (n == 0) {
 #pragma unroll
@@ -179,10 +194,10 @@ __device__ __forceinline__ void bvband(const GPParams &p, const BwdIir &b, const
             if (!AGG) {
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
-                    y1[q] = cp[(4 * q + 0) * cs];
-                    y2[q] = cp[(4 * q + 1) * cs];
-                    t1[q] = cp[(4 * q + 2) * cs];
-                    t2[q] = cp[(4 * q + 3) * cs];
+                    y1[q] = cin[4 * q + 0];
+                    y2[q] = cin[4 * q + 1];
+                    t1[q] = cin[4 * q + 2];
+                    t2[q] = cin[4 * q + 3];
                 }
             }
 #pragma unroll
@@ -212,10 +227,10 @@ __device__ __forceinline__ void bvband(const GPParams &p, const BwdIir &b, const
             if (!AGG) {
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
-                    z1[q] = cp[(8 + 4 * q + 0) * cs];
-                    z2[q] = cp[(8 + 4 * q + 1) * cs];
-                    t1[q] = cp[(8 + 4 * q + 2) * cs];
-                    t2[q] = cp[(8 + 4 * q + 3) * cs];
+                    z1[q] = cin[8 + 4 * q + 0];
+                    z2[q] = cin[8 + 4 * q + 1];
+                    t1[q] = cin[8 + 4 * q + 2];
+                    t2[q] = cin[8 + 4 * q + 3];
                 }
             }
 #pragma unroll
@@ -321,8 +336,26 @@ __device__ __forceinline__ void bhband(const GPParams &p, const BwdIir &b, const
             h3[i] = 0.0;
         }
     }
+    // channel order of the pass: ascending for the end states, descending for
+    // the Horner sums; the rerun reads the incoming states of the next channel
+    // while the current one is filtered (reading the stack rows ahead as well
+    // measured slower: the registers cost the pass half its waves)
+    auto chan = [&](int it) { return AGG ? cb + it : ce - 1 - it; };
+    float cinn[AGG ? 1 : 16];
+    auto load_in = [&](int n) {
+        const float *cq = b.chz + ((size_t)(band * p.C + n) * 16) * Hp + yl;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) cinn[k] = cq[k * Hp];
+    };
+    if (!AGG && ce > cb) load_in(chan(0));
     for (int it = 0; it < ce - cb; ++it) {
-        const int n = AGG ? cb + it : ce - 1 - it;
+        const int n = chan(it);
+        float cin[AGG ? 1 : 16];
+        if constexpr (!AGG) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) cin[k] = cinn[k];
+            if (it + 1 < ce - cb) load_in(chan(it + 1));
+        }
         // samples a-1 .. a+B+1 of stack row n (clamped loads, masked)
         float P[B + 3], Q[B + 3];
         const float *pt = b.PT + (size_t)n * p.W * Hp + yl;
@@ -353,10 +386,10 @@ __device__ __forceinline__ void bhband(const GPParams &p, const BwdIir &b, const
             if (!AGG) {
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
-                    y1[q] = cp[(4 * q + 0) * Hp];
-                    y2[q] = cp[(4 * q + 1) * Hp];
-                    t1[q] = cp[(4 * q + 2) * Hp];
-                    t2[q] = cp[(4 * q + 3) * Hp];
+                    y1[q] = cin[4 * q + 0];
+                    y2[q] = cin[4 * q + 1];
+                    t1[q] = cin[4 * q + 2];
+                    t2[q] = cin[4 * q + 3];
                 }
             }
 #pragma unroll
@@ -385,10 +418,10 @@ __device__ __forceinline__ void bhband(const GPParams &p, const BwdIir &b, const
             if (!AGG) {
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
-                    z1[q] = cp[(8 + 4 * q + 0) * Hp];
-                    z2[q] = cp[(8 + 4 * q + 1) * Hp];
-                    t1[q] = cp[(8 + 4 * q + 2) * Hp];
-                    t2[q] = cp[(8 + 4 * q + 3) * Hp];
+                    z1[q] = cin[8 + 4 * q + 0];
+                    z2[q] = cin[8 + 4 * q + 1];
+                    t1[q] = cin[8 + 4 * q + 2];
+                    t2[q] = cin[8 + 4 * q + 3];
                 }
             }
 #pragma unroll
