@@ -178,6 +178,15 @@ __device__ __forceinline__ void vband(const GPParams &p, const IirCoef &c, const
         }
     }
     const size_t cstride = (size_t)p.W;
+    // the rerun reads the next channel's incoming states while the current
+    // one is filtered
+    float in8n[AGG ? 1 : 8];
+    auto load_in = [&](int n) {
+        const float *cq = carry + ((size_t)(band * p.C + n) * 8) * cstride + col;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) in8n[k] = cq[k * cstride];
+    };
+    if (!AGG && ce > cb) load_in(cb);
     for (int n = cb; n < ce; ++n) {
         const int deg = JOINT ? n >> 1 : n;
         const bool dat = JOINT && (n & 1);  // a joint data channel (uniform)
@@ -219,9 +228,10 @@ __device__ __forceinline__ void vband(const GPParams &p, const IirCoef &c, const
         float *cp = carry + ((size_t)(band * p.C + n) * 8) * cstride + col;
         // incoming states of both directions
         float in8[8];
-        if (!AGG) {
+        if constexpr (!AGG) {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) in8[k] = cp[k * cstride];
+            for (int k = 0; k < 8; ++k) in8[k] = in8n[k];
+            if (n + 1 < ce) load_in(n + 1);
         }
         // causal: both sections advance together; the sum is staged in LDS
         {
