@@ -44,6 +44,7 @@ constexpr int kBatchMaxW = 8192;
 struct BatchImage {
     GPParams p;
     IirCoef c;
+    AggW aw;  // end-state weights for the image's band height
     RowCoef rc;
     FirTaps taps;
     int iir;       // 0 FIR, 1 IIR
@@ -147,7 +148,7 @@ __global__ __launch_bounds__(256) void k_bagg(const BatchImage *imgs, const Batc
     const Stats st = reduce_stats(B.p);
     if (w.idx == 0 && threadIdx.x == 0) publish_stats(B.p, st);
     if (!st.ok) return;
-    agg_weights<BH>(B.c, wts);
+    for (int k = threadIdx.x; k < (BH + 3) * 8; k += blockDim.x) wts[k] = B.aw.w[k];
     const int G = BH == 32 ? agg_groups(B.p.H, B.p.W, B.p.C) : 4;
     const int cgr = (B.p.W + 63) / 64;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -380,6 +381,7 @@ int bf_gp_plan_upload(void *plan, void *ws, size_t ws_bytes, void *stream) {
         B.Sr = sh.Hs;
         if (B.iir) {
             B.c = iir_coef_for(it.sigma_s, sh.B, sh.Lo);
+            B.aw = make_agg_w(B.c, sh.B);
             B.rc = row_coef_for(it.sigma_s, sh.L);
             B.carry = (float *)(w + P->off_carry[i]);
             B.S = (float *)(w + P->off_S[i]);

@@ -38,6 +38,16 @@ struct IirCoef {
     float phiW[2][4];     // Phi^(64 L)
 };
 
+// Weights of the band end states as sums over the band's inputs (the
+// recursions' responses to unit inputs, agg_weight_task), computed once per
+// call on the host for bands of up to kAggMaxB rows and passed by value: the
+// kernels read them with scalar loads.  w[i * 8 + k]; one more row of eight
+// as the read-ahead pad.
+constexpr int kAggMaxB = 64;
+struct AggW {
+    float w[(kAggMaxB + 4) * 8];
+};
+
 // x^e for a small non-negative integer e (binary powering)
 __device__ __forceinline__ double ipow(double x, int e) {
     double r = 1.0;
@@ -309,48 +319,54 @@ __device__ __forceinline__ void vband(const GPParams &p, const IirCoef &c, const
 // z_{a+1} of both sections, from rest, with the true halo inputs) are linear
 // in the band's B + 3 input samples (rows a-1 .. a+B+1):
 //     e_k = sum_i w_k(i) u_n(x_i),   k = 0..7.
-// The weights are the recursion's responses to unit inputs; agg_weights
-// computes them (by running the same recursions on e_i, one thread per i)
-// into LDS.  Per sample and channel this costs one multiply (the next power)
+// The weights are the recursion's responses to unit inputs (agg_weight_task
+// runs the same recursions on e_i; the table is made once per call on the
+// host).  Per sample and channel this costs one multiply (the next power)
 // and eight FMAs instead of both recursions.  The channels are taken
 // unnormalised, p_n = exp(-x^2/2) x^n, and the end states are scaled by
 // 1/sqrt(n!) at the store; the powers stay in the FP32 range up to degree 47
 // (N <= 46), which the caller checks.
-// wts: (B + 3) * 8 floats, wts[i * 8 + k]; the workgroup's threads share
-// the 4 (B + 3) responses (position i, section s, direction).
-template <int B>
-__device__ __forceinline__ void agg_weights(const IirCoef &c, float *wts) {
-    for (int task = threadIdx.x; task < 4 * (B + 3); task += blockDim.x) {
-        const int i = task % (B + 3), s = (task / (B + 3)) & 1, anti = task / (2 * (B + 3));
-        if (!anti) {
-            // causal: inputs rows a-1 (i = 0) .. a+B-1 (i = B)
-            float y1 = 0.f, y2 = 0.f, xp = i == 0 ? 1.f : 0.f;
-            for (int j = 0; j < B; ++j) {
-                const float v = (j + 1 == i) ? 1.f : 0.f;
-                const float b = fmaf(c.n0[s], v, fmaf(c.n1[s], xp, -c.d2[s] * y2));
-                const float y = fmaf(-c.d1[s], y1, b);
-                y2 = y1;
-                y1 = y;
-                xp = v;
-            }
-            wts[i * 8 + 2 * s] = y1;
-            wts[i * 8 + 2 * s + 1] = y2;
-        } else {
-            // anticausal: inputs rows a+1 (i = 2) .. a+B+1 (i = B+2)
-            float z1 = 0.f, z2 = 0.f;
-            float xn1 = (B + 1 == i) ? 1.f : 0.f, xn2 = (B + 2 == i) ? 1.f : 0.f;
-            for (int j = B - 1; j >= 0; --j) {
-                const float b = fmaf(c.m1[s], xn1, fmaf(c.m2[s], xn2, -c.d2[s] * z2));
-                const float z = fmaf(-c.d1[s], z1, b);
-                z2 = z1;
-                z1 = z;
-                xn2 = xn1;
-                xn1 = (j + 1 == i) ? 1.f : 0.f;
-            }
-            wts[i * 8 + 4 + 2 * s] = z1;
-            wts[i * 8 + 5 + 2 * s] = z2;
+
+// One of the 4 (B + 3) responses (position i, section s, direction anti):
+// the two end states that the recursion from rest leaves for a unit input at
+// band position i (causal: rows a-1 (i = 0) .. a+B-1 (i = B); anticausal:
+// rows a+1 (i = 2) .. a+B+1 (i = B+2)), into wts[i * 8 + ...].
+__host__ __device__ inline void agg_weight_task(const IirCoef &c, int B, int task, float *wts) {
+    const int i = task % (B + 3), s = (task / (B + 3)) & 1, anti = task / (2 * (B + 3));
+    if (!anti) {
+        float y1 = 0.f, y2 = 0.f, xp = i == 0 ? 1.f : 0.f;
+        for (int j = 0; j < B; ++j) {
+            const float v = (j + 1 == i) ? 1.f : 0.f;
+            const float b = fmaf(c.n0[s], v, fmaf(c.n1[s], xp, -c.d2[s] * y2));
+            const float y = fmaf(-c.d1[s], y1, b);
+            y2 = y1;
+            y1 = y;
+            xp = v;
         }
+        wts[i * 8 + 2 * s] = y1;
+        wts[i * 8 + 2 * s + 1] = y2;
+    } else {
+        float z1 = 0.f, z2 = 0.f;
+        float xn1 = (B + 1 == i) ? 1.f : 0.f, xn2 = (B + 2 == i) ? 1.f : 0.f;
+        for (int j = B - 1; j >= 0; --j) {
+            const float b = fmaf(c.m1[s], xn1, fmaf(c.m2[s], xn2, -c.d2[s] * z2));
+            const float z = fmaf(-c.d1[s], z1, b);
+            z2 = z1;
+            z1 = z;
+            xn2 = xn1;
+            xn1 = (j + 1 == i) ? 1.f : 0.f;
+        }
+        wts[i * 8 + 4 + 2 * s] = z1;
+        wts[i * 8 + 5 + 2 * s] = z2;
     }
+}
+
+// The whole table for bands of B <= kAggMaxB rows (pad row zeroed).
+inline AggW make_agg_w(const IirCoef &c, int B) {
+    AggW a;
+    for (int k = 0; k < (kAggMaxB + 4) * 8; ++k) a.w[k] = 0.f;
+    for (int task = 0; task < 4 * (B + 3); ++task) agg_weight_task(c, B, task, a.w);
+    return a;
 }
 
 // Prologue of vagg_moments for the band's rows a-1 .. a+B+1 of one column
@@ -472,7 +488,8 @@ __host__ __device__ inline int agg_groups(int H, int W, int C) {
 }
 
 // LDS floats of one workgroup of the weighted-sum end states holding NBW
-// bands: the weights, one prologue per band and a pad row.
+// bands: the weights (the batched kernel's copy), one prologue per band and a
+// pad row.
 __host__ __device__ constexpr int vagg_smem_floats(int B, int NBW) {
     return (B + 3) * 8 + NBW * 2 * (B + 3) * 64 + 64;  // + the pad row of the read-ahead
 }

@@ -125,13 +125,11 @@ __global__ __launch_bounds__(512, 3) void k_vbandg(GPParams p, IirCoef c, float 
 // per-sample shift (xmax > 12) take the BIG branch, uniform over the launch.
 // The first kernel after the statistics pass: it reduces the partials itself.
 template <int B, int G, int NBW = 4 / G>
-__global__ __launch_bounds__(64 * G * NBW) void k_vagg(GPParams p, IirCoef c, float *carry, int cgr) {
+__global__ __launch_bounds__(64 * G * NBW) void k_vagg(GPParams p, AggW aw, float *carry, int cgr) {
     __shared__ float sm[vagg_smem_floats(B, NBW)];
-    float *wts = sm;
     const Stats st = reduce_stats(p);
     if (blockIdx.x == 0 && threadIdx.x == 0) publish_stats(p, st);
     if (!st.ok) return;  // uniform over the launch
-    agg_weights<B>(c, wts);
     const int nb = (p.H + B - 1) / B;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int pr = wave / G, gw = wave % G;
@@ -139,7 +137,7 @@ __global__ __launch_bounds__(64 * G * NBW) void k_vagg(GPParams p, IirCoef c, fl
     const bool live = pair < cgr * nb;
     const int cg = pair % cgr, band = pair / cgr;
     const int col = cg * 64 + (threadIdx.x & 63);
-    float *pro = sm + (B + 3) * 8 + pr * 2 * (B + 3) * 64;
+    float *pro = sm + pr * 2 * (B + 3) * 64;
     const bool big = st.xmax > 12.0;
     if (live) {
         if (big)
@@ -150,9 +148,9 @@ __global__ __launch_bounds__(64 * G * NBW) void k_vagg(GPParams p, IirCoef c, fl
     __syncthreads();
     if (!live) return;
     if (big)
-        vagg_moments<B, kAggG, true>(p, col, band, carry, gw, G, wts, pro);
+        vagg_moments<B, kAggG, true>(p, col, band, carry, gw, G, aw.w, pro);
     else
-        vagg_moments<B, kAggG, false>(p, col, band, carry, gw, G, wts, pro);
+        vagg_moments<B, kAggG, false>(p, col, band, carry, gw, G, aw.w, pro);
 }
 
 __global__ __launch_bounds__(64) void k_vresolve(GPParams p, IirCoef c, int nb, float *carry) {
@@ -419,16 +417,18 @@ hipError_t launch_iir(const GPParams &p, const IirCoef &c, const RowCoef &rc, co
         // band per workgroup (two groups in a workgroup of two waves measured
         // 2.5 % slower at 4096^2: half the waves per CU for the same LDS)
         const long bands = (long)cgr * nb;
-        BF_LAUNCH("k_vband_agg", (k_vagg<64, 4>), dim3((unsigned)bands), dim3(256), 0, s, p, c, carry, cgr);
+        BF_LAUNCH("k_vband_agg", (k_vagg<64, 4>), dim3((unsigned)bands), dim3(256), 0, s, p, make_agg_w(c, 64), carry,
+                  cgr);
     } else if (!joint && sh.B == 32 && p.C <= kAggMaxC) {
         // end states by weighted sums, 2 or 4 channel groups per band
         const int G = agg_groups(p.H, p.W, p.C);
         const long bands = (long)cgr * nb;
         if (G == 2)
-            BF_LAUNCH("k_vband_agg", (k_vagg<32, 2>), dim3((unsigned)((bands + 1) / 2)), dim3(256), 0, s, p, c, carry,
-                      cgr);
+            BF_LAUNCH("k_vband_agg", (k_vagg<32, 2>), dim3((unsigned)((bands + 1) / 2)), dim3(256), 0, s, p,
+                      make_agg_w(c, 32), carry, cgr);
         else
-            BF_LAUNCH("k_vband_agg", (k_vagg<32, 4>), dim3((unsigned)bands), dim3(256), 0, s, p, c, carry, cgr);
+            BF_LAUNCH("k_vband_agg", (k_vagg<32, 4>), dim3((unsigned)bands), dim3(256), 0, s, p, make_agg_w(c, 32),
+                      carry, cgr);
     } else if (grouped)
         e = vbandg_launch<true>(p, c, sh, carry, S, cgr, cgp, s);
     else if (sh.B == 64)

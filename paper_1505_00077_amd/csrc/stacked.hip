@@ -90,15 +90,13 @@ __global__ __launch_bounds__(kBlock) void ks_fir(const GPParams *pd, FirTaps tap
 // ---- recursive passes (the kernels of launch_iir, image blockIdx.z) -------------
 
 template <int B, int G>
-__global__ __launch_bounds__(256) void ks_vagg(const GPParams *pd, IirCoef c, float *carry0, StkOfs o, int cgr) {
+__global__ __launch_bounds__(256) void ks_vagg(const GPParams *pd, AggW aw, float *carry0, StkOfs o, int cgr) {
     __shared__ float sm[vagg_smem_floats(B, 4 / G)];
-    float *wts = sm;
     const GPParams &p = pd[blockIdx.z];
     float *carry = shifted(carry0, o.ws * blockIdx.z);
     const Stats st = reduce_stats(p);
     if (blockIdx.x == 0 && threadIdx.x == 0) publish_stats(p, st);
     if (!st.ok) return;
-    agg_weights<B>(c, wts);
     const int nb = (p.H + B - 1) / B;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int pr = wave / G, gw = wave % G;
@@ -106,7 +104,7 @@ __global__ __launch_bounds__(256) void ks_vagg(const GPParams *pd, IirCoef c, fl
     const bool live = pair < cgr * nb;
     const int cg = pair % cgr, band = pair / cgr;
     const int col = cg * 64 + (threadIdx.x & 63);
-    float *pro = sm + (B + 3) * 8 + pr * 2 * (B + 3) * 64;
+    float *pro = sm + pr * 2 * (B + 3) * 64;
     const bool big = st.xmax > 12.0;
     if (live) {
         if (big)
@@ -117,9 +115,9 @@ __global__ __launch_bounds__(256) void ks_vagg(const GPParams *pd, IirCoef c, fl
     __syncthreads();
     if (!live) return;
     if (big)
-        vagg_moments<B, kAggG, true>(p, col, band, carry, gw, G, wts, pro);
+        vagg_moments<B, kAggG, true>(p, col, band, carry, gw, G, aw.w, pro);
     else
-        vagg_moments<B, kAggG, false>(p, col, band, carry, gw, G, wts, pro);
+        vagg_moments<B, kAggG, false>(p, col, band, carry, gw, G, aw.w, pro);
 }
 
 template <int B, bool AGG>
@@ -348,8 +346,8 @@ hipError_t launch_stk_iir(const GPParams &p0, const GPParams *pd, const StkOfs &
     const unsigned B = (unsigned)o.B;
     if (sh.B != 32 && sh.B != 64) return hipErrorInvalidValue;
     if (sh.B == 64 && p0.C <= kAggMaxC) {
-        BF_LAUNCH("k_vband_agg", (ks_vagg<64, 4>), dim3((unsigned)(cgr * nb), 1, B), dim3(256), 0, s, pd, c, carry, o,
-                  cgr);
+        BF_LAUNCH("k_vband_agg", (ks_vagg<64, 4>), dim3((unsigned)(cgr * nb), 1, B), dim3(256), 0, s, pd,
+                  make_agg_w(c, 64), carry, o, cgr);
     } else if (sh.B == 64) {
         BF_LAUNCH("k_vband_agg", (ks_vband<64, true>), dim3(cgr * nb * sh.G, 1, B), dim3(64), 0, s, pd, c, carry, S, o,
                   sh.P, sh.G, cgr, cgp);
@@ -357,11 +355,11 @@ hipError_t launch_stk_iir(const GPParams &p0, const GPParams *pd, const StkOfs &
         const int G = agg_groups(p0.H, p0.W, p0.C);
         const long bands = (long)cgr * nb;
         if (G == 2)
-            BF_LAUNCH("k_vband_agg", (ks_vagg<32, 2>), dim3((unsigned)((bands + 1) / 2), 1, B), dim3(256), 0, s, pd, c,
-                      carry, o, cgr);
+            BF_LAUNCH("k_vband_agg", (ks_vagg<32, 2>), dim3((unsigned)((bands + 1) / 2), 1, B), dim3(256), 0, s, pd,
+                      make_agg_w(c, 32), carry, o, cgr);
         else
-            BF_LAUNCH("k_vband_agg", (ks_vagg<32, 4>), dim3((unsigned)bands, 1, B), dim3(256), 0, s, pd, c, carry, o,
-                      cgr);
+            BF_LAUNCH("k_vband_agg", (ks_vagg<32, 4>), dim3((unsigned)bands, 1, B), dim3(256), 0, s, pd,
+                      make_agg_w(c, 32), carry, o, cgr);
     } else if (grouped) {
         static hipError_t attr = hipFuncSetAttribute((const void *)ks_vbandg<32, true>,
                                                      hipFuncAttributeMaxDynamicSharedMemorySize,
