@@ -159,7 +159,7 @@ BoxShape box_shape(int H, int W, int C, int R) {
 
 // C: channels of the stack (N + 2 for the filter, 2 (N + 1) for the joint
 // filter).
-Layout gp_layout_c(int H, int W, int C, unsigned spatial) {
+Layout gp_layout_c(int H, int W, int C, unsigned spatial, bool rows32) {
     Layout L;
     size_t off = 0;
     L.parts = off;
@@ -170,7 +170,7 @@ Layout gp_layout_c(int H, int W, int C, unsigned spatial) {
     off = align256(off + sizeof(Stats));
     L.carry = L.stack = L.segst = off;
     if (spatial == BF_SPATIAL_IIR) {
-        const IirShape sh = iir_shape(H, W, C);
+        const IirShape sh = iir_shape(H, W, C, false, rows32);
         const size_t nb = ((size_t)H + sh.B - 1) / sh.B;
         L.carry = off;
         off = align256(off + sizeof(float) * nb * (size_t)C * 8 * (size_t)W);
@@ -186,7 +186,7 @@ Layout gp_layout_c(int H, int W, int C, unsigned spatial) {
     return L;
 }
 
-Layout gp_layout(int H, int W, int N, unsigned spatial) { return gp_layout_c(H, W, N + 2, spatial); }
+Layout gp_layout(int H, int W, int N, unsigned spatial) { return gp_layout_c(H, W, N + 2, spatial, false); }
 
 int check_image(const void *img, const void *out, int H, int W, int pitch) {
     if (!img || !out) return fail(BF_EINVAL, "null image pointer");
@@ -424,7 +424,7 @@ BwdLayout bwd_layout(int H, int W, int N, unsigned spatial) {
 
 // Helpers shared with the batched path (batched.hip).
 namespace bfgp {
-IirShape iir_shape(int H, int W, int C, bool batch) {
+IirShape iir_shape(int H, int W, int C, bool batch, bool rows32) {
     IirShape sh;
     const long cols = (W + 63) / 64;  // one wave per 64 columns of one band
     // band height: 64 rows once the image gives at least kBand64Waves column
@@ -432,9 +432,12 @@ IirShape iir_shape(int H, int W, int C, bool batch) {
     // bytes per pixel written by the end-state pass and read by the column
     // pass, and half the resolve's traffic; measured on MI355X: 4096^2 1.30 ->
     // 1.21 ms, 2048^2 0.35 -> 0.34 ms), else 32 (more waves: 1024^2 is 0.11
-    // ms at 32 rows and 0.12 at 64).  A batch plan keeps 32 for all images.
+    // ms at 32 rows and 0.12 at 64).  A batch plan keeps 32 for all images,
+    // and so do the callers that run 32-row bands only (rows32: the joint
+    // filter, whose three arrays of band samples would not fit the registers
+    // of 64-row bands, and the volume filter).
     int B = g_band_rows.load();
-    if (B != 32 && B != 64) B = (!batch && cols * ((H + 63) / 64) >= kBand64Waves) ? 64 : 32;
+    if (B != 32 && B != 64) B = (!batch && !rows32 && cols * ((H + 63) / 64) >= kBand64Waves) ? 64 : 32;
     sh.B = B;
     // channel groups of the column passes: each repeats the band's channel
     // generation up to its first channel, so only images with too few waves
@@ -657,7 +660,7 @@ int bf_gp_forward(const float *img, float *out, int H, int W, int pitch, double 
 size_t bf_gp_joint_workspace_bytes(int H, int W, int N, double sigma_s, unsigned flags) {
     if (H < 1 || W < 1 || N < 0 || N > BF_MAX_DEGREE || !finite_pos(sigma_s)) return 0;
     if ((flags & BF_SPATIAL_MASK) == BF_SPATIAL_FIR || (flags & BF_SPATIAL_MASK) == BF_SPATIAL_BOX) return 0;
-    return gp_layout_c(H, W, 2 * (N + 1), BF_SPATIAL_IIR).total;
+    return gp_layout_c(H, W, 2 * (N + 1), BF_SPATIAL_IIR, true).total;
 }
 
 int bf_gp_joint_forward(const float *guide, const float *data, float *out, int H, int W, int pitch, double sigma_s,
@@ -676,7 +679,7 @@ int bf_gp_joint_forward(const float *guide, const float *data, float *out, int H
     if ((rc = check_spatial(BF_SPATIAL_IIR, sigma_s, W))) return rc;
     if (W > kIirMaxW) return fail(BF_EUNSUPPORTED, "the joint filter supports widths up to %d", kIirMaxW);
     const int C = 2 * (N + 1);
-    const Layout L = gp_layout_c(H, W, C, BF_SPATIAL_IIR);
+    const Layout L = gp_layout_c(H, W, C, BF_SPATIAL_IIR, true);
     if (ws_bytes < L.total) return fail(BF_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
     hipStream_t s = (hipStream_t)stream;
     char *w = (char *)ws;
@@ -687,7 +690,7 @@ int bf_gp_joint_forward(const float *guide, const float *data, float *out, int H
     p.xlim = range_limit(N - 1);
     hipError_t e = launch_stats(p, false, s);
     if (e != hipSuccess) return hip_fail(e, "statistics launch");
-    const IirShape sh = iir_shape(H, W, C);
+    const IirShape sh = iir_shape(H, W, C, false, true);
     e = launch_iir(p, make_iir(sigma_s, sh.B, sh.Lo), make_row_coef(sigma_s, sh.L), sh, (float *)(w + L.carry),
                    (float *)(w + L.stack), false, true,
                    s);
@@ -707,9 +710,10 @@ VolLayout vol_layout(int T, int H, int W, int N) {
     VolLayout L;
     memset(&L, 0, sizeof L);
     const size_t C = (size_t)N + 2, HW = (size_t)H * W;
-    L.shz = iir_shape(T, (int)HW, (int)C);
+    // the volume kernels run 32-row bands only (also under a band-rows override)
+    L.shz = iir_shape(T, (int)HW, (int)C, false, true);
     L.shz.B = 32;
-    L.shs = iir_shape(T * H, W, (int)C);
+    L.shs = iir_shape(T * H, W, (int)C, false, true);
     L.shs.B = 32;
     L.Hs = ((H + 31) / 32) * 32;
     const size_t nbz = ((size_t)T + 31) / 32, nby = ((size_t)H + 31) / 32;

@@ -47,7 +47,7 @@ struct IirShape {
 };
 // batch: the image is one of many filtered together, which fill the device by
 // themselves: no channel groups unless the tuning overrides ask for them.
-IirShape iir_shape(int H, int W, int C, bool batch = false);
+IirShape iir_shape(int H, int W, int C, bool batch = false, bool rows32 = false);
 // save: also store the terms bf_gp_backward needs (p.saved), with the row pass
 // in one channel group.  joint: the joint filter (p.img the guide, p.data the
 // data, p.C = 2 (N + 1) stack channels), row pass in one channel group.

@@ -257,6 +257,10 @@ def test_iir_shape_rule_and_overrides():
     assert bf.iir_shape(2048, 2048, 20)["band_rows"] == 64
     assert bf.iir_shape(4096, 4096, 20)["band_rows"] == 64
     assert bf.iir_shape(64, 16384, 20)["band_rows"] == 32
+    # the joint filter keeps 32-row bands: its workspace at 4096^2 holds the
+    # carries of 128 bands
+    C = 2 * (20 + 1)
+    assert bf.bf_gp_joint_workspace_bytes(4096, 4096, 20, 10.0, bf._flags("iir")) >= 4 * 128 * C * 8 * 4096
     # never more channel groups than channels (N = 0: two channels)
     s = bf.iir_shape(64, 64, 0)
     assert s["col_groups"] <= 2 and s["row_groups"] <= 2
