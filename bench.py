@@ -101,12 +101,12 @@ def launch_ids(stage, bf, H, W, C, fir_radii):
     nb = (H + B - 1) // B
     cg = (W + 63) // 64
     # 32-row bands in 2..8 channel groups run as k_vbandg (the groups of a
-    # band in one workgroup), with the same thread count; the end states of
-    # 32-row bands come from k_vagg (2 or 4 interleaved groups, 256 threads
-    # for one band (4 groups) or two (2 groups))
+    # band in one workgroup), with the same thread count; the end states come
+    # from k_vagg (32-row bands: 2 or 4 interleaved groups, 256 threads for
+    # one band (4 groups) or two (2 groups); 64-row bands: 4 groups, one band)
     vb = "k_vbandg" if B == 32 and 2 <= G <= 8 else "k_vband"
-    ga = 2 if 2 * cg * nb >= 2048 and C <= 24 else 4
-    agg = (f"k_vagg<32, {ga}>", (cg * nb if ga == 4 else (cg * nb + 1) // 2) * 256)
+    ga = 2 if B == 32 and 2 * cg * nb >= 2048 and C <= 24 else 4
+    agg = (f"k_vagg<{B}, {ga}, {4 // ga}>", (cg * nb if ga == 4 else (cg * nb + 1) // 2) * 256)
     return {
         "k_hrow": [(f"k_hrow2<{L}, false>", H * T * Gr)],
         "k_vband": [(f"{vb}<{B}, false, false>", ((P + 63) // 64) * nb * G * 64)],
