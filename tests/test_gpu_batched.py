@@ -66,6 +66,30 @@ def test_wide_rows_batch(bf):
         assert err <= 1e-3, (i, err)
 
 
+def test_batch_band_rows_64(bf):
+    # a plan made under the 64-row band override (end states by weighted sums
+    # in four channel groups, the two-wave column pass): equal to single calls
+    # under the same override, and to the oracle
+    shapes = [(200, 150), (97, 300), (64, 64)]
+    ss, sr = [7.0, 10.0, 6.0], [30.0, 25.0, 35.0]
+    host = [synthimg.voronoi_image(H, W, 40, seed=1400 + i) for i, (H, W) in enumerate(shapes)]
+    imgs = [to_dev(h) for h in host]
+    note("batched plan with 64-row bands")
+    f32 = lambda v: float(np.float32(v))
+    try:
+        bf.set_iir_tuning(64, 1, 1)
+        plan = bf.BatchPlan(imgs, ss, sr, 20, spatial="iir")
+        outs = [to_np(o) for o in plan.run()]
+        ref = [to_np(bf.gp_forward(x, f32(s), f32(r), 20, spatial="iir", check=True))
+               for x, s, r in zip(imgs, ss, sr)]
+    finally:
+        bf.set_iir_tuning(0, 0, 0)
+    for i in range(len(imgs)):
+        assert np.array_equal(outs[i], ref[i]), (i, np.max(np.abs(outs[i] - ref[i])))
+        err = np.max(np.abs(outs[i] - oracle_gp(host[i], f32(ss[i]), f32(sr[i]), 20, "iir")))
+        assert err <= 1e-3, (i, err)
+
+
 def test_small_uneven_batch(bf):
     shapes = [(37, 70), (128, 200), (300, 129), (1, 64), (64, 1), (513, 777), (90, 2048), (40, 3000), (20, 300)]
     ss = [1.0, 2.5, 6.0, 3.0, 1.5, 11.0, 4.5, 7.0, 5.0]
