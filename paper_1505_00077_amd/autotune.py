@@ -18,13 +18,25 @@ the library as its size-dependent crossover table and stores it in a JSON
 cache keyed by device architecture, compute-unit count and degree.  `ensure()` loads the cached table, or
 tunes once when there is none.  Timing uses synthetic images on the device;
 the filter's cost does not depend on the pixel values.
+
+`plan_batch()` chooses the launch shape of a batch plan's recursive images
+(band height, channel groups of the column and of the row passes; every
+recursive image of a plan shares it) by timing one plan per candidate shape
+on the batch itself, and caches the choice under the batch's composition
+(the sizes, and for each image the spatial mode AUTO resolves), so that later
+plans of the same composition are built directly.  The launch shape decides
+the rounding of the recursive images (at the 1e-5 level on 0..255 data), so
+the chosen shape is returned with the plan: single calls made under the same
+tuning override give the same bits.
 """
+import hashlib
 import json
 import os
 
 import torch
 
-from . import (FIR_MAX_RADIUS, get_fir_crossover_table, gp_forward, set_fir_crossover_table, workspace)
+from . import (FIR_MAX_RADIUS, BatchPlan, get_fir_crossover_table, gp_forward, resolve_spatial,
+               set_fir_crossover_table, set_iir_tuning, workspace)
 
 # (H, W) ladder; each entry covers images up to its pixel count
 SIZES = ((256, 256), (512, 512), (1024, 1024), (2048, 2048), (4096, 4096))
@@ -139,3 +151,74 @@ def ensure(N=20, device="cuda", log=None):
     if table is None:
         table = tune(N, device=device, log=log)["table"]
     return get_fir_crossover_table() if table is not None else None
+
+
+# candidate launch shapes of a batch plan's recursive images: (band rows,
+# column channel groups, row channel groups), as set_iir_tuning takes them
+BATCH_SHAPES = ((32, 1, 1), (64, 1, 1), (32, 2, 2))
+
+
+def _batch_key(device, imgs, sigmas_s, N, spatial):
+    comp = sorted((int(x.shape[0]), int(x.shape[1]), resolve_spatial(float(s), spatial, shape=tuple(x.shape)))
+                  for x, s in zip(imgs, sigmas_s))
+    digest = hashlib.sha1(json.dumps(comp).encode()).hexdigest()[:16]
+    return f"{_key(device, N)}|batch|{digest}"
+
+
+def _plan_with(shape, imgs, sigmas_s, sigmas_r, N, spatial):
+    # the plan takes its launch shapes when it is made; the process-wide
+    # tuning override is cleared afterwards
+    set_iir_tuning(*shape)
+    try:
+        return BatchPlan(imgs, sigmas_s, sigmas_r, N, spatial=spatial)
+    finally:
+        set_iir_tuning(0, 0, 0)
+
+
+def tune_batch(imgs, sigmas_s, sigmas_r, N=20, spatial="auto", shapes=BATCH_SHAPES, reps=5, save=True, log=None):
+    """Times one plan of the batch per candidate shape (graph replays, median
+    of `reps`), caches the fastest and returns (plan, shape, {shape: ms})."""
+    device = imgs[0].device
+    best, timings = None, {}
+    for shape in shapes:
+        plan = _plan_with(shape, imgs, sigmas_s, sigmas_r, N, spatial)
+        plan.run()
+        g = plan.graph()
+        timings[tuple(shape)] = _time_ms(g.replay, reps)
+        if log:
+            log(f"batch plan shape {tuple(shape)}: {timings[tuple(shape)]:.3f} ms")
+        if best is None or timings[tuple(shape)] < timings[best[1]]:
+            best = (plan, tuple(shape))
+        del g
+    if save:
+        path = cache_path()
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            cache = {}
+            if os.path.exists(path):
+                with open(path) as f:
+                    cache = json.load(f)
+            cache[_batch_key(device, imgs, sigmas_s, N, spatial)] = {
+                "shape": list(best[1]), "ms": {",".join(map(str, k)): v for k, v in timings.items()}}
+            with open(path, "w") as f:
+                json.dump(cache, f, indent=1)
+        except OSError:
+            pass
+    return best[0], best[1], timings
+
+
+def plan_batch(imgs, sigmas_s, sigmas_r, N=20, spatial="auto", log=None):
+    """A BatchPlan built with the cached launch shape for this batch's
+    composition, tuned (tune_batch) when there is none; returns (plan,
+    shape)."""
+    device = imgs[0].device
+    try:
+        with open(cache_path()) as f:
+            entry = json.load(f).get(_batch_key(device, imgs, sigmas_s, N, spatial))
+    except (OSError, ValueError):
+        entry = None
+    if entry:
+        shape = tuple(int(v) for v in entry["shape"])
+        return _plan_with(shape, imgs, sigmas_s, sigmas_r, N, spatial), shape
+    plan, shape, _ = tune_batch(imgs, sigmas_s, sigmas_r, N, spatial, log=log)
+    return plan, shape

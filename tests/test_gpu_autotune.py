@@ -47,3 +47,39 @@ def test_tune_installs_a_table(bf, tmp_path, monkeypatch):
         assert np.max(np.abs(got - oracle_gp(img, ss, 30.0, 20, mode))) <= 1e-3
     finally:
         bf.set_fir_crossover_table([])
+
+
+def test_batch_plan_shape_is_tuned_and_cached(bf, tmp_path, monkeypatch):
+    # the batch tuner times one plan per candidate launch shape, keeps the
+    # fastest and caches it by the batch's composition; the plan it returns
+    # gives the bits of single calls made under the same shape
+    from paper_1505_00077_amd import autotune
+    monkeypatch.setenv(autotune.CACHE_ENV, str(tmp_path / "crossover.json"))
+    shapes = [(300, 400), (128, 700), (520, 260)]
+    ss, sr = [8.0, 10.0, 7.0], [30.0, 25.0, 35.0]
+    host = [synthimg.voronoi_image(H, W, 50, seed=1500 + i) for i, (H, W) in enumerate(shapes)]
+    imgs = [to_dev(h) for h in host]
+    note("batch plan shape tuner")
+    plan, shape, timings = autotune.tune_batch(imgs, ss, sr, 20, spatial="iir", reps=3)
+    assert set(timings) == set(autotune.BATCH_SHAPES) and timings[shape] == min(timings.values())
+    outs = [to_np(o) for o in plan.run()]
+    f32 = lambda v: float(np.float32(v))
+    try:
+        bf.set_iir_tuning(*shape)
+        ref = [to_np(bf.gp_forward(x, f32(s), f32(r), 20, spatial="iir", check=True)) for x, s, r in zip(imgs, ss, sr)]
+    finally:
+        bf.set_iir_tuning(0, 0, 0)
+    for i in range(len(imgs)):
+        assert np.array_equal(outs[i], ref[i]), (i, shape)
+    err = np.max(np.abs(outs[0] - oracle_gp(host[0], f32(ss[0]), f32(sr[0]), 20, "iir")))
+    assert err <= 1e-3, err
+    # a later plan of the same composition takes the cached shape
+    plan2, shape2 = autotune.plan_batch(imgs, ss, sr, 20, spatial="iir")
+    assert shape2 == shape
+    for o2, o in zip(plan2.run(), outs):
+        assert np.array_equal(to_np(o2), o)
+    # every candidate shape computes the same filter
+    for cand in autotune.BATCH_SHAPES:
+        p = autotune._plan_with(cand, imgs, ss, sr, 20, "iir")
+        got = to_np(p.run()[0])
+        assert np.max(np.abs(got - outs[0])) <= 1e-3, cand
