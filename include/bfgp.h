@@ -226,7 +226,10 @@ int bf_gp_get_fir_crossover_table(long long *max_pixels, int *radius, int max);
 
 /* Launch-shape overrides of the IIR mode, process-wide, for tuning (0 restores
  * the automatic choice):
- *   band_rows   0, 32 or 64: rows per band of the column passes;
+ *   band_rows   0, 32 or 64: rows per band of the column passes (automatic:
+ *               64 where the image gives at least 1024 column waves of 64
+ *               rows, else 32; 32 for batched plans, the joint filter and
+ *               the volume filter, which runs 32 whatever the override);
  *   col_groups  0..8: channel groups of the column passes;
  *   row_groups  0..8: channel groups of the row pass (capped by the row width
  *               and by the channel count).
