@@ -108,7 +108,7 @@ double range_limit(int N) {
 // Launch-shape overrides of the IIR passes (0 = automatic), for tuning.
 std::atomic<int> g_band_rows{0}, g_col_groups{0}, g_row_groups{0};
 // Waves the column passes aim for: a few per SIMD of the 1024 on the device.
-constexpr long kTargetWaves = 2048, kBand64Waves = 1024;
+constexpr long kTargetWaves = 2048, kBand64Waves = 1024, kRowTargetWaves = 3072;
 constexpr int kIirMaxW = 8192;       // IIR widths of the saved terms, joint, volume, batched and stacked calls
 constexpr int kIirMaxWide = 2 * kRowSeg;  // IIR widths of the plain forward (row segments)
 
@@ -473,8 +473,12 @@ IirShape iir_shape(int H, int W, int C, bool batch, bool rows32) {
     int Gr = g_row_groups.load();
     if (Gr < 1 && batch) Gr = 1;
     if (Gr < 1) {
+        // the row pass holds three waves per SIMD (its registers): as many
+        // channel groups as fill that once, and no more (a second, partial
+        // round costs more than the groups gain: 1024^2 takes 104 us for the
+        // forward with three groups, 110 with two and 116 with four)
         const long waves = (long)H * (sh.T / 64);
-        Gr = (int)((kTargetWaves + waves - 1) / waves);
+        Gr = (int)(kRowTargetWaves / waves);
         if (Gr > 4) Gr = 4;
     }
     if (Gr > 512 / sh.T) Gr = 512 / sh.T;

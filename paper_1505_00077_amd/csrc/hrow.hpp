@@ -55,13 +55,13 @@ struct RowCoef {
 // homogeneous-response table (16 x 4), the per-lane power table (16 x 8), the
 // per-row power table (4 x 8), the wave totals of every group
 // (double-buffered, 2 x 8 x 8 each); then as doubles the centred intensities
-// of the row (T rows of L + 1, one pad) and the hand-over of groups 1.. to
-// group 0 (2 per pixel); then the top channel's filtered row (T rows of L + 1
-// floats).
+// of the row (T rows of L + 1, one pad) and, with groups, the hand-over of one
+// group at a time to group 0 (2 per pixel); then the top channel's filtered
+// row (T rows of L + 1 floats).
 constexpr int kRowSmemHead = 80 + 4 * kRowMaxL + 128 + 32;
 __host__ __device__ constexpr size_t hrow2_smem_bytes(int T, int groups, int L) {
     return sizeof(float) * ((size_t)kRowSmemHead + (size_t)groups * 128 + (size_t)T * (L + 1)) +
-           sizeof(double) * ((size_t)T * (L + 1) + 2 * (size_t)(groups - 1) * (size_t)T * (size_t)L);
+           sizeof(double) * ((size_t)T * (L + 1) + (groups > 1 ? 2 * (size_t)T * (size_t)L : 0));
 }
 
 // s[0..1] += P * (v0, v1), P a 2x2 matrix (row-major) in LDS
@@ -125,7 +125,7 @@ __device__ __forceinline__ void hrow2(const GPParams &p, const RowCoef &c, const
     // distinct banks; a thread's L values sit at immediate offsets)
     double *taus = (double *)(sm + kRowSmemHead + (size_t)groups * 128) + (size_t)t * (L + 1);  // taus[i]
     double *comb = (double *)(sm + kRowSmemHead + (size_t)groups * 128) + (size_t)T * (L + 1);
-    float *otop = (float *)(comb + 2 * (size_t)(groups - 1) * (size_t)T * L) + (size_t)t * (L + 1);  // otop[i]
+    float *otop = (float *)(comb + (groups > 1 ? 2 * (size_t)T * L : 0)) + (size_t)t * (L + 1);  // otop[i]
 
     // the coefficient tables go through LDS (as kernel arguments held in
     // scalar registers they would spill)
@@ -469,25 +469,27 @@ __device__ __forceinline__ void hrow2(const GPParams &p, const RowCoef &c, const
         }
     }
     if (groups > 1) {
-        // parts of groups 1.. in the full sums, through LDS
-        if (g > 0) {
-#pragma unroll
-            for (int i = 0; i < L; ++i) {
-                const double tv = taus[i];
-                const double tp = ipow(tv, cb - 1);  // tau^(cb - 1)
-                comb[((size_t)(g - 1) * 2 * L + 2 * i) * T + t] = bD[i] * (tp * tv);
-                comb[((size_t)(g - 1) * 2 * L + 2 * i + 1) * T + t] = (double)cb * tp * bP[i] + tp * tv * bC[i];
-            }
-        }
-        __syncthreads();
-        if (g == 0) {
-            for (int gg = 1; gg < groups; ++gg) {
+        // the parts of groups 1.. in the full sums, handed to group 0 one
+        // group at a time through one LDS buffer and added in group order
+        for (int gg = 1; gg < groups; ++gg) {
+            if (g == gg) {
 #pragma unroll
                 for (int i = 0; i < L; ++i) {
-                    bD[i] += comb[((size_t)(gg - 1) * 2 * L + 2 * i) * T + t];
-                    bC[i] += comb[((size_t)(gg - 1) * 2 * L + 2 * i + 1) * T + t];
+                    const double tv = taus[i];
+                    const double tp = ipow(tv, cb - 1);  // tau^(cb - 1)
+                    comb[(size_t)(2 * i) * T + t] = bD[i] * (tp * tv);
+                    comb[(size_t)(2 * i + 1) * T + t] = (double)cb * tp * bP[i] + tp * tv * bC[i];
                 }
             }
+            __syncthreads();
+            if (g == 0) {
+#pragma unroll
+                for (int i = 0; i < L; ++i) {
+                    bD[i] += comb[(size_t)(2 * i) * T + t];
+                    bC[i] += comb[(size_t)(2 * i + 1) * T + t];
+                }
+            }
+            __syncthreads();
         }
     }
     if (g == 0 && y < p.H) {

@@ -230,7 +230,10 @@ def test_fir_radius_rule():
 def test_iir_shape_rule_and_overrides():
     # automatic shapes: small images split the channels over more waves
     assert bf.iir_shape(1024, 1024, 20) == dict(band_rows=32, col_groups=4, row_chunk=16, row_threads=64,
-                                                row_groups=2)
+                                                row_groups=3)
+    # row groups fill three waves per SIMD once (1024 SIMDs): no more
+    assert bf.iir_shape(900, 1000, 20)["row_groups"] == 3
+    assert bf.iir_shape(1500, 900, 20)["row_groups"] == 2
     assert bf.iir_shape(4096, 4096, 20) == dict(band_rows=64, col_groups=1, row_chunk=16, row_threads=256,
                                                 row_groups=1)
     assert bf.iir_shape(512, 512, 20)["col_groups"] == 8
