@@ -91,7 +91,7 @@ def test_iir_launch_shapes(bf, shape):
     ref = oracle_gp(img, 6.0, 25.0, 20, "iir")
     outs = {}
     try:
-        for tune in [(0, 0, 0), (32, 1, 1), (64, 0, 0), (64, 1, 1), (64, 3, 2), (64, 8, 4), (32, 2, 8)]:
+        for tune in [(0, 0, 0), (32, 1, 1), (64, 0, 0), (64, 1, 1), (64, 3, 2), (64, 8, 4), (32, 2, 8), (32, 4, 3)]:
             bf.set_iir_tuning(*tune)
             note(f"iir tuning {tune} shape {bf.iir_shape(H, W, 20)}")
             outs[tune] = run(bf, img, 6.0, 25.0, 20, "iir")
