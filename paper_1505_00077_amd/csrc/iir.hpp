@@ -423,9 +423,10 @@ __device__ __forceinline__ void vagg_moments(const GPParams &p, int col, int ban
 #pragma unroll
         for (int k = 0; k < 8; ++k) acc[n][k] = 0.f;
     constexpr int NR = B + 3;
-    // the next sample's prologue and weights are read one step ahead; the
-    // reads past the band's last sample land in the next array of the LDS
-    // (or its pad row) and are not used
+    // the next sample's prologue and weights are read one step ahead; past
+    // the band's last sample these reads land in the weight table's pad row
+    // (or, for a table in LDS, in the prologue after it) and in the next
+    // prologue array or the LDS pad row, and are not used
     float xn = pro[lane], gn = pro[NR * 64 + lane];
     float4 w0n = *(const float4 *)wts, w1n = *(const float4 *)(wts + 4);
 #pragma unroll 1
